@@ -1,0 +1,131 @@
+"""Exact solutions and initial fields of Maxwell's equations (problem data only).
+
+Field layouts: 3D u = (Ex, Ey, Ez, Hx, Hy, Hz); 2D TE u = (Ex, Ey, Hz).
+Each exact solution is an object with
+  u(x, t)        -> (..., nc) field values at points x (..., d) and time t
+  dt(x, t, k)    -> k-th time derivative (plane waves only; used as boundary data)
+"""
+import numpy as np
+
+
+class PlaneWaveTE:
+    """2D TE plane wave  Hz = amp*sqrt(eps/mu) cos(psi), E = amp*(-dy, dx) cos(psi),
+    psi = k (d.x) - omega t + phase, omega = k / sqrt(eps mu)."""
+
+    def __init__(self, direction=(1.0, 1.0), k=2 * np.pi, amp=1.0, phase=0.0, eps=1.0, mu=1.0):
+        dvec = np.asarray(direction, dtype=np.float64)
+        self.d = dvec / np.linalg.norm(dvec)
+        self.k, self.amp, self.phase = float(k), float(amp), float(phase)
+        self.eps, self.mu = float(eps), float(mu)
+        self.omega = self.k / np.sqrt(self.eps * self.mu)
+
+    def dt(self, x, t, n=0):
+        x = np.asarray(x, dtype=np.float64)
+        psi = self.k * (x @ self.d) - self.omega * t + self.phase
+        s = self.omega ** n * np.cos(psi - n * np.pi / 2)
+        out = np.empty(x.shape[:-1] + (3,))
+        out[..., 0] = -self.d[1] * self.amp * s
+        out[..., 1] = self.d[0] * self.amp * s
+        out[..., 2] = self.amp * np.sqrt(self.eps / self.mu) * s
+        return out
+
+    def u(self, x, t):
+        return self.dt(x, t, 0)
+
+
+class PlaneWave3D:
+    """3D plane wave  E = aE cos(psi), H = sqrt(eps/mu) d x aE cos(psi), aE orthogonal to d."""
+
+    def __init__(self, direction=(1.0, 0.0, 0.0), k=2 * np.pi, amp_e=(0.0, 1.0, 0.0), phase=0.0, eps=1.0, mu=1.0):
+        dvec = np.asarray(direction, dtype=np.float64)
+        self.d = dvec / np.linalg.norm(dvec)
+        a = np.asarray(amp_e, dtype=np.float64)
+        self.aE = a - (a @ self.d) * self.d
+        self.k, self.phase, self.eps, self.mu = float(k), float(phase), float(eps), float(mu)
+        self.omega = self.k / np.sqrt(self.eps * self.mu)
+        self.aH = np.sqrt(self.eps / self.mu) * np.cross(self.d, self.aE)
+
+    def dt(self, x, t, n=0):
+        x = np.asarray(x, dtype=np.float64)
+        psi = self.k * (x @ self.d) - self.omega * t + self.phase
+        s = self.omega ** n * np.cos(psi - n * np.pi / 2)
+        return np.concatenate([s[..., None] * self.aE, s[..., None] * self.aH], axis=-1)
+
+    def u(self, x, t):
+        return self.dt(x, t, 0)
+
+
+class CavityTE_PMC:
+    """TE dual of the paper's 2D TM cavity mode on [0, pi]^2 (eps = mu = 1), exact with
+    magnetic walls:  Hz = sin x sin y cos(sqrt2 t),
+    Ex = (1/sqrt2) sin x cos y sin(sqrt2 t),  Ey = -(1/sqrt2) cos x sin y sin(sqrt2 t)."""
+
+    def u(self, x, t):
+        x = np.asarray(x, dtype=np.float64)
+        X, Y = x[..., 0], x[..., 1]
+        w = np.sqrt(2.0)
+        out = np.empty(x.shape[:-1] + (3,))
+        out[..., 0] = np.sin(X) * np.cos(Y) * np.sin(w * t) / w
+        out[..., 1] = -np.cos(X) * np.sin(Y) * np.sin(w * t) / w
+        out[..., 2] = np.sin(X) * np.sin(Y) * np.cos(w * t)
+        return out
+
+
+class CavityTE_PEC:
+    """TE cavity mode on the unit square with perfectly conducting walls (eps = mu = 1):
+    Hz = cos(pi x) cos(pi y) cos(w t), w = sqrt2 pi,
+    Ex = -(1/sqrt2) cos(pi x) sin(pi y) sin(w t), Ey = (1/sqrt2) sin(pi x) cos(pi y) sin(w t)."""
+
+    def u(self, x, t):
+        x = np.asarray(x, dtype=np.float64)
+        X, Y = np.pi * x[..., 0], np.pi * x[..., 1]
+        w = np.sqrt(2.0) * np.pi
+        out = np.empty(x.shape[:-1] + (3,))
+        out[..., 0] = -np.cos(X) * np.sin(Y) * np.sin(w * t) / np.sqrt(2.0)
+        out[..., 1] = np.sin(X) * np.cos(Y) * np.sin(w * t) / np.sqrt(2.0)
+        out[..., 2] = np.cos(X) * np.cos(Y) * np.cos(w * t)
+        return out
+
+
+class Cavity3D_PEC:
+    """Unit-cube PEC cavity mode (eps = mu = 1):
+    E = (0, 0, sin(pi x) sin(pi y) cos(w t)), w = sqrt2 pi,
+    H = (sin(w t)/sqrt2) (-sin(pi x) cos(pi y), cos(pi x) sin(pi y), 0)."""
+
+    def u(self, x, t):
+        x = np.asarray(x, dtype=np.float64)
+        X, Y = np.pi * x[..., 0], np.pi * x[..., 1]
+        w = np.sqrt(2.0) * np.pi
+        out = np.zeros(x.shape[:-1] + (6,))
+        out[..., 2] = np.sin(X) * np.sin(Y) * np.cos(w * t)
+        s = np.sin(w * t) / np.sqrt(2.0)
+        out[..., 3] = -s * np.sin(X) * np.cos(Y)
+        out[..., 4] = s * np.cos(X) * np.sin(Y)
+        return out
+
+
+class GaussianPulse3D:
+    """Initial E = curl(a exp(-|x-x0|^2/(2 s^2))) (divergence free), H = 0;
+    a ~ N(0, I) normalised, x0 ~ U[0.35, 0.65]^3, s ~ U[0.06, 0.10]."""
+
+    def __init__(self, seed=11030):
+        rng = np.random.default_rng(seed)
+        a = rng.standard_normal(3)
+        self.a = a / np.linalg.norm(a)
+        self.x0 = rng.uniform(0.35, 0.65, size=3)
+        self.s = rng.uniform(0.06, 0.10)
+
+    def u(self, x, t=0.0):
+        x = np.asarray(x, dtype=np.float64)
+        r = x - self.x0
+        gfac = np.exp(-np.sum(r * r, axis=-1) / (2 * self.s ** 2))
+        grad = -(r / self.s ** 2) * gfac[..., None]   # grad of the Gaussian
+        E = np.cross(grad, self.a)                      # curl(a g) = grad g x a
+        out = np.zeros(x.shape[:-1] + (6,))
+        out[..., :3] = E
+        return out
+
+
+def nodal_fields(exact, nodes, t=0.0):
+    """Nodal values u(node, t) of an exact solution, shape (ne, Np, nc)."""
+    return exact.u(nodes, t)

@@ -1,0 +1,142 @@
+"""Synthetic simplicial meshes (seeded, deterministic).
+
+Every generator returns a dict with
+  coords : float64 (nv, d)   vertex coordinates
+  cells  : int32  (ne, d+1)  vertex ids of each simplex, positively oriented
+Boundary-condition kinds are given per (element, local face); local face j is the face
+opposite local vertex j.  The kind is only read for faces on the domain boundary.
+"""
+import itertools
+
+import numpy as np
+
+# boundary-condition kinds (same values as the C interface)
+PEC, PMC, DATA = 0, 1, 2
+
+
+def _orient(coords, cells):
+    """Swap two vertices of negatively oriented simplices so every det J > 0."""
+    X = coords[cells]
+    J = X[:, 1:, :] - X[:, :1, :]
+    det = np.linalg.det(J)
+    bad = det < 0
+    cells = cells.copy()
+    cells[bad, 0], cells[bad, 1] = cells[bad, 1].copy(), cells[bad, 0].copy()
+    return cells
+
+
+def square_tri(n, length=1.0, origin=(0.0, 0.0)):
+    """n x n squares on [ox, ox+L]^2, each split along its (0,0)-(1,1) diagonal."""
+    h = length / n
+    xs = origin[0] + h * np.arange(n + 1)
+    ys = origin[1] + h * np.arange(n + 1)
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    coords = np.stack([X.ravel(), Y.ravel()], axis=1)
+    vid = lambda i, j: j * (n + 1) + i  # noqa: E731
+    cells = []
+    for j in range(n):
+        for i in range(n):
+            v00, v10, v01, v11 = vid(i, j), vid(i + 1, j), vid(i, j + 1), vid(i + 1, j + 1)
+            cells.append((v00, v10, v11))
+            cells.append((v00, v11, v01))
+    cells = np.asarray(cells, dtype=np.int32)
+    return {"coords": coords, "cells": _orient(coords, cells)}
+
+
+def cube_kuhn(n, length=1.0, axis_map=None):
+    """n^3 cubes on [0,L]^3, each split into the 6 Kuhn (Freudenthal) tetrahedra that
+    share the cube's main diagonal; conforming across cubes.
+
+    axis_map, if given, maps the uniform lattice coordinate in [0, L] to a graded one
+    (applied to each axis)."""
+    g = np.linspace(0.0, length, n + 1)
+    if axis_map is not None:
+        g = axis_map(g)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    coords = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+    def vid(i, j, k):
+        return (i * (n + 1) + j) * (n + 1) + k
+
+    steps = np.eye(3, dtype=np.int64)
+    cells = []
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                for perm in itertools.permutations(range(3)):
+                    c = np.array([i, j, k])
+                    tet = [vid(*c)]
+                    for ax in perm:
+                        c = c + steps[ax]
+                        tet.append(vid(*c))
+                    cells.append(tet)
+    cells = np.asarray(cells, dtype=np.int32)
+    return {"coords": coords, "cells": _orient(coords, cells)}
+
+
+def graded_delaunay_cube(n=32, a=2.0 / 9.0, jitter=0.15, seed=11029):
+    """(n+1)^3 lattice on the unit cube graded toward the corner 0 by x -> a x + (1-a) x^2
+    per axis (h_max/h_min = (2-a)/a), interior points jittered by jitter*h_local
+    (tangential only on faces, none on edges/corners), Delaunay-triangulated.
+    Zero-volume simplices are dropped."""
+    from scipy.spatial import Delaunay
+
+    rng = np.random.default_rng(seed)
+    u = np.linspace(0.0, 1.0, n + 1)
+    g = a * u + (1.0 - a) * u * u
+    hloc = np.gradient(g)
+    I, J, K = np.meshgrid(np.arange(n + 1), np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    idx = np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1)
+    coords = g[idx]
+    h = np.min(hloc[idx], axis=1)
+    on_bnd = (idx == 0) | (idx == n)  # per axis: fixed coordinate
+    delta = rng.uniform(-1.0, 1.0, size=coords.shape) * jitter * h[:, None]
+    delta[on_bnd] = 0.0
+    coords = coords + delta
+    tri = Delaunay(coords, qhull_options="Qbb Qc Qz Q12")
+    cells = tri.simplices.astype(np.int32)
+    X = coords[cells]
+    vol = np.abs(np.linalg.det(X[:, 1:, :] - X[:, :1, :])) / 6.0
+    hmin = g[1] - g[0]
+    cells = cells[vol > 1e-9 * hmin ** 3]
+    return {"coords": coords, "cells": _orient(coords, cells)}
+
+
+def uniform_bc(ne, dim, kind):
+    """Per (element, local face) boundary kind array, all faces of one kind."""
+    return np.full((ne, dim + 1), kind, dtype=np.int32)
+
+
+def element_centroids(mesh):
+    return mesh["coords"][mesh["cells"]].mean(axis=1)
+
+
+def materials_split(mesh, eps_right=2.25, x_split=0.5):
+    """eps = eps_right where the element centroid has x > x_split, else 1; mu = 1."""
+    c = element_centroids(mesh)
+    eps = np.where(c[:, 0] > x_split, eps_right, 1.0)
+    mu = np.ones(len(eps))
+    return eps, mu
+
+
+def equispaced_nodes(mesh, p):
+    """Physical coordinates of the documented equispaced nodes, shape (ne, Np, d).
+
+    Node order (the interchange format of nodal fields): reference coordinates
+    (i/p, j/p[, k/p]) with i fastest, then j, then k, restricted to i+j(+k) <= p;
+    x = v0 + sum_l xhat_l (v_l - v0) with v the element's vertices in cell order."""
+    d = mesh["coords"].shape[1]
+    pts = []
+    if d == 2:
+        for j in range(p + 1):
+            for i in range(p + 1 - j):
+                pts.append((i / p, j / p))
+    else:
+        for k in range(p + 1):
+            for j in range(p + 1 - k):
+                for i in range(p + 1 - j - k):
+                    pts.append((i / p, j / p, k / p))
+    ref = np.asarray(pts)
+    X = mesh["coords"][mesh["cells"]]  # (ne, d+1, d)
+    J = X[:, 1:, :] - X[:, :1, :]      # rows = v_l - v0
+    return X[:, :1, :] + np.einsum("nl,eld->end", ref, J)

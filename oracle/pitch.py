@@ -1,0 +1,114 @@
+"""Tent pitching for the oracle (section "Mesh generation by tent pitching").
+
+The paper fixes: the front is a P1 function given by one time per vertex; a tent moves
+one vertex up; its projection is the vertex patch; vertices at graph distance >= 2 can
+move independently; the advance is limited by causality (|grad phi| < sqrt(eps mu)),
+and the experiments bound the front slope by 1/(2c).  The paper defers the pitching
+algorithm to earlier work, so the concrete rule below is a documented reading that both
+implementations follow:
+
+  per element T:   k_T = sigma sqrt(eps_T mu_T) / min_i sum_{j != i} |grad lambda_j^T|
+  per edge (v,w):  k_vw = min over elements T containing the edge of k_T
+  repeat: take the vertex v with the smallest (tau_v, v) below t_end;
+          t_plus = min over neighbours w of (tau_w + k_vw);
+          t_new  = min(t_end, Q floor(t_plus / Q - 1e-3)),  Q = 2^-24;
+          emit tent (v, tau_v, t_new) in layer 1 + max(last layer of v and of its
+          neighbours); tau_v = t_new.
+
+Invariant: |tau_v - tau_w| <= k_vw on every edge, hence on every element
+grad phi = sum_{j != i} (tau_j - tau_i) grad lambda_j has |grad phi| <= sigma sqrt(eps mu)
+(the slope bound 1/(2c) for sigma = 1/2).  The minimum vertex always advances by at least
+min k_vw, so the rule never stalls.  Quantising times down to multiples of Q keeps the
+invariant and makes two implementations that round differently in the last bits emit
+identical tents.
+
+Pins: validate() checks every tent against the definitions (slope bound on every element
+after each move, heights positive, element-disjoint patches within a layer, layer order
+respects every dependency, flat final front); tests check small cases by hand.
+"""
+import heapq
+
+import numpy as np
+
+QUANTUM = 2.0 ** -24
+SAFETY = 1e-3
+
+
+def edge_steps(mesh, sigma):
+    """k_vw per vertex: list of (neighbour ids, k values) aligned with mesh.adj."""
+    norms = np.linalg.norm(mesh.grad_lam, axis=2)              # (ne, d+1)
+    sums = norms.sum(axis=1, keepdims=True) - norms             # sum over j != i
+    k_T = sigma * np.sqrt(mesh.eps * mesh.mu) / sums.min(axis=1)
+    kv = []
+    for v in range(mesh.nv):
+        nb = mesh.adj[v]
+        k = np.full(len(nb), np.inf)
+        pos = {int(w): i for i, w in enumerate(nb)}
+        for e in mesh.v2e[v]:
+            for w in mesh.cells[e]:
+                if w != v:
+                    i = pos[int(w)]
+                    k[i] = min(k[i], k_T[e])
+        kv.append(k)
+    return kv
+
+
+def pitch(mesh, t_end, sigma=0.5):
+    """Pitch tents from the flat front 0 to the flat front t_end.
+
+    Returns dict with int arrays vertex, layer and float arrays t_bot, t_top, in
+    emission order."""
+    nv = mesh.nv
+    tau = np.zeros(nv)
+    kv = edge_steps(mesh, sigma)
+    last_layer = -np.ones(nv, dtype=np.int64)
+    heap = [(0.0, v) for v in range(nv)]
+    heapq.heapify(heap)
+    V, TB, TT, L = [], [], [], []
+    while heap:
+        tv, v = heapq.heappop(heap)
+        if tv >= t_end:
+            continue
+        nb = mesh.adj[v]
+        t_plus = np.min(tau[nb] + kv[v])
+        t_new = min(t_end, QUANTUM * np.floor(t_plus / QUANTUM - SAFETY))
+        if not t_new > tv:
+            raise RuntimeError(f"vertex {v} cannot advance")
+        lay = 1 + max(last_layer[v], int(np.max(last_layer[nb])))
+        last_layer[v] = lay
+        V.append(v)
+        TB.append(tv)
+        TT.append(t_new)
+        L.append(lay)
+        tau[v] = t_new
+        if t_new < t_end:
+            heapq.heappush(heap, (t_new, v))
+    return {"vertex": np.asarray(V, dtype=np.int64), "t_bot": np.asarray(TB),
+            "t_top": np.asarray(TT), "layer": np.asarray(L, dtype=np.int64)}
+
+
+def validate(mesh, tents, t_end, sigma=0.5, rtol=1e-12):
+    """Check a tent list against the definitions; raises AssertionError on violation."""
+    s_T = sigma * np.sqrt(mesh.eps * mesh.mu)
+    tau = np.zeros(mesh.nv)
+    V, TB, TT, L = tents["vertex"], tents["t_bot"], tents["t_top"], tents["layer"]
+    # replay in layer order (stable), which must be a valid execution order
+    order = np.argsort(L, kind="stable")
+    last = -np.ones(mesh.nv, dtype=np.int64)
+    for i in order:
+        v = int(V[i])
+        assert TT[i] > TB[i], f"tent {i}: non-positive height"
+        assert tau[v] == TB[i], f"tent {i}: bottom time {TB[i]} != front {tau[v]}"
+        tau[v] = TT[i]
+        for e in mesh.v2e[v]:
+            g = tau[mesh.cells[e]] @ mesh.grad_lam[e]
+            assert np.linalg.norm(g) <= s_T[e] * (1 + rtol), f"tent {i}: slope bound on element {e}"
+        # layers respect dependencies: previous tents at v or neighbours are in earlier layers
+        prev = max(last[v], int(np.max(last[mesh.adj[v]])))
+        assert L[i] > prev, f"tent {i}: layer {L[i]} not after a dependency in layer {prev}"
+        last[v] = L[i]
+    assert np.all(tau == t_end), "final front is not flat at t_end"
+    for lay in np.unique(L):
+        els = np.concatenate([mesh.v2e[int(v)] for v in V[L == lay]])
+        assert len(els) == len(np.unique(els)), f"layer {lay}: patches overlap"
+    return True
