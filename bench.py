@@ -1,0 +1,150 @@
+"""Benchmark of the MTP tent sweep on one MI355X.
+
+One step = one slab: every layer of the tent table from a flat front to the flat front
+one slab height later (all tents: gather, SAT stages, scatter).  Inputs are resident in
+HBM before the timed region.  Prints one JSON line.
+
+Workload (default): 3D PEC cavity, unit cube 16^3 x 6 Kuhn tetrahedra (24576 tets),
+P3 DG, q = 4 Taylor stages, m = 6 sub-intervals, slab height T = 1, FP64.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6  # TFLOP/s, MI355X FP64 vector and matrix
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from mtp_inputs import fields, meshes
+    if name == "cavity3d_p3":
+        mm = meshes.cube_kuhn(16)
+        desc = "3D PEC cavity mode, unit cube 16^3x6 Kuhn tets (24576), P3, q=4, m=6, slab T=1, FP64"
+        return dict(mm=mm, p=3, q=4, m=6, T=1.0, ex=fields.Cavity3D_PEC(), desc=desc)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(W, budget_s):
+    """The oracle as it stands, on the first tents of the same workload (layer order),
+    until budget_s of CPU time; one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from mtp_inputs import meshes
+    from oracle.mesh import Mesh as OMesh
+    from oracle.pitch import pitch as opitch
+    from oracle.solve import OracleSolver
+    with threadpool_limits(limits=1):
+        om = OMesh(W["mm"]["coords"], W["mm"]["cells"])
+        tents = opitch(om, W["T"], 0.5)
+        O = OracleSolver(om, W["p"], W["q"], W["m"])
+        O.set_nodal_u(W["ex"].u(meshes.equispaced_nodes(W["mm"], W["p"]), 0.0))
+        order = np.argsort(tents["layer"], kind="stable")
+        nc, npn = 6, (W["p"] + 1) * (W["p"] + 2) * (W["p"] + 3) // 6
+        dofs, done = 0.0, 0
+        t0 = time.perf_counter()
+        for i in order:
+            v = int(tents["vertex"][i])
+            O.run_tent(v, float(tents["t_top"][i]))
+            dofs += nc * npn * len(om.v2e[v]) * W["m"] * W["q"]
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        el = time.perf_counter() - t0
+    return {"value": dofs / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {done} tents (layer order) of the same workload, {el:.1f} s, numpy FP64, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cavity3d_p3")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(sharding is described in the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from mtp_inputs import meshes
+    from paper_1906_11029_amd import mtp
+
+    W = workload(args.workload)
+    mm = W["mm"]
+    t0 = time.perf_counter()
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    T = mtp.Tents(M, W["T"], 0.5)
+    t_pitch = time.perf_counter() - t0
+    S = mtp.Solver(M, T, W["p"], W["q"], W["m"])
+    u0 = W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), 0.0)
+    S.set_fields(u0, 0.0)
+    dof_slab, n_tents = S.slab_dof_updates()
+    flops_slab = S.slab_flops()
+    log(f"mesh {M.info} tents {n_tents} layers {T.n_layers} pitch {t_pitch:.2f}s")
+
+    front = 0.0
+    for _ in range(args.warmup):
+        front += W["T"]
+        S.advance_to(front)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    nl = T.n_layers
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps * nl + 1)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    evs[0].record(stream)
+    k = 1
+    for _ in range(args.steps):
+        for l in range(nl):
+            S.layer_advance(l)
+            evs[k].record(stream)
+            k += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    durs = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps * nl)]) * 1e-3
+    kern_avg = durs.mean()
+    flops_avg = flops_slab / nl
+    achieved = flops_avg / kern_avg / 1e12
+
+    u = S.get_fields()
+    err = np.linalg.norm(u - W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), (args.warmup + args.steps) * W["T"]))
+    err /= np.linalg.norm(u)
+    log(f"wall {wall:.3f}s for {args.steps} slabs; sum of launch intervals {durs.sum():.3f}s; "
+        f"nodal rel. error vs exact {err:.2e}")
+
+    value = dof_slab * args.steps / wall
+    out = {
+        "metric": "DOF-updates/s, 3D Maxwell p=4 MTP: mixed/batched vs FP64 GPU at equal L2 error",
+        "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": W["desc"], "tets": int(M.info["ne"]), "p": W["p"], "q": W["q"], "m": W["m"],
+                   "tents_per_step": int(n_tents), "layers_per_step": int(nl), "slope_fraction": 0.5,
+                   "nodal_rel_error_vs_exact": float(err)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64, "traffic": None,
+                     "kernel": "tent_kernel (one launch per layer)",
+                     "avg_launch_ms": kern_avg * 1e3, "launches": int(args.steps * nl)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

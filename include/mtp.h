@@ -1,0 +1,159 @@
+/*
+ * mtp.h -- C interface of the MI355X (gfx950) library for explicit mapped tent pitching
+ * (MTP) with structure-aware Taylor (SAT) time stepping for DG Maxwell.
+ *
+ * Method (Gopalakrishnan, Hochsteger, Schoeberl, Wintersteiger, "An Explicit Mapped Tent
+ * Pitching Scheme for Maxwell Equations"):
+ *   - section 2: the front is a P1 function (one time per vertex); a tent moves one
+ *     vertex up; its spatial projection is the vertex patch; tents at vertices of graph
+ *     distance >= 2 are independent and form a layer;
+ *   - section 3: each tent is mapped to the cylinder patch x (0,1) by
+ *     phi = (1-t) phi_b + t phi_t; the pulled-back system
+ *     d_t (g(u) - f(u) grad phi) + div(delta f(u)) = 0, delta = phi_t - phi_b, is
+ *     discretised by upwind DG of degree p, giving d/dt (M U) = A U;
+ *   - section 4: q-stage SAT on m sub-intervals (eqs. coeff_rec, recursion-init) with
+ *     the closed-form pointwise inverse of the mass form; Y = M U passes unchanged
+ *     from one tent to the next.
+ *
+ * Conventions
+ *   - Every call returns an mtp_status (0 = MTP_OK, < 0 error) and never aborts;
+ *     mtp_last_error() returns a thread-local message for the last failure.
+ *   - Arrays passed in are copied; the caller keeps ownership.  Handles are owned by
+ *     the caller and released with the matching *_destroy.
+ *   - Device memory comes from the caller: mtp_solver_workspace_size() reports the
+ *     bytes, the caller allocates them (e.g. a torch uint8 tensor) and passes the
+ *     device pointer to mtp_solver_create(); the library allocates no device memory.
+ *     All device work is enqueued on the hip stream given at creation.
+ *   - Field arrays in the interchange format are (ne, Np, nc) doubles: for each element
+ *     its Np nodal values, each node holding the nc components (3D: Ex Ey Ez Hx Hy Hz;
+ *     2D TE: Ex Ey Hz).  Nodes: reference coordinates (i/p, j/p[, k/p]), i fastest, then
+ *     j, then k, with i+j(+k) <= p, mapped by x = v0 + sum_l xhat_l (v_l - v0) with the
+ *     element's vertices in the order given to mtp_mesh_create.
+ *   - Cells: (ne, dim+1) vertex ids; local face j is the face opposite local vertex j.
+ */
+#ifndef MTP_H
+#define MTP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mtp_status;
+typedef struct mtp_mesh_s* mtp_mesh;
+typedef struct mtp_tents_s* mtp_tents;
+typedef struct mtp_solver_s* mtp_solver;
+
+enum {
+  MTP_OK = 0,
+  MTP_ERR_ARG = -1,         /* invalid argument (null pointer, size, range)            */
+  MTP_ERR_MESH = -2,        /* non-conforming mesh, degenerate element, bad face kind  */
+  MTP_ERR_CAUSALITY = -3,   /* slope fraction outside (0,1): tents would not be causal */
+  MTP_ERR_PITCH = -4,       /* pitching made no progress                               */
+  MTP_ERR_NONFINITE = -5,   /* non-finite field values                                 */
+  MTP_ERR_DEVICE = -6,      /* HIP runtime error or a device-side check failed         */
+  MTP_ERR_STATE = -7,       /* call out of order (e.g. advancing past the tent table)  */
+  MTP_ERR_UNSUPPORTED = -9  /* (dim, p) or patch size outside what the kernels cover   */
+};
+
+/* boundary-condition kinds of boundary faces */
+enum { MTP_BC_PEC = 0, MTP_BC_PMC = 1, MTP_BC_DATA = 2 };
+
+/* arithmetic of the tent kernels */
+enum { MTP_FP64 = 0 };
+
+/* Conforming simplicial mesh (section 2).  dim = 2 (triangles, TE fields) or 3 (tets).
+ * coords (nv*dim), cells (ne*(dim+1)), eps/mu (ne) per-element material constants,
+ * face_bc (ne*(dim+1)) boundary kind per local face, read only where the face lies on the
+ * domain boundary; NULL means PEC everywhere.  Errors: MTP_ERR_ARG, MTP_ERR_MESH
+ * (zero-volume element, a face shared by more than two elements, eps or mu <= 0). */
+mtp_status mtp_mesh_create(int32_t dim, int64_t nv, const double* coords, int64_t ne,
+                           const int32_t* cells, const double* eps, const double* mu,
+                           const int32_t* face_bc, mtp_mesh* out);
+mtp_status mtp_mesh_info(mtp_mesh mesh, int32_t* dim, int64_t* nv, int64_t* ne,
+                         int32_t* max_patch);
+void mtp_mesh_destroy(mtp_mesh mesh);
+
+/* Tent pitching on the host (section 2), from the flat front t = 0 to the flat front
+ * t = t_end.  Rule (the paper defers the algorithm to earlier work; this is the
+ * library's documented choice): per element k_T = slope_fraction*sqrt(eps mu) /
+ * min_i sum_{j!=i} |grad lambda_j|, per edge k_vw = min over its elements; repeatedly
+ * the vertex with the smallest (time, id) moves to min(t_end, Q floor((min over
+ * neighbours w of tau_w + k_vw)/Q - 1e-3)), Q = 2^-24, in layer 1 + the largest layer
+ * of itself and its neighbours.  Keeps |grad tau| <= slope_fraction*sqrt(eps mu) on every
+ * element (the paper's experiments use 1/2).  Errors: MTP_ERR_ARG (t_end <= 0),
+ * MTP_ERR_CAUSALITY (slope_fraction not in (0,1)), MTP_ERR_PITCH. */
+mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_end, double slope_fraction, mtp_tents* out);
+/* n_tents, n_layers; layer_ptr (n_layers+1 entries, may be NULL) receives the start of
+ * each layer in the layer-sorted tent order used by mtp_tents_export. */
+mtp_status mtp_tents_query(mtp_tents tents, int64_t* n_tents, int64_t* n_layers, int64_t* layer_ptr);
+/* Tent list sorted by layer (stable in pitching order): central vertex, bottom and top
+ * time, layer.  Any pointer may be NULL. */
+mtp_status mtp_tents_export(mtp_tents tents, int32_t* vertex, double* t_bot, double* t_top,
+                            int32_t* layer);
+void mtp_tents_destroy(mtp_tents tents);
+
+/* Device workspace needed by a solver for (mesh, tents, p, q, m, precision). */
+mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q,
+                                     int32_t m, int32_t precision, size_t* bytes);
+/* Create a solver: spatial degree p (1..5 in 2D, 1..4 in 3D), Taylor order q >= 1 and
+ * m >= 1 sub-intervals per tent (section 4; the paper uses q = p+1, m = 2p), flux
+ * penalty alpha (1/2 is the exact upwind flux for unit impedance, 1 the printed
+ * coefficient).  d_workspace: device pointer of at least the reported bytes, owned by
+ * the caller and kept alive until mtp_solver_destroy.  hip_stream: a hipStream_t (NULL =
+ * default stream).  Uploads mesh, tents and reference operators; fields start at zero.
+ * Errors: MTP_ERR_ARG, MTP_ERR_UNSUPPORTED, MTP_ERR_DEVICE. */
+mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q, int32_t m,
+                             int32_t precision, double alpha, void* d_workspace, size_t bytes,
+                             void* hip_stream, mtp_solver* out);
+void mtp_solver_destroy(mtp_solver solver);
+
+/* Physical coordinates of the interchange nodes, host array (ne*Np*dim). */
+mtp_status mtp_node_coords(mtp_solver solver, double* xyz);
+
+/* Set the fields u on the flat front t0 (must be a multiple of the slab height times an
+ * integer, normally 0).  nodal: (ne, Np, nc) doubles, host pointer if on_device == 0,
+ * else a device pointer.  Stores w = g(u) (section 4: Y = MU continuous across tents).
+ * Errors: MTP_ERR_ARG, MTP_ERR_NONFINITE (host input), MTP_ERR_DEVICE. */
+mtp_status mtp_set_fields(mtp_solver solver, const double* nodal, int32_t on_device, double t0);
+
+/* Boundary data for MTP_BC_DATA faces: the plane wave
+ * u(x,t) = amp * cos(k.x - omega t + phase), amp = (E amplitude, H amplitude) with nc
+ * entries, kvec (dim entries), omega.  The ghost state on a data face of a tent is
+ * u(x, phi(x,t)), entering the SAT recursion through its t-derivatives
+ * delta^n d_t^n u (chain rule of the tent map), interpolated at the face nodes. */
+mtp_status mtp_set_planewave_bc(mtp_solver solver, const double* amp, const double* kvec,
+                                double omega, double phase);
+
+/* Enqueue the tents of one layer of the current slab (stream ordered, asynchronous). */
+mtp_status mtp_layer_advance(mtp_solver solver, int64_t layer);
+/* Enqueue whole slabs until the flat front reaches T (T must be the current front time
+ * plus a whole number of slab heights).  Asynchronous. */
+mtp_status mtp_advance_to(mtp_solver solver, double T);
+/* Current front time (flat) and number of layers done in the current slab. */
+mtp_status mtp_front(mtp_solver solver, double* t_front, int64_t* layers_done);
+
+/* Read-out on the current flat front: u = K(grad tau)^{-1} w node by node, written in the
+ * interchange format to a host (on_device == 0, synchronises the stream) or device
+ * pointer.  Also surfaces device-side error flags (MTP_ERR_DEVICE: a tent met
+ * eps*mu - |grad phi|^2 <= 0; MTP_ERR_NONFINITE). */
+mtp_status mtp_get_fields(mtp_solver solver, double* nodal, int32_t on_device);
+/* Raw state w (interchange layout), host or device pointer. */
+mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
+
+/* Spacetime DOF updates of one slab: sum over tents of nc*Np*n_T(tent)*m*q (the paper's
+ * spacetime DOF count, section 5), and the tent count. */
+mtp_status mtp_slab_dof_updates(mtp_solver solver, double* dof_updates, int64_t* n_tents);
+
+/* Algorithmic flop count of one slab, per the kernel's arithmetic (volume and lift
+ * contractions, flux, pointwise inverse, Taylor sum). */
+mtp_status mtp_slab_flops(mtp_solver solver, double* flops);
+
+const char* mtp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTP_H */

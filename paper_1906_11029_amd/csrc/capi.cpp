@@ -1,0 +1,507 @@
+// C interface (include/mtp.h): mesh, pitching, solver set-up, layer sweep, read-out.
+// Every entry point converts exceptions into an mtp_status and a thread-local message.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+struct mtp_mesh_s { mtp::Mesh m; };
+struct mtp_tents_s { mtp::Tents t; };
+
+namespace mtp {
+
+static thread_local std::string g_last_error;
+
+static void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(MTP_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device workspace layout: every array 256-byte aligned.
+struct Layout {
+  size_t off = 0;
+  size_t add(size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
+
+struct Offsets {
+  size_t W, tau, stage, grad_lam, cells, eps, mu, coords, pptr, pelem, pinfo, tv, tt, S, L, fnode,
+      perm, mi, err, total;
+};
+
+static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
+  Layout L;
+  Offsets o;
+  const int d = m.d;
+  const size_t ptot = m.v2e.size();
+  o.W = L.add(sizeof(double) * m.ne * nc * R.np);
+  o.tau = L.add(sizeof(double) * m.nv);
+  o.stage = L.add(sizeof(double) * m.ne * nc * R.np);
+  o.grad_lam = L.add(sizeof(double) * m.ne * (d + 1) * d);
+  o.cells = L.add(sizeof(int32_t) * m.ne * (d + 1));
+  o.eps = L.add(sizeof(double) * m.ne);
+  o.mu = L.add(sizeof(double) * m.ne);
+  o.coords = L.add(sizeof(double) * m.nv * d);
+  o.pptr = L.add(sizeof(int32_t) * (m.nv + 1));
+  o.pelem = L.add(sizeof(int32_t) * ptot);
+  o.pinfo = L.add(sizeof(int32_t) * ptot * (1 + d));
+  o.tv = L.add(sizeof(int32_t) * std::max<size_t>(1, t.vertex.size()));
+  o.tt = L.add(sizeof(double) * std::max<size_t>(1, t.vertex.size()));
+  o.S = L.add(sizeof(double) * R.S.size());
+  o.L = L.add(sizeof(double) * R.L.size());
+  o.fnode = L.add(sizeof(int32_t) * R.fnode.size());
+  o.perm = L.add(sizeof(int32_t) * R.perm.size());
+  o.mi = L.add(sizeof(int32_t) * R.mi.size());
+  o.err = L.add(sizeof(int32_t) * 4);
+  o.total = L.off;
+  return o;
+}
+
+// Static per-vertex patch tables: for every element of the patch of V, the local index
+// k of V and, for each face j (1..d) of the element renumbered with V first, the
+// patch-local neighbour, its face index in its own renumbering and the relative
+// orientation of the two faces' vertex orders (3D), or -1 - boundary kind.
+static void patch_tables(const Mesh& m, std::vector<int32_t>& ptr, std::vector<int32_t>& elem,
+                         std::vector<int32_t>& info) {
+  const int d = m.d, nv = d + 1;
+  ptr.assign(m.nv + 1, 0);
+  elem.assign(m.v2e.size(), 0);
+  info.assign(m.v2e.size() * (1 + d), 0);
+  for (int64_t v = 0; v <= m.nv; ++v) ptr[v] = (int32_t)m.v2e_ptr[v];
+  for (int64_t V = 0; V < m.nv; ++V) {
+    const int64_t b0 = m.v2e_ptr[V], b1 = m.v2e_ptr[V + 1];
+    for (int64_t i = b0; i < b1; ++i) {
+      const int32_t e = m.v2e[i];
+      const int k = m.v2e_k[i];
+      elem[i] = e;
+      int32_t* inf = &info[i * (1 + d)];
+      inf[0] = k;
+      int order[4];
+      vertex_order(d, k, order);
+      for (int jn = 1; jn <= d; ++jn) {
+        const int f = order[jn];  // original local face index
+        const int32_t e2 = m.nbr[e * nv + f];
+        if (e2 < 0) {
+          inf[jn] = -1 - m.face_bc[e * nv + f];
+          continue;
+        }
+        int64_t pos = -1;
+        for (int64_t q = b0; q < b1; ++q)
+          if (m.v2e[q] == e2) { pos = q - b0; break; }
+        if (pos < 0) throw Error(MTP_ERR_MESH, "face neighbour outside the vertex patch");
+        const int k2 = m.v2e_k[b0 + pos];
+        int order2[4];
+        vertex_order(d, k2, order2);
+        const int f2 = m.nbr_face[e * nv + f];
+        int j2 = -1;
+        for (int q = 1; q <= d; ++q)
+          if (order2[q] == f2) j2 = q;
+        if (j2 < 1) throw Error(MTP_ERR_MESH, "inconsistent face neighbour");
+        int o = 0;
+        if (d == 3) {
+          // the face's two vertices other than V, in e's renumbered order
+          int fv[2], c = 0;
+          for (int q = 1; q <= 3; ++q)
+            if (q != jn) fv[c++] = m.cells[e * nv + order[q]];
+          // their positions in e2's renumbered order
+          int p0 = -1, p1 = -1;
+          for (int q = 1; q <= 3; ++q) {
+            int g = m.cells[e2 * nv + order2[q]];
+            if (g == fv[0]) p0 = q;
+            if (g == fv[1]) p1 = q;
+          }
+          if (p0 < 0 || p1 < 0) throw Error(MTP_ERR_MESH, "face vertices do not match");
+          o = (p0 < p1) ? 0 : 1;
+        }
+        inf[jn] = (int32_t)((pos << 4) | (j2 << 1) | o);
+      }
+    }
+  }
+}
+
+}  // namespace mtp
+
+struct mtp_solver_s {
+  mtp::Mesh mesh;
+  mtp::Tents tents;
+  mtp::RefElem ref;
+  mtp::Offsets off;
+  mtp::KernelParams kp;
+  int p = 0, q = 0, m = 0, nc = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  int64_t slab = 0;          // completed slabs
+  int64_t layers_done = 0;   // layers done in the current slab
+  double t_base = 0.0;       // front time at the start of slab 0
+  bool has_data_faces = false;
+};
+
+using namespace mtp;
+
+#define MTP_TRY try {
+#define MTP_CATCH                                        \
+  }                                                      \
+  catch (const mtp::Error& e) {                          \
+    g_last_error = e.what();                             \
+    return e.code;                                       \
+  }                                                      \
+  catch (const std::exception& e) {                      \
+    g_last_error = e.what();                             \
+    return MTP_ERR_ARG;                                  \
+  }                                                      \
+  return MTP_OK;
+
+static void require(bool c, mtp_status code, const char* msg) {
+  if (!c) throw Error(code, msg);
+}
+
+extern "C" {
+
+const char* mtp_last_error(void) { return g_last_error.c_str(); }
+
+mtp_status mtp_mesh_create(int32_t dim, int64_t nv, const double* coords, int64_t ne, const int32_t* cells,
+                           const double* eps, const double* mu, const int32_t* face_bc, mtp_mesh* out) {
+  MTP_TRY
+  require(out && coords && cells, MTP_ERR_ARG, "null pointer");
+  require(dim == 2 || dim == 3, MTP_ERR_ARG, "dim must be 2 or 3");
+  require(nv > 0 && ne > 0 && nv < (1LL << 31) && ne < (1LL << 31), MTP_ERR_ARG, "bad sizes");
+  auto* h = new mtp_mesh_s();
+  try {
+    Mesh& m = h->m;
+    m.d = dim;
+    m.nv = nv;
+    m.ne = ne;
+    m.coords.assign(coords, coords + nv * dim);
+    m.cells.assign(cells, cells + ne * (dim + 1));
+    m.eps = eps ? std::vector<double>(eps, eps + ne) : std::vector<double>(ne, 1.0);
+    m.mu = mu ? std::vector<double>(mu, mu + ne) : std::vector<double>(ne, 1.0);
+    m.face_bc = face_bc ? std::vector<int32_t>(face_bc, face_bc + ne * (dim + 1))
+                        : std::vector<int32_t>(ne * (dim + 1), MTP_BC_PEC);
+    for (double c : m.coords) require(std::isfinite(c), MTP_ERR_MESH, "non-finite coordinate");
+    build_topology(m);
+  } catch (...) {
+    delete h;
+    throw;
+  }
+  *out = h;
+  MTP_CATCH
+}
+
+mtp_status mtp_mesh_info(mtp_mesh mesh, int32_t* dim, int64_t* nv, int64_t* ne, int32_t* max_patch) {
+  MTP_TRY
+  require(mesh, MTP_ERR_ARG, "null mesh");
+  if (dim) *dim = mesh->m.d;
+  if (nv) *nv = mesh->m.nv;
+  if (ne) *ne = mesh->m.ne;
+  if (max_patch) *max_patch = mesh->m.max_patch;
+  MTP_CATCH
+}
+
+void mtp_mesh_destroy(mtp_mesh mesh) { delete mesh; }
+
+mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_end, double slope_fraction, mtp_tents* out) {
+  MTP_TRY
+  require(mesh && out, MTP_ERR_ARG, "null pointer");
+  require(t_end > 0 && std::isfinite(t_end), MTP_ERR_ARG, "t_end must be positive");
+  require(slope_fraction > 0 && slope_fraction < 1, MTP_ERR_CAUSALITY, "slope fraction must be in (0,1)");
+  auto* h = new mtp_tents_s();
+  try {
+    pitch(mesh->m, t_end, slope_fraction, h->t);
+  } catch (...) {
+    delete h;
+    throw;
+  }
+  *out = h;
+  MTP_CATCH
+}
+
+mtp_status mtp_tents_query(mtp_tents tents, int64_t* n_tents, int64_t* n_layers, int64_t* layer_ptr) {
+  MTP_TRY
+  require(tents, MTP_ERR_ARG, "null tents");
+  const Tents& t = tents->t;
+  if (n_tents) *n_tents = (int64_t)t.vertex.size();
+  if (n_layers) *n_layers = (int64_t)t.layer_ptr.size() - 1;
+  if (layer_ptr) std::copy(t.layer_ptr.begin(), t.layer_ptr.end(), layer_ptr);
+  MTP_CATCH
+}
+
+mtp_status mtp_tents_export(mtp_tents tents, int32_t* vertex, double* t_bot, double* t_top, int32_t* layer) {
+  MTP_TRY
+  require(tents, MTP_ERR_ARG, "null tents");
+  const Tents& t = tents->t;
+  if (vertex) std::copy(t.vertex.begin(), t.vertex.end(), vertex);
+  if (t_bot) std::copy(t.t_bot.begin(), t.t_bot.end(), t_bot);
+  if (t_top) std::copy(t.t_top.begin(), t.t_top.end(), t_top);
+  if (layer) std::copy(t.layer.begin(), t.layer.end(), layer);
+  MTP_CATCH
+}
+
+void mtp_tents_destroy(mtp_tents tents) { delete tents; }
+
+static void check_config(const Mesh& m, int p, int q, int mm, int precision) {
+  require(precision == MTP_FP64, MTP_ERR_UNSUPPORTED, "only MTP_FP64 is available");
+  require(q >= 1 && q <= 32 && mm >= 1 && mm <= 1024, MTP_ERR_ARG, "q must be in 1..32 and m in 1..1024");
+  require(tent_kernel_supported(m.d, p), MTP_ERR_UNSUPPORTED, "degree p not covered for this dimension");
+  const size_t lds = tent_kernel_lds_bytes(m.d, p, m.max_patch);
+  require(lds <= 160 * 1024, MTP_ERR_UNSUPPORTED, "largest vertex patch does not fit the 160 KiB of LDS");
+  const int np = (m.d == 2) ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
+  const int block = (m.d == 2) ? 128 : 256;
+  require(m.max_patch * np <= block * 8, MTP_ERR_UNSUPPORTED, "largest vertex patch has too many nodes");
+}
+
+mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q, int32_t m,
+                                     int32_t precision, size_t* bytes) {
+  MTP_TRY
+  require(mesh && tents && bytes, MTP_ERR_ARG, "null pointer");
+  check_config(mesh->m, p, q, m, precision);
+  RefElem R = build_refelem(mesh->m.d, p);
+  *bytes = plan(mesh->m, tents->t, R, mesh->m.d == 3 ? 6 : 3).total;
+  MTP_CATCH
+}
+
+mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q, int32_t m, int32_t precision,
+                             double alpha, void* d_workspace, size_t bytes, void* hip_stream, mtp_solver* out) {
+  MTP_TRY
+  require(mesh && tents && out && d_workspace, MTP_ERR_ARG, "null pointer");
+  require(alpha >= 0 && std::isfinite(alpha), MTP_ERR_ARG, "alpha must be >= 0");
+  check_config(mesh->m, p, q, m, precision);
+  auto* s = new mtp_solver_s();
+  try {
+    s->mesh = mesh->m;
+    s->tents = tents->t;
+    s->ref = build_refelem(mesh->m.d, p);
+    s->p = p;
+    s->q = q;
+    s->m = m;
+    s->nc = mesh->m.d == 3 ? 6 : 3;
+    s->off = plan(s->mesh, s->tents, s->ref, s->nc);
+    require(bytes >= s->off.total, MTP_ERR_ARG, "workspace too small");
+    s->ws = static_cast<char*>(d_workspace);
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    const Mesh& M = s->mesh;
+    for (int64_t i = 0; i < M.ne * (M.d + 1); ++i)
+      if (M.nbr[i] < 0 && M.face_bc[i] == MTP_BC_DATA) s->has_data_faces = true;
+
+    std::vector<int32_t> pptr, pelem, pinfo;
+    patch_tables(M, pptr, pelem, pinfo);
+    auto up = [&](size_t off, const void* src, size_t n) {
+      if (n) check_hip(hipMemcpyAsync(s->ws + off, src, n, hipMemcpyHostToDevice, s->stream), "upload");
+    };
+    up(s->off.grad_lam, M.grad_lam.data(), M.grad_lam.size() * 8);
+    up(s->off.cells, M.cells.data(), M.cells.size() * 4);
+    up(s->off.eps, M.eps.data(), M.eps.size() * 8);
+    up(s->off.mu, M.mu.data(), M.mu.size() * 8);
+    up(s->off.coords, M.coords.data(), M.coords.size() * 8);
+    up(s->off.pptr, pptr.data(), pptr.size() * 4);
+    up(s->off.pelem, pelem.data(), pelem.size() * 4);
+    up(s->off.pinfo, pinfo.data(), pinfo.size() * 4);
+    up(s->off.tv, s->tents.vertex.data(), s->tents.vertex.size() * 4);
+    up(s->off.tt, s->tents.t_top.data(), s->tents.t_top.size() * 8);
+    up(s->off.S, s->ref.S.data(), s->ref.S.size() * 8);
+    up(s->off.L, s->ref.L.data(), s->ref.L.size() * 8);
+    up(s->off.fnode, s->ref.fnode.data(), s->ref.fnode.size() * 4);
+    up(s->off.perm, s->ref.perm.data(), s->ref.perm.size() * 4);
+    up(s->off.mi, s->ref.mi.data(), s->ref.mi.size() * 4);
+    check_hip(hipMemsetAsync(s->ws + s->off.W, 0, sizeof(double) * M.ne * s->nc * s->ref.np, s->stream), "memset");
+    check_hip(hipMemsetAsync(s->ws + s->off.tau, 0, sizeof(double) * M.nv, s->stream), "memset");
+    check_hip(hipMemsetAsync(s->ws + s->off.err, 0, 16, s->stream), "memset");
+
+    KernelParams& kp = s->kp;
+    std::memset(&kp, 0, sizeof(kp));
+    kp.d = M.d;
+    kp.p = p;
+    kp.q = q;
+    kp.m = m;
+    kp.nc = s->nc;
+    kp.np = s->ref.np;
+    kp.nf = s->ref.nf;
+    kp.alpha = alpha;
+    kp.grad_lam = reinterpret_cast<const double*>(s->ws + s->off.grad_lam);
+    kp.cells = reinterpret_cast<const int32_t*>(s->ws + s->off.cells);
+    kp.eps = reinterpret_cast<const double*>(s->ws + s->off.eps);
+    kp.mu = reinterpret_cast<const double*>(s->ws + s->off.mu);
+    kp.coords = reinterpret_cast<const double*>(s->ws + s->off.coords);
+    kp.patch_ptr = reinterpret_cast<const int32_t*>(s->ws + s->off.pptr);
+    kp.patch_elem = reinterpret_cast<const int32_t*>(s->ws + s->off.pelem);
+    kp.patch_info = reinterpret_cast<const int32_t*>(s->ws + s->off.pinfo);
+    kp.S = reinterpret_cast<const double*>(s->ws + s->off.S);
+    kp.L = reinterpret_cast<const double*>(s->ws + s->off.L);
+    kp.fnode = reinterpret_cast<const int32_t*>(s->ws + s->off.fnode);
+    kp.perm = reinterpret_cast<const int32_t*>(s->ws + s->off.perm);
+    kp.mi = reinterpret_cast<const int32_t*>(s->ws + s->off.mi);
+    kp.W = reinterpret_cast<double*>(s->ws + s->off.W);
+    kp.tau = reinterpret_cast<double*>(s->ws + s->off.tau);
+    kp.err = reinterpret_cast<int32_t*>(s->ws + s->off.err);
+    kp.tent_vertex = reinterpret_cast<const int32_t*>(s->ws + s->off.tv);
+    kp.tent_top = reinterpret_cast<const double*>(s->ws + s->off.tt);
+    kp.max_patch = M.max_patch;
+    check_hip(hipStreamSynchronize(s->stream), "upload sync");
+  } catch (...) {
+    delete s;
+    throw;
+  }
+  *out = s;
+  MTP_CATCH
+}
+
+void mtp_solver_destroy(mtp_solver solver) {
+  if (solver && solver->stream) (void)hipStreamSynchronize(solver->stream);
+  delete solver;
+}
+
+mtp_status mtp_node_coords(mtp_solver s, double* xyz) {
+  MTP_TRY
+  require(s && xyz, MTP_ERR_ARG, "null pointer");
+  const Mesh& M = s->mesh;
+  const int d = M.d, np = s->ref.np, p = s->p;
+  for (int64_t e = 0; e < M.ne; ++e)
+    for (int a = 0; a < np; ++a)
+      for (int i = 0; i < d; ++i) {
+        double x = 0.0;
+        for (int v = 0; v <= d; ++v)
+          x += (double)s->ref.mi[a * (d + 1) + v] / p * M.coords[M.cells[e * (d + 1) + v] * d + i];
+        xyz[(e * np + a) * d + i] = x;
+      }
+  MTP_CATCH
+}
+
+mtp_status mtp_set_fields(mtp_solver s, const double* nodal, int32_t on_device, double t0) {
+  MTP_TRY
+  require(s && nodal, MTP_ERR_ARG, "null pointer");
+  require(std::isfinite(t0), MTP_ERR_ARG, "t0 must be finite");
+  const Mesh& M = s->mesh;
+  const size_t n = (size_t)M.ne * s->ref.np * s->nc;
+  const double* src = nodal;
+  if (!on_device) {
+    for (size_t i = 0; i < n; ++i) require(std::isfinite(nodal[i]), MTP_ERR_NONFINITE, "non-finite field value");
+    check_hip(hipMemcpyAsync(s->ws + s->off.stage, nodal, n * 8, hipMemcpyHostToDevice, s->stream), "copy");
+    src = reinterpret_cast<const double*>(s->ws + s->off.stage);
+  }
+  check_hip(launch_set_fields(s->kp, M.ne, src, t0, M.nv, s->stream), "set_fields");
+  if (!on_device) check_hip(hipStreamSynchronize(s->stream), "sync");
+  s->t_base = t0;
+  s->slab = 0;
+  s->layers_done = 0;
+  MTP_CATCH
+}
+
+mtp_status mtp_set_planewave_bc(mtp_solver s, const double* amp, const double* kvec, double omega, double phase) {
+  MTP_TRY
+  require(s && amp && kvec, MTP_ERR_ARG, "null pointer");
+  for (int c = 0; c < s->nc; ++c) s->kp.pw_amp[c] = amp[c];
+  for (int i = 0; i < s->mesh.d; ++i) s->kp.pw_k[i] = kvec[i];
+  s->kp.pw_omega = omega;
+  s->kp.pw_phase = phase;
+  s->kp.has_data = 1;
+  MTP_CATCH
+}
+
+static void run_layer(mtp_solver s, int64_t layer) {
+  const Tents& T = s->tents;
+  const int64_t first = T.layer_ptr[layer], count = T.layer_ptr[layer + 1] - first;
+  s->kp.t_offset = s->t_base + s->slab * T.t_end;
+  check_hip(launch_tent_layer(s->kp, first, count, s->stream), "tent kernel");
+}
+
+mtp_status mtp_layer_advance(mtp_solver s, int64_t layer) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
+  const int64_t nl = (int64_t)s->tents.layer_ptr.size() - 1;
+  require(layer == s->layers_done && layer < nl, MTP_ERR_STATE, "layers must run in order");
+  run_layer(s, layer);
+  s->layers_done++;
+  if (s->layers_done == nl) {
+    s->layers_done = 0;
+    s->slab++;
+  }
+  MTP_CATCH
+}
+
+mtp_status mtp_advance_to(mtp_solver s, double T) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
+  const double h = s->tents.t_end;
+  const double now = s->t_base + s->slab * h;
+  const double k = (T - now) / h;
+  const int64_t nslab = (int64_t)std::llround(k);
+  require(std::fabs(k - (double)nslab) < 1e-9 && nslab >= 0, MTP_ERR_STATE,
+          "T must be the front time plus a whole number of slabs");
+  const int64_t nl = (int64_t)s->tents.layer_ptr.size() - 1;
+  for (int64_t j = 0; j < nslab; ++j) {
+    for (int64_t l = 0; l < nl; ++l) run_layer(s, l);
+    s->slab++;
+  }
+  MTP_CATCH
+}
+
+mtp_status mtp_front(mtp_solver s, double* t_front, int64_t* layers_done) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  if (t_front) *t_front = s->t_base + s->slab * s->tents.t_end;
+  if (layers_done) *layers_done = s->layers_done;
+  MTP_CATCH
+}
+
+static mtp_status read_out(mtp_solver s, double* nodal, int32_t on_device, int raw) {
+  MTP_TRY
+  require(s && nodal, MTP_ERR_ARG, "null pointer");
+  const Mesh& M = s->mesh;
+  const size_t n = (size_t)M.ne * s->ref.np * s->nc;
+  double* dst = on_device ? nodal : reinterpret_cast<double*>(s->ws + s->off.stage);
+  check_hip(launch_get_fields(s->kp, M.ne, dst, raw, s->stream), "get_fields");
+  int32_t err[4] = {0, 0, 0, 0};
+  check_hip(hipMemcpyAsync(err, s->ws + s->off.err, 16, hipMemcpyDeviceToHost, s->stream), "copy");
+  if (!on_device) check_hip(hipMemcpyAsync(nodal, dst, n * 8, hipMemcpyDeviceToHost, s->stream), "copy");
+  check_hip(hipStreamSynchronize(s->stream), "sync");
+  if (err[0] & ERRF_CAUSALITY) throw Error(MTP_ERR_DEVICE, "a tent met eps*mu - |grad phi|^2 <= 0");
+  if (err[1] & ERRF_NONFINITE) throw Error(MTP_ERR_NONFINITE, "non-finite field values");
+  MTP_CATCH
+}
+
+mtp_status mtp_get_fields(mtp_solver s, double* nodal, int32_t on_device) { return read_out(s, nodal, on_device, 0); }
+mtp_status mtp_get_state(mtp_solver s, double* nodal, int32_t on_device) { return read_out(s, nodal, on_device, 1); }
+
+mtp_status mtp_slab_dof_updates(mtp_solver s, double* dof_updates, int64_t* n_tents) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  const Mesh& M = s->mesh;
+  double tot = 0.0;
+  for (int32_t v : s->tents.vertex) tot += (double)(M.v2e_ptr[v + 1] - M.v2e_ptr[v]);
+  if (dof_updates) *dof_updates = tot * s->nc * s->ref.np * s->m * s->q;
+  if (n_tents) *n_tents = (int64_t)s->tents.vertex.size();
+  MTP_CATCH
+}
+
+mtp_status mtp_slab_flops(mtp_solver s, double* flops) {
+  MTP_TRY
+  require(s && flops, MTP_ERR_ARG, "null pointer");
+  const Mesh& M = s->mesh;
+  const int d = M.d, np = s->ref.np, nf = s->ref.nf, nc = s->nc;
+  // per element and stage: volume 2 d np^2 nc, lift 2 d np nf nc, A(grad lambda) on d
+  // directions (2 nc flops each per node), flux (about 40 flops per face node in 3D,
+  // 20 in 2D), pointwise inverse with the M' correction (about 60 flops per node in 3D,
+  // 25 in 2D), Taylor update 2 nc per node
+  const double vol = 2.0 * d * np * np * nc;
+  const double lift = 2.0 * d * np * nf * nc;
+  const double adir = 2.0 * d * nc * np;
+  const double flx = (d == 3 ? 40.0 : 20.0) * d * nf;
+  const double kin = (d == 3 ? 60.0 : 25.0) * np;
+  const double tay = 2.0 * nc * np;
+  double elem_tents = 0.0;
+  for (int32_t v : s->tents.vertex) elem_tents += (double)(M.v2e_ptr[v + 1] - M.v2e_ptr[v]);
+  *flops = elem_tents * s->m * s->q * (vol + lift + adir + flx + kin + tay);
+  MTP_CATCH
+}
+
+}  // extern "C"

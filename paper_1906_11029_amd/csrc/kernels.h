@@ -1,0 +1,54 @@
+// Device-side parameter blocks shared by the host solver and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mtp {
+
+struct KernelParams {
+  int d, p, q, m, nc, np, nf;
+  double alpha;
+  // mesh
+  const double* grad_lam;  // ne*(d+1)*d
+  const int32_t* cells;    // ne*(d+1)
+  const double* eps;       // ne
+  const double* mu;        // ne
+  const double* coords;    // nv*d
+  // vertex patches (static): per entry element id and info = [k, fcode_1..fcode_d]
+  //   fcode >= 0: (patch-local neighbour << 4) | (neighbour face (1..d) << 1) | orientation
+  //   fcode <  0: -1 - boundary kind
+  const int32_t* patch_ptr;
+  const int32_t* patch_elem;
+  const int32_t* patch_info;
+  // reference tables
+  const double* S;         // d*np*np [l][a][b]
+  const double* L;         // d*nf*np [j][s][b]
+  const int32_t* fnode;    // d*2*nf
+  const int32_t* perm;     // (d+1)*np
+  const int32_t* mi;       // np*(d+1)
+  // state
+  double* W;               // ne*nc*np  [e][c][node]
+  double* tau;             // nv
+  int32_t* err;            // device error flags
+  // tents of the launch
+  const int32_t* tent_vertex;
+  const double* tent_top;
+  double t_offset;
+  // plane-wave boundary data
+  int has_data;
+  double pw_amp[6], pw_k[3], pw_omega, pw_phase;
+  int max_patch;
+};
+
+// error flag bits
+enum { ERRF_CAUSALITY = 1, ERRF_NONFINITE = 2 };
+
+size_t tent_kernel_lds_bytes(int d, int p, int max_patch);
+bool tent_kernel_supported(int d, int p);
+hipError_t launch_tent_layer(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s);
+hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
+                             int64_t nv, hipStream_t s);
+hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);
+
+}  // namespace mtp

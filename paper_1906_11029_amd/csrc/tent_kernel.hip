@@ -1,0 +1,599 @@
+// HIP kernels for gfx950: the per-tent SAT evolution of mapped-tent DG Maxwell, and
+// the set / read-out conversions of the state.
+//
+// One workgroup advances one tent (one launch per layer; the tents of a layer have
+// element-disjoint patches, section 2).  For a tent at vertex V with height H:
+//   - every patch element is renumbered so that V is its local vertex 0 (node gather
+//     through a permutation table), so all elements share the reference operators
+//     S_l (volume) and L_j (lift) staged once in LDS;
+//   - per element: grad phi_b = sum_i tau_i grad lambda_i, b' = grad delta = H grad lambda_V,
+//     b_i = grad phi_b + (i/m) b'  (the tent map's gradient at the sub-interval start);
+//   - SAT (section 4, eqs. coeff_rec and recursion-init) with the state w = nodal values
+//     of g(u) - f(u) grad phi (Y with the element mass divided out):
+//       U_{i,0} = K(b_i)^{-1} W                                (closed form, FP64)
+//       Y_{i,n} = H [ sum_l A(grad lambda_l) S_l U - sum_j L_j G_j(U) ]   n = 1..q
+//       U_{i,n} = K(b_i)^{-1} (Y_{i,n} + n A(b') U_{i,n-1})    n = 1..q-1 (M'U = -A(b')U)
+//       W <- sum_n Y_{i,n} / (m^n n!)                          (Taylor sum, FP64)
+//     where G_j is the upwind flux times |grad lambda_j| at the face nodes of the faces
+//     containing V (faces of the patch boundary carry delta = 0 and are skipped);
+//   - scatter W back and set tau_V = t_top.
+// The patch state U lives in LDS; each thread owns (element, node) pairs and keeps the
+// Taylor accumulator in registers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace mtp {
+
+namespace {
+
+template <int D> struct Dims;
+template <> struct Dims<2> { static constexpr int NC = 3; };
+template <> struct Dims<3> { static constexpr int NC = 6; };
+
+__host__ __device__ constexpr int binom_c(int n, int k) {
+  int r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+// A(g) u = f(u) g : 3D (H x g, g x E);  2D TE (-g_y Hz, g_x Hz, g_x Ey - g_y Ex)
+template <int D>
+__device__ __forceinline__ void applyA(const double* g, const double* u, double* out);
+template <>
+__device__ __forceinline__ void applyA<3>(const double* g, const double* u, double* out) {
+  const double Ex = u[0], Ey = u[1], Ez = u[2], Hx = u[3], Hy = u[4], Hz = u[5];
+  out[0] = Hy * g[2] - Hz * g[1];
+  out[1] = Hz * g[0] - Hx * g[2];
+  out[2] = Hx * g[1] - Hy * g[0];
+  out[3] = g[1] * Ez - g[2] * Ey;
+  out[4] = g[2] * Ex - g[0] * Ez;
+  out[5] = g[0] * Ey - g[1] * Ex;
+}
+template <>
+__device__ __forceinline__ void applyA<2>(const double* g, const double* u, double* out) {
+  out[0] = -g[1] * u[2];
+  out[1] = g[0] * u[2];
+  out[2] = g[0] * u[1] - g[1] * u[0];
+}
+
+// Closed-form inverse of u -> g(u) - f(u) b  (section 4):
+//   E = s (I - b b^T/(eps mu)) (mu w_E + w_H x b),  H = s (I - b b^T/(eps mu)) (eps w_H - w_E x b),
+//   s = 1/(eps mu - |b|^2).  Returns false if eps mu - |b|^2 <= 0 (causality violated).
+template <int D>
+__device__ __forceinline__ bool kinv(const double* b, double eps, double mu, const double* w, double* u);
+template <>
+__device__ __forceinline__ bool kinv<3>(const double* b, double eps, double mu, const double* w, double* u) {
+  const double em = eps * mu;
+  const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  const double den = em - bb;
+  const double s = 1.0 / den;
+  const double iem = 1.0 / em;
+  double rE[3], rH[3];
+  rE[0] = mu * w[0] + (w[4] * b[2] - w[5] * b[1]);
+  rE[1] = mu * w[1] + (w[5] * b[0] - w[3] * b[2]);
+  rE[2] = mu * w[2] + (w[3] * b[1] - w[4] * b[0]);
+  rH[0] = eps * w[3] - (w[1] * b[2] - w[2] * b[1]);
+  rH[1] = eps * w[4] - (w[2] * b[0] - w[0] * b[2]);
+  rH[2] = eps * w[5] - (w[0] * b[1] - w[1] * b[0]);
+  const double pE = (b[0] * rE[0] + b[1] * rE[1] + b[2] * rE[2]) * iem;
+  const double pH = (b[0] * rH[0] + b[1] * rH[1] + b[2] * rH[2]) * iem;
+  for (int i = 0; i < 3; ++i) {
+    u[i] = s * (rE[i] - b[i] * pE);
+    u[3 + i] = s * (rH[i] - b[i] * pH);
+  }
+  return den > 0.0;
+}
+template <>
+__device__ __forceinline__ bool kinv<2>(const double* b, double eps, double mu, const double* w, double* u) {
+  const double em = eps * mu;
+  const double bb = b[0] * b[0] + b[1] * b[1];
+  const double den = em - bb;
+  const double s = 1.0 / den;
+  const double rx = mu * w[0] - w[2] * b[1];
+  const double ry = mu * w[1] + w[2] * b[0];
+  const double pE = (b[0] * rx + b[1] * ry) / em;
+  u[0] = s * (rx - b[0] * pE);
+  u[1] = s * (ry - b[1] * pE);
+  u[2] = s * (eps * w[2] - (w[0] * b[1] - w[1] * b[0]));
+  return den > 0.0;
+}
+
+// Upwind flux times |g| for the outward direction g = -grad lambda_j (unnormalised):
+//   G = 1/2 A(g)(u_in + u_out) + alpha |g| P_t (u_in - u_out),   P_t = tangential part.
+template <int D>
+__device__ __forceinline__ void flux(const double* g, double alpha, const double* um, const double* up, double* G);
+template <>
+__device__ __forceinline__ void flux<3>(const double* g, double alpha, const double* um, const double* up, double* G) {
+  double s[6], dlt[6];
+  for (int c = 0; c < 6; ++c) { s[c] = 0.5 * (um[c] + up[c]); dlt[c] = um[c] - up[c]; }
+  applyA<3>(g, s, G);
+  const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  const double gn = sqrt(gg);
+  const double ig = 1.0 / gg;
+  const double nE = (g[0] * dlt[0] + g[1] * dlt[1] + g[2] * dlt[2]) * ig;
+  const double nH = (g[0] * dlt[3] + g[1] * dlt[4] + g[2] * dlt[5]) * ig;
+  const double ag = alpha * gn;
+  for (int i = 0; i < 3; ++i) {
+    G[i] += ag * (dlt[i] - nE * g[i]);
+    G[3 + i] += ag * (dlt[3 + i] - nH * g[i]);
+  }
+}
+template <>
+__device__ __forceinline__ void flux<2>(const double* g, double alpha, const double* um, const double* up, double* G) {
+  double s[3], dlt[3];
+  for (int c = 0; c < 3; ++c) { s[c] = 0.5 * (um[c] + up[c]); dlt[c] = um[c] - up[c]; }
+  applyA<2>(g, s, G);
+  const double gg = g[0] * g[0] + g[1] * g[1];
+  const double gn = sqrt(gg);
+  const double nE = (g[0] * dlt[0] + g[1] * dlt[1]) / gg;
+  const double ag = alpha * gn;
+  G[0] += ag * (dlt[0] - nE * g[0]);
+  G[1] += ag * (dlt[1] - nE * g[1]);
+  G[2] += ag * dlt[2];
+}
+
+template <int D>
+__device__ __forceinline__ void vertex_order_dev(int k, int* order) {
+  order[0] = k;
+  int c = 1;
+#pragma unroll
+  for (int i = 0; i <= D; ++i)
+    if (i != k) order[c++] = i;
+}
+
+template <int D, int P>
+struct Shape {
+  static constexpr int NC = Dims<D>::NC;
+  static constexpr int NP = binom_c(P + D, D);
+  static constexpr int NF = binom_c(P + D - 1, D - 1);
+  static constexpr int NV = D + 1;
+};
+
+// LDS layout (doubles first, then ints), per workgroup
+template <int D, int P>
+struct Lds {
+  using SH = Shape<D, P>;
+  static __host__ __device__ size_t doubles(int nt) {
+    return (size_t)D * SH::NP * SH::NP          // S
+           + (size_t)D * SH::NF * SH::NP        // L
+           + (size_t)nt * SH::NC * SH::NP       // U
+           + (size_t)nt * D * SH::NC * SH::NF   // G
+           + (size_t)nt * SH::NV * D            // permuted grad lambda
+           + (size_t)nt * D                     // grad phi_b
+           + (size_t)nt * 2;                    // eps, mu
+  }
+  static __host__ __device__ size_t ints(int nt) {
+    return (size_t)D * 2 * SH::NF + (size_t)nt * (2 + D);
+  }
+  static __host__ __device__ size_t bytes(int nt) { return doubles(nt) * 8 + ints(nt) * 4; }
+};
+
+template <int D, int P, int BLOCK, int MAXPAIR>
+__global__ void __launch_bounds__(BLOCK) tent_kernel(KernelParams kp, int64_t first, int64_t count) {
+  using SH = Shape<D, P>;
+  constexpr int NC = SH::NC, NP = SH::NP, NF = SH::NF, NV = SH::NV;
+  extern __shared__ double lds[];
+  const int nt_max = kp.max_patch;
+  double* sS = lds;
+  double* sL = sS + D * NP * NP;
+  double* sU = sL + D * NF * NP;
+  double* sG = sU + (size_t)nt_max * NC * NP;
+  double* sGL = sG + (size_t)nt_max * D * NC * NF;
+  double* sBb = sGL + (size_t)nt_max * NV * D;
+  double* sEM = sBb + (size_t)nt_max * D;
+  int* sFn = reinterpret_cast<int*>(sEM + (size_t)nt_max * 2);
+  int* sElem = sFn + D * 2 * NF;   // [e]: element id
+  int* sK = sElem + nt_max;        // [e]: local index of V
+  int* sF = sK + nt_max;           // [e][j]: face codes
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < D * NP * NP; i += BLOCK) sS[i] = kp.S[i];
+  for (int i = tid; i < D * NF * NP; i += BLOCK) sL[i] = kp.L[i];
+  for (int i = tid; i < D * 2 * NF; i += BLOCK) sFn[i] = kp.fnode[i];
+
+  const double invm = 1.0 / kp.m;
+
+  for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const int32_t V = kp.tent_vertex[first + t];
+    const double t_top = kp.t_offset + kp.tent_top[first + t];
+    const int32_t p0 = kp.patch_ptr[V];
+    const int nT = kp.patch_ptr[V + 1] - p0;
+    const double t_bot = kp.tau[V];
+    const double H = t_top - t_bot;
+
+    // element setup
+    for (int e = tid; e < nT; e += BLOCK) {
+      const int el = kp.patch_elem[p0 + e];
+      const int32_t* info = kp.patch_info + (size_t)(p0 + e) * (1 + D);
+      const int k = info[0];
+      int order[NV];
+      vertex_order_dev<D>(k, order);
+      const double* gl = kp.grad_lam + (size_t)el * NV * D;
+      double gb[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) gb[i] = 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double tv = kp.tau[kp.cells[(size_t)el * NV + v]];
+#pragma unroll
+        for (int i = 0; i < D; ++i) gb[i] += tv * gl[v * D + i];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int i = 0; i < D; ++i) sGL[(e * NV + v) * D + i] = gl[order[v] * D + i];
+#pragma unroll
+      for (int i = 0; i < D; ++i) sBb[e * D + i] = gb[i];
+      sEM[2 * e] = kp.eps[el];
+      sEM[2 * e + 1] = kp.mu[el];
+      sElem[e] = el;
+      sK[e] = k;
+#pragma unroll
+      for (int j = 0; j < D; ++j) sF[e * D + j] = info[1 + j];
+    }
+    __syncthreads();
+
+    // gather W for the owned (element, node) pairs
+    const int npairs = nT * NP;
+    double acc[MAXPAIR][NC];
+    double unew[MAXPAIR][NC];
+#pragma unroll
+    for (int r = 0; r < MAXPAIR; ++r) {
+      const int P_ = tid + r * BLOCK;
+      if (P_ < npairs) {
+        const int e = P_ / NP, b = P_ - e * NP;
+        const int nold = kp.perm[sK[e] * NP + b];
+        const double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] = Wp[c * NP];
+      }
+    }
+    bool ok = true;
+    // U_{0,0} = K(b_0)^{-1} W
+#pragma unroll
+    for (int r = 0; r < MAXPAIR; ++r) {
+      const int P_ = tid + r * BLOCK;
+      if (P_ < npairs) {
+        const int e = P_ / NP, b = P_ - e * NP;
+        double u[NC];
+        ok &= kinv<D>(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sU[(e * NC + c) * NP + b] = u[c];
+      }
+    }
+    __syncthreads();
+
+    for (int i = 0; i < kp.m; ++i) {
+      const double th = i * invm;
+      double coef = 1.0;
+      for (int n = 1; n <= kp.q; ++n) {
+        coef *= invm / n;
+        // ---- face fluxes G_j at the face nodes of the faces containing V
+        for (int it = tid; it < nT * D * NF; it += BLOCK) {
+          const int e = it / (D * NF);
+          const int rem = it - e * (D * NF);
+          const int j = rem / NF;
+          const int s = rem - j * NF;
+          const int nin = sFn[(j * 2) * NF + s];
+          double um[NC], up[NC], G[NC], g[D];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) um[c] = sU[(e * NC + c) * NP + nin];
+#pragma unroll
+          for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
+          const int code = sF[e * D + j];
+          if (code >= 0) {
+            const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
+            const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) up[c] = sU[(pe * NC + c) * NP + nout];
+          } else {
+            const int kind = -1 - code;
+            if (kind == 2 && kp.has_data) {
+              // ghost u_ex(x, phi(x, th)); its (n-1)-th th-derivative is
+              // delta^(n-1) d_t^(n-1) u_ex with delta = H lambda_V
+              const int el = sElem[e];
+              int order[NV];
+              vertex_order_dev<D>(sK[e], order);
+              double x[D], phib = 0.0;
+#pragma unroll
+              for (int xx = 0; xx < D; ++xx) x[xx] = 0.0;
+              const int* alpha = kp.mi + nin * NV;
+#pragma unroll
+              for (int v = 0; v < NV; ++v) {
+                const int gv = kp.cells[(size_t)el * NV + order[v]];
+                const double lam = (double)alpha[v] / P;
+                phib += lam * kp.tau[gv];
+#pragma unroll
+                for (int xx = 0; xx < D; ++xx) x[xx] += lam * kp.coords[(size_t)gv * D + xx];
+              }
+              const double delta = H * (double)alpha[0] / P;
+              const double phi = phib + th * delta;
+              double psi = kp.pw_phase - kp.pw_omega * phi;
+#pragma unroll
+              for (int xx = 0; xx < D; ++xx) psi += kp.pw_k[xx] * x[xx];
+              const int kd = n - 1;
+              double scale = 1.0;
+              for (int z = 0; z < kd; ++z) scale *= delta * kp.pw_omega;
+              const double val = scale * cos(psi - kd * 1.5707963267948966);  // d_t^k cos = omega^k cos(. - k pi/2)
+#pragma unroll
+              for (int c = 0; c < NC; ++c) up[c] = kp.pw_amp[c] * val;
+            } else if (kind == 1) {  // PMC mirror: E_out = E_in, H_out = -H_in
+#pragma unroll
+              for (int c = 0; c < NC; ++c) up[c] = (c < (D == 3 ? 3 : 2)) ? um[c] : -um[c];
+            } else {                 // PEC mirror: E_out = -E_in, H_out = H_in
+#pragma unroll
+              for (int c = 0; c < NC; ++c) up[c] = (c < (D == 3 ? 3 : 2)) ? -um[c] : um[c];
+            }
+          }
+          flux<D>(g, kp.alpha, um, up, G);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) sG[((e * D + j) * NC + c) * NF + s] = G[c];
+        }
+        __syncthreads();
+
+        // ---- volume + lift for the owned pairs, Taylor accumulation, next U
+#pragma unroll
+        for (int r = 0; r < MAXPAIR; ++r) {
+          const int P_ = tid + r * BLOCK;
+          if (P_ < npairs) {
+            const int e = P_ / NP, b = P_ - e * NP;
+            const double* Ue = sU + (size_t)e * NC * NP;
+            double Y[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Y[c] = 0.0;
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+              double tl[NC];
+#pragma unroll
+              for (int c = 0; c < NC; ++c) tl[c] = 0.0;
+              const double* Sl = sS + l * NP * NP + b;
+              for (int a = 0; a < NP; ++a) {
+                const double sv = Sl[a * NP];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) tl[c] = fma(sv, Ue[c * NP + a], tl[c]);
+              }
+              double gl[D], at[NC];
+#pragma unroll
+              for (int x = 0; x < D; ++x) gl[x] = sGL[(e * NV + l + 1) * D + x];
+              applyA<D>(gl, tl, at);
+#pragma unroll
+              for (int c = 0; c < NC; ++c) Y[c] += at[c];
+            }
+            const double* Ge = sG + (size_t)e * D * NC * NF;
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+              const double* Lj = sL + j * NF * NP + b;
+              for (int s = 0; s < NF; ++s) {
+                const double lv = Lj[s * NP];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) Y[c] = fma(-lv, Ge[(j * NC + c) * NF + s], Y[c]);
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              Y[c] *= H;
+              acc[r][c] = fma(coef, Y[c], acc[r][c]);
+            }
+            const double* gv = &sGL[(e * NV + 0) * D];
+            if (n < kp.q) {
+              // U_n = K(b_i)^{-1} (Y_n + n A(b') U_{n-1}),  b' = H grad lambda_V
+              double bi[D], bp[D], uo[NC], au[NC], rhs[NC];
+#pragma unroll
+              for (int x = 0; x < D; ++x) {
+                bp[x] = H * gv[x];
+                bi[x] = sBb[e * D + x] + th * bp[x];
+              }
+#pragma unroll
+              for (int c = 0; c < NC; ++c) uo[c] = Ue[c * NP + b];
+              applyA<D>(bp, uo, au);
+#pragma unroll
+              for (int c = 0; c < NC; ++c) rhs[c] = Y[c] + n * au[c];
+              ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], rhs, unew[r]);
+            } else if (i + 1 < kp.m) {
+              // next sub-interval: U_{i+1,0} = K(b_{i+1})^{-1} W
+              double bi[D];
+              const double th1 = (i + 1) * invm;
+#pragma unroll
+              for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * H * gv[x];
+              ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], unew[r]);
+            }
+          }
+        }
+        __syncthreads();
+        if (n < kp.q || i + 1 < kp.m) {
+#pragma unroll
+          for (int r = 0; r < MAXPAIR; ++r) {
+            const int P_ = tid + r * BLOCK;
+            if (P_ < npairs) {
+              const int e = P_ / NP, b = P_ - e * NP;
+#pragma unroll
+              for (int c = 0; c < NC; ++c) sU[(e * NC + c) * NP + b] = unew[r][c];
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+
+    // scatter the tent top
+#pragma unroll
+    for (int r = 0; r < MAXPAIR; ++r) {
+      const int P_ = tid + r * BLOCK;
+      if (P_ < npairs) {
+        const int e = P_ / NP, b = P_ - e * NP;
+        const int nold = kp.perm[sK[e] * NP + b];
+        double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Wp[c * NP] = acc[r][c];
+      }
+    }
+    if (!ok) kp.err[0] = ERRF_CAUSALITY;
+    __syncthreads();
+    if (tid == 0) kp.tau[V] = t_top;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ conversions
+// set: W[e][c][node] = K(grad tau_e) u[e][node][c]   (w = g(u) - f(u) grad tau)
+template <int D>
+__global__ void set_fields_kernel(KernelParams kp, int64_t ne, const double* u) {
+  constexpr int NC = Dims<D>::NC, NV = D + 1;
+  const int np = kp.np;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ne * np) return;
+  const int64_t e = idx / np;
+  const int a = (int)(idx - e * np);
+  double g[D];
+  for (int i = 0; i < D; ++i) g[i] = 0.0;
+  for (int v = 0; v < NV; ++v) {
+    const double tv = kp.tau[kp.cells[e * NV + v]];
+    for (int i = 0; i < D; ++i) g[i] += tv * kp.grad_lam[(e * NV + v) * D + i];
+  }
+  double uu[NC], fu[NC];
+  bool fin = true;
+  for (int c = 0; c < NC; ++c) {
+    uu[c] = u[(e * np + a) * NC + c];
+    fin &= isfinite(uu[c]);
+  }
+  applyA<D>(g, uu, fu);
+  const double eps = kp.eps[e], mu = kp.mu[e];
+  for (int c = 0; c < NC; ++c) {
+    const double gm = (c < (D == 3 ? 3 : 2)) ? eps : mu;
+    kp.W[(e * NC + c) * np + a] = gm * uu[c] - fu[c];
+  }
+  if (!fin) kp.err[1] = ERRF_NONFINITE;
+}
+
+template <int D>
+__global__ void get_fields_kernel(KernelParams kp, int64_t ne, double* out, int raw) {
+  constexpr int NC = Dims<D>::NC, NV = D + 1;
+  const int np = kp.np;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ne * np) return;
+  const int64_t e = idx / np;
+  const int a = (int)(idx - e * np);
+  double w[NC], u[NC];
+  bool fin = true;
+  for (int c = 0; c < NC; ++c) {
+    w[c] = kp.W[(e * NC + c) * np + a];
+    fin &= isfinite(w[c]);
+  }
+  if (raw) {
+    for (int c = 0; c < NC; ++c) out[(e * np + a) * NC + c] = w[c];
+  } else {
+    double g[D];
+    for (int i = 0; i < D; ++i) g[i] = 0.0;
+    for (int v = 0; v < NV; ++v) {
+      const double tv = kp.tau[kp.cells[e * NV + v]];
+      for (int i = 0; i < D; ++i) g[i] += tv * kp.grad_lam[(e * NV + v) * D + i];
+    }
+    if (!kinv<D>(g, kp.eps[e], kp.mu[e], w, u)) kp.err[0] = ERRF_CAUSALITY;
+    for (int c = 0; c < NC; ++c) out[(e * np + a) * NC + c] = u[c];
+  }
+  if (!fin) kp.err[1] = ERRF_NONFINITE;
+}
+
+__global__ void fill_kernel(double* x, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+// ------------------------------------------------------------------ dispatch
+template <int D, int P, int BLOCK, int MAXPAIR>
+hipError_t launch_tp(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
+  const size_t lds = Lds<D, P>::bytes(kp.max_patch);
+  auto kfn = tent_kernel<D, P, BLOCK, MAXPAIR>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(BLOCK), lds, s, kp, first, count);
+  return hipGetLastError();
+}
+
+template <int D, int P, int BLOCK>
+hipError_t launch_dp(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
+  const int need = (kp.max_patch * Shape<D, P>::NP + BLOCK - 1) / BLOCK;
+  if (need <= 1) return launch_tp<D, P, BLOCK, 1>(kp, first, count, s);
+  if (need <= 2) return launch_tp<D, P, BLOCK, 2>(kp, first, count, s);
+  if (need <= 4) return launch_tp<D, P, BLOCK, 4>(kp, first, count, s);
+  if (need <= 8) return launch_tp<D, P, BLOCK, 8>(kp, first, count, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool tent_kernel_supported(int d, int p) {
+  return (d == 2 && p >= 1 && p <= 5) || (d == 3 && p >= 1 && p <= 4);
+}
+
+size_t tent_kernel_lds_bytes(int d, int p, int nt) {
+  if (d == 2) {
+    switch (p) {
+      case 1: return Lds<2, 1>::bytes(nt);
+      case 2: return Lds<2, 2>::bytes(nt);
+      case 3: return Lds<2, 3>::bytes(nt);
+      case 4: return Lds<2, 4>::bytes(nt);
+      case 5: return Lds<2, 5>::bytes(nt);
+    }
+  } else {
+    switch (p) {
+      case 1: return Lds<3, 1>::bytes(nt);
+      case 2: return Lds<3, 2>::bytes(nt);
+      case 3: return Lds<3, 3>::bytes(nt);
+      case 4: return Lds<3, 4>::bytes(nt);
+    }
+  }
+  return 0;
+}
+
+// maximum (element, node) pairs a workgroup can own
+int tent_kernel_max_pairs(int d) { return d == 2 ? 128 * 8 : 256 * 8; }
+
+hipError_t launch_tent_layer(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (kp.d == 2) {
+    switch (kp.p) {
+      case 1: return launch_dp<2, 1, 128>(kp, first, count, s);
+      case 2: return launch_dp<2, 2, 128>(kp, first, count, s);
+      case 3: return launch_dp<2, 3, 128>(kp, first, count, s);
+      case 4: return launch_dp<2, 4, 128>(kp, first, count, s);
+      case 5: return launch_dp<2, 5, 128>(kp, first, count, s);
+    }
+  } else {
+    switch (kp.p) {
+      case 1: return launch_dp<3, 1, 256>(kp, first, count, s);
+      case 2: return launch_dp<3, 2, 256>(kp, first, count, s);
+      case 3: return launch_dp<3, 3, 256>(kp, first, count, s);
+      case 4: return launch_dp<3, 4, 256>(kp, first, count, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
+                             int64_t nv, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, kp.tau, nv, t0);
+  const int64_t n = ne * kp.np;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (kp.d == 2)
+    hipLaunchKernelGGL(set_fields_kernel<2>, dim3(grid), dim3(256), 0, s, kp, ne, u_nodal);
+  else
+    hipLaunchKernelGGL(set_fields_kernel<3>, dim3(grid), dim3(256), 0, s, kp, ne, u_nodal);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s) {
+  const int64_t n = ne * kp.np;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  if (kp.d == 2)
+    hipLaunchKernelGGL(get_fields_kernel<2>, dim3(grid), dim3(256), 0, s, kp, ne, out, raw);
+  else
+    hipLaunchKernelGGL(get_fields_kernel<3>, dim3(grid), dim3(256), 0, s, kp, ne, out, raw);
+  return hipGetLastError();
+}
+
+}  // namespace mtp

@@ -1,0 +1,297 @@
+"""Thin Python binding of the MTP C interface (include/mtp.h).
+
+Argument marshalling only: every function forwards to the C function of the same name
+in libmtp.so; all tent arithmetic runs in the library's HIP kernels.  PyTorch supplies
+device memory (the solver workspace) and the HIP stream.  Importing this module never
+falls back to anything: if libmtp.so is missing, load() raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmtp.so")
+
+MTP_OK = 0
+MTP_BC_PEC, MTP_BC_PMC, MTP_BC_DATA = 0, 1, 2
+MTP_FP64 = 0
+
+_lib = None
+
+
+class MTPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mtp error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not built: run python -m paper_1906_11029_amd.build")
+    # torch first: the library then binds to the HIP runtime torch already loaded, so
+    # workspace tensors and torch streams belong to the same runtime instance
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, dbl, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+    pp = C.POINTER(C.c_void_p)
+    sig = {
+        "mtp_mesh_create": [i32, i64, P, i64, P, P, P, P, pp],
+        "mtp_mesh_info": [P, P, P, P, P],
+        "mtp_pitch_layers": [P, dbl, dbl, pp],
+        "mtp_tents_query": [P, P, P, P],
+        "mtp_tents_export": [P, P, P, P, P],
+        "mtp_solver_workspace_size": [P, P, i32, i32, i32, i32, P],
+        "mtp_solver_create": [P, P, i32, i32, i32, i32, dbl, P, sz, P, pp],
+        "mtp_node_coords": [P, P],
+        "mtp_set_fields": [P, P, i32, dbl],
+        "mtp_set_planewave_bc": [P, P, P, dbl, dbl],
+        "mtp_layer_advance": [P, i64],
+        "mtp_advance_to": [P, dbl],
+        "mtp_front": [P, P, P],
+        "mtp_get_fields": [P, P, i32],
+        "mtp_get_state": [P, P, i32],
+        "mtp_slab_dof_updates": [P, P, P],
+        "mtp_slab_flops": [P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int32
+    for name in ("mtp_mesh_destroy", "mtp_tents_destroy", "mtp_solver_destroy"):
+        f = getattr(L, name)
+        f.argtypes = [P]
+        f.restype = None
+    L.mtp_last_error.argtypes = []
+    L.mtp_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != MTP_OK:
+        raise MTPError(status, load().mtp_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ----------------------------------------------------------------- C-named functions
+def mtp_mesh_create(coords, cells, eps=None, mu=None, face_bc=None):
+    coords = np.ascontiguousarray(coords, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    dim = coords.shape[1]
+    eps = None if eps is None else np.ascontiguousarray(eps, dtype=np.float64)
+    mu = None if mu is None else np.ascontiguousarray(mu, dtype=np.float64)
+    face_bc = None if face_bc is None else np.ascontiguousarray(face_bc, dtype=np.int32)
+    h = C.c_void_p()
+    _check(load().mtp_mesh_create(dim, coords.shape[0], _ptr(coords), cells.shape[0], _ptr(cells),
+                                  _ptr(eps), _ptr(mu), _ptr(face_bc), C.byref(h)))
+    return h
+
+
+def mtp_mesh_info(mesh):
+    d, nv, ne, mp = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int32()
+    _check(load().mtp_mesh_info(mesh, C.byref(d), C.byref(nv), C.byref(ne), C.byref(mp)))
+    return {"dim": d.value, "nv": nv.value, "ne": ne.value, "max_patch": mp.value}
+
+
+def mtp_mesh_destroy(mesh):
+    load().mtp_mesh_destroy(mesh)
+
+
+def mtp_pitch_layers(mesh, t_end, slope_fraction=0.5):
+    h = C.c_void_p()
+    _check(load().mtp_pitch_layers(mesh, float(t_end), float(slope_fraction), C.byref(h)))
+    return h
+
+
+def mtp_tents_query(tents):
+    nt, nl = C.c_int64(), C.c_int64()
+    _check(load().mtp_tents_query(tents, C.byref(nt), C.byref(nl), None))
+    ptr = np.zeros(nl.value + 1, dtype=np.int64)
+    _check(load().mtp_tents_query(tents, None, None, _ptr(ptr)))
+    return nt.value, nl.value, ptr
+
+
+def mtp_tents_export(tents):
+    nt, _, _ = mtp_tents_query(tents)
+    v = np.zeros(nt, dtype=np.int32)
+    tb = np.zeros(nt)
+    tt = np.zeros(nt)
+    lay = np.zeros(nt, dtype=np.int32)
+    _check(load().mtp_tents_export(tents, _ptr(v), _ptr(tb), _ptr(tt), _ptr(lay)))
+    return {"vertex": v, "t_bot": tb, "t_top": tt, "layer": lay}
+
+
+def mtp_tents_destroy(tents):
+    load().mtp_tents_destroy(tents)
+
+
+def mtp_solver_workspace_size(mesh, tents, p, q, m, precision=MTP_FP64):
+    n = C.c_size_t()
+    _check(load().mtp_solver_workspace_size(mesh, tents, p, q, m, precision, C.byref(n)))
+    return n.value
+
+
+def mtp_solver_create(mesh, tents, p, q, m, precision, alpha, workspace_ptr, nbytes, stream_ptr):
+    h = C.c_void_p()
+    _check(load().mtp_solver_create(mesh, tents, p, q, m, precision, float(alpha), C.c_void_p(workspace_ptr),
+                                    nbytes, C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def mtp_solver_destroy(solver):
+    load().mtp_solver_destroy(solver)
+
+
+def mtp_node_coords(solver, ne, np_, dim):
+    out = np.zeros((ne, np_, dim))
+    _check(load().mtp_node_coords(solver, _ptr(out)))
+    return out
+
+
+def mtp_set_fields(solver, nodal, t0=0.0):
+    """nodal: numpy array (host) or torch CUDA tensor (device), shape (ne, Np, nc), float64."""
+    if isinstance(nodal, np.ndarray):
+        a = np.ascontiguousarray(nodal, dtype=np.float64)
+        _check(load().mtp_set_fields(solver, _ptr(a), 0, float(t0)))
+    else:
+        assert nodal.is_cuda and nodal.is_contiguous() and str(nodal.dtype) == "torch.float64"
+        _check(load().mtp_set_fields(solver, C.c_void_p(nodal.data_ptr()), 1, float(t0)))
+
+
+def mtp_set_planewave_bc(solver, amp, kvec, omega, phase):
+    a = np.ascontiguousarray(amp, dtype=np.float64)
+    k = np.ascontiguousarray(kvec, dtype=np.float64)
+    _check(load().mtp_set_planewave_bc(solver, _ptr(a), _ptr(k), float(omega), float(phase)))
+
+
+def mtp_layer_advance(solver, layer):
+    _check(load().mtp_layer_advance(solver, int(layer)))
+
+
+def mtp_advance_to(solver, T):
+    _check(load().mtp_advance_to(solver, float(T)))
+
+
+def mtp_front(solver):
+    t, l = C.c_double(), C.c_int64()
+    _check(load().mtp_front(solver, C.byref(t), C.byref(l)))
+    return t.value, l.value
+
+
+def _read(fn, solver, shape, out):
+    if out is None:
+        host = np.zeros(shape)
+        _check(fn(solver, _ptr(host), 0))
+        return host
+    assert out.is_cuda and out.is_contiguous() and tuple(out.shape) == tuple(shape)
+    _check(fn(solver, C.c_void_p(out.data_ptr()), 1))
+    return out
+
+
+def mtp_get_fields(solver, shape, out=None):
+    return _read(load().mtp_get_fields, solver, shape, out)
+
+
+def mtp_get_state(solver, shape, out=None):
+    return _read(load().mtp_get_state, solver, shape, out)
+
+
+def mtp_slab_dof_updates(solver):
+    d, n = C.c_double(), C.c_int64()
+    _check(load().mtp_slab_dof_updates(solver, C.byref(d), C.byref(n)))
+    return d.value, n.value
+
+
+def mtp_slab_flops(solver):
+    f = C.c_double()
+    _check(load().mtp_slab_flops(solver, C.byref(f)))
+    return f.value
+
+
+# ----------------------------------------------------------------- thin object wrappers
+class Mesh:
+    def __init__(self, coords, cells, eps=None, mu=None, face_bc=None):
+        self.h = mtp_mesh_create(coords, cells, eps, mu, face_bc)
+        self.info = mtp_mesh_info(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            mtp_mesh_destroy(self.h)
+            self.h = None
+
+
+class Tents:
+    def __init__(self, mesh, t_end, slope_fraction=0.5):
+        self.mesh = mesh
+        self.h = mtp_pitch_layers(mesh.h, t_end, slope_fraction)
+        self.n_tents, self.n_layers, self.layer_ptr = mtp_tents_query(self.h)
+        self.t_end = t_end
+
+    def export(self):
+        return mtp_tents_export(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            mtp_tents_destroy(self.h)
+            self.h = None
+
+
+class Solver:
+    """Device state of one solve.  The workspace is a torch uint8 tensor on `device`;
+    work is enqueued on torch's current stream of that device (or `stream`)."""
+
+    def __init__(self, mesh, tents, p, q, m, alpha=0.5, precision=MTP_FP64, device="cuda:0", stream=None):
+        import torch
+        self.mesh, self.tents, self.p, self.q, self.m = mesh, tents, p, q, m
+        d = mesh.info["dim"]
+        self.dim, self.nc = d, (6 if d == 3 else 3)
+        self.np = (p + 1) * (p + 2) // 2 if d == 2 else (p + 1) * (p + 2) * (p + 3) // 6
+        self.shape = (mesh.info["ne"], self.np, self.nc)
+        nbytes = mtp_solver_workspace_size(mesh.h, tents.h, p, q, m, precision)
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = mtp_solver_create(mesh.h, tents.h, p, q, m, precision, alpha, self.workspace.data_ptr(),
+                                   nbytes, self.stream.cuda_stream)
+
+    def node_coords(self):
+        return mtp_node_coords(self.h, self.shape[0], self.np, self.dim)
+
+    def set_fields(self, nodal, t0=0.0):
+        mtp_set_fields(self.h, nodal, t0)
+
+    def set_planewave_bc(self, amp, kvec, omega, phase):
+        mtp_set_planewave_bc(self.h, amp, kvec, omega, phase)
+
+    def layer_advance(self, layer):
+        mtp_layer_advance(self.h, layer)
+
+    def advance_to(self, T):
+        mtp_advance_to(self.h, T)
+
+    def front(self):
+        return mtp_front(self.h)
+
+    def get_fields(self, out=None):
+        return mtp_get_fields(self.h, self.shape, out)
+
+    def get_state(self, out=None):
+        return mtp_get_state(self.h, self.shape, out)
+
+    def slab_dof_updates(self):
+        return mtp_slab_dof_updates(self.h)
+
+    def slab_flops(self):
+        return mtp_slab_flops(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            mtp_solver_destroy(self.h)
+            self.h = None

@@ -1,0 +1,81 @@
+"""Parity cases shared by the oracle fixture script and the GPU tests (problem data only:
+meshes, materials, boundary kinds, initial fields, plane-wave parameters)."""
+import numpy as np
+
+from mtp_inputs import fields, meshes
+
+DATA, PEC, PMC = meshes.DATA, meshes.PEC, meshes.PMC
+
+CASES = {
+    # config-1 workload: 2D TE, 8x8 squares split in two, P2, plane wave on all sides
+    "te_planewave_p2": dict(mesh=("square", 8), p=2, q=3, m=4, T=0.5, kind=DATA, exact="pw_te"),
+    "te_pmc_p1": dict(mesh=("square_pi", 4), p=1, q=2, m=2, T=0.5, kind=PMC, exact="pmc_te"),
+    "te_pmc_p3": dict(mesh=("square_pi", 4), p=3, q=4, m=6, T=0.5, kind=PMC, exact="pmc_te"),
+    "te_pmc_p5": dict(mesh=("square_pi", 3), p=5, q=6, m=10, T=0.4, kind=PMC, exact="pmc_te"),
+    "te_pec_p4_alpha025": dict(mesh=("square", 3), p=4, q=5, m=8, T=0.3, kind=PEC, exact="pec_te", alpha=0.25),
+    "te_pec_p2_eps": dict(mesh=("square", 5), p=2, q=3, m=4, T=0.4, kind=PEC, exact="pec_te", eps_split=True),
+    "cav3d_p1": dict(mesh=("kuhn", 2), p=1, q=2, m=2, T=0.25, kind=PEC, exact="pec_3d"),
+    "cav3d_p2": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.25, kind=PEC, exact="pec_3d"),
+    "cav3d_p3": dict(mesh=("kuhn", 2), p=3, q=4, m=6, T=0.25, kind=PEC, exact="pec_3d"),
+    "cav3d_p4": dict(mesh=("kuhn", 2), p=4, q=5, m=8, T=0.125, kind=PEC, exact="pec_3d"),
+    "cav3d_p2_pmc_eps": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.2, kind=PMC, exact="pec_3d", eps_split=True),
+    "planewave3d_p2": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.2, kind=DATA, exact="pw_3d"),
+    "graded3d_p3_eps": dict(mesh=("kuhn_graded", 3), p=3, q=4, m=6, T=0.06, kind=PEC, exact="pulse",
+                            eps_split=True),
+    "single_tri_p2": dict(mesh=("tri1", 1), p=2, q=3, m=4, T=0.5, kind=PEC, exact="pec_te"),
+    "single_tet_p3": dict(mesh=("tet1", 1), p=3, q=4, m=6, T=0.3, kind=PMC, exact="pec_3d"),
+    "te_pmc_p2_two_slabs": dict(mesh=("square_pi", 4), p=2, q=3, m=4, T=0.25, kind=PMC, exact="pmc_te", slabs=2),
+}
+
+
+def build_mesh(spec):
+    kind, n = spec
+    if kind == "square":
+        return meshes.square_tri(n)
+    if kind == "square_pi":
+        return meshes.square_tri(n, length=np.pi)
+    if kind == "kuhn":
+        return meshes.cube_kuhn(n)
+    if kind == "kuhn_graded":
+        return meshes.cube_kuhn(n, axis_map=lambda g: 0.25 * g + 0.75 * g * g)
+    if kind == "tri1":
+        return {"coords": np.array([[0.1, 0.0], [1.0, 0.2], [0.3, 0.9]]), "cells": np.array([[0, 1, 2]], np.int32)}
+    if kind == "tet1":
+        return {"coords": np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.0], [0.2, 0.9, 0.1], [0.1, 0.2, 0.8]]),
+                "cells": np.array([[0, 1, 2, 3]], np.int32)}
+    raise ValueError(kind)
+
+
+def exact_solution(name):
+    return {"pw_te": fields.PlaneWaveTE(direction=(1.0, 1.0), k=2 * np.pi),
+            "pmc_te": fields.CavityTE_PMC(),
+            "pec_te": fields.CavityTE_PEC(),
+            "pec_3d": fields.Cavity3D_PEC(),
+            "pw_3d": fields.PlaneWave3D(direction=(1.0, 0.5, 0.25), k=np.pi, amp_e=(0.0, 1.0, -1.0), phase=0.3),
+            "pulse": fields.GaussianPulse3D(seed=11030)}[name]
+
+
+def planewave_params(ex, dim):
+    """(amp, kvec, omega, phase) of a plane-wave exact solution for the C interface."""
+    if dim == 2:
+        amp = np.array([-ex.d[1] * ex.amp, ex.d[0] * ex.amp, ex.amp * np.sqrt(ex.eps / ex.mu)])
+    else:
+        amp = np.concatenate([ex.aE, ex.aH])
+    return amp, ex.k * ex.d, ex.omega, ex.phase
+
+
+def setup(name):
+    c = dict(CASES[name])
+    c.setdefault("alpha", 0.5)
+    c.setdefault("slabs", 1)
+    c.setdefault("eps_split", False)
+    mm = build_mesh(c["mesh"])
+    dim = mm["coords"].shape[1]
+    ne = len(mm["cells"])
+    if c["eps_split"]:
+        eps, mu = meshes.materials_split(mm)
+    else:
+        eps, mu = np.ones(ne), np.ones(ne)
+    ex = exact_solution(c["exact"])
+    u0 = ex.u(meshes.equispaced_nodes(mm, c["p"]), 0.0)
+    return c, mm, dim, eps, mu, meshes.uniform_bc(ne, dim, c["kind"]), ex, u0

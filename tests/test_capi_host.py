@@ -1,0 +1,103 @@
+"""Host-side checks of the C-ABI library (no GPU needed): symbols, argument and mesh
+errors, and the library's tent pitcher against the oracle's independent one (the tent
+list is integer/index work plus quantised times: bit-exact)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from mtp_inputs import meshes
+from oracle.mesh import Mesh as OMesh
+from oracle.pitch import pitch as opitch, validate
+from paper_1906_11029_amd import mtp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "mtp.h")).read()
+    names = set(re.findall(r"^(?:mtp_status|void|const char\*)\s+(mtp_[a-z_]+)\s*\(", hdr, re.M))
+    assert len(names) >= 20
+    lib = ctypes.CDLL(mtp.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("dim,n,T", [(2, 4, 0.5), (2, 8, 0.5), (3, 2, 0.4), (3, 4, 0.3)])
+def test_pitch_matches_oracle_bit_exact(dim, n, T):
+    mm = meshes.cube_kuhn(n) if dim == 3 else meshes.square_tri(n)
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    tents = mtp.Tents(M, T, 0.5)
+    ex = tents.export()
+    om = OMesh(mm["coords"], mm["cells"])
+    ot = opitch(om, T, 0.5)
+    order = np.argsort(ot["layer"], kind="stable")
+    for k in ("vertex", "t_bot", "t_top", "layer"):
+        assert np.array_equal(ex[k], ot[k][order]), k
+    assert tents.n_layers == ot["layer"].max() + 1
+    assert np.array_equal(np.diff(tents.layer_ptr), np.bincount(ex["layer"]))
+    # and the library's list passes the oracle's validator
+    validate(om, {k: np.asarray(v) for k, v in ex.items()}, T, 0.5)
+
+
+def test_pitch_graded_materials_matches_oracle():
+    mm = meshes.cube_kuhn(3, axis_map=lambda g: 0.3 * g + 0.7 * g * g)
+    eps, mu = meshes.materials_split(mm)
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    ex = mtp.Tents(M, 0.2, 0.5).export()
+    om = OMesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    ot = opitch(om, 0.2, 0.5)
+    order = np.argsort(ot["layer"], kind="stable")
+    for k in ("vertex", "t_bot", "t_top", "layer"):
+        assert np.array_equal(ex[k], ot[k][order]), k
+
+
+def test_mesh_info_patch_sizes():
+    mm = meshes.cube_kuhn(3)
+    info = mtp.Mesh(mm["coords"], mm["cells"]).info
+    assert info == {"dim": 3, "nv": 64, "ne": 162, "max_patch": 24}
+    mm = meshes.square_tri(3)
+    assert mtp.Mesh(mm["coords"], mm["cells"]).info["max_patch"] == 6
+
+
+def test_mesh_errors():
+    with pytest.raises(mtp.MTPError) as e:   # degenerate (collinear) triangle
+        mtp.Mesh(np.array([[0, 0], [1, 0], [2, 0.0]]), np.array([[0, 1, 2]]))
+    assert e.value.code == -2
+    with pytest.raises(mtp.MTPError) as e:   # vertex id out of range
+        mtp.Mesh(np.array([[0, 0], [1, 0], [0, 1.0]]), np.array([[0, 1, 3]]))
+    assert e.value.code == -2
+    with pytest.raises(mtp.MTPError) as e:   # face shared by three triangles
+        X = np.array([[0, 0], [1, 0], [0, 1.0], [0, -1.0], [-1, 0.5]])
+        mtp.Mesh(X, np.array([[0, 1, 2], [0, 3, 1], [0, 1, 4]]))
+    assert e.value.code == -2
+    with pytest.raises(mtp.MTPError) as e:   # non-positive material
+        mtp.Mesh(np.array([[0, 0], [1, 0], [0, 1.0]]), np.array([[0, 1, 2]]), eps=np.array([0.0]))
+    assert e.value.code == -2
+
+
+def test_pitch_errors():
+    mm = meshes.square_tri(2)
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    for s in (0.0, 1.0, 1.5):
+        with pytest.raises(mtp.MTPError) as e:
+            mtp.Tents(M, 0.5, s)
+        assert e.value.code == -3
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.Tents(M, -1.0, 0.5)
+    assert e.value.code == -1
+
+
+def test_workspace_size_and_unsupported_degree():
+    mm = meshes.square_tri(2)
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    T = mtp.Tents(M, 0.5)
+    assert mtp.mtp_solver_workspace_size(M.h, T.h, 2, 3, 4) > 0
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.mtp_solver_workspace_size(M.h, T.h, 9, 3, 4)
+    assert e.value.code == -9
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.mtp_solver_workspace_size(M.h, T.h, 2, 3, 4, precision=7)
+    assert e.value.code == -9
