@@ -18,7 +18,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64 = 78.6  # TFLOP/s, MI355X FP64 vector and matrix
+PEAK_FP64 = 78.6   # TFLOP/s, MI355X FP64 vector and matrix
+PEAK_FP32 = 157.3  # TFLOP/s, MI355X FP32 matrix
 
 
 def log(*a):
@@ -70,8 +71,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cavity3d_p3")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp64-valu"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -79,6 +83,15 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calibration:
+        x = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": x.numel() * 8, "copies": 3}))
+        return
 
     from mtp_inputs import meshes
     from paper_1906_11029_amd import mtp
@@ -89,7 +102,10 @@ def main():
     M = mtp.Mesh(mm["coords"], mm["cells"])
     T = mtp.Tents(M, W["T"], 0.5)
     t_pitch = time.perf_counter() - t0
-    S = mtp.Solver(M, T, W["p"], W["q"], W["m"])
+    prec = {"fp64": mtp.MTP_FP64, "mixed": mtp.MTP_MIXED_FP32, "fp64-valu": mtp.MTP_FP64_VALU}[args.precision]
+    S = mtp.Solver(M, T, W["p"], W["q"], W["m"], precision=prec)
+    kernel_name = {0: "tent_kernel (vector-ALU FP64)", 1: "tent_mfma_kernel<double> (FP64 MFMA)",
+                   2: "tent_mfma_kernel<float> (FP32 MFMA, FP64 inversion and Taylor sum)"}[S.kernel()]
     u0 = W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), 0.0)
     S.set_fields(u0, 0.0)
     dof_slab, n_tents = S.slab_dof_updates()
@@ -128,17 +144,18 @@ def main():
         f"nodal rel. error vs exact {err:.2e}")
 
     value = dof_slab * args.steps / wall
+    peak = PEAK_FP32 if S.kernel() == 2 else PEAK_FP64
     out = {
         "metric": "DOF-updates/s, 3D Maxwell p=4 MTP: mixed/batched vs FP64 GPU at equal L2 error",
         "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if S.kernel() != 2 else "f32+f64", "data": "synthetic",
         "config": {"workload": W["desc"], "tets": int(M.info["ne"]), "p": W["p"], "q": W["q"], "m": W["m"],
                    "tents_per_step": int(n_tents), "layers_per_step": int(nl), "slope_fraction": 0.5,
-                   "nodal_rel_error_vs_exact": float(err)},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64, "traffic": None,
-                     "kernel": "tent_kernel (one launch per layer)",
+                   "precision": args.precision, "nodal_rel_error_vs_exact": float(err)},
+        "roofline": {"bound": "alu" if S.kernel() == 0 else "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": kernel_name + ", one launch per layer",
                      "avg_launch_ms": kern_avg * 1e3, "launches": int(args.steps * nl)},
     }
     if not args.no_cpu_baseline:

@@ -61,8 +61,14 @@ enum {
 /* boundary-condition kinds of boundary faces */
 enum { MTP_BC_PEC = 0, MTP_BC_PMC = 1, MTP_BC_DATA = 2 };
 
-/* arithmetic of the tent kernels */
-enum { MTP_FP64 = 0 };
+/* arithmetic of the tent kernels
+ *   MTP_FP64       plain FP64; contractions on the FP64 matrix cores (falls back to the
+ *                  vector-ALU kernel when a patch does not fit the matrix-core kernel)
+ *   MTP_MIXED_FP32 contractions, face fluxes and the n >= 1 inversions in FP32 on the
+ *                  matrix cores; the inversion that starts each sub-interval and the
+ *                  Taylor sum into the state in FP64
+ *   MTP_FP64_VALU  plain FP64 on the vector ALUs (reference kernel)                    */
+enum { MTP_FP64 = 0, MTP_MIXED_FP32 = 1, MTP_FP64_VALU = 2 };
 
 /* Conforming simplicial mesh (section 2).  dim = 2 (triangles, TE fields) or 3 (tets).
  * coords (nv*dim), cells (ne*(dim+1)), eps/mu (ne) per-element material constants,
@@ -146,6 +152,9 @@ mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
 /* Spacetime DOF updates of one slab: sum over tents of nc*Np*n_T(tent)*m*q (the paper's
  * spacetime DOF count, section 5), and the tent count. */
 mtp_status mtp_slab_dof_updates(mtp_solver solver, double* dof_updates, int64_t* n_tents);
+
+/* Kernel the solver runs: 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32. */
+mtp_status mtp_solver_kernel(mtp_solver solver, int32_t* kernel);
 
 /* Algorithmic flop count of one slab, per the kernel's arithmetic (volume and lift
  * contractions, flux, pointwise inverse, Taylor sum). */

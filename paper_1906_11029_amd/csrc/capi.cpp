@@ -142,6 +142,7 @@ struct mtp_solver_s {
   int64_t layers_done = 0;   // layers done in the current slab
   double t_base = 0.0;       // front time at the start of slab 0
   bool has_data_faces = false;
+  int kernel = 0;            // 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32
 };
 
 using namespace mtp;
@@ -246,15 +247,25 @@ mtp_status mtp_tents_export(mtp_tents tents, int32_t* vertex, double* t_bot, dou
 
 void mtp_tents_destroy(mtp_tents tents) { delete tents; }
 
-static void check_config(const Mesh& m, int p, int q, int mm, int precision) {
-  require(precision == MTP_FP64, MTP_ERR_UNSUPPORTED, "only MTP_FP64 is available");
+// Kernel choice: 0 = vector-ALU FP64, 1 = matrix-core FP64, 2 = matrix-core FP32 (mixed).
+static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
+  require(precision == MTP_FP64 || precision == MTP_MIXED_FP32 || precision == MTP_FP64_VALU,
+          MTP_ERR_UNSUPPORTED, "unknown precision");
   require(q >= 1 && q <= 32 && mm >= 1 && mm <= 1024, MTP_ERR_ARG, "q must be in 1..32 and m in 1..1024");
   require(tent_kernel_supported(m.d, p), MTP_ERR_UNSUPPORTED, "degree p not covered for this dimension");
-  const size_t lds = tent_kernel_lds_bytes(m.d, p, m.max_patch);
-  require(lds <= 160 * 1024, MTP_ERR_UNSUPPORTED, "largest vertex patch does not fit the 160 KiB of LDS");
+  const size_t lim = 160 * 1024;
+  const size_t lds_valu = tent_kernel_lds_bytes(m.d, p, m.max_patch);
   const int np = (m.d == 2) ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
   const int block = (m.d == 2) ? 128 : 256;
-  require(m.max_patch * np <= block * 8, MTP_ERR_UNSUPPORTED, "largest vertex patch has too many nodes");
+  const bool valu_ok = lds_valu <= lim && m.max_patch * np <= block * 8;
+  if (precision == MTP_MIXED_FP32) {
+    require(tent_mfma_lds_bytes(m.d, p, m.max_patch, 1) <= lim, MTP_ERR_UNSUPPORTED,
+            "largest vertex patch does not fit the matrix-core kernel's LDS");
+    return 2;
+  }
+  if (precision == MTP_FP64 && tent_mfma_lds_bytes(m.d, p, m.max_patch, 0) <= lim) return 1;
+  require(valu_ok, MTP_ERR_UNSUPPORTED, "largest vertex patch does not fit the 160 KiB of LDS");
+  return 0;
 }
 
 mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q, int32_t m,
@@ -272,8 +283,9 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
   MTP_TRY
   require(mesh && tents && out && d_workspace, MTP_ERR_ARG, "null pointer");
   require(alpha >= 0 && std::isfinite(alpha), MTP_ERR_ARG, "alpha must be >= 0");
-  check_config(mesh->m, p, q, m, precision);
+  const int kernel = check_config(mesh->m, p, q, m, precision);
   auto* s = new mtp_solver_s();
+  s->kernel = kernel;
   try {
     s->mesh = mesh->m;
     s->tents = tents->t;
@@ -408,7 +420,10 @@ static void run_layer(mtp_solver s, int64_t layer) {
   const Tents& T = s->tents;
   const int64_t first = T.layer_ptr[layer], count = T.layer_ptr[layer + 1] - first;
   s->kp.t_offset = s->t_base + s->slab * T.t_end;
-  check_hip(launch_tent_layer(s->kp, first, count, s->stream), "tent kernel");
+  if (s->kernel == 0)
+    check_hip(launch_tent_layer(s->kp, first, count, s->stream), "tent kernel");
+  else
+    check_hip(launch_tent_layer_mfma(s->kp, first, count, s->kernel == 2, s->stream), "tent kernel");
 }
 
 mtp_status mtp_layer_advance(mtp_solver s, int64_t layer) {
@@ -480,6 +495,13 @@ mtp_status mtp_slab_dof_updates(mtp_solver s, double* dof_updates, int64_t* n_te
   for (int32_t v : s->tents.vertex) tot += (double)(M.v2e_ptr[v + 1] - M.v2e_ptr[v]);
   if (dof_updates) *dof_updates = tot * s->nc * s->ref.np * s->m * s->q;
   if (n_tents) *n_tents = (int64_t)s->tents.vertex.size();
+  MTP_CATCH
+}
+
+mtp_status mtp_solver_kernel(mtp_solver s, int32_t* kernel) {
+  MTP_TRY
+  require(s && kernel, MTP_ERR_ARG, "null pointer");
+  *kernel = s->kernel;
   MTP_CATCH
 }
 

@@ -47,6 +47,9 @@ enum { ERRF_CAUSALITY = 1, ERRF_NONFINITE = 2 };
 size_t tent_kernel_lds_bytes(int d, int p, int max_patch);
 bool tent_kernel_supported(int d, int p);
 hipError_t launch_tent_layer(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s);
+// matrix-core variant: fp32 = 0 contracts in FP64, fp32 = 1 in FP32 (mixed path)
+size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32);
+hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t count, int fp32, hipStream_t s);
 hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
                              int64_t nv, hipStream_t s);
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);

@@ -24,125 +24,11 @@
 #include <cmath>
 
 #include "kernels.h"
+#include "tent_common.h"
 
 namespace mtp {
 
 namespace {
-
-template <int D> struct Dims;
-template <> struct Dims<2> { static constexpr int NC = 3; };
-template <> struct Dims<3> { static constexpr int NC = 6; };
-
-__host__ __device__ constexpr int binom_c(int n, int k) {
-  int r = 1;
-  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
-  return r;
-}
-
-// A(g) u = f(u) g : 3D (H x g, g x E);  2D TE (-g_y Hz, g_x Hz, g_x Ey - g_y Ex)
-template <int D>
-__device__ __forceinline__ void applyA(const double* g, const double* u, double* out);
-template <>
-__device__ __forceinline__ void applyA<3>(const double* g, const double* u, double* out) {
-  const double Ex = u[0], Ey = u[1], Ez = u[2], Hx = u[3], Hy = u[4], Hz = u[5];
-  out[0] = Hy * g[2] - Hz * g[1];
-  out[1] = Hz * g[0] - Hx * g[2];
-  out[2] = Hx * g[1] - Hy * g[0];
-  out[3] = g[1] * Ez - g[2] * Ey;
-  out[4] = g[2] * Ex - g[0] * Ez;
-  out[5] = g[0] * Ey - g[1] * Ex;
-}
-template <>
-__device__ __forceinline__ void applyA<2>(const double* g, const double* u, double* out) {
-  out[0] = -g[1] * u[2];
-  out[1] = g[0] * u[2];
-  out[2] = g[0] * u[1] - g[1] * u[0];
-}
-
-// Closed-form inverse of u -> g(u) - f(u) b  (section 4):
-//   E = s (I - b b^T/(eps mu)) (mu w_E + w_H x b),  H = s (I - b b^T/(eps mu)) (eps w_H - w_E x b),
-//   s = 1/(eps mu - |b|^2).  Returns false if eps mu - |b|^2 <= 0 (causality violated).
-template <int D>
-__device__ __forceinline__ bool kinv(const double* b, double eps, double mu, const double* w, double* u);
-template <>
-__device__ __forceinline__ bool kinv<3>(const double* b, double eps, double mu, const double* w, double* u) {
-  const double em = eps * mu;
-  const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-  const double den = em - bb;
-  const double s = 1.0 / den;
-  const double iem = 1.0 / em;
-  double rE[3], rH[3];
-  rE[0] = mu * w[0] + (w[4] * b[2] - w[5] * b[1]);
-  rE[1] = mu * w[1] + (w[5] * b[0] - w[3] * b[2]);
-  rE[2] = mu * w[2] + (w[3] * b[1] - w[4] * b[0]);
-  rH[0] = eps * w[3] - (w[1] * b[2] - w[2] * b[1]);
-  rH[1] = eps * w[4] - (w[2] * b[0] - w[0] * b[2]);
-  rH[2] = eps * w[5] - (w[0] * b[1] - w[1] * b[0]);
-  const double pE = (b[0] * rE[0] + b[1] * rE[1] + b[2] * rE[2]) * iem;
-  const double pH = (b[0] * rH[0] + b[1] * rH[1] + b[2] * rH[2]) * iem;
-  for (int i = 0; i < 3; ++i) {
-    u[i] = s * (rE[i] - b[i] * pE);
-    u[3 + i] = s * (rH[i] - b[i] * pH);
-  }
-  return den > 0.0;
-}
-template <>
-__device__ __forceinline__ bool kinv<2>(const double* b, double eps, double mu, const double* w, double* u) {
-  const double em = eps * mu;
-  const double bb = b[0] * b[0] + b[1] * b[1];
-  const double den = em - bb;
-  const double s = 1.0 / den;
-  const double rx = mu * w[0] - w[2] * b[1];
-  const double ry = mu * w[1] + w[2] * b[0];
-  const double pE = (b[0] * rx + b[1] * ry) / em;
-  u[0] = s * (rx - b[0] * pE);
-  u[1] = s * (ry - b[1] * pE);
-  u[2] = s * (eps * w[2] - (w[0] * b[1] - w[1] * b[0]));
-  return den > 0.0;
-}
-
-// Upwind flux times |g| for the outward direction g = -grad lambda_j (unnormalised):
-//   G = 1/2 A(g)(u_in + u_out) + alpha |g| P_t (u_in - u_out),   P_t = tangential part.
-template <int D>
-__device__ __forceinline__ void flux(const double* g, double alpha, const double* um, const double* up, double* G);
-template <>
-__device__ __forceinline__ void flux<3>(const double* g, double alpha, const double* um, const double* up, double* G) {
-  double s[6], dlt[6];
-  for (int c = 0; c < 6; ++c) { s[c] = 0.5 * (um[c] + up[c]); dlt[c] = um[c] - up[c]; }
-  applyA<3>(g, s, G);
-  const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-  const double gn = sqrt(gg);
-  const double ig = 1.0 / gg;
-  const double nE = (g[0] * dlt[0] + g[1] * dlt[1] + g[2] * dlt[2]) * ig;
-  const double nH = (g[0] * dlt[3] + g[1] * dlt[4] + g[2] * dlt[5]) * ig;
-  const double ag = alpha * gn;
-  for (int i = 0; i < 3; ++i) {
-    G[i] += ag * (dlt[i] - nE * g[i]);
-    G[3 + i] += ag * (dlt[3 + i] - nH * g[i]);
-  }
-}
-template <>
-__device__ __forceinline__ void flux<2>(const double* g, double alpha, const double* um, const double* up, double* G) {
-  double s[3], dlt[3];
-  for (int c = 0; c < 3; ++c) { s[c] = 0.5 * (um[c] + up[c]); dlt[c] = um[c] - up[c]; }
-  applyA<2>(g, s, G);
-  const double gg = g[0] * g[0] + g[1] * g[1];
-  const double gn = sqrt(gg);
-  const double nE = (g[0] * dlt[0] + g[1] * dlt[1]) / gg;
-  const double ag = alpha * gn;
-  G[0] += ag * (dlt[0] - nE * g[0]);
-  G[1] += ag * (dlt[1] - nE * g[1]);
-  G[2] += ag * dlt[2];
-}
-
-template <int D>
-__device__ __forceinline__ void vertex_order_dev(int k, int* order) {
-  order[0] = k;
-  int c = 1;
-#pragma unroll
-  for (int i = 0; i <= D; ++i)
-    if (i != k) order[c++] = i;
-}
 
 template <int D, int P>
 struct Shape {
@@ -290,43 +176,7 @@ __global__ void __launch_bounds__(BLOCK) tent_kernel(KernelParams kp, int64_t fi
 #pragma unroll
             for (int c = 0; c < NC; ++c) up[c] = sU[(pe * NC + c) * NP + nout];
           } else {
-            const int kind = -1 - code;
-            if (kind == 2 && kp.has_data) {
-              // ghost u_ex(x, phi(x, th)); its (n-1)-th th-derivative is
-              // delta^(n-1) d_t^(n-1) u_ex with delta = H lambda_V
-              const int el = sElem[e];
-              int order[NV];
-              vertex_order_dev<D>(sK[e], order);
-              double x[D], phib = 0.0;
-#pragma unroll
-              for (int xx = 0; xx < D; ++xx) x[xx] = 0.0;
-              const int* alpha = kp.mi + nin * NV;
-#pragma unroll
-              for (int v = 0; v < NV; ++v) {
-                const int gv = kp.cells[(size_t)el * NV + order[v]];
-                const double lam = (double)alpha[v] / P;
-                phib += lam * kp.tau[gv];
-#pragma unroll
-                for (int xx = 0; xx < D; ++xx) x[xx] += lam * kp.coords[(size_t)gv * D + xx];
-              }
-              const double delta = H * (double)alpha[0] / P;
-              const double phi = phib + th * delta;
-              double psi = kp.pw_phase - kp.pw_omega * phi;
-#pragma unroll
-              for (int xx = 0; xx < D; ++xx) psi += kp.pw_k[xx] * x[xx];
-              const int kd = n - 1;
-              double scale = 1.0;
-              for (int z = 0; z < kd; ++z) scale *= delta * kp.pw_omega;
-              const double val = scale * cos(psi - kd * 1.5707963267948966);  // d_t^k cos = omega^k cos(. - k pi/2)
-#pragma unroll
-              for (int c = 0; c < NC; ++c) up[c] = kp.pw_amp[c] * val;
-            } else if (kind == 1) {  // PMC mirror: E_out = E_in, H_out = -H_in
-#pragma unroll
-              for (int c = 0; c < NC; ++c) up[c] = (c < (D == 3 ? 3 : 2)) ? um[c] : -um[c];
-            } else {                 // PEC mirror: E_out = -E_in, H_out = H_in
-#pragma unroll
-              for (int c = 0; c < NC; ++c) up[c] = (c < (D == 3 ? 3 : 2)) ? -um[c] : um[c];
-            }
+            ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
           }
           flux<D>(g, kp.alpha, um, up, G);
 #pragma unroll

@@ -1,0 +1,455 @@
+// MFMA tent kernel for gfx950: the same per-tent SAT evolution as the VALU kernel, with
+// the per-stage contraction of every patch element done as one matrix product on the
+// matrix cores:
+//
+//   R = [ S_1 .. S_d | -L_1 .. -L_d ] . [ A(grad lambda_1) U ; .. ; A(grad lambda_d) U ; F ]
+//        (np x (d np + d nf))              ((d np + d nf) x (nc nT))
+//
+// with U the patch state (node-major, one column per (element, component)), F the upwind
+// face fluxes at the face nodes of the faces containing the tent vertex, and R the mass-
+// divided right-hand side dY/dth / H of every node.  A(grad lambda_l) U is formed while
+// loading the B operand (two LDS reads and two multiply-adds per value: A(g) is a cross
+// product), so only U and F are stored.  Accumulators stay in registers until every wave
+// has finished reading F, then R overwrites F in LDS.  T = double uses
+// v_mfma_f64_16x16x4f64 (the plain FP64 path); T = float uses v_mfma_f32_16x16x4f32 for
+// the contractions while the closed-form inverse that starts each sub-interval and the
+// Taylor sum stay in FP64 (the mixed path).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+#include "tent_common.h"
+
+namespace mtp {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using acc_t = v4d;
+  // output value r of lane l sits in row l/16 + 4 r (measured lane layout)
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+  static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  using acc_t = v4f;
+  // output value r of lane l sits in row 4 (l/16) + r
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// component c of A(g) u = u[p1] g[q1] s1 + u[p2] g[q2] s2
+template <int D> struct ACoef;
+template <> struct ACoef<3> {
+  // c: (p1, q1, s1, p2, q2, s2)
+  static __device__ __forceinline__ void get(int c, int* p1, int* q1, double* s1, int* p2, int* q2, double* s2) {
+    // P1 = {4,5,3,2,0,1}, Q1 = {2,0,1,1,2,0}, P2 = {5,3,4,1,2,0}, Q2 = {1,2,0,2,0,1}
+    switch (c) {
+      case 0: *p1 = 4; *q1 = 2; *p2 = 5; *q2 = 1; break;
+      case 1: *p1 = 5; *q1 = 0; *p2 = 3; *q2 = 2; break;
+      case 2: *p1 = 3; *q1 = 1; *p2 = 4; *q2 = 0; break;
+      case 3: *p1 = 2; *q1 = 1; *p2 = 1; *q2 = 2; break;
+      case 4: *p1 = 0; *q1 = 2; *p2 = 2; *q2 = 0; break;
+      default: *p1 = 1; *q1 = 0; *p2 = 0; *q2 = 1; break;
+    }
+    *s1 = 1.0;
+    *s2 = -1.0;
+  }
+};
+template <> struct ACoef<2> {
+  // (-g1 Hz, g0 Hz, g0 Ey - g1 Ex)
+  static __device__ __forceinline__ void get(int c, int* p1, int* q1, double* s1, int* p2, int* q2, double* s2) {
+    if (c == 0) { *p1 = 2; *q1 = 1; *s1 = -1.0; *p2 = 2; *q2 = 0; *s2 = 0.0; }
+    else if (c == 1) { *p1 = 2; *q1 = 0; *s1 = 1.0; *p2 = 2; *q2 = 1; *s2 = 0.0; }
+    else { *p1 = 1; *q1 = 0; *s1 = 1.0; *p2 = 0; *q2 = 1; *s2 = -1.0; }
+  }
+};
+
+template <int D, int P, int NTMAX>
+struct MShape {
+  static constexpr int NC = (D == 3) ? 6 : 3;
+  static constexpr int NP = binom_c(P + D, D);
+  static constexpr int NF = binom_c(P + D - 1, D - 1);
+  static constexpr int NV = D + 1;
+  static constexpr int NPK = (NP + 3) / 4 * 4;            // one volume block of K (padded)
+  static constexpr int KV = D * NPK;                      // volume part of K
+  static constexpr int KF = D * NF;                       // lift part of K
+  static constexpr int KFP = (KF + 3) / 4 * 4;            // lift part padded to the MFMA depth
+  static constexpr int KT = KV + KFP;
+  static constexpr int MT = (NP + 15) / 16;               // 16-row tiles of R
+  static constexpr int MP = MT * 16;
+  static constexpr int NCOL = (NC * NTMAX + 15) / 16 * 16;  // columns (element, component)
+  static constexpr int RS = NCOL + 1;   // row stride of U and F/R: odd, so that threads owning
+                                        // consecutive nodes of one element hit distinct banks
+  static constexpr int NTILE_MAX = NCOL / 16;
+  static constexpr int FROWS = (KFP > MP) ? KFP : MP;     // F during the product, R after
+  static constexpr int BLOCK = 512;                      // 8 waves, 2 per SIMD
+  static constexpr int WAVES = BLOCK / 64;
+  static constexpr int TILES_PER_WAVE = (MT * NTILE_MAX + WAVES - 1) / WAVES;
+  static constexpr int MAXPAIR = (NTMAX * NP + BLOCK - 1) / BLOCK;
+};
+
+template <int D, int P, typename T, int NTMAX>
+struct MLds {
+  using SH = MShape<D, P, NTMAX>;
+  // A-operand row stride: the four k-groups of a wave land in different banks
+  static constexpr int OPS = SH::MP + (sizeof(T) == 4 ? 16 : 0);
+  static constexpr size_t op_elems = (size_t)SH::KT * OPS;
+  static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
+  static constexpr size_t f_elems = (size_t)SH::FROWS * SH::RS;
+  static constexpr size_t t_bytes = (op_elems + u_elems + f_elems) * sizeof(T);
+  static constexpr size_t geo_doubles = (size_t)NTMAX * (SH::NV * D + D + 2);
+  static constexpr size_t ints = (size_t)D * 2 * SH::NF + (size_t)NTMAX * (2 + D);
+  static constexpr size_t bytes = (t_bytes + 7) / 8 * 8 + geo_doubles * 8 + ints * 4;
+};
+
+template <int D, int P, typename T, int NTMAX>
+__global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
+  using SH = MShape<D, P, NTMAX>;
+  using MM = Mfma<T>;
+  constexpr int NC = SH::NC, NP = SH::NP, NF = SH::NF, NV = SH::NV;
+  constexpr int NPK = SH::NPK, KV = SH::KV, KF = SH::KF, KFP = SH::KFP, KT = SH::KT, MT = SH::MT, MP = SH::MP,
+                RS = SH::RS;
+  constexpr int OPS = MLds<D, P, T, NTMAX>::OPS;
+  constexpr int TPW = SH::TILES_PER_WAVE, MAXPAIR = SH::MAXPAIR, BLOCK = SH::BLOCK, WAVES = SH::WAVES;
+  extern __shared__ double lds_d[];
+  T* sOp = reinterpret_cast<T*>(lds_d);          // [k][m], m fastest
+  using LD = MLds<D, P, T, NTMAX>;
+  T* sU = sOp + LD::op_elems;                     // [node][col]
+  T* sFR = sU + LD::u_elems;                      // [row][col]: F, then R
+  double* sGL = lds_d + (LD::t_bytes + 7) / 8;   // [e][v][x]
+  double* sBb = sGL + NTMAX * NV * D;             // [e][x]
+  double* sEM = sBb + NTMAX * D;                  // [e][2]
+  int* sFn = reinterpret_cast<int*>(sEM + NTMAX * 2);
+  int* sElem = sFn + D * 2 * NF;
+  int* sK = sElem + NTMAX;
+  int* sF = sK + NTMAX;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  // A operand [k][m]: S_l[m][a] at k = l NPK + a (a < NP), -L_j[m][s] at k = KV + j NF + s,
+  // zero in the padding rows and columns
+  for (int i = tid; i < KT * OPS; i += BLOCK) {
+    const int k = i / OPS, m = i - k * OPS;
+    double v = 0.0;
+    if (m < NP) {
+      if (k < KV) {
+        const int l = k / NPK, a = k - l * NPK;
+        if (a < NP) v = kp.S[(l * NP + a) * NP + m];
+      } else if (k < KV + KF) {
+        const int j = (k - KV) / NF, s = (k - KV) - j * NF;
+        v = -kp.L[(j * NF + s) * NP + m];
+      }
+    }
+    sOp[i] = (T)v;
+  }
+  // padding rows of U and F are read by the product (times zero): keep them finite
+  for (int i = tid; i < (NPK - NP) * RS; i += BLOCK) sU[NP * RS + i] = (T)0;
+  for (int i = tid; i < (SH::FROWS - KF) * RS; i += BLOCK) sFR[KF * RS + i] = (T)0;
+  for (int i = tid; i < D * 2 * NF; i += BLOCK) sFn[i] = kp.fnode[i];
+
+  const double invm = 1.0 / kp.m;
+
+  for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+    const int32_t V = kp.tent_vertex[first + t];
+    const double t_top = kp.t_offset + kp.tent_top[first + t];
+    const int32_t p0 = kp.patch_ptr[V];
+    const int nT = kp.patch_ptr[V + 1] - p0;
+    const double H = t_top - kp.tau[V];
+    const int ncols = nT * NC;
+    const int ntiles = (ncols + 15) / 16;
+
+    for (int e = tid; e < nT; e += BLOCK) {
+      const int el = kp.patch_elem[p0 + e];
+      const int32_t* info = kp.patch_info + (size_t)(p0 + e) * (1 + D);
+      const int k = info[0];
+      int order[NV];
+      vertex_order_dev<D>(k, order);
+      const double* gl = kp.grad_lam + (size_t)el * NV * D;
+      double gb[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) gb[i] = 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double tv = kp.tau[kp.cells[(size_t)el * NV + v]];
+#pragma unroll
+        for (int i = 0; i < D; ++i) gb[i] += tv * gl[v * D + i];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int i = 0; i < D; ++i) sGL[(e * NV + v) * D + i] = gl[order[v] * D + i];
+#pragma unroll
+      for (int i = 0; i < D; ++i) sBb[e * D + i] = gb[i];
+      sEM[2 * e] = kp.eps[el];
+      sEM[2 * e + 1] = kp.mu[el];
+      sElem[e] = el;
+      sK[e] = k;
+#pragma unroll
+      for (int j = 0; j < D; ++j) sF[e * D + j] = info[1 + j];
+    }
+    __syncthreads();
+
+    // gather W (FP64, registers) and U_{0,0} = K(b_0)^{-1} W (closed form in FP64)
+    const int npairs = nT * NP;
+    double acc[MAXPAIR][NC];
+    bool ok = true;
+#pragma unroll
+    for (int r = 0; r < MAXPAIR; ++r) {
+      const int P_ = tid + r * BLOCK;
+      if (P_ < npairs) {
+        const int e = P_ / NP, b = P_ - e * NP;
+        const int nold = kp.perm[sK[e] * NP + b];
+        const double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] = Wp[c * NP];
+        double u[NC];
+        ok &= kinv<D>(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = (T)u[c];
+      }
+    }
+    __syncthreads();
+
+    for (int i = 0; i < kp.m; ++i) {
+      const double th = i * invm;
+      double coef = 1.0;
+      for (int n = 1; n <= kp.q; ++n) {
+        coef *= invm / n;
+        // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col]
+        for (int it = tid; it < nT * D * NF; it += BLOCK) {
+          const int e = it / (D * NF);
+          const int rem = it - e * (D * NF);
+          const int j = rem / NF;
+          const int s = rem - j * NF;
+          const int nin = sFn[(j * 2) * NF + s];
+          double um[NC], up[NC], G[NC], g[D];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) um[c] = (double)sU[nin * RS + e * NC + c];
+#pragma unroll
+          for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
+          const int code = sF[e * D + j];
+          if (code >= 0) {
+            const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
+            const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) up[c] = (double)sU[nout * RS + pe * NC + c];
+          } else {
+            ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
+          }
+          flux<D>(g, kp.alpha, um, up, G);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = (T)G[c];
+        }
+        __syncthreads();
+
+        // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
+        typename MM::acc_t accs[TPW];
+#pragma unroll
+        for (int ts = 0; ts < TPW; ++ts) {
+          accs[ts] = typename MM::acc_t{0, 0, 0, 0};
+          const int tile = wave + WAVES * ts;
+          if (tile < MT * ntiles) {
+            const int mt = tile / ntiles, nt = tile - mt * ntiles;
+            const int col = nt * 16 + (lane & 15);
+            const bool live = col < ncols;
+            const int e = live ? col / NC : 0;
+            const int c = live ? col - e * NC : 0;
+            int p1, q1, p2, q2;
+            double s1, s2;
+            ACoef<D>::get(c, &p1, &q1, &s1, &p2, &q2, &s2);
+            T cf1[D], cf2[D];
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+              const double* gl = &sGL[(e * NV + l + 1) * D];
+              cf1[l] = live ? (T)(s1 * gl[q1]) : (T)0;
+              cf2[l] = live ? (T)(s2 * gl[q2]) : (T)0;
+            }
+            const int c1 = e * NC + p1, c2 = e * NC + p2;
+            const int kq = lane >> 4;
+            const T* acol = sOp + mt * 16 + (lane & 15) + kq * OPS;
+            const T* u1 = sU + kq * RS + c1;
+            const T* u2 = sU + kq * RS + c2;
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+#pragma unroll
+              for (int as = 0; as < NPK / 4; ++as) {
+                const T b = cf1[l] * u1[4 * as * RS] + cf2[l] * u2[4 * as * RS];
+                accs[ts] = MM::mma(acol[(l * NPK + 4 * as) * OPS], b, accs[ts]);
+              }
+            }
+            const T* fr = sFR + kq * RS + (live ? col : 0);
+            const T fm = live ? (T)1 : (T)0;
+#pragma unroll
+            for (int fs = 0; fs < KFP / 4; ++fs)
+              accs[ts] = MM::mma(acol[(KV + 4 * fs) * OPS], fm * fr[4 * fs * RS], accs[ts]);
+          }
+        }
+        __syncthreads();   // every wave is done reading F and U
+#pragma unroll
+        for (int ts = 0; ts < TPW; ++ts) {
+          const int tile = wave + WAVES * ts;
+          if (tile < MT * ntiles) {
+            const int mt = tile / ntiles, nt = tile - mt * ntiles;
+            const int col = nt * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sFR[(mt * 16 + MM::row(lane, r)) * RS + col] = accs[ts][r];
+          }
+        }
+        __syncthreads();
+
+        // ---- Taylor accumulation (FP64) and the next U for the owned (element, node) pairs
+#pragma unroll
+        for (int r = 0; r < MAXPAIR; ++r) {
+          const int P_ = tid + r * BLOCK;
+          if (P_ < npairs) {
+            const int e = P_ / NP, b = P_ - e * NP;
+            double Y[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              Y[c] = H * (double)sFR[b * RS + e * NC + c];
+              acc[r][c] = fma(coef, Y[c], acc[r][c]);
+            }
+            const double* gv = &sGL[(e * NV + 0) * D];
+            double un[NC];
+            bool write = false;
+            if (n < kp.q) {
+              double bi[D], bp[D], uo[NC], au[NC], rhs[NC];
+#pragma unroll
+              for (int x = 0; x < D; ++x) {
+                bp[x] = H * gv[x];
+                bi[x] = sBb[e * D + x] + th * bp[x];
+              }
+#pragma unroll
+              for (int c = 0; c < NC; ++c) uo[c] = (double)sU[b * RS + e * NC + c];
+              applyA<D>(bp, uo, au);
+#pragma unroll
+              for (int c = 0; c < NC; ++c) rhs[c] = Y[c] + n * au[c];
+              ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], rhs, un);
+              write = true;
+            } else if (i + 1 < kp.m) {
+              double bi[D];
+              const double th1 = (i + 1) * invm;
+#pragma unroll
+              for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * H * gv[x];
+              ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], un);
+              write = true;
+            }
+            if (write) {
+#pragma unroll
+              for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = (T)un[c];
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    // scatter the tent top
+#pragma unroll
+    for (int r = 0; r < MAXPAIR; ++r) {
+      const int P_ = tid + r * BLOCK;
+      if (P_ < npairs) {
+        const int e = P_ / NP, b = P_ - e * NP;
+        const int nold = kp.perm[sK[e] * NP + b];
+        double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Wp[c * NP] = acc[r][c];
+      }
+    }
+    if (!ok) kp.err[0] = ERRF_CAUSALITY;
+    __syncthreads();
+    if (tid == 0) kp.tau[V] = t_top;
+    __syncthreads();
+  }
+}
+
+template <int D, int P, typename T, int NTMAX>
+hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
+  const size_t lds = MLds<D, P, T, NTMAX>::bytes;
+  auto kfn = tent_mfma_kernel<D, P, T, NTMAX>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
+  return hipGetLastError();
+}
+
+template <int D, int P, typename T>
+hipError_t launch_mp(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
+  if (kp.max_patch <= 8) return launch_m<D, P, T, 8>(kp, first, count, s);
+  if (kp.max_patch <= 24) return launch_m<D, P, T, 24>(kp, first, count, s);
+  if (kp.max_patch <= 48) return launch_m<D, P, T, 48>(kp, first, count, s);
+  return hipErrorInvalidValue;
+}
+
+template <int D, int P, typename T>
+size_t lds_mp(int max_patch) {
+  if (max_patch <= 8) return MLds<D, P, T, 8>::bytes;
+  if (max_patch <= 24) return MLds<D, P, T, 24>::bytes;
+  if (max_patch <= 48) return MLds<D, P, T, 48>::bytes;
+  return (size_t)-1;
+}
+
+template <typename T>
+hipError_t launch_t(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
+  if (kp.d == 2) {
+    switch (kp.p) {
+      case 1: return launch_mp<2, 1, T>(kp, first, count, s);
+      case 2: return launch_mp<2, 2, T>(kp, first, count, s);
+      case 3: return launch_mp<2, 3, T>(kp, first, count, s);
+      case 4: return launch_mp<2, 4, T>(kp, first, count, s);
+      case 5: return launch_mp<2, 5, T>(kp, first, count, s);
+    }
+  } else {
+    switch (kp.p) {
+      case 1: return launch_mp<3, 1, T>(kp, first, count, s);
+      case 2: return launch_mp<3, 2, T>(kp, first, count, s);
+      case 3: return launch_mp<3, 3, T>(kp, first, count, s);
+      case 4: return launch_mp<3, 4, T>(kp, first, count, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+size_t lds_t(int d, int p, int max_patch) {
+  if (d == 2) {
+    switch (p) {
+      case 1: return lds_mp<2, 1, T>(max_patch);
+      case 2: return lds_mp<2, 2, T>(max_patch);
+      case 3: return lds_mp<2, 3, T>(max_patch);
+      case 4: return lds_mp<2, 4, T>(max_patch);
+      case 5: return lds_mp<2, 5, T>(max_patch);
+    }
+  } else {
+    switch (p) {
+      case 1: return lds_mp<3, 1, T>(max_patch);
+      case 2: return lds_mp<3, 2, T>(max_patch);
+      case 3: return lds_mp<3, 3, T>(max_patch);
+      case 4: return lds_mp<3, 4, T>(max_patch);
+    }
+  }
+  return (size_t)-1;
+}
+
+}  // namespace
+
+size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32) {
+  return fp32 ? lds_t<float>(d, p, max_patch) : lds_t<double>(d, p, max_patch);
+}
+
+hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t count, int fp32, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  return fp32 ? launch_t<float>(kp, first, count, s) : launch_t<double>(kp, first, count, s);
+}
+
+}  // namespace mtp

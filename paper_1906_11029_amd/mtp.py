@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmtp.so")
 
 MTP_OK = 0
 MTP_BC_PEC, MTP_BC_PMC, MTP_BC_DATA = 0, 1, 2
-MTP_FP64 = 0
+MTP_FP64, MTP_MIXED_FP32, MTP_FP64_VALU = 0, 1, 2
 
 _lib = None
 
@@ -56,6 +56,7 @@ def load():
         "mtp_get_state": [P, P, i32],
         "mtp_slab_dof_updates": [P, P, P],
         "mtp_slab_flops": [P, P],
+        "mtp_solver_kernel": [P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -215,6 +216,12 @@ def mtp_slab_flops(solver):
     return f.value
 
 
+def mtp_solver_kernel(solver):
+    k = C.c_int32()
+    _check(load().mtp_solver_kernel(solver, C.byref(k)))
+    return k.value
+
+
 # ----------------------------------------------------------------- thin object wrappers
 class Mesh:
     def __init__(self, coords, cells, eps=None, mu=None, face_bc=None):
@@ -290,6 +297,9 @@ class Solver:
 
     def slab_flops(self):
         return mtp_slab_flops(self.h)
+
+    def kernel(self):
+        return mtp_solver_kernel(self.h)
 
     def __del__(self):
         if getattr(self, "h", None):

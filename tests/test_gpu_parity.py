@@ -23,12 +23,12 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def gpu_solver(name):
+def gpu_solver(name, precision=0):
     from paper_1906_11029_amd import mtp
     c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
     M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc)
     T = mtp.Tents(M, c["T"], 0.5)
-    S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"])
+    S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"], precision=precision)
     S.set_fields(u0, 0.0)
     if c["kind"] == DATA:
         S.set_planewave_bc(*planewave_params(ex, dim))
@@ -42,11 +42,17 @@ def fixture(name):
     pytest.skip(f"missing oracle fixture {path}")
 
 
+KERNELS = {"mfma64": 0, "valu64": 2}
+
+
+@pytest.mark.parametrize("kernel", list(KERNELS))
 @pytest.mark.parametrize("name", list(CASES))
-def test_parity_against_oracle(name):
-    print(f"[gpu parity] {name}", flush=True)
+def test_parity_against_oracle(name, kernel):
+    """FP64 paths (matrix-core and vector-ALU kernels): every nodal value, relative L2 <= 1e-10."""
+    print(f"[gpu parity] {name} {kernel}", flush=True)
     ref = fixture(name)
-    c, S, T = gpu_solver(name)
+    c, S, T = gpu_solver(name, KERNELS[kernel])
+    assert S.kernel() == (1 if kernel == "mfma64" else 0)
     ex = T.export()
     for k in ("vertex", "t_top", "layer"):
         assert np.array_equal(ex[k], ref[k]), f"tent list differs in {k}"
@@ -55,6 +61,24 @@ def test_parity_against_oracle(name):
     u = S.get_fields()
     assert rel(w, ref["w"]) <= TOL, rel(w, ref["w"])
     assert rel(u, ref["u"]) <= TOL, rel(u, ref["u"])
+
+
+MIXED_TOL = 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_fp32_against_oracle(name):
+    """Mixed path (FP32 matrix-core contractions, FP64 inversion at n = 0 and FP64 Taylor
+    sum) against the FP64 oracle: relative L2 <= 1e-5."""
+    print(f"[gpu parity] {name} mixed", flush=True)
+    ref = fixture(name)
+    c, S, T = gpu_solver(name, 1)
+    assert S.kernel() == 2
+    S.advance_to(c["slabs"] * c["T"])
+    w = S.get_state()
+    err = rel(w, ref["w"])
+    print(f"  mixed relative L2 {err:.3e}")
+    assert err <= MIXED_TOL, err
 
 
 def test_layer_api_equals_advance_and_is_deterministic():
