@@ -105,14 +105,23 @@ struct MLds {
   static constexpr size_t op_elems = (size_t)SH::KT * OPS;
   static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
   static constexpr size_t f_elems = (size_t)SH::FROWS * SH::RS;
-  static constexpr size_t t_bytes = (op_elems + u_elems + f_elems) * sizeof(T);
+  // mixed path: the tent's first stage keeps U and F in FP64 over the same (larger) region
+  static constexpr size_t work_bytes_t = (u_elems + f_elems) * sizeof(T);
+  static constexpr size_t work_bytes_64 = (sizeof(T) == 4) ? (size_t)(SH::NP + SH::KF) * SH::RS * 8 : 0;
+  // mixed path: Y_{i,1} of every node pair (FP64) after the FP32 buffers
+  static constexpr size_t y1_off = (work_bytes_t + 7) / 8 * 8;
+  static constexpr size_t y1_bytes = (sizeof(T) == 4) ? (size_t)NTMAX * SH::NP * SH::NC * 8 : 0;
+  static constexpr size_t work_a = y1_off + y1_bytes;
+  static constexpr size_t work_bytes = work_a > work_bytes_64 ? work_a : work_bytes_64;
+  static constexpr size_t t_bytes = op_elems * sizeof(T) + work_bytes;
   static constexpr size_t geo_doubles = (size_t)NTMAX * (SH::NV * D + D + 2);
   static constexpr size_t ints = (size_t)D * 2 * SH::NF + (size_t)NTMAX * (2 + D);
   static constexpr size_t bytes = (t_bytes + 7) / 8 * 8 + geo_doubles * 8 + ints * 4;
 };
 
-template <int D, int P, typename T, int NTMAX>
-__global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
+template <int D, int P, typename T, int NTMAX, int WPE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
   using SH = MShape<D, P, NTMAX>;
   using MM = Mfma<T>;
   constexpr int NC = SH::NC, NP = SH::NP, NF = SH::NF, NV = SH::NV;
@@ -199,8 +208,15 @@ __global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t
     __syncthreads();
 
     // gather W (FP64, registers) and U_{0,0} = K(b_0)^{-1} W (closed form in FP64)
+    constexpr bool MIXED = sizeof(T) == 4;
+    constexpr int MPX = MIXED ? MAXPAIR : 1;
     const int npairs = nT * NP;
     double acc[MAXPAIR][NC];
+    double u0p[MPX][NC];   // mixed: U_{i,0} in FP64
+    // mixed: Y_{i,1} in FP64, one entry per node pair, in LDS after the FP32 buffers
+    double* sY1 = reinterpret_cast<double*>(reinterpret_cast<char*>(sU) + LD::y1_off);
+    double* sU64 = reinterpret_cast<double*>(sU);     // mixed, first stage of the tent:
+    double* sF64 = sU64 + (size_t)NP * RS;            //   U and F in FP64
     bool ok = true;
 #pragma unroll
     for (int r = 0; r < MAXPAIR; ++r) {
@@ -213,17 +229,144 @@ __global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t
         for (int c = 0; c < NC; ++c) acc[r][c] = Wp[c * NP];
         double u[NC];
         ok &= kinv<D>(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
+        if constexpr (MIXED) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = (T)u[c];
+          for (int c = 0; c < NC; ++c) {
+            u0p[r][c] = u[c];
+            sU64[b * RS + e * NC + c] = u[c];
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = (T)u[c];
+        }
       }
     }
     __syncthreads();
+
+    if constexpr (MIXED) {
+      // ---- first stage of the tent, Y_{0,1} = H R(U_{0,0}), in FP64 on the vector ALUs
+      //      (later sub-intervals only apply R in FP32 to the small U_{i,0} - U_{i-1,0})
+      for (int it = tid; it < nT * D * NF; it += BLOCK) {
+        const int e = it / (D * NF);
+        const int rem = it - e * (D * NF);
+        const int j = rem / NF;
+        const int s = rem - j * NF;
+        const int nin = sFn[(j * 2) * NF + s];
+        double um[NC], up[NC], G[NC], g[D];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) um[c] = sU64[nin * RS + e * NC + c];
+#pragma unroll
+        for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
+        const int code = sF[e * D + j];
+        if (code >= 0) {
+          const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
+          const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) up[c] = sU64[nout * RS + pe * NC + c];
+        } else {
+          ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, 0.0, 1);
+        }
+        flux<D>(g, kp.alpha, um, up, G);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sF64[(j * NF + s) * RS + e * NC + c] = G[c];
+      }
+      __syncthreads();
+      double un[MPX][NC];
+      double y1[MPX][NC];
+#pragma unroll
+      for (int r = 0; r < MAXPAIR; ++r) {
+        const int P_ = tid + r * BLOCK;
+        if (P_ < npairs) {
+          const int e = P_ / NP, b = P_ - e * NP;
+          double Y[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) Y[c] = 0.0;
+#pragma unroll
+          for (int l = 0; l < D; ++l) {
+            double tl[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) tl[c] = 0.0;
+            const double* Sl = kp.S + (size_t)l * NP * NP + b;
+            const double* Ue = sU64 + e * NC;
+#pragma unroll 2
+            for (int a = 0; a < NP; ++a) {
+              const double sv = Sl[a * NP];
+#pragma unroll
+              for (int c = 0; c < NC; ++c) tl[c] = fma(sv, Ue[a * RS + c], tl[c]);
+            }
+            double at[NC];
+            applyA<D>(&sGL[(e * NV + l + 1) * D], tl, at);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Y[c] += at[c];
+          }
+          const double* Fe = sF64 + e * NC;
+#pragma unroll 2
+          for (int k = 0; k < KF; ++k) {
+            const double lv = kp.L[(size_t)k * NP + b];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) Y[c] = fma(-lv, Fe[k * RS + c], Y[c]);
+          }
+          const double* gv = &sGL[(e * NV + 0) * D];
+          double bp[D], au[NC], rhs[NC];
+#pragma unroll
+          for (int x = 0; x < D; ++x) bp[x] = H * gv[x];
+          applyA<D>(bp, u0p[r], au);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            Y[c] *= H;
+            y1[r][c] = Y[c];
+            acc[r][c] = fma(invm, Y[c], acc[r][c]);
+            rhs[c] = Y[c] + au[c];
+          }
+          if (kp.q > 1) ok &= kinv<D>(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], rhs, un[r]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < MAXPAIR; ++r) {
+        const int P_ = tid + r * BLOCK;
+        if (P_ < npairs) {
+          const int e = P_ / NP, b = P_ - e * NP;
+          double w[NC];
+          if (kp.q > 1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) w[c] = un[r][c];
+          } else if (kp.m > 1) {   // q = 1: the sub-interval ends here
+            double bi[D], u[NC];
+#pragma unroll
+            for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + invm * H * sGL[(e * NV + 0) * D + x];
+            ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], u);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              w[c] = u[c] - u0p[r][c];
+              u0p[r][c] = u[c];
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) w[c] = 0.0;
+          }
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            sU[b * RS + e * NC + c] = (T)w[c];
+            sY1[P_ * NC + c] = y1[r][c];
+          }
+        }
+      }
+      // the FP64 buffers overlapped the padding rows the product multiplies by zero:
+      // make them finite again
+      for (int x = tid; x < (NPK - NP) * RS; x += BLOCK) sU[NP * RS + x] = (T)0;
+      for (int x = tid; x < (SH::FROWS - KF) * RS; x += BLOCK) sFR[KF * RS + x] = (T)0;
+      __syncthreads();
+    }
 
     for (int i = 0; i < kp.m; ++i) {
       const double th = i * invm;
       double coef = 1.0;
       for (int n = 1; n <= kp.q; ++n) {
         coef *= invm / n;
+        if (MIXED && i == 0 && n == 1) continue;   // done in FP64 above
+        // mixed, first stage of a later sub-interval: U holds U_{i,0} - U_{i-1,0}
+        const bool diff = MIXED && n == 1;
         // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col]
         for (int it = tid; it < nT * D * NF; it += BLOCK) {
           const int e = it / (D * NF);
@@ -243,7 +386,14 @@ __global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t
 #pragma unroll
             for (int c = 0; c < NC; ++c) up[c] = (double)sU[nout * RS + pe * NC + c];
           } else {
-            ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
+            const int kind = -1 - code;
+            ghost_state<D, P>(kp, kind, um, up, sElem[e], sK[e], nin, H, th, n);
+            if (diff && kind == 2 && kp.has_data) {   // data ghost enters as a difference too
+              double up0[NC];
+              ghost_state<D, P>(kp, kind, um, up0, sElem[e], sK[e], nin, H, th - invm, n);
+#pragma unroll
+              for (int c = 0; c < NC; ++c) up[c] -= up0[c];
+            }
           }
           flux<D>(g, kp.alpha, um, up, G);
 #pragma unroll
@@ -316,6 +466,12 @@ __global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
               Y[c] = H * (double)sFR[b * RS + e * NC + c];
+              if constexpr (MIXED) {
+                if (diff) {   // Y_{i,1} = Y_{i-1,1} + H R(U_{i,0} - U_{i-1,0})
+                  Y[c] += sY1[P_ * NC + c];
+                  sY1[P_ * NC + c] = Y[c];
+                }
+              }
               acc[r][c] = fma(coef, Y[c], acc[r][c]);
             }
             const double* gv = &sGL[(e * NV + 0) * D];
@@ -328,8 +484,18 @@ __global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t
                 bp[x] = H * gv[x];
                 bi[x] = sBb[e * D + x] + th * bp[x];
               }
+              if constexpr (MIXED) {
+                if (diff) {
 #pragma unroll
-              for (int c = 0; c < NC; ++c) uo[c] = (double)sU[b * RS + e * NC + c];
+                  for (int c = 0; c < NC; ++c) uo[c] = u0p[r][c];
+                } else {
+#pragma unroll
+                  for (int c = 0; c < NC; ++c) uo[c] = (double)sU[b * RS + e * NC + c];
+                }
+              } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) uo[c] = (double)sU[b * RS + e * NC + c];
+              }
               applyA<D>(bp, uo, au);
 #pragma unroll
               for (int c = 0; c < NC; ++c) rhs[c] = Y[c] + n * au[c];
@@ -341,6 +507,14 @@ __global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t
 #pragma unroll
               for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * H * gv[x];
               ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], un);
+              if constexpr (MIXED) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                  const double u = un[c];
+                  un[c] = u - u0p[r][c];
+                  u0p[r][c] = u;
+                }
+              }
               write = true;
             }
             if (write) {
@@ -375,7 +549,8 @@ __global__ void __launch_bounds__(512) tent_mfma_kernel(KernelParams kp, int64_t
 template <int D, int P, typename T, int NTMAX>
 hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
-  auto kfn = tent_mfma_kernel<D, P, T, NTMAX>;
+  constexpr int WPE = 2;   // 8 waves per workgroup, one workgroup per CU
+  auto kfn = tent_mfma_kernel<D, P, T, NTMAX, WPE>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
