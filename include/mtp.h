@@ -136,7 +136,10 @@ mtp_status mtp_set_planewave_bc(mtp_solver solver, const double* amp, const doub
 /* Enqueue the tents of one layer of the current slab (stream ordered, asynchronous). */
 mtp_status mtp_layer_advance(mtp_solver solver, int64_t layer);
 /* Enqueue whole slabs until the flat front reaches T (T must be the current front time
- * plus a whole number of slab heights).  Asynchronous. */
+ * plus a whole number of slab heights).  Asynchronous.  By default the first call captures
+ * one slab (every layer launch, section 2's layer order) into a HIP graph on a private
+ * stream and every slab replays it on the solver's stream; the slab's time offset lives in
+ * device memory, so one graph serves all slabs. */
 mtp_status mtp_advance_to(mtp_solver solver, double T);
 /* Current front time (flat) and number of layers done in the current slab. */
 mtp_status mtp_front(mtp_solver solver, double* t_front, int64_t* layers_done);
@@ -152,6 +155,9 @@ mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
 /* Spacetime DOF updates of one slab: sum over tents of nc*Np*n_T(tent)*m*q (the paper's
  * spacetime DOF count, section 5), and the tent count. */
 mtp_status mtp_slab_dof_updates(mtp_solver solver, double* dof_updates, int64_t* n_tents);
+
+/* on = 0: advance_to launches layer by layer instead of replaying the captured slab graph. */
+mtp_status mtp_solver_set_graph(mtp_solver solver, int32_t on);
 
 /* Kernel the solver runs: 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32. */
 mtp_status mtp_solver_kernel(mtp_solver solver, int32_t* kernel);

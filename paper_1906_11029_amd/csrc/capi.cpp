@@ -34,7 +34,7 @@ struct Layout {
 
 struct Offsets {
   size_t W, tau, stage, grad_lam, cells, eps, mu, coords, pptr, pelem, pinfo, tv, tt, S, L, fnode,
-      perm, mi, err, total;
+      perm, mi, err, slab, total;
 };
 
 static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
@@ -61,6 +61,7 @@ static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
   o.perm = L.add(sizeof(int32_t) * R.perm.size());
   o.mi = L.add(sizeof(int32_t) * R.mi.size());
   o.err = L.add(sizeof(int32_t) * 4);
+  o.slab = L.add(sizeof(double) * 4);
   o.total = L.off;
   return o;
 }
@@ -143,6 +144,11 @@ struct mtp_solver_s {
   double t_base = 0.0;       // front time at the start of slab 0
   bool has_data_faces = false;
   int kernel = 0;            // 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32
+  // one slab (slab begin, every layer, slab end) captured once and replayed per slab
+  bool use_graph = true;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
 
 using namespace mtp;
@@ -354,7 +360,10 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     kp.err = reinterpret_cast<int32_t*>(s->ws + s->off.err);
     kp.tent_vertex = reinterpret_cast<const int32_t*>(s->ws + s->off.tv);
     kp.tent_top = reinterpret_cast<const double*>(s->ws + s->off.tt);
+    kp.slab = reinterpret_cast<double*>(s->ws + s->off.slab);
     kp.max_patch = M.max_patch;
+    check_hip(prepare_tent_kernel(kp, s->kernel), "tent kernel attributes");
+    check_hip(launch_slab_reset(kp, 0.0, s->tents.t_end, s->stream), "slab state");
     check_hip(hipStreamSynchronize(s->stream), "upload sync");
   } catch (...) {
     delete s;
@@ -364,8 +373,19 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
   MTP_CATCH
 }
 
+static void drop_graph(mtp_solver s) {
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->cap) (void)hipStreamDestroy(s->cap);
+  s->gexec = nullptr;
+  s->graph = nullptr;
+  s->cap = nullptr;
+}
+
 void mtp_solver_destroy(mtp_solver solver) {
-  if (solver && solver->stream) (void)hipStreamSynchronize(solver->stream);
+  if (!solver) return;
+  (void)hipStreamSynchronize(solver->stream);
+  drop_graph(solver);
   delete solver;
 }
 
@@ -398,6 +418,7 @@ mtp_status mtp_set_fields(mtp_solver s, const double* nodal, int32_t on_device, 
     src = reinterpret_cast<const double*>(s->ws + s->off.stage);
   }
   check_hip(launch_set_fields(s->kp, M.ne, src, t0, M.nv, s->stream), "set_fields");
+  check_hip(launch_slab_reset(s->kp, t0, s->tents.t_end, s->stream), "slab state");
   if (!on_device) check_hip(hipStreamSynchronize(s->stream), "sync");
   s->t_base = t0;
   s->slab = 0;
@@ -416,14 +437,37 @@ mtp_status mtp_set_planewave_bc(mtp_solver s, const double* amp, const double* k
   MTP_CATCH
 }
 
-static void run_layer(mtp_solver s, int64_t layer) {
+static void run_layer(mtp_solver s, int64_t layer, hipStream_t st) {
   const Tents& T = s->tents;
   const int64_t first = T.layer_ptr[layer], count = T.layer_ptr[layer + 1] - first;
-  s->kp.t_offset = s->t_base + s->slab * T.t_end;
   if (s->kernel == 0)
-    check_hip(launch_tent_layer(s->kp, first, count, s->stream), "tent kernel");
+    check_hip(launch_tent_layer(s->kp, first, count, st), "tent kernel");
   else
-    check_hip(launch_tent_layer_mfma(s->kp, first, count, s->kernel == 2, s->stream), "tent kernel");
+    check_hip(launch_tent_layer_mfma(s->kp, first, count, s->kernel == 2, st), "tent kernel");
+}
+
+static void run_slab(mtp_solver s, hipStream_t st) {
+  const int64_t nl = (int64_t)s->tents.layer_ptr.size() - 1;
+  check_hip(launch_slab_begin(s->kp, st), "slab begin");
+  for (int64_t l = 0; l < nl; ++l) run_layer(s, l, st);
+  check_hip(launch_slab_end(s->kp, st), "slab end");
+}
+
+// Capture one slab on a private stream (default priority) and instantiate it.
+static void build_graph(mtp_solver s) {
+  check_hip(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking), "capture stream");
+  check_hip(hipStreamBeginCapture(s->cap, hipStreamCaptureModeRelaxed), "begin capture");
+  try {
+    run_slab(s, s->cap);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(s->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    drop_graph(s);
+    throw;
+  }
+  check_hip(hipStreamEndCapture(s->cap, &s->graph), "end capture");
+  check_hip(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0), "graph instantiate");
 }
 
 mtp_status mtp_layer_advance(mtp_solver s, int64_t layer) {
@@ -432,9 +476,11 @@ mtp_status mtp_layer_advance(mtp_solver s, int64_t layer) {
   require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
   const int64_t nl = (int64_t)s->tents.layer_ptr.size() - 1;
   require(layer == s->layers_done && layer < nl, MTP_ERR_STATE, "layers must run in order");
-  run_layer(s, layer);
+  if (layer == 0) check_hip(launch_slab_begin(s->kp, s->stream), "slab begin");
+  run_layer(s, layer, s->stream);
   s->layers_done++;
   if (s->layers_done == nl) {
+    check_hip(launch_slab_end(s->kp, s->stream), "slab end");
     s->layers_done = 0;
     s->slab++;
   }
@@ -452,9 +498,12 @@ mtp_status mtp_advance_to(mtp_solver s, double T) {
   const int64_t nslab = (int64_t)std::llround(k);
   require(std::fabs(k - (double)nslab) < 1e-9 && nslab >= 0, MTP_ERR_STATE,
           "T must be the front time plus a whole number of slabs");
-  const int64_t nl = (int64_t)s->tents.layer_ptr.size() - 1;
+  if (nslab > 0 && s->use_graph && !s->gexec) build_graph(s);
   for (int64_t j = 0; j < nslab; ++j) {
-    for (int64_t l = 0; l < nl; ++l) run_layer(s, l);
+    if (s->use_graph)
+      check_hip(hipGraphLaunch(s->gexec, s->stream), "graph launch");
+    else
+      run_slab(s, s->stream);
     s->slab++;
   }
   MTP_CATCH
@@ -495,6 +544,13 @@ mtp_status mtp_slab_dof_updates(mtp_solver s, double* dof_updates, int64_t* n_te
   for (int32_t v : s->tents.vertex) tot += (double)(M.v2e_ptr[v + 1] - M.v2e_ptr[v]);
   if (dof_updates) *dof_updates = tot * s->nc * s->ref.np * s->m * s->q;
   if (n_tents) *n_tents = (int64_t)s->tents.vertex.size();
+  MTP_CATCH
+}
+
+mtp_status mtp_solver_set_graph(mtp_solver s, int32_t on) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  s->use_graph = on != 0;
   MTP_CATCH
 }
 

@@ -34,7 +34,9 @@ struct KernelParams {
   // tents of the launch
   const int32_t* tent_vertex;
   const double* tent_top;
-  double t_offset;
+  // slab state in device memory: [0] time of the current slab's bottom (tent times are
+  // relative to it), [1] slab height, [2] front time at slab 0, [3] completed slabs
+  double* slab;
   // plane-wave boundary data
   int has_data;
   double pw_amp[6], pw_k[3], pw_omega, pw_phase;
@@ -53,5 +55,11 @@ hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t
 hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
                              int64_t nv, hipStream_t s);
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);
+// slab bookkeeping on the device (graph-safe: kernels, no memsets)
+hipError_t launch_slab_reset(const KernelParams& kp, double t0, double height, hipStream_t s);
+hipError_t launch_slab_begin(const KernelParams& kp, hipStream_t s);
+hipError_t launch_slab_end(const KernelParams& kp, hipStream_t s);
+// set the dynamic-LDS attribute of the tent kernel a solver uses (outside graph capture)
+hipError_t prepare_tent_kernel(const KernelParams& kp, int kernel);
 
 }  // namespace mtp

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(BLOCK) tent_kernel(KernelParams kp, int64_t fi
 
   for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
     const int32_t V = kp.tent_vertex[first + t];
-    const double t_top = kp.t_offset + kp.tent_top[first + t];
+    const double t_top = kp.slab[0] + kp.tent_top[first + t];
     const int32_t p0 = kp.patch_ptr[V];
     const int nT = kp.patch_ptr[V + 1] - p0;
     const double t_bot = kp.tau[V];
@@ -347,6 +347,21 @@ __global__ void get_fields_kernel(KernelParams kp, int64_t ne, double* out, int 
   if (!fin) kp.err[1] = ERRF_NONFINITE;
 }
 
+__global__ void slab_reset_kernel(double* slab, double t0, double height) {
+  if (threadIdx.x == 0) {
+    slab[0] = t0;
+    slab[1] = height;
+    slab[2] = t0;
+    slab[3] = 0.0;
+  }
+}
+__global__ void slab_begin_kernel(double* slab) {
+  if (threadIdx.x == 0) slab[0] = slab[2] + slab[3] * slab[1];
+}
+__global__ void slab_end_kernel(double* slab) {
+  if (threadIdx.x == 0) slab[3] += 1.0;
+}
+
 __global__ void fill_kernel(double* x, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -357,9 +372,10 @@ template <int D, int P, int BLOCK, int MAXPAIR>
 hipError_t launch_tp(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
   const size_t lds = Lds<D, P>::bytes(kp.max_patch);
   auto kfn = tent_kernel<D, P, BLOCK, MAXPAIR>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  if (count < 0) {   // prepare: allow the dynamic LDS size (done once, outside graph capture)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+  }
   hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(BLOCK), lds, s, kp, first, count);
   return hipGetLastError();
 }
@@ -404,7 +420,7 @@ size_t tent_kernel_lds_bytes(int d, int p, int nt) {
 int tent_kernel_max_pairs(int d) { return d == 2 ? 128 * 8 : 256 * 8; }
 
 hipError_t launch_tent_layer(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
+  if (count == 0) return hipSuccess;
   if (kp.d == 2) {
     switch (kp.p) {
       case 1: return launch_dp<2, 1, 128>(kp, first, count, s);
@@ -422,6 +438,24 @@ hipError_t launch_tent_layer(const KernelParams& kp, int64_t first, int64_t coun
     }
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_slab_reset(const KernelParams& kp, double t0, double height, hipStream_t s) {
+  hipLaunchKernelGGL(slab_reset_kernel, dim3(1), dim3(64), 0, s, kp.slab, t0, height);
+  return hipGetLastError();
+}
+hipError_t launch_slab_begin(const KernelParams& kp, hipStream_t s) {
+  hipLaunchKernelGGL(slab_begin_kernel, dim3(1), dim3(64), 0, s, kp.slab);
+  return hipGetLastError();
+}
+hipError_t launch_slab_end(const KernelParams& kp, hipStream_t s) {
+  hipLaunchKernelGGL(slab_end_kernel, dim3(1), dim3(64), 0, s, kp.slab);
+  return hipGetLastError();
+}
+
+hipError_t prepare_tent_kernel(const KernelParams& kp, int kernel) {
+  if (kernel == 0) return launch_tent_layer(kp, 0, -1, nullptr);
+  return launch_tent_layer_mfma(kp, 0, -1, kernel == 2, nullptr);
 }
 
 hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,

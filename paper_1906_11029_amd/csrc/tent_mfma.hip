@@ -169,7 +169,7 @@ tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
 
   for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
     const int32_t V = kp.tent_vertex[first + t];
-    const double t_top = kp.t_offset + kp.tent_top[first + t];
+    const double t_top = kp.slab[0] + kp.tent_top[first + t];
     const int32_t p0 = kp.patch_ptr[V];
     const int nT = kp.patch_ptr[V + 1] - p0;
     const double H = t_top - kp.tau[V];
@@ -551,9 +551,10 @@ hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStr
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
   constexpr int WPE = 2;   // 8 waves per workgroup, one workgroup per CU
   auto kfn = tent_mfma_kernel<D, P, T, NTMAX, WPE>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
+  if (count < 0) {   // prepare: allow the dynamic LDS size (done once, outside graph capture)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+  }
   hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
   return hipGetLastError();
 }
@@ -623,7 +624,7 @@ size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32) {
 }
 
 hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t count, int fp32, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
+  if (count == 0) return hipSuccess;
   return fp32 ? launch_t<float>(kp, first, count, s) : launch_t<double>(kp, first, count, s);
 }
 

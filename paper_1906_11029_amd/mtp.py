@@ -57,6 +57,7 @@ def load():
         "mtp_slab_dof_updates": [P, P, P],
         "mtp_slab_flops": [P, P],
         "mtp_solver_kernel": [P, P],
+        "mtp_solver_set_graph": [P, i32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -216,6 +217,10 @@ def mtp_slab_flops(solver):
     return f.value
 
 
+def mtp_solver_set_graph(solver, on):
+    _check(load().mtp_solver_set_graph(solver, int(on)))
+
+
 def mtp_solver_kernel(solver):
     k = C.c_int32()
     _check(load().mtp_solver_kernel(solver, C.byref(k)))
@@ -300,6 +305,9 @@ class Solver:
 
     def kernel(self):
         return mtp_solver_kernel(self.h)
+
+    def set_graph(self, on):
+        mtp_solver_set_graph(self.h, int(bool(on)))
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -191,3 +191,20 @@ def test_full_size_cavity_properties():
     uex = ex.u(meshes.equispaced_nodes(mm, 3), 1.0)
     assert rel(u, uex) < 1e-3
     assert np.all(np.isfinite(u))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_eager_layers(precision):
+    """advance_to replays one captured slab graph; three replays, with reads (eager work
+    and synchronisation) between them, must equal the layer-by-layer launches bitwise."""
+    name = "te_pmc_p2_two_slabs"
+    c, A, TA = gpu_solver(name, precision)
+    c, B, TB = gpu_solver(name, precision)
+    B.set_graph(False)
+    for k in range(1, 4):
+        A.advance_to(k * c["T"])
+        for l in range(TB.n_layers):
+            B.layer_advance(l)
+        wa, wb = A.get_state(), B.get_state()
+        assert np.array_equal(wa, wb), f"replay {k}"
+        assert A.front() == B.front() == (k * c["T"], 0)
