@@ -45,6 +45,7 @@ typedef int32_t mtp_status;
 typedef struct mtp_mesh_s* mtp_mesh;
 typedef struct mtp_tents_s* mtp_tents;
 typedef struct mtp_solver_s* mtp_solver;
+typedef struct mtp_batch_s* mtp_batch;
 
 enum {
   MTP_OK = 0,
@@ -151,6 +152,21 @@ mtp_status mtp_front(mtp_solver solver, double* t_front, int64_t* layers_done);
 mtp_status mtp_get_fields(mtp_solver solver, double* nodal, int32_t on_device);
 /* Raw state w (interchange layout), host or device pointer. */
 mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
+
+/* Batches of independent solves (section 2: tents on different meshes are independent).
+ * Every launch of a batch runs layer l of every solver in it, so small solves share the
+ * GPU: solvers must use the matrix-core kernels with one dimension, degree and precision
+ * (q, m, meshes, materials and boundary data may differ).  mtp_batch_advance moves every
+ * solver forward by n_slabs of its own slab height; the first call captures one batched
+ * slab into a HIP graph that later calls replay.  Solvers keep their handles and state;
+ * a solver must not be advanced on its own while a batch call is in flight.
+ * d_workspace: caller-owned device memory of mtp_batch_workspace_size bytes. */
+mtp_status mtp_batch_workspace_size(const mtp_solver* solvers, int32_t n, size_t* bytes);
+mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_workspace, size_t bytes,
+                            void* hip_stream, mtp_batch* out);
+mtp_status mtp_batch_advance(mtp_batch batch, int64_t n_slabs);
+mtp_status mtp_batch_set_graph(mtp_batch batch, int32_t on);
+void mtp_batch_destroy(mtp_batch batch);
 
 /* Spacetime DOF updates of one slab: sum over tents of nc*Np*n_T(tent)*m*q (the paper's
  * spacetime DOF count, section 5), and the tent count. */

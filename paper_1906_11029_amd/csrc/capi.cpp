@@ -151,6 +151,22 @@ struct mtp_solver_s {
   hipGraphExec_t gexec = nullptr;
 };
 
+struct mtp_batch_s {
+  std::vector<mtp_solver> solvers;
+  int kernel = 0, d = 0, p = 0, max_patch = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  mtp::KernelParams* d_kps = nullptr;
+  mtp::BatchSeg* d_segs = nullptr;
+  std::vector<mtp::KernelParams> h_kps;
+  std::vector<int64_t> seg_ptr;   // per global layer: first segment
+  std::vector<int64_t> blocks;    // per global layer: workgroups
+  bool use_graph = true;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
 using namespace mtp;
 
 #define MTP_TRY try {
@@ -545,6 +561,173 @@ mtp_status mtp_slab_dof_updates(mtp_solver s, double* dof_updates, int64_t* n_te
   if (dof_updates) *dof_updates = tot * s->nc * s->ref.np * s->m * s->q;
   if (n_tents) *n_tents = (int64_t)s->tents.vertex.size();
   MTP_CATCH
+}
+
+// ------------------------------------------------------------------ batches of solves
+static void batch_check(const mtp_solver* solvers, int32_t n) {
+  require(solvers && n >= 1, MTP_ERR_ARG, "empty batch");
+  for (int i = 0; i < n; ++i) {
+    const mtp_solver s = solvers[i];
+    require(s != nullptr, MTP_ERR_ARG, "null solver in batch");
+    require(s->kernel == 1 || s->kernel == 2, MTP_ERR_UNSUPPORTED, "batches need the matrix-core kernels");
+    require(s->kernel == solvers[0]->kernel && s->mesh.d == solvers[0]->mesh.d && s->p == solvers[0]->p,
+            MTP_ERR_UNSUPPORTED, "a batch needs one dimension, degree and precision");
+    for (int j = 0; j < i; ++j) require(solvers[j] != s, MTP_ERR_ARG, "solver listed twice");
+  }
+}
+
+static size_t batch_segments(const mtp_solver* solvers, int32_t n) {
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) tot += solvers[i]->tents.layer_ptr.size() - 1;
+  return tot;
+}
+
+mtp_status mtp_batch_workspace_size(const mtp_solver* solvers, int32_t n, size_t* bytes) {
+  MTP_TRY
+  require(bytes, MTP_ERR_ARG, "null pointer");
+  batch_check(solvers, n);
+  Layout L;
+  L.add(sizeof(KernelParams) * n);
+  L.add(sizeof(BatchSeg) * batch_segments(solvers, n));
+  *bytes = L.off;
+  MTP_CATCH
+}
+
+mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_workspace, size_t bytes, void* hip_stream,
+                            mtp_batch* out) {
+  MTP_TRY
+  require(out && d_workspace, MTP_ERR_ARG, "null pointer");
+  batch_check(solvers, n);
+  auto* b = new mtp_batch_s();
+  try {
+    b->solvers.assign(solvers, solvers + n);
+    b->kernel = solvers[0]->kernel;
+    b->d = solvers[0]->mesh.d;
+    b->p = solvers[0]->p;
+    for (int i = 0; i < n; ++i) b->max_patch = std::max(b->max_patch, solvers[i]->mesh.max_patch);
+    require(tent_mfma_lds_bytes(b->d, b->p, b->max_patch, b->kernel == 2) <= 160 * 1024, MTP_ERR_UNSUPPORTED,
+            "largest vertex patch of the batch does not fit the matrix-core kernel's LDS");
+    Layout L;
+    const size_t o_kps = L.add(sizeof(KernelParams) * n);
+    const size_t o_segs = L.add(sizeof(BatchSeg) * batch_segments(solvers, n));
+    require(bytes >= L.off, MTP_ERR_ARG, "workspace too small");
+    b->ws = static_cast<char*>(d_workspace);
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->d_kps = reinterpret_cast<KernelParams*>(b->ws + o_kps);
+    b->d_segs = reinterpret_cast<BatchSeg*>(b->ws + o_segs);
+    // global layer l runs layer l of every solver that has it
+    int64_t nl = 0;
+    for (int i = 0; i < n; ++i) nl = std::max<int64_t>(nl, (int64_t)solvers[i]->tents.layer_ptr.size() - 1);
+    std::vector<BatchSeg> segs;
+    for (int64_t l = 0; l < nl; ++l) {
+      b->seg_ptr.push_back((int64_t)segs.size());
+      int64_t blk = 0;
+      for (int i = 0; i < n; ++i) {
+        const Tents& T = solvers[i]->tents;
+        if (l + 1 >= (int64_t)T.layer_ptr.size()) continue;
+        BatchSeg sg;
+        sg.block0 = blk;
+        sg.first = T.layer_ptr[l];
+        sg.count = T.layer_ptr[l + 1] - T.layer_ptr[l];
+        sg.solver = i;
+        sg.pad = 0;
+        segs.push_back(sg);
+        blk += sg.count;
+      }
+      b->blocks.push_back(blk);
+    }
+    b->seg_ptr.push_back((int64_t)segs.size());
+    check_hip(hipMemcpyAsync(b->d_segs, segs.data(), segs.size() * sizeof(BatchSeg), hipMemcpyHostToDevice,
+                             b->stream), "upload");
+    BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, b->p, b->max_patch};
+    check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, nullptr), "batch kernel attributes");
+    check_hip(hipStreamSynchronize(b->stream), "sync");
+  } catch (...) {
+    delete b;
+    throw;
+  }
+  *out = b;
+  MTP_CATCH
+}
+
+static void batch_slab(mtp_batch b, hipStream_t st) {
+  const int n = (int)b->solvers.size();
+  check_hip(launch_batch_slab(b->d_kps, n, 0, st), "batch slab begin");
+  for (size_t l = 0; l + 1 < b->seg_ptr.size(); ++l) {
+    BatchLaunch bl{b->d_kps, b->d_segs + b->seg_ptr[l], (int)(b->seg_ptr[l + 1] - b->seg_ptr[l]), b->blocks[l],
+                   b->d, b->p, b->max_patch};
+    check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, st), "batched tent kernel");
+  }
+  check_hip(launch_batch_slab(b->d_kps, n, 1, st), "batch slab end");
+}
+
+static void drop_batch_graph(mtp_batch b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->cap = nullptr;
+}
+
+mtp_status mtp_batch_advance(mtp_batch b, int64_t n_slabs) {
+  MTP_TRY
+  require(b, MTP_ERR_ARG, "null batch");
+  require(n_slabs >= 0, MTP_ERR_ARG, "negative slab count");
+  const int n = (int)b->solvers.size();
+  b->h_kps.resize(n);
+  for (int i = 0; i < n; ++i) {
+    mtp_solver s = b->solvers[i];
+    require(s->layers_done == 0, MTP_ERR_STATE, "a solver of the batch is in the middle of a slab");
+    require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
+    b->h_kps[i] = s->kp;
+    // work the solvers enqueued on their own streams comes first
+    if (s->stream != b->stream) check_hip(hipStreamSynchronize(s->stream), "sync solver stream");
+  }
+  if (n_slabs == 0) return MTP_OK;
+  check_hip(hipMemcpyAsync(b->d_kps, b->h_kps.data(), n * sizeof(KernelParams), hipMemcpyHostToDevice, b->stream),
+            "upload");
+  if (b->use_graph && !b->gexec) {
+    check_hip(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
+    check_hip(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed), "begin capture");
+    try {
+      batch_slab(b, b->cap);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(b->cap, &g);
+      if (g) (void)hipGraphDestroy(g);
+      drop_batch_graph(b);
+      throw;
+    }
+    check_hip(hipStreamEndCapture(b->cap, &b->graph), "end capture");
+    check_hip(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+  }
+  for (int64_t k = 0; k < n_slabs; ++k) {
+    if (b->use_graph)
+      check_hip(hipGraphLaunch(b->gexec, b->stream), "graph launch");
+    else
+      batch_slab(b, b->stream);
+  }
+  for (int i = 0; i < n; ++i) {
+    b->solvers[i]->slab += n_slabs;
+    // later work on a solver's own stream waits for the batch
+    if (b->solvers[i]->stream != b->stream) check_hip(hipStreamSynchronize(b->stream), "sync batch stream");
+  }
+  MTP_CATCH
+}
+
+mtp_status mtp_batch_set_graph(mtp_batch b, int32_t on) {
+  MTP_TRY
+  require(b, MTP_ERR_ARG, "null batch");
+  b->use_graph = on != 0;
+  MTP_CATCH
+}
+
+void mtp_batch_destroy(mtp_batch b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  drop_batch_graph(b);
+  delete b;
 }
 
 mtp_status mtp_solver_set_graph(mtp_solver s, int32_t on) {

@@ -43,6 +43,24 @@ struct KernelParams {
   int max_patch;
 };
 
+// One segment of a batched launch: layer slice (first, count) of solver `solver`, run by
+// workgroups block0 .. block0 + count - 1.
+struct BatchSeg {
+  int64_t block0;
+  int64_t first;
+  int64_t count;
+  int32_t solver;
+  int32_t pad;
+};
+
+struct BatchLaunch {
+  const KernelParams* kps;   // device array, one entry per solver
+  const BatchSeg* segs;      // device array, nseg entries sorted by block0
+  int nseg;
+  int64_t blocks;            // total workgroups (-1: only set the LDS attribute)
+  int d, p, max_patch;
+};
+
 // error flag bits
 enum { ERRF_CAUSALITY = 1, ERRF_NONFINITE = 2 };
 
@@ -55,6 +73,8 @@ hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t
 hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
                              int64_t nv, hipStream_t s);
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);
+hipError_t launch_tent_batch_mfma(const BatchLaunch& bl, int fp32, hipStream_t s);
+hipError_t launch_batch_slab(const KernelParams* kps, int n, int end, hipStream_t s);
 // slab bookkeeping on the device (graph-safe: kernels, no memsets)
 hipError_t launch_slab_reset(const KernelParams& kp, double t0, double height, hipStream_t s);
 hipError_t launch_slab_begin(const KernelParams& kp, hipStream_t s);

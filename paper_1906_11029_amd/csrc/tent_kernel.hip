@@ -362,6 +362,15 @@ __global__ void slab_end_kernel(double* slab) {
   if (threadIdx.x == 0) slab[3] += 1.0;
 }
 
+__global__ void batch_slab_kernel(const KernelParams* kps, int n, int end) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    double* slab = kps[i].slab;
+    if (end) slab[3] += 1.0;
+    else slab[0] = slab[2] + slab[3] * slab[1];
+  }
+}
+
 __global__ void fill_kernel(double* x, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -444,6 +453,11 @@ hipError_t launch_slab_reset(const KernelParams& kp, double t0, double height, h
   hipLaunchKernelGGL(slab_reset_kernel, dim3(1), dim3(64), 0, s, kp.slab, t0, height);
   return hipGetLastError();
 }
+hipError_t launch_batch_slab(const KernelParams* kps, int n, int end, hipStream_t s) {
+  hipLaunchKernelGGL(batch_slab_kernel, dim3((n + 63) / 64), dim3(64), 0, s, kps, n, end);
+  return hipGetLastError();
+}
+
 hipError_t launch_slab_begin(const KernelParams& kp, hipStream_t s) {
   hipLaunchKernelGGL(slab_begin_kernel, dim3(1), dim3(64), 0, s, kp.slab);
   return hipGetLastError();

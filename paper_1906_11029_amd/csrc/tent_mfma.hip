@@ -119,9 +119,11 @@ struct MLds {
   static constexpr size_t bytes = (t_bytes + 7) / 8 * 8 + geo_doubles * 8 + ints * 4;
 };
 
-template <int D, int P, typename T, int NTMAX, int WPE>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
-tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
+// Body shared by the single-solve and the batched entry points: tents t_begin,
+// t_begin + t_step, ... < count of the tent table slice starting at `first`.
+template <int D, int P, typename T, int NTMAX>
+__device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t first, int64_t count,
+                                               int64_t t_begin, int64_t t_step) {
   using SH = MShape<D, P, NTMAX>;
   using MM = Mfma<T>;
   constexpr int NC = SH::NC, NP = SH::NP, NF = SH::NF, NV = SH::NV;
@@ -167,7 +169,7 @@ tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
 
   const double invm = 1.0 / kp.m;
 
-  for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+  for (int64_t t = t_begin; t < count; t += t_step) {
     const int32_t V = kp.tent_vertex[first + t];
     const double t_top = kp.slab[0] + kp.tent_top[first + t];
     const int32_t p0 = kp.patch_ptr[V];
@@ -546,6 +548,27 @@ tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
   }
 }
 
+template <int D, int P, typename T, int NTMAX, int WPE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
+  tent_mfma_body<D, P, T, NTMAX>(kp, first, count, blockIdx.x, gridDim.x);
+}
+
+// Batched entry point: workgroup b runs tent b - seg.block0 of segment seg, i.e. of the
+// layer slice (first, count) of solver seg.solver; all solvers share (D, P, T).
+template <int D, int P, typename T, int NTMAX, int WPE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = nseg - 1;   // last segment with block0 <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].block0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const BatchSeg sg = segs[lo];
+  tent_mfma_body<D, P, T, NTMAX>(kps[sg.solver], sg.first, sg.count, b - sg.block0, (int64_t)1 << 62);
+}
+
 template <int D, int P, typename T, int NTMAX>
 hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
@@ -557,6 +580,49 @@ hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStr
   }
   hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
   return hipGetLastError();
+}
+
+template <int D, int P, typename T, int NTMAX>
+hipError_t launch_mb(const BatchLaunch& bl, hipStream_t s) {
+  const size_t lds = MLds<D, P, T, NTMAX>::bytes;
+  constexpr int WPE = 2;
+  auto kfn = tent_mfma_batch_kernel<D, P, T, NTMAX, WPE>;
+  if (bl.blocks < 0)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+  if (bl.blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(kfn, dim3((unsigned)bl.blocks), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, bl.kps, bl.segs,
+                     bl.nseg);
+  return hipGetLastError();
+}
+
+template <int D, int P, typename T>
+hipError_t launch_mbp(const BatchLaunch& bl, hipStream_t s) {
+  if (bl.max_patch <= 8) return launch_mb<D, P, T, 8>(bl, s);
+  if (bl.max_patch <= 24) return launch_mb<D, P, T, 24>(bl, s);
+  if (bl.max_patch <= 48) return launch_mb<D, P, T, 48>(bl, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_bt(const BatchLaunch& bl, hipStream_t s) {
+  if (bl.d == 2) {
+    switch (bl.p) {
+      case 1: return launch_mbp<2, 1, T>(bl, s);
+      case 2: return launch_mbp<2, 2, T>(bl, s);
+      case 3: return launch_mbp<2, 3, T>(bl, s);
+      case 4: return launch_mbp<2, 4, T>(bl, s);
+      case 5: return launch_mbp<2, 5, T>(bl, s);
+    }
+  } else {
+    switch (bl.p) {
+      case 1: return launch_mbp<3, 1, T>(bl, s);
+      case 2: return launch_mbp<3, 2, T>(bl, s);
+      case 3: return launch_mbp<3, 3, T>(bl, s);
+      case 4: return launch_mbp<3, 4, T>(bl, s);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int D, int P, typename T>
@@ -621,6 +687,10 @@ size_t lds_t(int d, int p, int max_patch) {
 
 size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32) {
   return fp32 ? lds_t<float>(d, p, max_patch) : lds_t<double>(d, p, max_patch);
+}
+
+hipError_t launch_tent_batch_mfma(const BatchLaunch& bl, int fp32, hipStream_t s) {
+  return fp32 ? launch_bt<float>(bl, s) : launch_bt<double>(bl, s);
 }
 
 hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t count, int fp32, hipStream_t s) {

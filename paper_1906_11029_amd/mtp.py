@@ -58,12 +58,16 @@ def load():
         "mtp_slab_flops": [P, P],
         "mtp_solver_kernel": [P, P],
         "mtp_solver_set_graph": [P, i32],
+        "mtp_batch_workspace_size": [P, i32, P],
+        "mtp_batch_create": [P, i32, P, sz, P, pp],
+        "mtp_batch_advance": [P, i64],
+        "mtp_batch_set_graph": [P, i32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = C.c_int32
-    for name in ("mtp_mesh_destroy", "mtp_tents_destroy", "mtp_solver_destroy"):
+    for name in ("mtp_mesh_destroy", "mtp_tents_destroy", "mtp_solver_destroy", "mtp_batch_destroy"):
         f = getattr(L, name)
         f.argtypes = [P]
         f.restype = None
@@ -227,6 +231,36 @@ def mtp_solver_kernel(solver):
     return k.value
 
 
+def _handles(solvers):
+    arr = (C.c_void_p * len(solvers))(*[s.h.value for s in solvers])
+    return arr
+
+
+def mtp_batch_workspace_size(solvers):
+    n = C.c_size_t()
+    _check(load().mtp_batch_workspace_size(_handles(solvers), len(solvers), C.byref(n)))
+    return n.value
+
+
+def mtp_batch_create(solvers, workspace_ptr, nbytes, stream_ptr):
+    h = C.c_void_p()
+    _check(load().mtp_batch_create(_handles(solvers), len(solvers), C.c_void_p(workspace_ptr), nbytes,
+                                   C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def mtp_batch_advance(batch, n_slabs):
+    _check(load().mtp_batch_advance(batch, int(n_slabs)))
+
+
+def mtp_batch_set_graph(batch, on):
+    _check(load().mtp_batch_set_graph(batch, int(on)))
+
+
+def mtp_batch_destroy(batch):
+    load().mtp_batch_destroy(batch)
+
+
 # ----------------------------------------------------------------- thin object wrappers
 class Mesh:
     def __init__(self, coords, cells, eps=None, mu=None, face_bc=None):
@@ -312,4 +346,27 @@ class Solver:
     def __del__(self):
         if getattr(self, "h", None):
             mtp_solver_destroy(self.h)
+            self.h = None
+
+
+class Batch:
+    """Solvers advanced together, one launch per layer index across all of them."""
+
+    def __init__(self, solvers, device="cuda:0", stream=None):
+        import torch
+        self.solvers = list(solvers)
+        nbytes = mtp_batch_workspace_size(self.solvers)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=torch.device(device))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        self.h = mtp_batch_create(self.solvers, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def advance(self, n_slabs=1):
+        mtp_batch_advance(self.h, n_slabs)
+
+    def set_graph(self, on):
+        mtp_batch_set_graph(self.h, int(bool(on)))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            mtp_batch_destroy(self.h)
             self.h = None

@@ -208,3 +208,49 @@ def test_graph_replay_matches_eager_layers(precision):
         wa, wb = A.get_state(), B.get_state()
         assert np.array_equal(wa, wb), f"replay {k}"
         assert A.front() == B.front() == (k * c["T"], 0)
+
+
+def _pw_solver(n, p, q, m, T, theta, k, phase, precision):
+    from mtp_inputs import fields, meshes
+    from paper_1906_11029_amd import mtp
+    mm = meshes.square_tri(n)
+    bc = meshes.uniform_bc(len(mm["cells"]), 2, meshes.DATA)
+    ex = fields.PlaneWaveTE(direction=(np.cos(theta), np.sin(theta)), k=k, phase=phase)
+    M = mtp.Mesh(mm["coords"], mm["cells"], face_bc=bc)
+    Tt = mtp.Tents(M, T, 0.5)
+    S = mtp.Solver(M, Tt, p, q, m, precision=precision)
+    S.set_fields(ex.u(meshes.equispaced_nodes(mm, p), 0.0))
+    S.set_planewave_bc(*planewave_params(ex, 2))
+    return S, ex, mm
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_single_solves(precision):
+    """Solvers on different meshes, plane waves, q and m, advanced as one batch (one launch
+    per layer index), equal the same solvers advanced one by one, bitwise."""
+    from paper_1906_11029_amd import mtp
+    specs = [(5, 2, 3, 4, 0.3, 0.2, 6.0, 0.1), (9, 2, 3, 4, 0.3, 1.3, 9.0, 2.0),
+             (3, 2, 4, 2, 0.25, 2.9, 4.0, 0.7), (7, 2, 3, 6, 0.2, 4.4, 7.5, 5.1)]
+    single = [_pw_solver(*sp, precision)[0] for sp in specs]
+    batched = [_pw_solver(*sp, precision)[0] for sp in specs]
+    for S, sp in zip(single, specs):
+        S.advance_to(2 * sp[4])
+    B = mtp.Batch(batched)
+    B.advance(1)
+    B.advance(1)
+    for S1, S2, sp in zip(single, batched, specs):
+        assert S2.front() == (2 * sp[4], 0)
+        assert np.array_equal(S1.get_state(), S2.get_state())
+
+
+def test_batch_3d_mixed_against_oracle_fixture():
+    """A 3D batch (two copies of a parity case plus another case of the same degree)
+    reproduces the oracle fixtures."""
+    from paper_1906_11029_amd import mtp
+    names = ["cav3d_p2", "cav3d_p2_pmc_eps", "planewave3d_p2"]
+    solvers = [gpu_solver(nm, 0)[1] for nm in names]
+    B = mtp.Batch(solvers)
+    B.advance(1)
+    for S, nm in zip(solvers, names):
+        ref = fixture(nm)
+        assert rel(S.get_state(), ref["w"]) <= TOL
