@@ -65,9 +65,10 @@ enum { MTP_BC_PEC = 0, MTP_BC_PMC = 1, MTP_BC_DATA = 2 };
 /* arithmetic of the tent kernels
  *   MTP_FP64       plain FP64; contractions on the FP64 matrix cores (falls back to the
  *                  vector-ALU kernel when a patch does not fit the matrix-core kernel)
- *   MTP_MIXED_FP32 contractions, face fluxes and the n >= 1 inversions in FP32 on the
- *                  matrix cores; the inversion that starts each sub-interval and the
- *                  Taylor sum into the state in FP64
+ *   MTP_MIXED_FP32 the contractions of SAT stages n >= 2, which act on the small Taylor
+ *                  coefficients U_{i,n-1}, n-1 >= 1, run on the FP32 matrix cores; the first
+ *                  stage of every sub-interval (acting on U_{i,0}, the size of the fields),
+ *                  the closed-form inversions, fluxes and the Taylor sum stay FP64
  *   MTP_FP64_VALU  plain FP64 on the vector ALUs (reference kernel)                    */
 enum { MTP_FP64 = 0, MTP_MIXED_FP32 = 1, MTP_FP64_VALU = 2 };
 

@@ -10,10 +10,11 @@
 // divided right-hand side dY/dth / H of every node.  A(grad lambda_l) U is formed while
 // loading the B operand (two LDS reads and two multiply-adds per value: A(g) is a cross
 // product), so only U and F are stored.  Accumulators stay in registers until every wave
-// has finished reading F, then R overwrites F in LDS.  T = double uses
-// v_mfma_f64_16x16x4f64 (the plain FP64 path); T = float uses v_mfma_f32_16x16x4f32 for
-// the contractions while the closed-form inverse that starts each sub-interval and the
-// Taylor sum stay in FP64 (the mixed path).
+// has finished reading F, then R overwrites F in LDS.  The plain path (T = double) runs
+// every product on v_mfma_f64_16x16x4f64.  The mixed path (T = float) keeps the same FP64
+// storage and FP64 first stage of every sub-interval, and runs the products of the later
+// stages, which act on the small Taylor coefficients U_{i,n} (n >= 1), on
+// v_mfma_f32_16x16x4f32; the closed-form inverses, fluxes and the Taylor sum stay FP64.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -97,46 +98,109 @@ struct MShape {
   static constexpr int MAXPAIR = (NTMAX * NP + BLOCK - 1) / BLOCK;
 };
 
+// LDS layout, identical for both variants (state, fluxes and operators stored in FP64; the
+// mixed variant only changes the precision of the products of stages n >= 2)
 template <int D, int P, typename T, int NTMAX>
 struct MLds {
   using SH = MShape<D, P, NTMAX>;
-  // A-operand row stride: the four k-groups of a wave land in different banks
-  static constexpr int OPS = SH::MP + (sizeof(T) == 4 ? 16 : 0);
+  static constexpr int OPS = SH::MP;
   static constexpr size_t op_elems = (size_t)SH::KT * OPS;
   static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
   static constexpr size_t f_elems = (size_t)SH::FROWS * SH::RS;
-  // mixed path: the tent's first stage keeps U and F in FP64 over the same (larger) region
-  static constexpr size_t work_bytes_t = (u_elems + f_elems) * sizeof(T);
-  static constexpr size_t work_bytes_64 = (sizeof(T) == 4) ? (size_t)(SH::NP + SH::KF) * SH::RS * 8 : 0;
-  // mixed path: Y_{i,1} of every node pair (FP64) after the FP32 buffers
-  static constexpr size_t y1_off = (work_bytes_t + 7) / 8 * 8;
-  static constexpr size_t y1_bytes = (sizeof(T) == 4) ? (size_t)NTMAX * SH::NP * SH::NC * 8 : 0;
-  static constexpr size_t work_a = y1_off + y1_bytes;
-  static constexpr size_t work_bytes = work_a > work_bytes_64 ? work_a : work_bytes_64;
-  static constexpr size_t t_bytes = op_elems * sizeof(T) + work_bytes;
+  static constexpr size_t t_bytes = (op_elems + u_elems + f_elems) * 8;
   static constexpr size_t geo_doubles = (size_t)NTMAX * (SH::NV * D + D + 2);
   static constexpr size_t ints = (size_t)D * 2 * SH::NF + (size_t)NTMAX * (2 + D);
-  static constexpr size_t bytes = (t_bytes + 7) / 8 * 8 + geo_doubles * 8 + ints * 4;
+  static constexpr size_t bytes = t_bytes + geo_doubles * 8 + ints * 4;
 };
+
+// R = [S | -L] [A(grad lambda) U ; F] for this wave's tiles with TM-precision products
+// (operands converted from the FP64 LDS values as they are loaded), written back to
+// sFR as FP64 once every wave has finished reading F.
+template <typename TM, int D, int P, int NTMAX>
+__device__ __forceinline__ void tile_product(const double* sOp, const double* sU, double* sFR, const double* sGL,
+                                             int wave, int lane, int ncols, int ntiles) {
+  using SH = MShape<D, P, NTMAX>;
+  using MM = Mfma<TM>;
+  constexpr int NC = SH::NC, NV = SH::NV, NPK = SH::NPK, KV = SH::KV, KFP = SH::KFP, MT = SH::MT,
+                RS = SH::RS, WAVES = SH::WAVES, TPW = SH::TILES_PER_WAVE;
+  constexpr int OPS = MLds<D, P, double, NTMAX>::OPS;
+  typename MM::acc_t accs[TPW];
+#pragma unroll
+  for (int ts = 0; ts < TPW; ++ts) {
+    accs[ts] = typename MM::acc_t{0, 0, 0, 0};
+    const int tile = wave + WAVES * ts;
+    if (tile < MT * ntiles) {
+      const int mt = tile / ntiles, nt = tile - mt * ntiles;
+      const int col = nt * 16 + (lane & 15);
+      const bool live = col < ncols;
+      const int e = live ? col / NC : 0;
+      const int c = live ? col - e * NC : 0;
+      int p1, q1, p2, q2;
+      double s1, s2;
+      ACoef<D>::get(c, &p1, &q1, &s1, &p2, &q2, &s2);
+      double cf1[D], cf2[D];
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+        const double* gl = &sGL[(e * NV + l + 1) * D];
+        cf1[l] = live ? s1 * gl[q1] : 0.0;
+        cf2[l] = live ? s2 * gl[q2] : 0.0;
+      }
+      const int c1 = e * NC + p1, c2 = e * NC + p2;
+      const int kq = lane >> 4;
+      const double* acol = sOp + mt * 16 + (lane & 15) + kq * OPS;
+      const double* u1 = sU + kq * RS + c1;
+      const double* u2 = sU + kq * RS + c2;
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
+#pragma unroll
+        for (int as = 0; as < NPK / 4; ++as) {
+          const TM b = (TM)(cf1[l] * u1[4 * as * RS] + cf2[l] * u2[4 * as * RS]);
+          accs[ts] = MM::mma((TM)acol[(l * NPK + 4 * as) * OPS], b, accs[ts]);
+        }
+      }
+      const double* fr = sFR + kq * RS + (live ? col : 0);
+      const double fm = live ? 1.0 : 0.0;
+#pragma unroll
+      for (int fs = 0; fs < KFP / 4; ++fs)
+        accs[ts] = MM::mma((TM)acol[(KV + 4 * fs) * OPS], (TM)(fm * fr[4 * fs * RS]), accs[ts]);
+    }
+  }
+  __syncthreads();   // every wave is done reading F and U
+#pragma unroll
+  for (int ts = 0; ts < TPW; ++ts) {
+    const int tile = wave + WAVES * ts;
+    if (tile < MT * ntiles) {
+      const int mt = tile / ntiles, nt = tile - mt * ntiles;
+      const int col = nt * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sFR[(mt * 16 + MM::row(lane, r)) * RS + col] = (double)accs[ts][r];
+    }
+  }
+  __syncthreads();
+}
 
 // Body shared by the single-solve and the batched entry points: tents t_begin,
 // t_begin + t_step, ... < count of the tent table slice starting at `first`.
+// Body shared by the single-solve and the batched entry points: tents t_begin,
+// t_begin + t_step, ... < count of the tent table slice starting at `first`.
+// T = double: every product in FP64.  T = float (mixed): the first stage of every
+// sub-interval, whose U_{i,0} has the full size of the fields, stays FP64; the later
+// stages act on the small Taylor coefficients U_{i,n}, n >= 1, and run on the FP32 cores.
 template <int D, int P, typename T, int NTMAX>
 __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t first, int64_t count,
                                                int64_t t_begin, int64_t t_step) {
   using SH = MShape<D, P, NTMAX>;
-  using MM = Mfma<T>;
+  constexpr bool MIXED = sizeof(T) == 4;
   constexpr int NC = SH::NC, NP = SH::NP, NF = SH::NF, NV = SH::NV;
-  constexpr int NPK = SH::NPK, KV = SH::KV, KF = SH::KF, KFP = SH::KFP, KT = SH::KT, MT = SH::MT, MP = SH::MP,
-                RS = SH::RS;
+  constexpr int NPK = SH::NPK, KV = SH::KV, KF = SH::KF, KT = SH::KT, MP = SH::MP, RS = SH::RS;
   constexpr int OPS = MLds<D, P, T, NTMAX>::OPS;
-  constexpr int TPW = SH::TILES_PER_WAVE, MAXPAIR = SH::MAXPAIR, BLOCK = SH::BLOCK, WAVES = SH::WAVES;
-  extern __shared__ double lds_d[];
-  T* sOp = reinterpret_cast<T*>(lds_d);          // [k][m], m fastest
+  constexpr int MAXPAIR = SH::MAXPAIR, BLOCK = SH::BLOCK;
   using LD = MLds<D, P, T, NTMAX>;
-  T* sU = sOp + LD::op_elems;                     // [node][col]
-  T* sFR = sU + LD::u_elems;                      // [row][col]: F, then R
-  double* sGL = lds_d + (LD::t_bytes + 7) / 8;   // [e][v][x]
+  extern __shared__ double lds_d[];
+  double* sOp = lds_d;                            // [k][m], m fastest
+  double* sU = sOp + LD::op_elems;                // [node][col]
+  double* sFR = sU + LD::u_elems;                 // [row][col]: F, then R
+  double* sGL = sFR + LD::f_elems;                // [e][v][x]
   double* sBb = sGL + NTMAX * NV * D;             // [e][x]
   double* sEM = sBb + NTMAX * D;                  // [e][2]
   int* sFn = reinterpret_cast<int*>(sEM + NTMAX * 2);
@@ -160,11 +224,11 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
         v = -kp.L[(j * NF + s) * NP + m];
       }
     }
-    sOp[i] = (T)v;
+    sOp[i] = v;
   }
   // padding rows of U and F are read by the product (times zero): keep them finite
-  for (int i = tid; i < (NPK - NP) * RS; i += BLOCK) sU[NP * RS + i] = (T)0;
-  for (int i = tid; i < (SH::FROWS - KF) * RS; i += BLOCK) sFR[KF * RS + i] = (T)0;
+  for (int i = tid; i < (NPK - NP) * RS; i += BLOCK) sU[NP * RS + i] = 0.0;
+  for (int i = tid; i < (SH::FROWS - KF) * RS; i += BLOCK) sFR[KF * RS + i] = 0.0;
   for (int i = tid; i < D * 2 * NF; i += BLOCK) sFn[i] = kp.fnode[i];
 
   const double invm = 1.0 / kp.m;
@@ -210,15 +274,8 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
     __syncthreads();
 
     // gather W (FP64, registers) and U_{0,0} = K(b_0)^{-1} W (closed form in FP64)
-    constexpr bool MIXED = sizeof(T) == 4;
-    constexpr int MPX = MIXED ? MAXPAIR : 1;
     const int npairs = nT * NP;
     double acc[MAXPAIR][NC];
-    double u0p[MPX][NC];   // mixed: U_{i,0} in FP64
-    // mixed: Y_{i,1} in FP64, one entry per node pair, in LDS after the FP32 buffers
-    double* sY1 = reinterpret_cast<double*>(reinterpret_cast<char*>(sU) + LD::y1_off);
-    double* sU64 = reinterpret_cast<double*>(sU);     // mixed, first stage of the tent:
-    double* sF64 = sU64 + (size_t)NP * RS;            //   U and F in FP64
     bool ok = true;
 #pragma unroll
     for (int r = 0; r < MAXPAIR; ++r) {
@@ -231,144 +288,17 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
         for (int c = 0; c < NC; ++c) acc[r][c] = Wp[c * NP];
         double u[NC];
         ok &= kinv<D>(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
-        if constexpr (MIXED) {
 #pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            u0p[r][c] = u[c];
-            sU64[b * RS + e * NC + c] = u[c];
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = (T)u[c];
-        }
+        for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = u[c];
       }
     }
     __syncthreads();
-
-    if constexpr (MIXED) {
-      // ---- first stage of the tent, Y_{0,1} = H R(U_{0,0}), in FP64 on the vector ALUs
-      //      (later sub-intervals only apply R in FP32 to the small U_{i,0} - U_{i-1,0})
-      for (int it = tid; it < nT * D * NF; it += BLOCK) {
-        const int e = it / (D * NF);
-        const int rem = it - e * (D * NF);
-        const int j = rem / NF;
-        const int s = rem - j * NF;
-        const int nin = sFn[(j * 2) * NF + s];
-        double um[NC], up[NC], G[NC], g[D];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) um[c] = sU64[nin * RS + e * NC + c];
-#pragma unroll
-        for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
-        const int code = sF[e * D + j];
-        if (code >= 0) {
-          const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
-          const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) up[c] = sU64[nout * RS + pe * NC + c];
-        } else {
-          ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, 0.0, 1);
-        }
-        flux<D>(g, kp.alpha, um, up, G);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) sF64[(j * NF + s) * RS + e * NC + c] = G[c];
-      }
-      __syncthreads();
-      double un[MPX][NC];
-      double y1[MPX][NC];
-#pragma unroll
-      for (int r = 0; r < MAXPAIR; ++r) {
-        const int P_ = tid + r * BLOCK;
-        if (P_ < npairs) {
-          const int e = P_ / NP, b = P_ - e * NP;
-          double Y[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) Y[c] = 0.0;
-#pragma unroll
-          for (int l = 0; l < D; ++l) {
-            double tl[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) tl[c] = 0.0;
-            const double* Sl = kp.S + (size_t)l * NP * NP + b;
-            const double* Ue = sU64 + e * NC;
-#pragma unroll 2
-            for (int a = 0; a < NP; ++a) {
-              const double sv = Sl[a * NP];
-#pragma unroll
-              for (int c = 0; c < NC; ++c) tl[c] = fma(sv, Ue[a * RS + c], tl[c]);
-            }
-            double at[NC];
-            applyA<D>(&sGL[(e * NV + l + 1) * D], tl, at);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) Y[c] += at[c];
-          }
-          const double* Fe = sF64 + e * NC;
-#pragma unroll 2
-          for (int k = 0; k < KF; ++k) {
-            const double lv = kp.L[(size_t)k * NP + b];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) Y[c] = fma(-lv, Fe[k * RS + c], Y[c]);
-          }
-          const double* gv = &sGL[(e * NV + 0) * D];
-          double bp[D], au[NC], rhs[NC];
-#pragma unroll
-          for (int x = 0; x < D; ++x) bp[x] = H * gv[x];
-          applyA<D>(bp, u0p[r], au);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            Y[c] *= H;
-            y1[r][c] = Y[c];
-            acc[r][c] = fma(invm, Y[c], acc[r][c]);
-            rhs[c] = Y[c] + au[c];
-          }
-          if (kp.q > 1) ok &= kinv<D>(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], rhs, un[r]);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < MAXPAIR; ++r) {
-        const int P_ = tid + r * BLOCK;
-        if (P_ < npairs) {
-          const int e = P_ / NP, b = P_ - e * NP;
-          double w[NC];
-          if (kp.q > 1) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) w[c] = un[r][c];
-          } else if (kp.m > 1) {   // q = 1: the sub-interval ends here
-            double bi[D], u[NC];
-#pragma unroll
-            for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + invm * H * sGL[(e * NV + 0) * D + x];
-            ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], u);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              w[c] = u[c] - u0p[r][c];
-              u0p[r][c] = u[c];
-            }
-          } else {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) w[c] = 0.0;
-          }
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            sU[b * RS + e * NC + c] = (T)w[c];
-            sY1[P_ * NC + c] = y1[r][c];
-          }
-        }
-      }
-      // the FP64 buffers overlapped the padding rows the product multiplies by zero:
-      // make them finite again
-      for (int x = tid; x < (NPK - NP) * RS; x += BLOCK) sU[NP * RS + x] = (T)0;
-      for (int x = tid; x < (SH::FROWS - KF) * RS; x += BLOCK) sFR[KF * RS + x] = (T)0;
-      __syncthreads();
-    }
 
     for (int i = 0; i < kp.m; ++i) {
       const double th = i * invm;
       double coef = 1.0;
       for (int n = 1; n <= kp.q; ++n) {
         coef *= invm / n;
-        if (MIXED && i == 0 && n == 1) continue;   // done in FP64 above
-        // mixed, first stage of a later sub-interval: U holds U_{i,0} - U_{i-1,0}
-        const bool diff = MIXED && n == 1;
         // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col]
         for (int it = tid; it < nT * D * NF; it += BLOCK) {
           const int e = it / (D * NF);
@@ -378,7 +308,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
           const int nin = sFn[(j * 2) * NF + s];
           double um[NC], up[NC], G[NC], g[D];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) um[c] = (double)sU[nin * RS + e * NC + c];
+          for (int c = 0; c < NC; ++c) um[c] = sU[nin * RS + e * NC + c];
 #pragma unroll
           for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
           const int code = sF[e * D + j];
@@ -386,77 +316,21 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
             const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
             const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) up[c] = (double)sU[nout * RS + pe * NC + c];
+            for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
           } else {
-            const int kind = -1 - code;
-            ghost_state<D, P>(kp, kind, um, up, sElem[e], sK[e], nin, H, th, n);
-            if (diff && kind == 2 && kp.has_data) {   // data ghost enters as a difference too
-              double up0[NC];
-              ghost_state<D, P>(kp, kind, um, up0, sElem[e], sK[e], nin, H, th - invm, n);
-#pragma unroll
-              for (int c = 0; c < NC; ++c) up[c] -= up0[c];
-            }
+            ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
           }
           flux<D>(g, kp.alpha, um, up, G);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = (T)G[c];
+          for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
         }
         __syncthreads();
 
         // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
-        typename MM::acc_t accs[TPW];
-#pragma unroll
-        for (int ts = 0; ts < TPW; ++ts) {
-          accs[ts] = typename MM::acc_t{0, 0, 0, 0};
-          const int tile = wave + WAVES * ts;
-          if (tile < MT * ntiles) {
-            const int mt = tile / ntiles, nt = tile - mt * ntiles;
-            const int col = nt * 16 + (lane & 15);
-            const bool live = col < ncols;
-            const int e = live ? col / NC : 0;
-            const int c = live ? col - e * NC : 0;
-            int p1, q1, p2, q2;
-            double s1, s2;
-            ACoef<D>::get(c, &p1, &q1, &s1, &p2, &q2, &s2);
-            T cf1[D], cf2[D];
-#pragma unroll
-            for (int l = 0; l < D; ++l) {
-              const double* gl = &sGL[(e * NV + l + 1) * D];
-              cf1[l] = live ? (T)(s1 * gl[q1]) : (T)0;
-              cf2[l] = live ? (T)(s2 * gl[q2]) : (T)0;
-            }
-            const int c1 = e * NC + p1, c2 = e * NC + p2;
-            const int kq = lane >> 4;
-            const T* acol = sOp + mt * 16 + (lane & 15) + kq * OPS;
-            const T* u1 = sU + kq * RS + c1;
-            const T* u2 = sU + kq * RS + c2;
-#pragma unroll
-            for (int l = 0; l < D; ++l) {
-#pragma unroll
-              for (int as = 0; as < NPK / 4; ++as) {
-                const T b = cf1[l] * u1[4 * as * RS] + cf2[l] * u2[4 * as * RS];
-                accs[ts] = MM::mma(acol[(l * NPK + 4 * as) * OPS], b, accs[ts]);
-              }
-            }
-            const T* fr = sFR + kq * RS + (live ? col : 0);
-            const T fm = live ? (T)1 : (T)0;
-#pragma unroll
-            for (int fs = 0; fs < KFP / 4; ++fs)
-              accs[ts] = MM::mma(acol[(KV + 4 * fs) * OPS], fm * fr[4 * fs * RS], accs[ts]);
-          }
-        }
-        __syncthreads();   // every wave is done reading F and U
-#pragma unroll
-        for (int ts = 0; ts < TPW; ++ts) {
-          const int tile = wave + WAVES * ts;
-          if (tile < MT * ntiles) {
-            const int mt = tile / ntiles, nt = tile - mt * ntiles;
-            const int col = nt * 16 + (lane & 15);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) sFR[(mt * 16 + MM::row(lane, r)) * RS + col] = accs[ts][r];
-          }
-        }
-        __syncthreads();
+        if (MIXED && n >= 2)
+          tile_product<float, D, P, NTMAX>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+        else
+          tile_product<double, D, P, NTMAX>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
 
         // ---- Taylor accumulation (FP64) and the next U for the owned (element, node) pairs
 #pragma unroll
@@ -467,13 +341,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
             double Y[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-              Y[c] = H * (double)sFR[b * RS + e * NC + c];
-              if constexpr (MIXED) {
-                if (diff) {   // Y_{i,1} = Y_{i-1,1} + H R(U_{i,0} - U_{i-1,0})
-                  Y[c] += sY1[P_ * NC + c];
-                  sY1[P_ * NC + c] = Y[c];
-                }
-              }
+              Y[c] = H * sFR[b * RS + e * NC + c];
               acc[r][c] = fma(coef, Y[c], acc[r][c]);
             }
             const double* gv = &sGL[(e * NV + 0) * D];
@@ -486,18 +354,8 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
                 bp[x] = H * gv[x];
                 bi[x] = sBb[e * D + x] + th * bp[x];
               }
-              if constexpr (MIXED) {
-                if (diff) {
 #pragma unroll
-                  for (int c = 0; c < NC; ++c) uo[c] = u0p[r][c];
-                } else {
-#pragma unroll
-                  for (int c = 0; c < NC; ++c) uo[c] = (double)sU[b * RS + e * NC + c];
-                }
-              } else {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) uo[c] = (double)sU[b * RS + e * NC + c];
-              }
+              for (int c = 0; c < NC; ++c) uo[c] = sU[b * RS + e * NC + c];
               applyA<D>(bp, uo, au);
 #pragma unroll
               for (int c = 0; c < NC; ++c) rhs[c] = Y[c] + n * au[c];
@@ -509,19 +367,11 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
 #pragma unroll
               for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * H * gv[x];
               ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], un);
-              if constexpr (MIXED) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                  const double u = un[c];
-                  un[c] = u - u0p[r][c];
-                  u0p[r][c] = u;
-                }
-              }
               write = true;
             }
             if (write) {
 #pragma unroll
-              for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = (T)un[c];
+              for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = un[c];
             }
           }
         }

@@ -69,8 +69,8 @@ MIXED_TOL = 1e-6
 @pytest.mark.parametrize("name", list(CASES))
 def test_mixed_fp32_against_oracle(name):
     """Mixed path against the FP64 oracle: relative L2 <= 1e-6.  FP32 matrix-core
-    contractions for every stage but the first of a tent (FP64); the first stage of later
-    sub-intervals acts on U_{i,0} - U_{i-1,0}; FP64 inversion at n = 0 and Taylor sum."""
+    contractions for the stages n >= 2 of every sub-interval (acting on the small Taylor
+    coefficients); FP64 first stage, inversions, fluxes and Taylor sum."""
     print(f"[gpu parity] {name} mixed", flush=True)
     ref = fixture(name)
     c, S, T = gpu_solver(name, 1)
