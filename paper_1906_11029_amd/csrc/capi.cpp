@@ -33,8 +33,8 @@ struct Layout {
 };
 
 struct Offsets {
-  size_t W, tau, stage, grad_lam, cells, eps, mu, coords, pptr, pelem, pinfo, tv, tt, S, L, fnode,
-      perm, mi, err, slab, total;
+  size_t W, tau, stage, grad_lam, cells, eps, mu, coords, pptr, pelem, pinfo, fptr, face, tv, tt, S, L,
+      fnode, fswap, perm, mi, err, slab, total;
 };
 
 static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
@@ -53,11 +53,14 @@ static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
   o.pptr = L.add(sizeof(int32_t) * (m.nv + 1));
   o.pelem = L.add(sizeof(int32_t) * ptot);
   o.pinfo = L.add(sizeof(int32_t) * ptot * (1 + d));
+  o.fptr = L.add(sizeof(int32_t) * (m.nv + 1));
+  o.face = L.add(sizeof(int32_t) * ptot * d);
   o.tv = L.add(sizeof(int32_t) * std::max<size_t>(1, t.vertex.size()));
   o.tt = L.add(sizeof(double) * std::max<size_t>(1, t.vertex.size()));
   o.S = L.add(sizeof(double) * R.S.size());
   o.L = L.add(sizeof(double) * R.L.size());
   o.fnode = L.add(sizeof(int32_t) * R.fnode.size());
+  o.fswap = L.add(sizeof(int32_t) * R.fswap.size());
   o.perm = L.add(sizeof(int32_t) * R.perm.size());
   o.mi = L.add(sizeof(int32_t) * R.mi.size());
   o.err = L.add(sizeof(int32_t) * 4);
@@ -125,6 +128,26 @@ static void patch_tables(const Mesh& m, std::vector<int32_t>& ptr, std::vector<i
         inf[jn] = (int32_t)((pos << 4) | (j2 << 1) | o);
       }
     }
+  }
+}
+
+// Owned faces per vertex patch, from the patch info codes: each interior face once (by
+// the lower patch index of its two elements), each boundary face by its element.
+static void patch_faces(const Mesh& m, const std::vector<int32_t>& info, std::vector<int32_t>& ptr,
+                        std::vector<int32_t>& faces) {
+  const int d = m.d;
+  ptr.assign(m.nv + 1, 0);
+  faces.clear();
+  for (int64_t V = 0; V < m.nv; ++V) {
+    const int64_t b0 = m.v2e_ptr[V], b1 = m.v2e_ptr[V + 1];
+    for (int64_t i = b0; i < b1; ++i) {
+      const int e = (int)(i - b0);
+      for (int j = 1; j <= d; ++j) {
+        const int32_t code = info[i * (1 + d) + j];
+        if (code < 0 || (code >> 4) > e) faces.push_back((e << 2) | (j - 1));
+      }
+    }
+    ptr[V + 1] = (int32_t)faces.size();
   }
 }
 
@@ -324,8 +347,9 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     for (int64_t i = 0; i < M.ne * (M.d + 1); ++i)
       if (M.nbr[i] < 0 && M.face_bc[i] == MTP_BC_DATA) s->has_data_faces = true;
 
-    std::vector<int32_t> pptr, pelem, pinfo;
+    std::vector<int32_t> pptr, pelem, pinfo, fptr, faces;
     patch_tables(M, pptr, pelem, pinfo);
+    patch_faces(M, pinfo, fptr, faces);
     auto up = [&](size_t off, const void* src, size_t n) {
       if (n) check_hip(hipMemcpyAsync(s->ws + off, src, n, hipMemcpyHostToDevice, s->stream), "upload");
     };
@@ -337,11 +361,14 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     up(s->off.pptr, pptr.data(), pptr.size() * 4);
     up(s->off.pelem, pelem.data(), pelem.size() * 4);
     up(s->off.pinfo, pinfo.data(), pinfo.size() * 4);
+    up(s->off.fptr, fptr.data(), fptr.size() * 4);
+    up(s->off.face, faces.data(), faces.size() * 4);
     up(s->off.tv, s->tents.vertex.data(), s->tents.vertex.size() * 4);
     up(s->off.tt, s->tents.t_top.data(), s->tents.t_top.size() * 8);
     up(s->off.S, s->ref.S.data(), s->ref.S.size() * 8);
     up(s->off.L, s->ref.L.data(), s->ref.L.size() * 8);
     up(s->off.fnode, s->ref.fnode.data(), s->ref.fnode.size() * 4);
+    up(s->off.fswap, s->ref.fswap.data(), s->ref.fswap.size() * 4);
     up(s->off.perm, s->ref.perm.data(), s->ref.perm.size() * 4);
     up(s->off.mi, s->ref.mi.data(), s->ref.mi.size() * 4);
     check_hip(hipMemsetAsync(s->ws + s->off.W, 0, sizeof(double) * M.ne * s->nc * s->ref.np, s->stream), "memset");
@@ -366,6 +393,9 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     kp.patch_ptr = reinterpret_cast<const int32_t*>(s->ws + s->off.pptr);
     kp.patch_elem = reinterpret_cast<const int32_t*>(s->ws + s->off.pelem);
     kp.patch_info = reinterpret_cast<const int32_t*>(s->ws + s->off.pinfo);
+    kp.pface_ptr = reinterpret_cast<const int32_t*>(s->ws + s->off.fptr);
+    kp.pface = reinterpret_cast<const int32_t*>(s->ws + s->off.face);
+    kp.fswap = reinterpret_cast<const int32_t*>(s->ws + s->off.fswap);
     kp.S = reinterpret_cast<const double*>(s->ws + s->off.S);
     kp.L = reinterpret_cast<const double*>(s->ws + s->off.L);
     kp.fnode = reinterpret_cast<const int32_t*>(s->ws + s->off.fnode);

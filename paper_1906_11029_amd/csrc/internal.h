@@ -52,6 +52,7 @@ struct RefElem {
   std::vector<double> S;      // d*np*np : S_l = Mhat^{-1} D_l, stored [l][a][b] (b = test)
   std::vector<double> L;      // d*nf*np : L_j = Mhat^{-1} E_j, stored [j][s][b]
   std::vector<int> fnode;     // d*2*nf  : volume node of face node s, [j][o][s]
+  std::vector<int> fswap;     // nf: face node with the two non-V face vertices exchanged
   std::vector<int> perm;      // (d+1)*np: node of the original numbering for each node
                               //           of the numbering with vertex k moved to 0
   std::vector<double> Mhat;   // np*np reference mass (for tests / diagnostics)

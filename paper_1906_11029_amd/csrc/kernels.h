@@ -21,12 +21,17 @@ struct KernelParams {
   const int32_t* patch_ptr;
   const int32_t* patch_elem;
   const int32_t* patch_info;
+  // faces of the patch computed once each: (patch element << 2) | face j (0-based), the
+  // face owned by the lower patch index of its two elements, boundary faces by their element
+  const int32_t* pface_ptr;   // nv+1
+  const int32_t* pface;
   // reference tables
   const double* S;         // d*np*np [l][a][b]
   const double* L;         // d*nf*np [j][s][b]
   const int32_t* fnode;    // d*2*nf
   const int32_t* perm;     // (d+1)*np
   const int32_t* mi;       // np*(d+1)
+  const int32_t* fswap;    // nf
   // state
   double* W;               // ne*nc*np  [e][c][node]
   double* tau;             // nv

@@ -239,6 +239,19 @@ RefElem build_refelem(int d, int p) {
     }
   }
 
+  // face node s <-> (beta_1, beta_2) in the order above; fswap[s] = index of (beta_2, beta_1)
+  R.fswap.assign(nf, 0);
+  if (d == 2) {
+    for (int s = 0; s < nf; ++s) R.fswap[s] = s;
+  } else {
+    std::vector<int> idx((p + 1) * (p + 1), -1);
+    int s = 0;
+    for (int b2 = 0; b2 <= p; ++b2)
+      for (int b1 = 0; b1 <= p - b2; ++b1) idx[b1 * (p + 1) + b2] = s++;
+    for (int b2 = 0; b2 <= p; ++b2)
+      for (int b1 = 0; b1 <= p - b2; ++b1) R.fswap[idx[b1 * (p + 1) + b2]] = idx[b2 * (p + 1) + b1];
+  }
+
   Lagrange B(d, p, R.mi);
   // volume integrals
   std::vector<double> qp, qw;

@@ -241,6 +241,8 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
     const double H = t_top - kp.tau[V];
     const int ncols = nT * NC;
     const int ntiles = (ncols + 15) / 16;
+    const int32_t f0 = kp.pface_ptr[V];
+    const int nFace = kp.pface_ptr[V + 1] - f0;
 
     for (int e = tid; e < nT; e += BLOCK) {
       const int el = kp.patch_elem[p0 + e];
@@ -299,12 +301,14 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
       double coef = 1.0;
       for (int n = 1; n <= kp.q; ++n) {
         coef *= invm / n;
-        // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col]
-        for (int it = tid; it < nT * D * NF; it += BLOCK) {
-          const int e = it / (D * NF);
-          const int rem = it - e * (D * NF);
-          const int j = rem / NF;
-          const int s = rem - j * NF;
+        // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col], each face once:
+        //      the other side of an interior face gets -(|grad lambda_jn| / |grad lambda_j|) G
+        //      at its own face-node order (exchanged when the two orders differ)
+        for (int it = tid; it < nFace * NF; it += BLOCK) {
+          const int fi = it / NF;
+          const int s = it - fi * NF;
+          const int fc = kp.pface[f0 + fi];
+          const int e = fc >> 2, j = fc & 3;
           const int nin = sFn[(j * 2) * NF + s];
           double um[NC], up[NC], G[NC], g[D];
 #pragma unroll
@@ -317,12 +321,27 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
             const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
 #pragma unroll
             for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
+            flux<D>(g, kp.alpha, um, up, G);
+            double gg = 0.0, gn = 0.0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) {
+              gg += g[x] * g[x];
+              const double h = sGL[(pe * NV + jn) * D + x];
+              gn += h * h;
+            }
+            const double ratio = -sqrt(gn / gg);
+            const int s2 = o ? kp.fswap[s] : s;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              sFR[(j * NF + s) * RS + e * NC + c] = G[c];
+              sFR[((jn - 1) * NF + s2) * RS + pe * NC + c] = ratio * G[c];
+            }
           } else {
             ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
-          }
-          flux<D>(g, kp.alpha, um, up, G);
+            flux<D>(g, kp.alpha, um, up, G);
 #pragma unroll
-          for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
+            for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
+          }
         }
         __syncthreads();
 
