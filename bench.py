@@ -4,8 +4,13 @@ One step = one slab: every layer of the tent table from a flat front to the flat
 one slab height later (all tents: gather, SAT stages, scatter).  Inputs are resident in
 HBM before the timed region.  Prints one JSON line.
 
-Workload (default): 3D PEC cavity, unit cube 16^3 x 6 Kuhn tetrahedra (24576 tets),
-P3 DG, q = 4 Taylor stages, m = 6 sub-intervals, slab height T = 1, FP64.
+Workload (default): 3D Maxwell on the unit cube, 32^3 x 6 Kuhn tetrahedra (196608 tets)
+graded toward one corner (h ratio 1:8), eps in {1, 2.25} split at x = 0.5, Gaussian-pulse
+initial E, P4 DG, q = 5 Taylor stages, m = 8 sub-intervals, slab height 0.05, mixed
+precision (FP64 first stage of every sub-interval, FP32 matrix cores for the later stages).
+Beside it, in the same run: the plain FP64 path on the same workload (DOF-updates/s,
+speedup, relative L2 difference of the fields) and the equal-error check, one slab of
+the graded mesh with a closed-form PEC cavity mode in both precisions.
 """
 import argparse
 import json
@@ -34,21 +39,21 @@ def workload(name):
     if name == "cavity3d_p3":
         mm = meshes.cube_kuhn(16)
         desc = "3D PEC cavity mode, unit cube 16^3x6 Kuhn tets (24576), P3, q=4, m=6, slab T=1"
-        return dict(mm=mm, p=3, q=4, m=6, T=1.0, ex=fields.Cavity3D_PEC(), desc=desc, exact=True)
+        return dict(name=name, mm=mm, p=3, q=4, m=6, T=1.0, ex=fields.Cavity3D_PEC(), desc=desc, exact=True)
     if name == "graded3d_p4":
         grade = lambda g: GRADE_A * g + (1 - GRADE_A) * g * g  # noqa: E731
         mm = meshes.cube_kuhn(32, axis_map=grade)
         eps, mu = meshes.materials_split(mm)
         desc = ("3D PEC, unit cube 32^3x6 Kuhn tets (196608) graded toward one corner (h ratio 1:8), "
                 "eps in {1, 2.25} split at x=0.5, Gaussian-pulse E, P4, q=5, m=8, slab T=0.05")
-        return dict(mm=mm, p=4, q=5, m=8, T=0.05, ex=fields.GaussianPulse3D(seed=11030), desc=desc,
-                    eps=eps, mu=mu, exact=False)
+        return dict(name=name, mm=mm, p=4, q=5, m=8, T=0.05, ex=fields.GaussianPulse3D(seed=11030),
+                    desc=desc, eps=eps, mu=mu, exact=False, cert="graded3d_p4_cavity")
     if name == "graded3d_p4_cavity":
         grade = lambda g: GRADE_A * g + (1 - GRADE_A) * g * g  # noqa: E731
         mm = meshes.cube_kuhn(32, axis_map=grade)
         desc = ("3D PEC cavity mode, unit cube 32^3x6 Kuhn tets (196608) graded toward one corner "
                 "(h ratio 1:8), eps = mu = 1, P4, q=5, m=8, slab T=0.05 (equal-error certification)")
-        return dict(mm=mm, p=4, q=5, m=8, T=0.05, ex=fields.Cavity3D_PEC(), desc=desc, exact=True)
+        return dict(name=name, mm=mm, p=4, q=5, m=8, T=0.05, ex=fields.Cavity3D_PEC(), desc=desc, exact=True)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -82,13 +87,72 @@ def cpu_baseline(W, budget_s):
             "sample": f"first {done} tents (layer order) of the same workload, {el:.1f} s, numpy FP64, 1 thread"}
 
 
+def blended_peak(prec_kernel, dof_slab, flops_slab, W):
+    """Peak for the kernel's mix of units: FP64 (vector or matrix, 78.6) for everything
+    except, in the mixed kernel, the contractions of stages n >= 2 (FP32 matrix, 157.3)."""
+    if prec_kernel != 2:
+        return PEAK_FP64, 0.0
+    d, p, q = 3, W["p"], W["q"]
+    npn = (p + 1) * (p + 2) * (p + 3) // 6
+    nf = (p + 1) * (p + 2) // 2
+    c32 = dof_slab * (q - 1) / q * 2 * d * (npn + nf)
+    t = (flops_slab - c32) / PEAK_FP64 + c32 / PEAK_FP32
+    return flops_slab / t, c32
+
+
+def run(W, precision, steps, warmup, M=None, T=None):
+    """Set up one solver on workload W, advance `warmup` untimed and `steps` timed slabs
+    (each a replay of the captured slab graph); returns timings and the final fields."""
+    import torch
+
+    from mtp_inputs import meshes
+    from paper_1906_11029_amd import mtp
+    mm = W["mm"]
+    if M is None:
+        M = mtp.Mesh(mm["coords"], mm["cells"], eps=W.get("eps"), mu=W.get("mu"))
+        T = mtp.Tents(M, W["T"], 0.5)
+    prec = {"fp64": mtp.MTP_FP64, "mixed": mtp.MTP_MIXED_FP32, "fp64-valu": mtp.MTP_FP64_VALU}[precision]
+    S = mtp.Solver(M, T, W["p"], W["q"], W["m"], precision=prec)
+    S.set_fields(W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), 0.0), 0.0)
+    dof_slab, n_tents = S.slab_dof_updates()
+    front = 0.0
+    for _ in range(warmup):
+        front += W["T"]
+        S.advance_to(front)
+    stream = torch.cuda.current_stream()   # the solver's stream: graphs replay on it
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        front += W["T"]
+        S.advance_to(front)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_s = ev0.elapsed_time(ev1) * 1e-3
+    u = S.get_fields()
+    err = None
+    if W["exact"]:
+        uex = W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), front)
+        err = float(np.linalg.norm(u - uex) / np.linalg.norm(uex))
+    r = dict(S=S, M=M, T=T, wall=wall, gpu_s=gpu_s, u=u, err=err, dof_slab=dof_slab, n_tents=n_tents,
+             flops_slab=S.slab_flops(), kernel=S.kernel(), layers=T.n_layers, value=dof_slab * steps / wall)
+    log(f"{precision:6s} {W['name']}: {steps} slabs in {wall:.3f}s (events {gpu_s:.3f}s), "
+        f"{r['value']:.4e} DOF-updates/s, error vs exact {err}")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cavity3d_p3")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "fp64-valu"])
+    ap.add_argument("--workload", default="graded3d_p4")
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "fp64-valu"])
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP64 run of the same workload and the equal-error check")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -110,73 +174,53 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": x.numel() * 8, "copies": 3}))
         return
 
-    from mtp_inputs import meshes
-    from paper_1906_11029_amd import mtp
-
     W = workload(args.workload)
-    mm = W["mm"]
-    t0 = time.perf_counter()
-    M = mtp.Mesh(mm["coords"], mm["cells"], eps=W.get("eps"), mu=W.get("mu"))
-    T = mtp.Tents(M, W["T"], 0.5)
-    t_pitch = time.perf_counter() - t0
-    prec = {"fp64": mtp.MTP_FP64, "mixed": mtp.MTP_MIXED_FP32, "fp64-valu": mtp.MTP_FP64_VALU}[args.precision]
-    S = mtp.Solver(M, T, W["p"], W["q"], W["m"], precision=prec)
+    head = run(W, args.precision, args.steps, args.warmup)
+    M, T, S = head["M"], head["T"], head["S"]
+    log(f"mesh {M.info} tents {head['n_tents']} layers {head['layers']}")
     kernel_name = {0: "tent_kernel (vector-ALU FP64)", 1: "tent_mfma_kernel<double> (FP64 MFMA)",
-                   2: "tent_mfma_kernel<float> (FP32 MFMA, FP64 inversion and Taylor sum)"}[S.kernel()]
-    u0 = W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), 0.0)
-    S.set_fields(u0, 0.0)
-    dof_slab, n_tents = S.slab_dof_updates()
-    flops_slab = S.slab_flops()
-    log(f"mesh {M.info} tents {n_tents} layers {T.n_layers} pitch {t_pitch:.2f}s")
+                   2: "tent_mfma_kernel<float> (FP64 first stage, FP32 MFMA later stages)"}[head["kernel"]]
+    nl = head["layers"]
+    launches = args.steps * nl
+    kern_avg = head["gpu_s"] / launches
+    achieved = head["flops_slab"] / nl / kern_avg / 1e12
+    peak, c32 = blended_peak(head["kernel"], head["dof_slab"], head["flops_slab"], W)
 
-    front = 0.0
-    for _ in range(args.warmup):
-        front += W["T"]
-        S.advance_to(front)
-    torch.cuda.synchronize()
+    compare = None
+    if not args.no_compare and args.precision == "mixed":
+        # the plain FP64 path on the same workload and inputs, and the equal-error check on
+        # the same graded mesh with a closed-form solution
+        ref = run(W, "fp64", args.steps, args.warmup, M=M, T=T)
+        diff = float(np.linalg.norm(head["u"] - ref["u"]) / np.linalg.norm(ref["u"]))
+        del ref["S"]
+        cert = {}
+        if W.get("cert"):
+            Wc = workload(W["cert"])
+            for prec in ("fp64", "mixed"):
+                rc = run(Wc, prec, 1, 0)
+                cert[prec + "_rel_l2_error_vs_exact"] = rc["err"]
+                del rc
+            cert["workload"] = Wc["desc"]
+        compare = {"fp64_dof_updates_per_s": ref["value"], "speedup_vs_fp64": head["value"] / ref["value"],
+                   "mixed_vs_fp64_rel_l2": diff, "equal_error_check": cert or None}
 
-    stream = torch.cuda.current_stream()
-    nl = T.n_layers
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):     # each step replays the captured slab graph
-        front += W["T"]
-        S.advance_to(front)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_s = ev0.elapsed_time(ev1) * 1e-3
-    durs = np.full(args.steps * nl, gpu_s / (args.steps * nl))
-    kern_avg = durs.mean()
-    flops_avg = flops_slab / nl
-    achieved = flops_avg / kern_avg / 1e12
-
-    u = S.get_fields()
-    err = None
-    if W["exact"]:
-        uex = W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), front)
-        err = float(np.linalg.norm(u - uex) / np.linalg.norm(uex))
-    log(f"wall {wall:.3f}s for {args.steps} slabs; GPU time (events) {durs.sum():.3f}s; "
-        f"nodal rel. error vs exact {err}")
-
-    value = dof_slab * args.steps / wall
-    peak = PEAK_FP32 if S.kernel() == 2 else PEAK_FP64
     out = {
         "metric": "DOF-updates/s, 3D Maxwell p=4 MTP: mixed/batched vs FP64 GPU at equal L2 error",
-        "value": value, "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if S.kernel() != 2 else "f32+f64", "data": "synthetic",
+        "value": head["value"], "unit": "DOF-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["wall"] / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if head["kernel"] == 2 else "f64", "data": "synthetic",
         "config": {"workload": W["desc"], "tets": int(M.info["ne"]), "p": W["p"], "q": W["q"], "m": W["m"],
-                   "tents_per_step": int(n_tents), "layers_per_step": int(nl), "slope_fraction": 0.5,
-                   "precision": args.precision, "nodal_rel_error_vs_exact": err},
-        "roofline": {"bound": "alu" if S.kernel() == 0 else "mfma", "achieved": achieved, "peak": peak,
+                   "tents_per_step": int(head["n_tents"]), "layers_per_step": int(nl), "slope_fraction": 0.5,
+                   "precision": args.precision, "nodal_rel_error_vs_exact": head["err"]},
+        "roofline": {"bound": "alu" if head["kernel"] == 0 else "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "kernel": kernel_name + ", one launch per layer, slab captured in a HIP graph",
-                     "avg_launch_ms": kern_avg * 1e3, "launches": int(args.steps * nl)},
+                     "avg_launch_ms": kern_avg * 1e3, "launches": int(launches),
+                     "fp32_mfma_flop_share": c32 / head["flops_slab"]},
     }
+    if compare:
+        out["config"]["compare"] = compare
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -47,30 +47,29 @@ template <> struct Mfma<float> {
   }
 };
 
-// component c of A(g) u = u[p1] g[q1] s1 + u[p2] g[q2] s2
+// component c of A(g) u = s1 g[q1] u[p1] + s2 g[q2] u[p2], from nibble tables (no branches)
 template <int D> struct ACoef;
 template <> struct ACoef<3> {
-  // c: (p1, q1, s1, p2, q2, s2)
+  // g x H and -(g x E) with u = (E, H):  P1 = {4,5,3,2,0,1}, Q1 = {2,0,1,1,2,0},
+  // P2 = {5,3,4,1,2,0}, Q2 = {1,2,0,2,0,1}, s1 = +1, s2 = -1
   static __device__ __forceinline__ void get(int c, int* p1, int* q1, double* s1, int* p2, int* q2, double* s2) {
-    // P1 = {4,5,3,2,0,1}, Q1 = {2,0,1,1,2,0}, P2 = {5,3,4,1,2,0}, Q2 = {1,2,0,2,0,1}
-    switch (c) {
-      case 0: *p1 = 4; *q1 = 2; *p2 = 5; *q2 = 1; break;
-      case 1: *p1 = 5; *q1 = 0; *p2 = 3; *q2 = 2; break;
-      case 2: *p1 = 3; *q1 = 1; *p2 = 4; *q2 = 0; break;
-      case 3: *p1 = 2; *q1 = 1; *p2 = 1; *q2 = 2; break;
-      case 4: *p1 = 0; *q1 = 2; *p2 = 2; *q2 = 0; break;
-      default: *p1 = 1; *q1 = 0; *p2 = 0; *q2 = 1; break;
-    }
+    *p1 = (0x102354 >> (4 * c)) & 15;
+    *q1 = (0x021102 >> (4 * c)) & 15;
+    *p2 = (0x021435 >> (4 * c)) & 15;
+    *q2 = (0x102021 >> (4 * c)) & 15;
     *s1 = 1.0;
     *s2 = -1.0;
   }
 };
 template <> struct ACoef<2> {
-  // (-g1 Hz, g0 Hz, g0 Ey - g1 Ex)
+  // (-g1 Hz, g0 Hz, g0 Ey - g1 Ex) with u = (Ex, Ey, Hz)
   static __device__ __forceinline__ void get(int c, int* p1, int* q1, double* s1, int* p2, int* q2, double* s2) {
-    if (c == 0) { *p1 = 2; *q1 = 1; *s1 = -1.0; *p2 = 2; *q2 = 0; *s2 = 0.0; }
-    else if (c == 1) { *p1 = 2; *q1 = 0; *s1 = 1.0; *p2 = 2; *q2 = 1; *s2 = 0.0; }
-    else { *p1 = 1; *q1 = 0; *s1 = 1.0; *p2 = 0; *q2 = 1; *s2 = -1.0; }
+    *p1 = (0x122 >> (4 * c)) & 15;
+    *q1 = (0x001 >> (4 * c)) & 15;
+    *p2 = (0x022 >> (4 * c)) & 15;
+    *q2 = (0x110 >> (4 * c)) & 15;
+    *s1 = (c == 0) ? -1.0 : 1.0;
+    *s2 = (c == 2) ? -1.0 : 0.0;
   }
 };
 
@@ -115,7 +114,11 @@ struct MLds {
 
 // R = [S | -L] [A(grad lambda) U ; F] for this wave's tiles with TM-precision products
 // (operands converted from the FP64 LDS values as they are loaded), written back to
-// sFR as FP64 once every wave has finished reading F.
+// sFR as FP64 once every wave has finished reading F.  The volume part of K runs node
+// block major: the two U values a lane needs for node block `as` serve the D products
+// (l = 1..D) of that block, which differ only in the coefficients of A(grad lambda_l).
+// The raw LDS operands of the next node block are loaded before the current block's
+// products are issued (register ring, no code motion across blocks).
 template <typename TM, int D, int P, int NTMAX>
 __device__ __forceinline__ void tile_product(const double* sOp, const double* sU, double* sFR, const double* sGL,
                                              int wave, int lane, int ncols, int ntiles) {
@@ -124,6 +127,9 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
   constexpr int NC = SH::NC, NV = SH::NV, NPK = SH::NPK, KV = SH::KV, KFP = SH::KFP, MT = SH::MT,
                 RS = SH::RS, WAVES = SH::WAVES, TPW = SH::TILES_PER_WAVE;
   constexpr int OPS = MLds<D, P, double, NTMAX>::OPS;
+  constexpr int NB = NPK / 4;              // node blocks of the volume part
+  constexpr int NG = NB + KFP / 4;         // K groups: node blocks, then lift steps
+  constexpr int PDG = 2;                   // ring depth in K groups
   typename MM::acc_t accs[TPW];
 #pragma unroll
   for (int ts = 0; ts < TPW; ++ts) {
@@ -138,31 +144,50 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       int p1, q1, p2, q2;
       double s1, s2;
       ACoef<D>::get(c, &p1, &q1, &s1, &p2, &q2, &s2);
-      double cf1[D], cf2[D];
+      TM cf1[D], cf2[D];
 #pragma unroll
       for (int l = 0; l < D; ++l) {
         const double* gl = &sGL[(e * NV + l + 1) * D];
-        cf1[l] = live ? s1 * gl[q1] : 0.0;
-        cf2[l] = live ? s2 * gl[q2] : 0.0;
+        cf1[l] = (TM)(live ? s1 * gl[q1] : 0.0);
+        cf2[l] = (TM)(live ? s2 * gl[q2] : 0.0);
       }
-      const int c1 = e * NC + p1, c2 = e * NC + p2;
+      const TM fm = live ? (TM)1 : (TM)0;
       const int kq = lane >> 4;
       const double* acol = sOp + mt * 16 + (lane & 15) + kq * OPS;
-      const double* u1 = sU + kq * RS + c1;
-      const double* u2 = sU + kq * RS + c2;
-#pragma unroll
-      for (int l = 0; l < D; ++l) {
-#pragma unroll
-        for (int as = 0; as < NPK / 4; ++as) {
-          const TM b = (TM)(cf1[l] * u1[4 * as * RS] + cf2[l] * u2[4 * as * RS]);
-          accs[ts] = MM::mma((TM)acol[(l * NPK + 4 * as) * OPS], b, accs[ts]);
-        }
-      }
+      const double* u1 = sU + kq * RS + e * NC + p1;
+      const double* u2 = sU + kq * RS + e * NC + p2;
       const double* fr = sFR + kq * RS + (live ? col : 0);
-      const double fm = live ? 1.0 : 0.0;
+      double ra[PDG][D], r1[PDG], r2[PDG];
+      auto load = [&](int g, int slot) {
+        if (g < NB) {
 #pragma unroll
-      for (int fs = 0; fs < KFP / 4; ++fs)
-        accs[ts] = MM::mma((TM)acol[(KV + 4 * fs) * OPS], (TM)(fm * fr[4 * fs * RS]), accs[ts]);
+          for (int l = 0; l < D; ++l) ra[slot][l] = acol[(l * NPK + 4 * g) * OPS];
+          r1[slot] = u1[4 * g * RS];
+          r2[slot] = u2[4 * g * RS];
+        } else {
+          ra[slot][0] = acol[(KV + 4 * (g - NB)) * OPS];
+          r1[slot] = fr[4 * (g - NB) * RS];
+        }
+      };
+#pragma unroll
+      for (int g = 0; g < PDG; ++g) load(g, g);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const int slot = g % PDG;
+        double a[D];
+#pragma unroll
+        for (int l = 0; l < D; ++l) a[l] = ra[slot][l];
+        const double x1 = r1[slot], x2 = r2[slot];
+        if (g + PDG < NG) load(g + PDG, slot);
+        if (g < NB) {
+          const TM v1 = (TM)x1, v2 = (TM)x2;
+#pragma unroll
+          for (int l = 0; l < D; ++l) accs[ts] = MM::mma((TM)a[l], cf1[l] * v1 + cf2[l] * v2, accs[ts]);
+        } else {
+          accs[ts] = MM::mma((TM)a[0], fm * (TM)x1, accs[ts]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
   __syncthreads();   // every wave is done reading F and U
@@ -179,8 +204,6 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
   __syncthreads();
 }
 
-// Body shared by the single-solve and the batched entry points: tents t_begin,
-// t_begin + t_step, ... < count of the tent table slice starting at `first`.
 // Body shared by the single-solve and the batched entry points: tents t_begin,
 // t_begin + t_step, ... < count of the tent table slice starting at `first`.
 // T = double: every product in FP64.  T = float (mixed): the first stage of every
