@@ -100,6 +100,24 @@ def blended_peak(prec_kernel, dof_slab, flops_slab, W):
     return flops_slab / t, c32
 
 
+def measured_traffic(tag):
+    """HBM bytes per launch of the tent kernel from the committed FETCH_SIZE / WRITE_SIZE
+    counter summary (copy-calibrated), or None once the kernel sources differ from the
+    ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tent_mfma_graded3d_p4_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["kernels"][tag]["hbm_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def run(W, precision, steps, warmup, M=None, T=None):
     """Set up one solver on workload W, advance `warmup` untimed and `steps` timed slabs
     (each a replay of the captured slab graph); returns timings and the final fields."""
@@ -185,6 +203,9 @@ def main():
     kern_avg = head["gpu_s"] / launches
     achieved = head["flops_slab"] / nl / kern_avg / 1e12
     peak, c32 = blended_peak(head["kernel"], head["dof_slab"], head["flops_slab"], W)
+    traffic = None
+    if args.workload == "graded3d_p4" and head["kernel"] in (1, 2):
+        traffic = measured_traffic("mixed" if head["kernel"] == 2 else "fp64")
 
     compare = None
     if not args.no_compare and args.precision == "mixed":
@@ -212,9 +233,11 @@ def main():
         "dtype": "f32+f64" if head["kernel"] == 2 else "f64", "data": "synthetic",
         "config": {"workload": W["desc"], "tets": int(M.info["ne"]), "p": W["p"], "q": W["q"], "m": W["m"],
                    "tents_per_step": int(head["n_tents"]), "layers_per_step": int(nl), "slope_fraction": 0.5,
-                   "precision": args.precision, "nodal_rel_error_vs_exact": head["err"]},
+                   "precision": args.precision, "nodal_rel_error_vs_exact": head["err"],
+                   "tent_dof_updates_per_s": head["value"] / (W["m"] * W["q"])},
         "roofline": {"bound": "alu" if head["kernel"] == 0 else "mfma", "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "hbm_gbs": traffic / kern_avg / 1e9 if traffic else None,
                      "kernel": kernel_name + ", one launch per layer, slab captured in a HIP graph",
                      "avg_launch_ms": kern_avg * 1e3, "launches": int(launches),
                      "fp32_mfma_flop_share": c32 / head["flops_slab"]},
