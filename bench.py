@@ -118,7 +118,7 @@ def measured_traffic(tag):
         return None
 
 
-def run(W, precision, steps, warmup, M=None, T=None):
+def run(W, precision, steps, warmup, M=None, T=None, schedule="layers"):
     """Set up one solver on workload W, advance `warmup` untimed and `steps` timed slabs
     (each a replay of the captured slab graph); returns timings and the final fields."""
     import torch
@@ -131,6 +131,7 @@ def run(W, precision, steps, warmup, M=None, T=None):
         T = mtp.Tents(M, W["T"], 0.5)
     prec = {"fp64": mtp.MTP_FP64, "mixed": mtp.MTP_MIXED_FP32, "fp64-valu": mtp.MTP_FP64_VALU}[precision]
     S = mtp.Solver(M, T, W["p"], W["q"], W["m"], precision=prec)
+    S.set_schedule({"layers": mtp.MTP_SCHEDULE_LAYERS, "dag": mtp.MTP_SCHEDULE_DAG}[schedule])
     S.set_fields(W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), 0.0), 0.0)
     dof_slab, n_tents = S.slab_dof_updates()
     front = 0.0
@@ -157,7 +158,7 @@ def run(W, precision, steps, warmup, M=None, T=None):
         err = float(np.linalg.norm(u - uex) / np.linalg.norm(uex))
     r = dict(S=S, M=M, T=T, wall=wall, gpu_s=gpu_s, u=u, err=err, dof_slab=dof_slab, n_tents=n_tents,
              flops_slab=S.slab_flops(), kernel=S.kernel(), layers=T.n_layers, value=dof_slab * steps / wall)
-    log(f"{precision:6s} {W['name']}: {steps} slabs in {wall:.3f}s (events {gpu_s:.3f}s), "
+    log(f"{precision:6s} {schedule:6s} {W['name']}: {steps} slabs in {wall:.3f}s (events {gpu_s:.3f}s), "
         f"{r['value']:.4e} DOF-updates/s, error vs exact {err}")
     return r
 
@@ -169,6 +170,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="graded3d_p4")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "fp64-valu"])
+    ap.add_argument("--schedule", default="dag", choices=["layers", "dag"],
+                    help="one launch per layer, or one persistent launch per slab over the tent DAG")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 run of the same workload and the equal-error check")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -193,32 +196,33 @@ def main():
         return
 
     W = workload(args.workload)
-    head = run(W, args.precision, args.steps, args.warmup)
+    head = run(W, args.precision, args.steps, args.warmup, schedule=args.schedule)
     M, T, S = head["M"], head["T"], head["S"]
     log(f"mesh {M.info} tents {head['n_tents']} layers {head['layers']}")
     kernel_name = {0: "tent_kernel (vector-ALU FP64)", 1: "tent_mfma_kernel<double> (FP64 MFMA)",
                    2: "tent_mfma_kernel<float> (FP64 first stage, FP32 MFMA later stages)"}[head["kernel"]]
     nl = head["layers"]
-    launches = args.steps * nl
+    per_slab = 1 if args.schedule == "dag" else nl   # tent-kernel launches per slab
+    launches = args.steps * per_slab
     kern_avg = head["gpu_s"] / launches
-    achieved = head["flops_slab"] / nl / kern_avg / 1e12
+    achieved = head["flops_slab"] / per_slab / kern_avg / 1e12
     peak, c32 = blended_peak(head["kernel"], head["dof_slab"], head["flops_slab"], W)
     traffic = None
-    if args.workload == "graded3d_p4" and head["kernel"] in (1, 2):
+    if args.workload == "graded3d_p4" and head["kernel"] in (1, 2) and args.schedule == "layers":
         traffic = measured_traffic("mixed" if head["kernel"] == 2 else "fp64")
 
     compare = None
     if not args.no_compare and args.precision == "mixed":
         # the plain FP64 path on the same workload and inputs, and the equal-error check on
         # the same graded mesh with a closed-form solution
-        ref = run(W, "fp64", args.steps, args.warmup, M=M, T=T)
+        ref = run(W, "fp64", args.steps, args.warmup, M=M, T=T, schedule=args.schedule)
         diff = float(np.linalg.norm(head["u"] - ref["u"]) / np.linalg.norm(ref["u"]))
         del ref["S"]
         cert = {}
         if W.get("cert"):
             Wc = workload(W["cert"])
             for prec in ("fp64", "mixed"):
-                rc = run(Wc, prec, 1, 0)
+                rc = run(Wc, prec, 1, 0, schedule=args.schedule)
                 cert[prec + "_rel_l2_error_vs_exact"] = rc["err"]
                 del rc
             cert["workload"] = Wc["desc"]
@@ -233,12 +237,15 @@ def main():
         "dtype": "f32+f64" if head["kernel"] == 2 else "f64", "data": "synthetic",
         "config": {"workload": W["desc"], "tets": int(M.info["ne"]), "p": W["p"], "q": W["q"], "m": W["m"],
                    "tents_per_step": int(head["n_tents"]), "layers_per_step": int(nl), "slope_fraction": 0.5,
-                   "precision": args.precision, "nodal_rel_error_vs_exact": head["err"],
+                   "precision": args.precision, "schedule": args.schedule,
+                   "nodal_rel_error_vs_exact": head["err"],
                    "tent_dof_updates_per_s": head["value"] / (W["m"] * W["q"])},
         "roofline": {"bound": "alu" if head["kernel"] == 0 else "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "hbm_gbs": traffic / kern_avg / 1e9 if traffic else None,
-                     "kernel": kernel_name + ", one launch per layer, slab captured in a HIP graph",
+                     "kernel": kernel_name + (", one persistent launch per slab over the tent DAG"
+                                              if args.schedule == "dag" else ", one launch per layer")
+                               + ", slab captured in a HIP graph",
                      "avg_launch_ms": kern_avg * 1e3, "launches": int(launches),
                      "fp32_mfma_flop_share": c32 / head["flops_slab"]},
     }

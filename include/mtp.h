@@ -72,6 +72,13 @@ enum { MTP_BC_PEC = 0, MTP_BC_PMC = 1, MTP_BC_DATA = 2 };
  *   MTP_FP64_VALU  plain FP64 on the vector ALUs (reference kernel)                    */
 enum { MTP_FP64 = 0, MTP_MIXED_FP32 = 1, MTP_FP64_VALU = 2 };
 
+/* how a slab's tents are scheduled on the device
+ *   MTP_SCHEDULE_LAYERS  one launch per layer (stream order is the layer barrier)
+ *   MTP_SCHEDULE_DAG     one persistent launch per slab: workgroups take tents from a
+ *                        device queue as soon as the tents they depend on are done
+ *                        (see mtp_tents_dag), with no barrier between layers        */
+enum { MTP_SCHEDULE_LAYERS = 0, MTP_SCHEDULE_DAG = 1 };
+
 /* Conforming simplicial mesh (section 2).  dim = 2 (triangles, TE fields) or 3 (tets).
  * coords (nv*dim), cells (ne*(dim+1)), eps/mu (ne) per-element material constants,
  * face_bc (ne*(dim+1)) boundary kind per local face, read only where the face lies on the
@@ -175,6 +182,36 @@ mtp_status mtp_slab_dof_updates(mtp_solver solver, double* dof_updates, int64_t*
 
 /* on = 0: advance_to launches layer by layer instead of replaying the captured slab graph. */
 mtp_status mtp_solver_set_graph(mtp_solver solver, int32_t on);
+
+/* Tent dependency graph of a tent table (section 2: a tent may be pitched, and evolved,
+ * once the tents it depends on are done).  Tent i (table order) at vertex V depends on
+ * the latest earlier tent at V and at every neighbour of V: those are the tents whose
+ * patch shares an element with its patch or whose vertex time it reads.  n_edges
+ * receives the number of dependencies.  mtp_tents_dag fills pred_count (n_tents),
+ * succ_ptr (n_tents + 1) and succ (n_edges; the dependants of tent i are
+ * succ[succ_ptr[i] .. succ_ptr[i+1]), in table order) and n_ready, the number of leading
+ * tents without dependency (the first layer).  Any output pointer may be NULL.  Host
+ * only; the caller owns the arrays.  Errors: MTP_ERR_ARG, MTP_ERR_PITCH (a tent without
+ * dependency outside the first layer: not a table made by mtp_pitch_layers). */
+mtp_status mtp_tents_dag_size(mtp_mesh mesh, mtp_tents tents, int64_t* n_edges);
+mtp_status mtp_tents_dag(mtp_mesh mesh, mtp_tents tents, int32_t* pred_count, int32_t* succ_ptr, int32_t* succ,
+                         int32_t* n_ready);
+
+/* Schedule of the solver's slabs (MTP_SCHEDULE_LAYERS by default).  MTP_SCHEDULE_DAG runs
+ * every tent of a slab in one launch of as many workgroups as the device holds at once;
+ * each takes the next released tent from a queue, runs it, and releases the tents that
+ * depended on it (device-scope release/acquire, so W and the front are visible across the
+ * chip's caches).  The result is identical to the layer schedule: every tent computes the
+ * same values from the same inputs.  mtp_layer_advance always runs single layers.
+ * Errors: MTP_ERR_ARG, MTP_ERR_STATE (half-done slab), MTP_ERR_UNSUPPORTED (vector-ALU
+ * kernel, or the kernel cannot be resident). */
+mtp_status mtp_solver_set_schedule(mtp_solver solver, int32_t schedule);
+
+/* Bound (seconds, default 10) on any single wait of the persistent schedule for a tent to
+ * be released.  A wait that exceeds it aborts the slab: every workgroup leaves, and the
+ * next mtp_get_fields / mtp_get_state returns MTP_ERR_DEVICE; the fields are then
+ * undefined.  No correct run waits anywhere near the default.  Errors: MTP_ERR_ARG. */
+mtp_status mtp_solver_set_dag_wait(mtp_solver solver, double seconds);
 
 /* Kernel the solver runs: 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32. */
 mtp_status mtp_solver_kernel(mtp_solver solver, int32_t* kernel);

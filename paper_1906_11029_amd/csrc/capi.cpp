@@ -34,7 +34,7 @@ struct Layout {
 
 struct Offsets {
   size_t W, tau, stage, grad_lam, cells, eps, mu, coords, pptr, pelem, pinfo, fptr, face, tv, tt, S, L,
-      fnode, fswap, perm, mi, err, slab, total;
+      fnode, fswap, perm, mi, err, slab, dag_indeg, dag_indeg0, dag_sptr, dag_succ, dag_queue, dag_ctl, total;
 };
 
 static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
@@ -65,6 +65,13 @@ static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
   o.mi = L.add(sizeof(int32_t) * R.mi.size());
   o.err = L.add(sizeof(int32_t) * 4);
   o.slab = L.add(sizeof(double) * 4);
+  const size_t nt = std::max<size_t>(1, t.vertex.size());
+  o.dag_indeg = L.add(sizeof(int32_t) * nt);
+  o.dag_indeg0 = L.add(sizeof(int32_t) * nt);
+  o.dag_sptr = L.add(sizeof(int32_t) * (nt + 1));
+  o.dag_succ = L.add(sizeof(int32_t) * std::max<int64_t>(1, tent_dag_edges(m, t)));
+  o.dag_queue = L.add(sizeof(int32_t) * nt);
+  o.dag_ctl = L.add(sizeof(int32_t) * 4);
   o.total = L.off;
   return o;
 }
@@ -167,7 +174,9 @@ struct mtp_solver_s {
   double t_base = 0.0;       // front time at the start of slab 0
   bool has_data_faces = false;
   int kernel = 0;            // 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32
-  // one slab (slab begin, every layer, slab end) captured once and replayed per slab
+  int schedule = MTP_SCHEDULE_LAYERS;
+  // one slab (slab begin, every layer or the persistent DAG launch, slab end) captured once
+  // and replayed per slab
   bool use_graph = true;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -408,6 +417,28 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     kp.tent_top = reinterpret_cast<const double*>(s->ws + s->off.tt);
     kp.slab = reinterpret_cast<double*>(s->ws + s->off.slab);
     kp.max_patch = M.max_patch;
+    // tent DAG for the persistent schedule
+    {
+      std::vector<int32_t> indeg, sptr, succ;
+      int32_t nready = 0;
+      tent_dag(M, s->tents, indeg, sptr, succ, nready);
+      up(s->off.dag_indeg0, indeg.data(), indeg.size() * 4);
+      up(s->off.dag_sptr, sptr.data(), sptr.size() * 4);
+      up(s->off.dag_succ, succ.data(), succ.size() * 4);
+      kp.dag_indeg = reinterpret_cast<int32_t*>(s->ws + s->off.dag_indeg);
+      kp.dag_indeg0 = reinterpret_cast<const int32_t*>(s->ws + s->off.dag_indeg0);
+      kp.dag_succ_ptr = reinterpret_cast<const int32_t*>(s->ws + s->off.dag_sptr);
+      kp.dag_succ = reinterpret_cast<const int32_t*>(s->ws + s->off.dag_succ);
+      kp.dag_queue = reinterpret_cast<int32_t*>(s->ws + s->off.dag_queue);
+      kp.dag_ctl = reinterpret_cast<int32_t*>(s->ws + s->off.dag_ctl);
+      kp.dag_n = (int32_t)s->tents.vertex.size();
+      kp.dag_nready = nready;
+      int dev = 0, khz = 0;
+      check_hip(hipGetDevice(&dev), "device");
+      check_hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+      kp.dag_wait_ticks = (int64_t)khz * 1000 * 10;   // 10 s
+      kp.dag_grid = s->kernel == 0 ? 0 : tent_dag_grid(kp, s->kernel == 2);
+    }
     check_hip(prepare_tent_kernel(kp, s->kernel), "tent kernel attributes");
     check_hip(launch_slab_reset(kp, 0.0, s->tents.t_end, s->stream), "slab state");
     check_hip(hipStreamSynchronize(s->stream), "upload sync");
@@ -495,7 +526,12 @@ static void run_layer(mtp_solver s, int64_t layer, hipStream_t st) {
 static void run_slab(mtp_solver s, hipStream_t st) {
   const int64_t nl = (int64_t)s->tents.layer_ptr.size() - 1;
   check_hip(launch_slab_begin(s->kp, st), "slab begin");
-  for (int64_t l = 0; l < nl; ++l) run_layer(s, l, st);
+  if (s->schedule == MTP_SCHEDULE_DAG) {
+    check_hip(launch_dag_reset(s->kp, st), "dag reset");
+    check_hip(launch_tent_dag_mfma(s->kp, s->kernel == 2, st), "persistent tent kernel");
+  } else {
+    for (int64_t l = 0; l < nl; ++l) run_layer(s, l, st);
+  }
   check_hip(launch_slab_end(s->kp, st), "slab end");
 }
 
@@ -576,6 +612,8 @@ static mtp_status read_out(mtp_solver s, double* nodal, int32_t on_device, int r
   check_hip(hipStreamSynchronize(s->stream), "sync");
   if (err[0] & ERRF_CAUSALITY) throw Error(MTP_ERR_DEVICE, "a tent met eps*mu - |grad phi|^2 <= 0");
   if (err[1] & ERRF_NONFINITE) throw Error(MTP_ERR_NONFINITE, "non-finite field values");
+  if (err[2] & ERRF_DAG_WAIT)
+    throw Error(MTP_ERR_DEVICE, "persistent schedule: a wait for a ready tent exceeded its bound (slab aborted)");
   MTP_CATCH
 }
 
@@ -764,6 +802,56 @@ mtp_status mtp_solver_set_graph(mtp_solver s, int32_t on) {
   MTP_TRY
   require(s, MTP_ERR_ARG, "null solver");
   s->use_graph = on != 0;
+  MTP_CATCH
+}
+
+mtp_status mtp_solver_set_schedule(mtp_solver s, int32_t schedule) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  require(schedule == MTP_SCHEDULE_LAYERS || schedule == MTP_SCHEDULE_DAG, MTP_ERR_ARG, "unknown schedule");
+  require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  if (schedule == MTP_SCHEDULE_DAG)
+    require(s->kernel != 0 && s->kp.dag_grid > 0, MTP_ERR_UNSUPPORTED,
+            "the persistent schedule needs the matrix-core kernel resident on the device");
+  if (schedule != s->schedule) {
+    check_hip(hipStreamSynchronize(s->stream), "sync");
+    drop_graph(s);
+    s->schedule = schedule;
+  }
+  MTP_CATCH
+}
+
+mtp_status mtp_solver_set_dag_wait(mtp_solver s, double seconds) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  require(seconds >= 0.0 && seconds <= 3600.0, MTP_ERR_ARG, "wait bound must be in [0, 3600] s");
+  int dev = 0, khz = 0;
+  check_hip(hipGetDevice(&dev), "device");
+  check_hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+  check_hip(hipStreamSynchronize(s->stream), "sync");
+  s->kp.dag_wait_ticks = (int64_t)(seconds * khz * 1000.0);
+  drop_graph(s);   // the captured launch holds the old parameter block
+  MTP_CATCH
+}
+
+mtp_status mtp_tents_dag_size(mtp_mesh mesh, mtp_tents tents, int64_t* n_edges) {
+  MTP_TRY
+  require(mesh && tents && n_edges, MTP_ERR_ARG, "null pointer");
+  *n_edges = tent_dag_edges(mesh->m, tents->t);
+  MTP_CATCH
+}
+
+mtp_status mtp_tents_dag(mtp_mesh mesh, mtp_tents tents, int32_t* pred_count, int32_t* succ_ptr, int32_t* succ,
+                         int32_t* n_ready) {
+  MTP_TRY
+  require(mesh && tents, MTP_ERR_ARG, "null pointer");
+  std::vector<int32_t> pc, sp, sc;
+  int32_t nr = 0;
+  tent_dag(mesh->m, tents->t, pc, sp, sc, nr);
+  if (pred_count) std::copy(pc.begin(), pc.end(), pred_count);
+  if (succ_ptr) std::copy(sp.begin(), sp.end(), succ_ptr);
+  if (succ) std::copy(sc.begin(), sc.end(), succ);
+  if (n_ready) *n_ready = nr;
   MTP_CATCH
 }
 

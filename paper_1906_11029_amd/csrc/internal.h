@@ -64,5 +64,10 @@ void vertex_order(int d, int k, int* order);
 
 void build_topology(Mesh& m);
 void pitch(const Mesh& m, double t_end, double slope, Tents& out);
+// dependency graph of the tents (table order): predecessor counts, successors (CSR) and the
+// number of leading tents without predecessor
+void tent_dag(const Mesh& m, const Tents& t, std::vector<int32_t>& pred_count, std::vector<int32_t>& succ_ptr,
+              std::vector<int32_t>& succ, int32_t& nready);
+int64_t tent_dag_edges(const Mesh& m, const Tents& t);
 
 }  // namespace mtp

@@ -42,6 +42,18 @@ struct KernelParams {
   // slab state in device memory: [0] time of the current slab's bottom (tent times are
   // relative to it), [1] slab height, [2] front time at slab 0, [3] completed slabs
   double* slab;
+  // tent DAG of the persistent schedule: in-degree (working copy, refreshed from dag_indeg0
+  // before every slab), successors (CSR), ready queue (-1 = slot not yet filled) and control
+  // words [0] next slot to claim, [1] next slot to fill, [2] abort.  The dag_nready tents
+  // without predecessor are the first ones of the tent table (layer 0).
+  int32_t* dag_indeg;
+  const int32_t* dag_indeg0;
+  const int32_t* dag_succ_ptr;
+  const int32_t* dag_succ;
+  int32_t* dag_queue;
+  int32_t* dag_ctl;
+  int32_t dag_n, dag_nready, dag_grid;
+  int64_t dag_wait_ticks;  // bound of any wait for a ready tent, in wall-clock ticks
   // plane-wave boundary data
   int has_data;
   double pw_amp[6], pw_k[3], pw_omega, pw_phase;
@@ -67,7 +79,7 @@ struct BatchLaunch {
 };
 
 // error flag bits
-enum { ERRF_CAUSALITY = 1, ERRF_NONFINITE = 2 };
+enum { ERRF_CAUSALITY = 1, ERRF_NONFINITE = 2, ERRF_DAG_WAIT = 4 };
 
 size_t tent_kernel_lds_bytes(int d, int p, int max_patch);
 bool tent_kernel_supported(int d, int p);
@@ -75,6 +87,12 @@ hipError_t launch_tent_layer(const KernelParams& kp, int64_t first, int64_t coun
 // matrix-core variant: fp32 = 0 contracts in FP64, fp32 = 1 in FP32 (mixed path)
 size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32);
 hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t count, int fp32, hipStream_t s);
+// persistent schedule: reset the DAG state for one slab, then run every tent of the slab in
+// one launch of kp.dag_grid workgroups (grid < 0: only set the kernel attributes)
+hipError_t launch_dag_reset(const KernelParams& kp, hipStream_t s);
+hipError_t launch_tent_dag_mfma(const KernelParams& kp, int fp32, hipStream_t s);
+// workgroups of the persistent kernel that fit the device at once (0 if it cannot run)
+int tent_dag_grid(const KernelParams& kp, int fp32);
 hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
                              int64_t nv, hipStream_t s);
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);

@@ -371,6 +371,23 @@ __global__ void batch_slab_kernel(const KernelParams* kps, int n, int end) {
   }
 }
 
+// Persistent-schedule state for one slab: in-degrees from the pristine copy, the tents
+// without predecessor (the first nready) in the first queue slots, every other slot
+// empty, claim counter 0, fill counter nready, abort clear.
+__global__ void dag_reset_kernel(int32_t* indeg, const int32_t* indeg0, int32_t* queue, int32_t* ctl, int n,
+                                 int nready) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    indeg[i] = indeg0[i];
+    queue[i] = i < nready ? i : -1;
+  }
+  if (i == 0) {
+    ctl[0] = 0;
+    ctl[1] = nready;
+    ctl[2] = 0;
+  }
+}
+
 __global__ void fill_kernel(double* x, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -455,6 +472,13 @@ hipError_t launch_slab_reset(const KernelParams& kp, double t0, double height, h
 }
 hipError_t launch_batch_slab(const KernelParams* kps, int n, int end, hipStream_t s) {
   hipLaunchKernelGGL(batch_slab_kernel, dim3((n + 63) / 64), dim3(64), 0, s, kps, n, end);
+  return hipGetLastError();
+}
+
+hipError_t launch_dag_reset(const KernelParams& kp, hipStream_t s) {
+  const int n = kp.dag_n > 0 ? kp.dag_n : 1;
+  hipLaunchKernelGGL(dag_reset_kernel, dim3((n + 255) / 256), dim3(256), 0, s, kp.dag_indeg, kp.dag_indeg0,
+                     kp.dag_queue, kp.dag_ctl, kp.dag_n, kp.dag_nready);
   return hipGetLastError();
 }
 

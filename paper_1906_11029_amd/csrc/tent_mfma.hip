@@ -204,12 +204,63 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
   __syncthreads();
 }
 
+// ---- persistent schedule over the tent DAG
+// Claim the next queue slot and wait (bounded) until a released tent fills it.  Returns the
+// tent, or -1 when every slot is claimed, on abort, or when the wait bound is exceeded
+// (which sets ERRF_DAG_WAIT and the abort word, so that every workgroup leaves).  The
+// acquire fence after the claim makes the predecessors' W and tau visible to this CU.
+__device__ __forceinline__ int dag_claim(const KernelParams& kp, int* sh, int tid) {
+  if (tid == 0) {
+    int t = -1;
+    if (__hip_atomic_load(&kp.dag_ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      const int slot = __hip_atomic_fetch_add(&kp.dag_ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (slot < kp.dag_n) {
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
+          t = __hip_atomic_load(&kp.dag_queue[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          if (t >= 0) break;
+          if (__hip_atomic_load(&kp.dag_ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+          if ((int64_t)(wall_clock64() - t0) > kp.dag_wait_ticks) {
+            atomicOr(&kp.err[2], (int32_t)ERRF_DAG_WAIT);
+            __hip_atomic_store(&kp.dag_ctl[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+    }
+    *sh = t;
+  }
+  __syncthreads();
+  const int t = *sh;
+  if (t >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return t;
+}
+
+// Tent t is done: make its W and tau visible device-wide, then count down its successors;
+// a successor whose count reaches zero goes into the next queue slot.
+__device__ __forceinline__ void dag_release(const KernelParams& kp, int t, int tid) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (tid == 0) {
+    const int b = kp.dag_succ_ptr[t], e = kp.dag_succ_ptr[t + 1];
+    for (int i = b; i < e; ++i) {
+      const int s = kp.dag_succ[i];
+      if (__hip_atomic_fetch_add(&kp.dag_indeg[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+        const int slot = __hip_atomic_fetch_add(&kp.dag_ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&kp.dag_queue[slot], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
 // Body shared by the single-solve and the batched entry points: tents t_begin,
 // t_begin + t_step, ... < count of the tent table slice starting at `first`.
 // T = double: every product in FP64.  T = float (mixed): the first stage of every
 // sub-interval, whose U_{i,0} has the full size of the fields, stays FP64; the later
 // stages act on the small Taylor coefficients U_{i,n}, n >= 1, and run on the FP32 cores.
-template <int D, int P, typename T, int NTMAX>
+// DAG = true: the persistent schedule, tents claimed from the ready queue (first = 0).
+template <int D, int P, typename T, int NTMAX, bool DAG = false>
 __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t first, int64_t count,
                                                int64_t t_begin, int64_t t_step) {
   using SH = MShape<D, P, NTMAX>;
@@ -256,7 +307,16 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
 
   const double invm = 1.0 / kp.m;
 
-  for (int64_t t = t_begin; t < count; t += t_step) {
+  __shared__ int sh_tent;
+  for (int64_t it = t_begin;; it += t_step) {
+    int64_t t;
+    if constexpr (DAG) {
+      t = dag_claim(kp, &sh_tent, tid);
+      if (t < 0) break;
+    } else {
+      if (it >= count) break;
+      t = it;
+    }
     const int32_t V = kp.tent_vertex[first + t];
     const double t_top = kp.slab[0] + kp.tent_top[first + t];
     const int32_t p0 = kp.patch_ptr[V];
@@ -437,6 +497,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
     __syncthreads();
     if (tid == 0) kp.tau[V] = t_top;
     __syncthreads();
+    if constexpr (DAG) dag_release(kp, (int)t, tid);
   }
 }
 
@@ -444,6 +505,13 @@ template <int D, int P, typename T, int NTMAX, int WPE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
   tent_mfma_body<D, P, T, NTMAX>(kp, first, count, blockIdx.x, gridDim.x);
+}
+
+// Persistent entry point: every tent of the slab, in DAG order, by kp.dag_grid workgroups.
+template <int D, int P, typename T, int NTMAX, int WPE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+tent_mfma_dag_kernel(KernelParams kp) {
+  tent_mfma_body<D, P, T, NTMAX, true>(kp, 0, kp.dag_n, 0, 1);
 }
 
 // Batched entry point: workgroup b runs tent b - seg.block0 of segment seg, i.e. of the
@@ -472,6 +540,59 @@ hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStr
   }
   hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
   return hipGetLastError();
+}
+
+// grid < 0 (kp.dag_grid): set the LDS attribute; grid == 0: report the resident grid in
+// *resident; otherwise launch.
+template <int D, int P, typename T, int NTMAX>
+hipError_t launch_md(const KernelParams& kp, hipStream_t s, int* resident) {
+  const size_t lds = MLds<D, P, T, NTMAX>::bytes;
+  auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
+  if (resident) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kfn),
+                                                     MShape<D, P, NTMAX>::BLOCK, lds);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    *resident = per_cu * cus;
+    return hipSuccess;
+  }
+  if (kp.dag_grid <= 0 || kp.dag_n <= 0) return kp.dag_n <= 0 ? hipSuccess : hipErrorInvalidValue;
+  hipLaunchKernelGGL(kfn, dim3((unsigned)kp.dag_grid), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp);
+  return hipGetLastError();
+}
+
+template <int D, int P, typename T>
+hipError_t launch_mdp(const KernelParams& kp, hipStream_t s, int* resident) {
+  if (kp.max_patch <= 8) return launch_md<D, P, T, 8>(kp, s, resident);
+  if (kp.max_patch <= 24) return launch_md<D, P, T, 24>(kp, s, resident);
+  if (kp.max_patch <= 48) return launch_md<D, P, T, 48>(kp, s, resident);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_dt(const KernelParams& kp, hipStream_t s, int* resident) {
+  if (kp.d == 2) {
+    switch (kp.p) {
+      case 1: return launch_mdp<2, 1, T>(kp, s, resident);
+      case 2: return launch_mdp<2, 2, T>(kp, s, resident);
+      case 3: return launch_mdp<2, 3, T>(kp, s, resident);
+      case 4: return launch_mdp<2, 4, T>(kp, s, resident);
+      case 5: return launch_mdp<2, 5, T>(kp, s, resident);
+    }
+  } else {
+    switch (kp.p) {
+      case 1: return launch_mdp<3, 1, T>(kp, s, resident);
+      case 2: return launch_mdp<3, 2, T>(kp, s, resident);
+      case 3: return launch_mdp<3, 3, T>(kp, s, resident);
+      case 4: return launch_mdp<3, 4, T>(kp, s, resident);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int D, int P, typename T, int NTMAX>
@@ -576,6 +697,16 @@ size_t lds_t(int d, int p, int max_patch) {
 }
 
 }  // namespace
+
+hipError_t launch_tent_dag_mfma(const KernelParams& kp, int fp32, hipStream_t s) {
+  return fp32 ? launch_dt<float>(kp, s, nullptr) : launch_dt<double>(kp, s, nullptr);
+}
+
+int tent_dag_grid(const KernelParams& kp, int fp32) {
+  int resident = 0;
+  const hipError_t e = fp32 ? launch_dt<float>(kp, nullptr, &resident) : launch_dt<double>(kp, nullptr, &resident);
+  return e == hipSuccess ? resident : 0;
+}
 
 size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32) {
   return fp32 ? lds_t<float>(d, p, max_patch) : lds_t<double>(d, p, max_patch);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmtp.so")
 MTP_OK = 0
 MTP_BC_PEC, MTP_BC_PMC, MTP_BC_DATA = 0, 1, 2
 MTP_FP64, MTP_MIXED_FP32, MTP_FP64_VALU = 0, 1, 2
+MTP_SCHEDULE_LAYERS, MTP_SCHEDULE_DAG = 0, 1
 
 _lib = None
 
@@ -58,6 +59,10 @@ def load():
         "mtp_slab_flops": [P, P],
         "mtp_solver_kernel": [P, P],
         "mtp_solver_set_graph": [P, i32],
+        "mtp_solver_set_schedule": [P, i32],
+        "mtp_solver_set_dag_wait": [P, dbl],
+        "mtp_tents_dag_size": [P, P, P],
+        "mtp_tents_dag": [P, P, P, P, P, P],
         "mtp_batch_workspace_size": [P, i32, P],
         "mtp_batch_create": [P, i32, P, sz, P, pp],
         "mtp_batch_advance": [P, i64],
@@ -132,6 +137,18 @@ def mtp_tents_export(tents):
     lay = np.zeros(nt, dtype=np.int32)
     _check(load().mtp_tents_export(tents, _ptr(v), _ptr(tb), _ptr(tt), _ptr(lay)))
     return {"vertex": v, "t_bot": tb, "t_top": tt, "layer": lay}
+
+
+def mtp_tents_dag(mesh, tents):
+    nt, _, _ = mtp_tents_query(tents)
+    ne = C.c_int64()
+    _check(load().mtp_tents_dag_size(mesh, tents, C.byref(ne)))
+    pc = np.zeros(nt, dtype=np.int32)
+    sp = np.zeros(nt + 1, dtype=np.int32)
+    sc = np.zeros(max(ne.value, 1), dtype=np.int32)
+    nr = C.c_int32()
+    _check(load().mtp_tents_dag(mesh, tents, _ptr(pc), _ptr(sp), _ptr(sc), C.byref(nr)))
+    return {"pred_count": pc, "succ_ptr": sp, "succ": sc[:ne.value], "n_ready": nr.value}
 
 
 def mtp_tents_destroy(tents):
@@ -225,6 +242,14 @@ def mtp_solver_set_graph(solver, on):
     _check(load().mtp_solver_set_graph(solver, int(on)))
 
 
+def mtp_solver_set_schedule(solver, schedule):
+    _check(load().mtp_solver_set_schedule(solver, int(schedule)))
+
+
+def mtp_solver_set_dag_wait(solver, seconds):
+    _check(load().mtp_solver_set_dag_wait(solver, float(seconds)))
+
+
 def mtp_solver_kernel(solver):
     k = C.c_int32()
     _check(load().mtp_solver_kernel(solver, C.byref(k)))
@@ -282,6 +307,9 @@ class Tents:
 
     def export(self):
         return mtp_tents_export(self.h)
+
+    def dag(self):
+        return mtp_tents_dag(self.mesh.h, self.h)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -342,6 +370,12 @@ class Solver:
 
     def set_graph(self, on):
         mtp_solver_set_graph(self.h, int(bool(on)))
+
+    def set_schedule(self, schedule):
+        mtp_solver_set_schedule(self.h, schedule)
+
+    def set_dag_wait(self, seconds):
+        mtp_solver_set_dag_wait(self.h, seconds)
 
     def __del__(self):
         if getattr(self, "h", None):
