@@ -174,6 +174,12 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
                             void* hip_stream, mtp_batch* out);
 mtp_status mtp_batch_advance(mtp_batch batch, int64_t n_slabs);
 mtp_status mtp_batch_set_graph(mtp_batch batch, int32_t on);
+/* Schedule of the batch's slabs: MTP_SCHEDULE_LAYERS (one launch per global layer index,
+ * the default) or MTP_SCHEDULE_DAG (one persistent launch per slab draining one queue of
+ * ready tents of every solver; tents of different solves and of uneven patch size share
+ * the workgroups; the wait bound is the largest of the solvers').  Results are identical.
+ * Errors: MTP_ERR_ARG, MTP_ERR_UNSUPPORTED (kernel cannot be resident). */
+mtp_status mtp_batch_set_schedule(mtp_batch batch, int32_t schedule);
 void mtp_batch_destroy(mtp_batch batch);
 
 /* Spacetime DOF updates of one slab: sum over tents of nc*Np*n_T(tent)*m*q (the paper's

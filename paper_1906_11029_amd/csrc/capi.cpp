@@ -193,6 +193,8 @@ struct mtp_batch_s {
   std::vector<mtp::KernelParams> h_kps;
   std::vector<int64_t> seg_ptr;   // per global layer: first segment
   std::vector<int64_t> blocks;    // per global layer: workgroups
+  int schedule = MTP_SCHEDULE_LAYERS;
+  mtp::BatchDag bd{};             // persistent schedule over every solver's tent DAG
   bool use_graph = true;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -650,14 +652,33 @@ static size_t batch_segments(const mtp_solver* solvers, int32_t n) {
   return tot;
 }
 
+static int64_t batch_tents(const mtp_solver* solvers, int32_t n) {
+  int64_t tot = 0;
+  for (int i = 0; i < n; ++i) tot += (int64_t)solvers[i]->tents.vertex.size();
+  return tot;
+}
+
+struct BatchLayout {
+  size_t kps, segs, queue, ctl, off, roff, total;
+};
+static BatchLayout batch_layout(const mtp_solver* solvers, int32_t n) {
+  Layout L;
+  BatchLayout o;
+  o.kps = L.add(sizeof(KernelParams) * n);
+  o.segs = L.add(sizeof(BatchSeg) * batch_segments(solvers, n));
+  o.queue = L.add(sizeof(int32_t) * std::max<int64_t>(1, batch_tents(solvers, n)));
+  o.ctl = L.add(sizeof(int32_t) * 4);
+  o.off = L.add(sizeof(int32_t) * (n + 1));
+  o.roff = L.add(sizeof(int32_t) * (n + 1));
+  o.total = L.off;
+  return o;
+}
+
 mtp_status mtp_batch_workspace_size(const mtp_solver* solvers, int32_t n, size_t* bytes) {
   MTP_TRY
   require(bytes, MTP_ERR_ARG, "null pointer");
   batch_check(solvers, n);
-  Layout L;
-  L.add(sizeof(KernelParams) * n);
-  L.add(sizeof(BatchSeg) * batch_segments(solvers, n));
-  *bytes = L.off;
+  *bytes = batch_layout(solvers, n).total;
   MTP_CATCH
 }
 
@@ -675,14 +696,35 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     for (int i = 0; i < n; ++i) b->max_patch = std::max(b->max_patch, solvers[i]->mesh.max_patch);
     require(tent_mfma_lds_bytes(b->d, b->p, b->max_patch, b->kernel == 2) <= 160 * 1024, MTP_ERR_UNSUPPORTED,
             "largest vertex patch of the batch does not fit the matrix-core kernel's LDS");
-    Layout L;
-    const size_t o_kps = L.add(sizeof(KernelParams) * n);
-    const size_t o_segs = L.add(sizeof(BatchSeg) * batch_segments(solvers, n));
-    require(bytes >= L.off, MTP_ERR_ARG, "workspace too small");
+    const BatchLayout lo = batch_layout(solvers, n);
+    require(bytes >= lo.total, MTP_ERR_ARG, "workspace too small");
+    require(batch_tents(solvers, n) < (int64_t)1 << 31, MTP_ERR_UNSUPPORTED, "more than 2^31 - 1 tents per batch slab");
     b->ws = static_cast<char*>(d_workspace);
     b->stream = static_cast<hipStream_t>(hip_stream);
-    b->d_kps = reinterpret_cast<KernelParams*>(b->ws + o_kps);
-    b->d_segs = reinterpret_cast<BatchSeg*>(b->ws + o_segs);
+    b->d_kps = reinterpret_cast<KernelParams*>(b->ws + lo.kps);
+    b->d_segs = reinterpret_cast<BatchSeg*>(b->ws + lo.segs);
+    // persistent schedule: global tent ids solver by solver, first-layer tents first
+    {
+      std::vector<int32_t> off(n + 1, 0), roff(n + 1, 0);
+      for (int i = 0; i < n; ++i) {
+        off[i + 1] = off[i] + (int32_t)solvers[i]->tents.vertex.size();
+        roff[i + 1] = roff[i] + solvers[i]->kp.dag_nready;
+      }
+      check_hip(hipMemcpyAsync(b->ws + lo.off, off.data(), off.size() * 4, hipMemcpyHostToDevice, b->stream),
+                "upload");
+      check_hip(hipMemcpyAsync(b->ws + lo.roff, roff.data(), roff.size() * 4, hipMemcpyHostToDevice, b->stream),
+                "upload");
+      b->bd.queue = reinterpret_cast<int32_t*>(b->ws + lo.queue);
+      b->bd.ctl = reinterpret_cast<int32_t*>(b->ws + lo.ctl);
+      b->bd.off = reinterpret_cast<const int32_t*>(b->ws + lo.off);
+      b->bd.roff = reinterpret_cast<const int32_t*>(b->ws + lo.roff);
+      b->bd.nsolv = n;
+      b->bd.n = off[n];
+      int64_t ticks = 0;
+      for (int i = 0; i < n; ++i) ticks = std::max(ticks, solvers[i]->kp.dag_wait_ticks);
+      b->bd.wait_ticks = ticks;
+      b->bd.grid = tent_batch_dag_grid(b->d, b->p, b->max_patch, b->kernel == 2);
+    }
     // global layer l runs layer l of every solver that has it
     int64_t nl = 0;
     for (int i = 0; i < n; ++i) nl = std::max<int64_t>(nl, (int64_t)solvers[i]->tents.layer_ptr.size() - 1);
@@ -721,10 +763,16 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
 static void batch_slab(mtp_batch b, hipStream_t st) {
   const int n = (int)b->solvers.size();
   check_hip(launch_batch_slab(b->d_kps, n, 0, st), "batch slab begin");
-  for (size_t l = 0; l + 1 < b->seg_ptr.size(); ++l) {
-    BatchLaunch bl{b->d_kps, b->d_segs + b->seg_ptr[l], (int)(b->seg_ptr[l + 1] - b->seg_ptr[l]), b->blocks[l],
-                   b->d, b->p, b->max_patch};
-    check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, st), "batched tent kernel");
+  if (b->schedule == MTP_SCHEDULE_DAG) {
+    check_hip(launch_batch_dag_reset(b->d_kps, b->bd, st), "batch dag reset");
+    check_hip(launch_tent_batch_dag_mfma(b->d_kps, b->bd, b->d, b->p, b->max_patch, b->kernel == 2, st),
+              "persistent batched tent kernel");
+  } else {
+    for (size_t l = 0; l + 1 < b->seg_ptr.size(); ++l) {
+      BatchLaunch bl{b->d_kps, b->d_segs + b->seg_ptr[l], (int)(b->seg_ptr[l + 1] - b->seg_ptr[l]), b->blocks[l],
+                     b->d, b->p, b->max_patch};
+      check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, st), "batched tent kernel");
+    }
   }
   check_hip(launch_batch_slab(b->d_kps, n, 1, st), "batch slab end");
 }
@@ -780,6 +828,20 @@ mtp_status mtp_batch_advance(mtp_batch b, int64_t n_slabs) {
     b->solvers[i]->slab += n_slabs;
     // later work on a solver's own stream waits for the batch
     if (b->solvers[i]->stream != b->stream) check_hip(hipStreamSynchronize(b->stream), "sync batch stream");
+  }
+  MTP_CATCH
+}
+
+mtp_status mtp_batch_set_schedule(mtp_batch b, int32_t schedule) {
+  MTP_TRY
+  require(b, MTP_ERR_ARG, "null batch");
+  require(schedule == MTP_SCHEDULE_LAYERS || schedule == MTP_SCHEDULE_DAG, MTP_ERR_ARG, "unknown schedule");
+  if (schedule == MTP_SCHEDULE_DAG)
+    require(b->bd.grid > 0, MTP_ERR_UNSUPPORTED, "the persistent batched kernel cannot be resident");
+  if (schedule != b->schedule) {
+    check_hip(hipStreamSynchronize(b->stream), "sync");
+    drop_batch_graph(b);
+    b->schedule = schedule;
   }
   MTP_CATCH
 }

@@ -70,6 +70,18 @@ struct BatchSeg {
   int32_t pad;
 };
 
+// Persistent schedule of a batch: one queue of global tent ids (solver offset + tent) over
+// the tent DAGs of every solver (each solver's in-degrees and successors in its own
+// parameter block).
+struct BatchDag {
+  int32_t* queue;        // n slots
+  int32_t* ctl;          // [0] next slot to claim, [1] next slot to fill, [2] abort
+  const int32_t* off;    // nsolv + 1: first global id of each solver
+  const int32_t* roff;   // nsolv + 1: first queue slot of each solver's first-layer tents
+  int32_t nsolv, n, grid;
+  int64_t wait_ticks;
+};
+
 struct BatchLaunch {
   const KernelParams* kps;   // device array, one entry per solver
   const BatchSeg* segs;      // device array, nseg entries sorted by block0
@@ -93,6 +105,11 @@ hipError_t launch_dag_reset(const KernelParams& kp, hipStream_t s);
 hipError_t launch_tent_dag_mfma(const KernelParams& kp, int fp32, hipStream_t s);
 // workgroups of the persistent kernel that fit the device at once (0 if it cannot run)
 int tent_dag_grid(const KernelParams& kp, int fp32);
+// the same for a batch (kps: device array of the solvers' parameter blocks)
+hipError_t launch_batch_dag_reset(const KernelParams* kps, const BatchDag& bd, hipStream_t s);
+hipError_t launch_tent_batch_dag_mfma(const KernelParams* kps, const BatchDag& bd, int d, int p, int max_patch,
+                                      int fp32, hipStream_t s);
+int tent_batch_dag_grid(int d, int p, int max_patch, int fp32);
 hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
                              int64_t nv, hipStream_t s);
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);

@@ -388,6 +388,37 @@ __global__ void dag_reset_kernel(int32_t* indeg, const int32_t* indeg0, int32_t*
   }
 }
 
+// Batch version: slot / global id i; in-degrees of every solver's tents from their pristine
+// copies, the first-layer tents of every solver in the leading queue slots.
+__device__ __forceinline__ int last_le(const int32_t* a, int n, int x) {   // last k < n with a[k] <= x
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__global__ void batch_dag_reset_kernel(const KernelParams* kps, BatchDag bd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < bd.n) {
+    const int s = last_le(bd.off, bd.nsolv, i);
+    const int t = i - bd.off[s];
+    kps[s].dag_indeg[t] = kps[s].dag_indeg0[t];
+    const int nr = bd.roff[bd.nsolv];
+    if (i < nr) {
+      const int r = last_le(bd.roff, bd.nsolv, i);
+      bd.queue[i] = bd.off[r] + (i - bd.roff[r]);
+    } else {
+      bd.queue[i] = -1;
+    }
+  }
+  if (i == 0) {
+    bd.ctl[0] = 0;
+    bd.ctl[1] = bd.roff[bd.nsolv];
+    bd.ctl[2] = 0;
+  }
+}
+
 __global__ void fill_kernel(double* x, int64_t n, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = v;
@@ -479,6 +510,12 @@ hipError_t launch_dag_reset(const KernelParams& kp, hipStream_t s) {
   const int n = kp.dag_n > 0 ? kp.dag_n : 1;
   hipLaunchKernelGGL(dag_reset_kernel, dim3((n + 255) / 256), dim3(256), 0, s, kp.dag_indeg, kp.dag_indeg0,
                      kp.dag_queue, kp.dag_ctl, kp.dag_n, kp.dag_nready);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_dag_reset(const KernelParams* kps, const BatchDag& bd, hipStream_t s) {
+  const int n = bd.n > 0 ? bd.n : 1;
+  hipLaunchKernelGGL(batch_dag_reset_kernel, dim3((n + 255) / 256), dim3(256), 0, s, kps, bd);
   return hipGetLastError();
 }
 

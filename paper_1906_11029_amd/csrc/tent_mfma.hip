@@ -254,15 +254,102 @@ __device__ __forceinline__ void dag_release(const KernelParams& kp, int t, int t
   }
 }
 
-// Body shared by the single-solve and the batched entry points: tents t_begin,
-// t_begin + t_step, ... < count of the tent table slice starting at `first`.
+// Tent sources of the body: next() yields the next tent and its solver's parameter block
+// (false: the workgroup is done), done() runs after the tent's scatter.
+struct SchedRange {   // tents first + it, it = begin, begin + step, ... < count
+  const KernelParams* kp;
+  int64_t first, count, it, step;
+  __device__ bool next(int*, int, const KernelParams*& k, int64_t& t) {
+    if (it >= count) return false;
+    k = kp;
+    t = first + it;
+    it += step;
+    return true;
+  }
+  __device__ void done(const KernelParams&, int64_t, int) {}
+};
+
+struct SchedDag {     // one solver's tent DAG
+  const KernelParams* kp;
+  __device__ bool next(int* sh, int tid, const KernelParams*& k, int64_t& t) {
+    const int c = dag_claim(*kp, sh, tid);
+    if (c < 0) return false;
+    k = kp;
+    t = c;
+    return true;
+  }
+  __device__ void done(const KernelParams& k, int64_t t, int tid) { dag_release(k, (int)t, tid); }
+};
+
+struct SchedBatchDag {   // the tent DAGs of a batch of solvers, one queue of global ids
+  const KernelParams* kps;
+  BatchDag bd;
+  int solver;
+  __device__ bool next(int* sh, int tid, const KernelParams*& k, int64_t& t) {
+    if (tid == 0) {
+      int g = -1;
+      if (__hip_atomic_load(&bd.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        const int slot = __hip_atomic_fetch_add(&bd.ctl[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (slot < bd.n) {
+          const uint64_t t0 = wall_clock64();
+          for (;;) {
+            g = __hip_atomic_load(&bd.queue[slot], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if (g >= 0) break;
+            if (__hip_atomic_load(&bd.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            if ((int64_t)(wall_clock64() - t0) > bd.wait_ticks) {
+              for (int i = 0; i < bd.nsolv; ++i) atomicOr(&kps[i].err[2], (int32_t)ERRF_DAG_WAIT);
+              __hip_atomic_store(&bd.ctl[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+          }
+        }
+      }
+      int s = 0;
+      if (g >= 0) {   // solver of g: last s with off[s] <= g
+        int lo = 0, hi = bd.nsolv - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (bd.off[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        s = lo;
+      }
+      sh[0] = g;
+      sh[1] = s;
+    }
+    __syncthreads();
+    const int g = sh[0];
+    solver = sh[1];
+    if (g < 0) return false;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    k = &kps[solver];
+    t = g - bd.off[solver];
+    return true;
+  }
+  __device__ void done(const KernelParams& k, int64_t t, int tid) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) {
+      const int b = k.dag_succ_ptr[t], e = k.dag_succ_ptr[t + 1];
+      const int base = bd.off[solver];
+      for (int i = b; i < e; ++i) {
+        const int s = k.dag_succ[i];
+        if (__hip_atomic_fetch_add(&k.dag_indeg[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+          const int slot = __hip_atomic_fetch_add(&bd.ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&bd.queue[slot], base + s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+  }
+};
+
+// Body shared by every entry point: tents from the Sched source, the operator staged from
+// kp0 (all solvers of a batch share dimension and degree, hence the reference operator).
 // T = double: every product in FP64.  T = float (mixed): the first stage of every
 // sub-interval, whose U_{i,0} has the full size of the fields, stays FP64; the later
 // stages act on the small Taylor coefficients U_{i,n}, n >= 1, and run on the FP32 cores.
-// DAG = true: the persistent schedule, tents claimed from the ready queue (first = 0).
-template <int D, int P, typename T, int NTMAX, bool DAG = false>
-__device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t first, int64_t count,
-                                               int64_t t_begin, int64_t t_step) {
+template <int D, int P, typename T, int NTMAX, class Sched>
+__device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sched) {
   using SH = MShape<D, P, NTMAX>;
   constexpr bool MIXED = sizeof(T) == 4;
   constexpr int NC = SH::NC, NP = SH::NP, NF = SH::NF, NV = SH::NV;
@@ -292,10 +379,10 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
     if (m < NP) {
       if (k < KV) {
         const int l = k / NPK, a = k - l * NPK;
-        if (a < NP) v = kp.S[(l * NP + a) * NP + m];
+        if (a < NP) v = kp0.S[(l * NP + a) * NP + m];
       } else if (k < KV + KF) {
         const int j = (k - KV) / NF, s = (k - KV) - j * NF;
-        v = -kp.L[(j * NF + s) * NP + m];
+        v = -kp0.L[(j * NF + s) * NP + m];
       }
     }
     sOp[i] = v;
@@ -303,22 +390,17 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
   // padding rows of U and F are read by the product (times zero): keep them finite
   for (int i = tid; i < (NPK - NP) * RS; i += BLOCK) sU[NP * RS + i] = 0.0;
   for (int i = tid; i < (SH::FROWS - KF) * RS; i += BLOCK) sFR[KF * RS + i] = 0.0;
-  for (int i = tid; i < D * 2 * NF; i += BLOCK) sFn[i] = kp.fnode[i];
+  for (int i = tid; i < D * 2 * NF; i += BLOCK) sFn[i] = kp0.fnode[i];
 
-  const double invm = 1.0 / kp.m;
-
-  __shared__ int sh_tent;
-  for (int64_t it = t_begin;; it += t_step) {
+  __shared__ int sh_tent[2];
+  for (;;) {
+    const KernelParams* kpp;
     int64_t t;
-    if constexpr (DAG) {
-      t = dag_claim(kp, &sh_tent, tid);
-      if (t < 0) break;
-    } else {
-      if (it >= count) break;
-      t = it;
-    }
-    const int32_t V = kp.tent_vertex[first + t];
-    const double t_top = kp.slab[0] + kp.tent_top[first + t];
+    if (!sched.next(sh_tent, tid, kpp, t)) break;
+    const KernelParams& kp = *kpp;
+    const double invm = 1.0 / kp.m;
+    const int32_t V = kp.tent_vertex[t];
+    const double t_top = kp.slab[0] + kp.tent_top[t];
     const int32_t p0 = kp.patch_ptr[V];
     const int nT = kp.patch_ptr[V + 1] - p0;
     const double H = t_top - kp.tau[V];
@@ -497,21 +579,28 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp, int64_t f
     __syncthreads();
     if (tid == 0) kp.tau[V] = t_top;
     __syncthreads();
-    if constexpr (DAG) dag_release(kp, (int)t, tid);
+    sched.done(kp, t, tid);
   }
 }
 
 template <int D, int P, typename T, int NTMAX, int WPE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
-  tent_mfma_body<D, P, T, NTMAX>(kp, first, count, blockIdx.x, gridDim.x);
+  tent_mfma_body<D, P, T, NTMAX>(kp, SchedRange{&kp, first, count, (int64_t)blockIdx.x, (int64_t)gridDim.x});
 }
 
 // Persistent entry point: every tent of the slab, in DAG order, by kp.dag_grid workgroups.
 template <int D, int P, typename T, int NTMAX, int WPE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_dag_kernel(KernelParams kp) {
-  tent_mfma_body<D, P, T, NTMAX, true>(kp, 0, kp.dag_n, 0, 1);
+  tent_mfma_body<D, P, T, NTMAX>(kp, SchedDag{&kp});
+}
+
+// Persistent entry point of a batch: every tent of every solver's slab, in DAG order.
+template <int D, int P, typename T, int NTMAX, int WPE>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+tent_mfma_batch_dag_kernel(const KernelParams* kps, BatchDag bd) {
+  tent_mfma_body<D, P, T, NTMAX>(kps[0], SchedBatchDag{kps, bd, 0});
 }
 
 // Batched entry point: workgroup b runs tent b - seg.block0 of segment seg, i.e. of the
@@ -526,7 +615,8 @@ tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) 
     if (segs[mid].block0 <= b) lo = mid; else hi = mid - 1;
   }
   const BatchSeg sg = segs[lo];
-  tent_mfma_body<D, P, T, NTMAX>(kps[sg.solver], sg.first, sg.count, b - sg.block0, (int64_t)1 << 62);
+  tent_mfma_body<D, P, T, NTMAX>(kps[sg.solver],
+                                 SchedRange{&kps[sg.solver], sg.first, sg.count, b - sg.block0, (int64_t)1 << 62});
 }
 
 template <int D, int P, typename T, int NTMAX>
@@ -542,54 +632,71 @@ hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStr
   return hipGetLastError();
 }
 
-// grid < 0 (kp.dag_grid): set the LDS attribute; grid == 0: report the resident grid in
-// *resident; otherwise launch.
+// Workgroups of a persistent kernel that are resident at once on the device (also sets the
+// kernel's dynamic LDS attribute).
+hipError_t resident_grid(const void* kfn, int block, size_t lds, int* resident) {
+  hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0, dev = 0, cus = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, block, lds)) != hipSuccess) return e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  *resident = per_cu * cus;
+  return hipSuccess;
+}
+
+// Persistent launches.  resident != null: only report the resident grid (and set the
+// LDS attribute, outside graph capture); otherwise launch the stated grid.
+struct PersistentArgs {
+  const KernelParams* kp;    // single solve (by value in the launch)
+  const KernelParams* kps;   // batch: device array
+  const BatchDag* bd;
+};
+
 template <int D, int P, typename T, int NTMAX>
-hipError_t launch_md(const KernelParams& kp, hipStream_t s, int* resident) {
+hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
-  auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
-  if (resident) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    int per_cu = 0, dev = 0, cus = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kfn),
-                                                     MShape<D, P, NTMAX>::BLOCK, lds);
-    if (e != hipSuccess) return e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    *resident = per_cu * cus;
-    return hipSuccess;
+  constexpr int BLOCK = MShape<D, P, NTMAX>::BLOCK;
+  if (a.bd) {
+    auto kfn = tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2>;
+    if (resident) return resident_grid(reinterpret_cast<const void*>(kfn), BLOCK, lds, resident);
+    if (a.bd->n <= 0) return hipSuccess;
+    if (a.bd->grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kfn, dim3((unsigned)a.bd->grid), dim3(BLOCK), lds, s, a.kps, *a.bd);
+    return hipGetLastError();
   }
-  if (kp.dag_grid <= 0 || kp.dag_n <= 0) return kp.dag_n <= 0 ? hipSuccess : hipErrorInvalidValue;
-  hipLaunchKernelGGL(kfn, dim3((unsigned)kp.dag_grid), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp);
+  auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
+  if (resident) return resident_grid(reinterpret_cast<const void*>(kfn), BLOCK, lds, resident);
+  if (a.kp->dag_n <= 0) return hipSuccess;
+  if (a.kp->dag_grid <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kfn, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds, s, *a.kp);
   return hipGetLastError();
 }
 
 template <int D, int P, typename T>
-hipError_t launch_mdp(const KernelParams& kp, hipStream_t s, int* resident) {
-  if (kp.max_patch <= 8) return launch_md<D, P, T, 8>(kp, s, resident);
-  if (kp.max_patch <= 24) return launch_md<D, P, T, 24>(kp, s, resident);
-  if (kp.max_patch <= 48) return launch_md<D, P, T, 48>(kp, s, resident);
+hipError_t launch_mdp(const PersistentArgs& a, int max_patch, hipStream_t s, int* resident) {
+  if (max_patch <= 8) return launch_md<D, P, T, 8>(a, s, resident);
+  if (max_patch <= 24) return launch_md<D, P, T, 24>(a, s, resident);
+  if (max_patch <= 48) return launch_md<D, P, T, 48>(a, s, resident);
   return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_dt(const KernelParams& kp, hipStream_t s, int* resident) {
-  if (kp.d == 2) {
-    switch (kp.p) {
-      case 1: return launch_mdp<2, 1, T>(kp, s, resident);
-      case 2: return launch_mdp<2, 2, T>(kp, s, resident);
-      case 3: return launch_mdp<2, 3, T>(kp, s, resident);
-      case 4: return launch_mdp<2, 4, T>(kp, s, resident);
-      case 5: return launch_mdp<2, 5, T>(kp, s, resident);
+hipError_t launch_dt(const PersistentArgs& a, int d, int p, int max_patch, hipStream_t s, int* resident) {
+  if (d == 2) {
+    switch (p) {
+      case 1: return launch_mdp<2, 1, T>(a, max_patch, s, resident);
+      case 2: return launch_mdp<2, 2, T>(a, max_patch, s, resident);
+      case 3: return launch_mdp<2, 3, T>(a, max_patch, s, resident);
+      case 4: return launch_mdp<2, 4, T>(a, max_patch, s, resident);
+      case 5: return launch_mdp<2, 5, T>(a, max_patch, s, resident);
     }
   } else {
-    switch (kp.p) {
-      case 1: return launch_mdp<3, 1, T>(kp, s, resident);
-      case 2: return launch_mdp<3, 2, T>(kp, s, resident);
-      case 3: return launch_mdp<3, 3, T>(kp, s, resident);
-      case 4: return launch_mdp<3, 4, T>(kp, s, resident);
+    switch (p) {
+      case 1: return launch_mdp<3, 1, T>(a, max_patch, s, resident);
+      case 2: return launch_mdp<3, 2, T>(a, max_patch, s, resident);
+      case 3: return launch_mdp<3, 3, T>(a, max_patch, s, resident);
+      case 4: return launch_mdp<3, 4, T>(a, max_patch, s, resident);
     }
   }
   return hipErrorInvalidValue;
@@ -699,12 +806,31 @@ size_t lds_t(int d, int p, int max_patch) {
 }  // namespace
 
 hipError_t launch_tent_dag_mfma(const KernelParams& kp, int fp32, hipStream_t s) {
-  return fp32 ? launch_dt<float>(kp, s, nullptr) : launch_dt<double>(kp, s, nullptr);
+  const PersistentArgs a{&kp, nullptr, nullptr};
+  return fp32 ? launch_dt<float>(a, kp.d, kp.p, kp.max_patch, s, nullptr)
+              : launch_dt<double>(a, kp.d, kp.p, kp.max_patch, s, nullptr);
 }
 
 int tent_dag_grid(const KernelParams& kp, int fp32) {
   int resident = 0;
-  const hipError_t e = fp32 ? launch_dt<float>(kp, nullptr, &resident) : launch_dt<double>(kp, nullptr, &resident);
+  const PersistentArgs a{&kp, nullptr, nullptr};
+  const hipError_t e = fp32 ? launch_dt<float>(a, kp.d, kp.p, kp.max_patch, nullptr, &resident)
+                            : launch_dt<double>(a, kp.d, kp.p, kp.max_patch, nullptr, &resident);
+  return e == hipSuccess ? resident : 0;
+}
+
+hipError_t launch_tent_batch_dag_mfma(const KernelParams* kps, const BatchDag& bd, int d, int p, int max_patch,
+                                      int fp32, hipStream_t s) {
+  const PersistentArgs a{nullptr, kps, &bd};
+  return fp32 ? launch_dt<float>(a, d, p, max_patch, s, nullptr) : launch_dt<double>(a, d, p, max_patch, s, nullptr);
+}
+
+int tent_batch_dag_grid(int d, int p, int max_patch, int fp32) {
+  int resident = 0;
+  BatchDag bd{};
+  const PersistentArgs a{nullptr, nullptr, &bd};
+  const hipError_t e = fp32 ? launch_dt<float>(a, d, p, max_patch, nullptr, &resident)
+                            : launch_dt<double>(a, d, p, max_patch, nullptr, &resident);
   return e == hipSuccess ? resident : 0;
 }
 

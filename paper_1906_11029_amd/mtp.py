@@ -67,6 +67,7 @@ def load():
         "mtp_batch_create": [P, i32, P, sz, P, pp],
         "mtp_batch_advance": [P, i64],
         "mtp_batch_set_graph": [P, i32],
+        "mtp_batch_set_schedule": [P, i32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -282,6 +283,10 @@ def mtp_batch_set_graph(batch, on):
     _check(load().mtp_batch_set_graph(batch, int(on)))
 
 
+def mtp_batch_set_schedule(batch, schedule):
+    _check(load().mtp_batch_set_schedule(batch, int(schedule)))
+
+
 def mtp_batch_destroy(batch):
     load().mtp_batch_destroy(batch)
 
@@ -399,6 +404,9 @@ class Batch:
 
     def set_graph(self, on):
         mtp_batch_set_graph(self.h, int(bool(on)))
+
+    def set_schedule(self, schedule):
+        mtp_batch_set_schedule(self.h, schedule)
 
     def __del__(self):
         if getattr(self, "h", None):
