@@ -79,6 +79,13 @@ enum { MTP_FP64 = 0, MTP_MIXED_FP32 = 1, MTP_FP64_VALU = 2 };
  *                        (see mtp_tents_dag), with no barrier between layers        */
 enum { MTP_SCHEDULE_LAYERS = 0, MTP_SCHEDULE_DAG = 1 };
 
+/* time stepping inside a tent (section 4)
+ *   MTP_METHOD_SAT  the structure-aware Taylor recursion with q stages (default)
+ *   MTP_METHOD_RK4  classical RK4 on dY/dth = A M(th)^{-1} Y + boundary data, m steps per
+ *                   tent: the naive approach the paper contrasts with SAT, which loses
+ *                   the order of the time stepping (for comparison studies)      */
+enum { MTP_METHOD_SAT = 0, MTP_METHOD_RK4 = 1 };
+
 /* Conforming simplicial mesh (section 2).  dim = 2 (triangles, TE fields) or 3 (tets).
  * coords (nv*dim), cells (ne*(dim+1)), eps/mu (ne) per-element material constants,
  * face_bc (ne*(dim+1)) boundary kind per local face, read only where the face lies on the
@@ -212,6 +219,14 @@ mtp_status mtp_tents_dag(mtp_mesh mesh, mtp_tents tents, int32_t* pred_count, in
  * Errors: MTP_ERR_ARG, MTP_ERR_STATE (half-done slab), MTP_ERR_UNSUPPORTED (vector-ALU
  * kernel, or the kernel cannot be resident). */
 mtp_status mtp_solver_set_schedule(mtp_solver solver, int32_t schedule);
+
+/* Time stepping of the solver's tents (MTP_METHOD_SAT by default).  MTP_METHOD_RK4 runs
+ * four evaluations of the mapped right-hand side per sub-interval, each with the
+ * closed-form pointwise inverse K(b(th))^{-1} at its own time th; q is then unused and
+ * mtp_slab_dof_updates / mtp_slab_flops count 4 stages.  Errors: MTP_ERR_ARG,
+ * MTP_ERR_STATE (half-done slab), MTP_ERR_UNSUPPORTED (RK4 needs the FP64 matrix-core
+ * kernel, i.e. precision MTP_FP64 with the patch fitting it). */
+mtp_status mtp_solver_set_method(mtp_solver solver, int32_t method);
 
 /* Bound (seconds, default 10) on any single wait of the persistent schedule for a tent to
  * be released.  A wait that exceeds it aborts the slab: every workgroup leaves, and the

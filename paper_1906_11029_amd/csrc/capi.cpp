@@ -175,6 +175,7 @@ struct mtp_solver_s {
   bool has_data_faces = false;
   int kernel = 0;            // 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32
   int schedule = MTP_SCHEDULE_LAYERS;
+  int method = MTP_METHOD_SAT;
   // one slab (slab begin, every layer or the persistent DAG launch, slab end) captured once
   // and replayed per slab
   bool use_graph = true;
@@ -628,7 +629,8 @@ mtp_status mtp_slab_dof_updates(mtp_solver s, double* dof_updates, int64_t* n_te
   const Mesh& M = s->mesh;
   double tot = 0.0;
   for (int32_t v : s->tents.vertex) tot += (double)(M.v2e_ptr[v + 1] - M.v2e_ptr[v]);
-  if (dof_updates) *dof_updates = tot * s->nc * s->ref.np * s->m * s->q;
+  const int stages = s->method == MTP_METHOD_RK4 ? 4 : s->q;
+  if (dof_updates) *dof_updates = tot * s->nc * s->ref.np * s->m * stages;
   if (n_tents) *n_tents = (int64_t)s->tents.vertex.size();
   MTP_CATCH
 }
@@ -642,6 +644,7 @@ static void batch_check(const mtp_solver* solvers, int32_t n) {
     require(s->kernel == 1 || s->kernel == 2, MTP_ERR_UNSUPPORTED, "batches need the matrix-core kernels");
     require(s->kernel == solvers[0]->kernel && s->mesh.d == solvers[0]->mesh.d && s->p == solvers[0]->p,
             MTP_ERR_UNSUPPORTED, "a batch needs one dimension, degree and precision");
+    require(s->method == MTP_METHOD_SAT, MTP_ERR_UNSUPPORTED, "batches run SAT only");
     for (int j = 0; j < i; ++j) require(solvers[j] != s, MTP_ERR_ARG, "solver listed twice");
   }
 }
@@ -883,6 +886,22 @@ mtp_status mtp_solver_set_schedule(mtp_solver s, int32_t schedule) {
   MTP_CATCH
 }
 
+mtp_status mtp_solver_set_method(mtp_solver s, int32_t method) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  require(method == MTP_METHOD_SAT || method == MTP_METHOD_RK4, MTP_ERR_ARG, "unknown method");
+  require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  if (method == MTP_METHOD_RK4)
+    require(s->kernel == 1, MTP_ERR_UNSUPPORTED, "the RK4 variant runs on the FP64 matrix-core kernel only");
+  if (method != s->method) {
+    check_hip(hipStreamSynchronize(s->stream), "sync");
+    drop_graph(s);   // the captured launches hold the old parameter block
+    s->method = method;
+    s->kp.method = method;
+  }
+  MTP_CATCH
+}
+
 mtp_status mtp_solver_set_dag_wait(mtp_solver s, double seconds) {
   MTP_TRY
   require(s, MTP_ERR_ARG, "null solver");
@@ -941,7 +960,8 @@ mtp_status mtp_slab_flops(mtp_solver s, double* flops) {
   const double tay = 2.0 * nc * np;
   double elem_tents = 0.0;
   for (int32_t v : s->tents.vertex) elem_tents += (double)(M.v2e_ptr[v + 1] - M.v2e_ptr[v]);
-  *flops = elem_tents * s->m * s->q * (vol + lift + adir + flx + kin + tay);
+  const int stages = s->method == MTP_METHOD_RK4 ? 4 : s->q;
+  *flops = elem_tents * s->m * stages * (vol + lift + adir + flx + kin + tay);
   MTP_CATCH
 }
 

@@ -54,6 +54,9 @@ struct KernelParams {
   int32_t* dag_ctl;
   int32_t dag_n, dag_nready, dag_grid;
   int64_t dag_wait_ticks;  // bound of any wait for a ready tent, in wall-clock ticks
+  // time stepping inside a tent: 0 = SAT (q stages), 1 = classical RK4 on W (the naive
+  // variant; FP64 matrix-core kernel only)
+  int method;
   // plane-wave boundary data
   int has_data;
   double pw_amp[6], pw_k[3], pw_omega, pw_phase;

@@ -17,7 +17,9 @@
 // v_mfma_f32_16x16x4f32; the closed-form inverses, fluxes and the Taylor sum stay FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 #include "tent_common.h"
@@ -348,7 +350,8 @@ struct SchedBatchDag {   // the tent DAGs of a batch of solvers, one queue of gl
 // T = double: every product in FP64.  T = float (mixed): the first stage of every
 // sub-interval, whose U_{i,0} has the full size of the fields, stays FP64; the later
 // stages act on the small Taylor coefficients U_{i,n}, n >= 1, and run on the FP32 cores.
-template <int D, int P, typename T, int NTMAX, class Sched>
+// RK4: the classical RK4 variant instead of SAT (FP64 only).
+template <int D, int P, typename T, int NTMAX, class Sched, bool RK4 = false>
 __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sched) {
   using SH = MShape<D, P, NTMAX>;
   constexpr bool MIXED = sizeof(T) == 4;
@@ -461,54 +464,105 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
     }
     __syncthreads();
 
+    // ---- face fluxes for stage input U at sub-interval time th (data ghosts: derivative
+    //      n - 1 of the boundary data)
+    auto face_fluxes = [&](double th, int n) {
+      // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col], each face once:
+      //      the other side of an interior face gets -(|grad lambda_jn| / |grad lambda_j|) G
+      //      at its own face-node order (exchanged when the two orders differ)
+      for (int it = tid; it < nFace * NF; it += BLOCK) {
+        const int fi = it / NF;
+        const int s = it - fi * NF;
+        const int fc = kp.pface[f0 + fi];
+        const int e = fc >> 2, j = fc & 3;
+        const int nin = sFn[(j * 2) * NF + s];
+        double um[NC], up[NC], G[NC], g[D];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) um[c] = sU[nin * RS + e * NC + c];
+#pragma unroll
+        for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
+        const int code = sF[e * D + j];
+        if (code >= 0) {
+          const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
+          const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
+          flux<D>(g, kp.alpha, um, up, G);
+          double gg = 0.0, gn = 0.0;
+#pragma unroll
+          for (int x = 0; x < D; ++x) {
+            gg += g[x] * g[x];
+            const double h = sGL[(pe * NV + jn) * D + x];
+            gn += h * h;
+          }
+          const double ratio = -sqrt(gn / gg);
+          const int s2 = o ? kp.fswap[s] : s;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            sFR[(j * NF + s) * RS + e * NC + c] = G[c];
+            sFR[((jn - 1) * NF + s2) * RS + pe * NC + c] = ratio * G[c];
+          }
+        } else {
+          ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
+          flux<D>(g, kp.alpha, um, up, G);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
+        }
+      }
+      __syncthreads();
+    };
+
+    if constexpr (RK4) {
+      // classical RK4 on dW/dth = H R(K(b(th))^{-1} W) + data source, the naive variant the
+      // paper contrasts with SAT: four evaluations per sub-interval, each with the pointwise
+      // inverse at its own time; FP64 step-start state (acc) and stage sum (ks)
+      double ks[MAXPAIR][NC];
+      for (int i = 0; i < kp.m; ++i) {
+        for (int s = 0; s < 4; ++s) {
+          const double th = (i + (s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5))) * invm;
+          face_fluxes(th, 1);
+          tile_product<double, D, P, NTMAX>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          const double thn = (s == 3) ? (i + 1) * invm : (i + (s == 2 ? 1.0 : 0.5)) * invm;
+          const double a = (s == 2) ? invm : 0.5 * invm;   // weight of k_s in the next stage input
+          const double wk = (s == 0 || s == 3) ? 1.0 : 2.0;
+#pragma unroll
+          for (int r = 0; r < MAXPAIR; ++r) {
+            const int P_ = tid + r * BLOCK;
+            if (P_ < npairs) {
+              const int e = P_ / NP, b = P_ - e * NP;
+              double wst[NC];
+#pragma unroll
+              for (int c = 0; c < NC; ++c) {
+                const double k = H * sFR[b * RS + e * NC + c];
+                ks[r][c] = (s == 0) ? k : fma(wk, k, ks[r][c]);
+                if (s < 3) {
+                  wst[c] = fma(a, k, acc[r][c]);
+                } else {
+                  acc[r][c] = fma(invm / 6.0, ks[r][c], acc[r][c]);
+                  wst[c] = acc[r][c];
+                }
+              }
+              if (s < 3 || i + 1 < kp.m) {
+                const double* gv = &sGL[(e * NV + 0) * D];
+                double bi[D], un[NC];
+#pragma unroll
+                for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + thn * H * gv[x];
+                ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], wst, un);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = un[c];
+              }
+            }
+          }
+          __syncthreads();
+        }
+      }
+    } else
     for (int i = 0; i < kp.m; ++i) {
       const double th = i * invm;
       double coef = 1.0;
       for (int n = 1; n <= kp.q; ++n) {
         coef *= invm / n;
-        // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col], each face once:
-        //      the other side of an interior face gets -(|grad lambda_jn| / |grad lambda_j|) G
-        //      at its own face-node order (exchanged when the two orders differ)
-        for (int it = tid; it < nFace * NF; it += BLOCK) {
-          const int fi = it / NF;
-          const int s = it - fi * NF;
-          const int fc = kp.pface[f0 + fi];
-          const int e = fc >> 2, j = fc & 3;
-          const int nin = sFn[(j * 2) * NF + s];
-          double um[NC], up[NC], G[NC], g[D];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) um[c] = sU[nin * RS + e * NC + c];
-#pragma unroll
-          for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
-          const int code = sF[e * D + j];
-          if (code >= 0) {
-            const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
-            const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
-            flux<D>(g, kp.alpha, um, up, G);
-            double gg = 0.0, gn = 0.0;
-#pragma unroll
-            for (int x = 0; x < D; ++x) {
-              gg += g[x] * g[x];
-              const double h = sGL[(pe * NV + jn) * D + x];
-              gn += h * h;
-            }
-            const double ratio = -sqrt(gn / gg);
-            const int s2 = o ? kp.fswap[s] : s;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              sFR[(j * NF + s) * RS + e * NC + c] = G[c];
-              sFR[((jn - 1) * NF + s2) * RS + pe * NC + c] = ratio * G[c];
-            }
-          } else {
-            ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
-            flux<D>(g, kp.alpha, um, up, G);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
-          }
-        }
-        __syncthreads();
+        face_fluxes(th, n);
 
         // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
         if (MIXED && n >= 2)
@@ -583,17 +637,18 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   }
 }
 
-template <int D, int P, typename T, int NTMAX, int WPE>
+template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
-  tent_mfma_body<D, P, T, NTMAX>(kp, SchedRange{&kp, first, count, (int64_t)blockIdx.x, (int64_t)gridDim.x});
+  tent_mfma_body<D, P, T, NTMAX, SchedRange, RK4>(
+      kp, SchedRange{&kp, first, count, (int64_t)blockIdx.x, (int64_t)gridDim.x});
 }
 
 // Persistent entry point: every tent of the slab, in DAG order, by kp.dag_grid workgroups.
-template <int D, int P, typename T, int NTMAX, int WPE>
+template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_dag_kernel(KernelParams kp) {
-  tent_mfma_body<D, P, T, NTMAX>(kp, SchedDag{&kp});
+  tent_mfma_body<D, P, T, NTMAX, SchedDag, RK4>(kp, SchedDag{&kp});
 }
 
 // Persistent entry point of a batch: every tent of every solver's slab, in DAG order.
@@ -624,11 +679,21 @@ hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStr
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
   constexpr int WPE = 2;   // 8 waves per workgroup, one workgroup per CU
   auto kfn = tent_mfma_kernel<D, P, T, NTMAX, WPE>;
+  auto kfn_rk4 = tent_mfma_kernel<D, P, double, NTMAX, WPE, true>;
   if (count < 0) {   // prepare: allow the dynamic LDS size (done once, outside graph capture)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess && sizeof(T) == 8)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn_rk4), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    return e;
   }
-  hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
+  if (kp.method == 1) {
+    if (sizeof(T) != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
+  } else {
+    hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
+  }
   return hipGetLastError();
 }
 
@@ -666,10 +731,24 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
     return hipGetLastError();
   }
   auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
-  if (resident) return resident_grid(reinterpret_cast<const void*>(kfn), BLOCK, lds, resident);
+  auto kfn_rk4 = tent_mfma_dag_kernel<D, P, double, NTMAX, 2, true>;
+  if (resident) {   // the smaller residency of the SAT and (FP64) RK4 variants
+    hipError_t e = resident_grid(reinterpret_cast<const void*>(kfn), BLOCK, lds, resident);
+    if (e == hipSuccess && sizeof(T) == 8) {
+      int r2 = 0;
+      e = resident_grid(reinterpret_cast<const void*>(kfn_rk4), BLOCK, lds, &r2);
+      *resident = std::min(*resident, r2);
+    }
+    return e;
+  }
   if (a.kp->dag_n <= 0) return hipSuccess;
   if (a.kp->dag_grid <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kfn, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds, s, *a.kp);
+  if (a.kp->method == 1) {
+    if (sizeof(T) != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds, s, *a.kp);
+  } else {
+    hipLaunchKernelGGL(kfn, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds, s, *a.kp);
+  }
   return hipGetLastError();
 }
 

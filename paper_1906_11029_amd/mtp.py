@@ -17,6 +17,7 @@ MTP_OK = 0
 MTP_BC_PEC, MTP_BC_PMC, MTP_BC_DATA = 0, 1, 2
 MTP_FP64, MTP_MIXED_FP32, MTP_FP64_VALU = 0, 1, 2
 MTP_SCHEDULE_LAYERS, MTP_SCHEDULE_DAG = 0, 1
+MTP_METHOD_SAT, MTP_METHOD_RK4 = 0, 1
 
 _lib = None
 
@@ -60,6 +61,7 @@ def load():
         "mtp_solver_kernel": [P, P],
         "mtp_solver_set_graph": [P, i32],
         "mtp_solver_set_schedule": [P, i32],
+        "mtp_solver_set_method": [P, i32],
         "mtp_solver_set_dag_wait": [P, dbl],
         "mtp_tents_dag_size": [P, P, P],
         "mtp_tents_dag": [P, P, P, P, P, P],
@@ -247,6 +249,10 @@ def mtp_solver_set_schedule(solver, schedule):
     _check(load().mtp_solver_set_schedule(solver, int(schedule)))
 
 
+def mtp_solver_set_method(solver, method):
+    _check(load().mtp_solver_set_method(solver, int(method)))
+
+
 def mtp_solver_set_dag_wait(solver, seconds):
     _check(load().mtp_solver_set_dag_wait(solver, float(seconds)))
 
@@ -381,6 +387,9 @@ class Solver:
 
     def set_dag_wait(self, seconds):
         mtp_solver_set_dag_wait(self.h, seconds)
+
+    def set_method(self, method):
+        mtp_solver_set_method(self.h, method)
 
     def __del__(self):
         if getattr(self, "h", None):

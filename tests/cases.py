@@ -27,6 +27,15 @@ CASES = {
     "te_pmc_p2_two_slabs": dict(mesh=("square_pi", 4), p=2, q=3, m=4, T=0.25, kind=PMC, exact="pmc_te", slabs=2),
 }
 
+# the classical RK4 variant (method="rk4"): same inputs, RK4 on the tent ODE
+RK4_CASES = {
+    "te_planewave_p2_rk4": dict(mesh=("square", 8), p=2, q=3, m=4, T=0.5, kind=DATA, exact="pw_te", method="rk4"),
+    "te_pmc_p3_rk4": dict(mesh=("square_pi", 4), p=3, q=4, m=6, T=0.5, kind=PMC, exact="pmc_te", method="rk4"),
+    "cav3d_p2_rk4": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.25, kind=PEC, exact="pec_3d", method="rk4"),
+    "te_pec_p2_eps_rk4": dict(mesh=("square", 5), p=2, q=3, m=4, T=0.4, kind=PEC, exact="pec_te", eps_split=True,
+                              method="rk4"),
+}
+
 
 def build_mesh(spec):
     kind, n = spec
@@ -65,7 +74,8 @@ def planewave_params(ex, dim):
 
 
 def setup(name):
-    c = dict(CASES[name])
+    c = dict(CASES[name] if name in CASES else RK4_CASES[name])
+    c.setdefault("method", "sat")
     c.setdefault("alpha", 0.5)
     c.setdefault("slabs", 1)
     c.setdefault("eps_split", False)

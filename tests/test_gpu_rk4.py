@@ -1,0 +1,94 @@
+"""GPU checks of the classical RK4 variant (the naive time stepping of the mapped system
+that the paper contrasts with SAT, section 4): element-by-element parity with the
+oracle's RK4 on the same tents (relative L2 <= 1e-10, FP64), both schedules; and, at
+sizes the oracle would take long for, the order loss itself: on the 2D PMC cavity at
+P4, SAT keeps the h-convergence rate p + 1 while RK4 falls clearly behind."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+from cases import DATA, RK4_CASES, planewave_params, setup  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def fixture(name):
+    path = os.path.join(HERE, "golden", f"oracle_{name}.npz")
+    if os.path.exists(path):
+        return np.load(path)
+    pytest.skip(f"missing oracle fixture {path}")
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("name", list(RK4_CASES))
+def test_rk4_parity_against_oracle(name, schedule):
+    from paper_1906_11029_amd import mtp
+    print(f"[gpu rk4] {name} schedule {schedule}", flush=True)
+    ref = fixture(name)
+    c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc)
+    T = mtp.Tents(M, c["T"], 0.5)
+    S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"])
+    S.set_method(mtp.MTP_METHOD_RK4)
+    S.set_schedule(schedule)
+    S.set_fields(u0, 0.0)
+    if c["kind"] == DATA:
+        S.set_planewave_bc(*planewave_params(ex, dim))
+    S.advance_to(c["slabs"] * c["T"])
+    assert rel(S.get_state(), ref["w"]) <= TOL
+    assert rel(S.get_fields(), ref["u"]) <= TOL
+
+
+def _cavity_error(n, p, method):
+    from mtp_inputs import fields, meshes
+    from paper_1906_11029_amd import mtp
+    mm = meshes.square_tri(n, length=np.pi)
+    ex = fields.CavityTE_PMC()
+    M = mtp.Mesh(mm["coords"], mm["cells"], face_bc=meshes.uniform_bc(len(mm["cells"]), 2, meshes.PMC))
+    T = mtp.Tents(M, 0.5, 0.5)
+    S = mtp.Solver(M, T, p, p + 1, 2 * p)
+    S.set_method(method)
+    S.set_schedule(mtp.MTP_SCHEDULE_DAG)
+    nodes = meshes.equispaced_nodes(mm, p)
+    S.set_fields(ex.u(nodes, 0.0), 0.0)
+    S.advance_to(0.5)
+    return rel(S.get_fields(), ex.u(nodes, 0.5))
+
+
+def test_rk4_loses_order_at_scale():
+    from paper_1906_11029_amd import mtp
+    p, ns = 4, (8, 16, 32)
+    sat = [_cavity_error(n, p, mtp.MTP_METHOD_SAT) for n in ns]
+    rk4 = [_cavity_error(n, p, mtp.MTP_METHOD_RK4) for n in ns]
+    rs = [np.log2(sat[i] / sat[i + 1]) for i in range(2)]
+    rr = [np.log2(rk4[i] / rk4[i + 1]) for i in range(2)]
+    print(f"[gpu rk4] P{p} PMC cavity, n = {ns}: SAT errors {sat} rates {rs}; RK4 errors {rk4} rates {rr}",
+          flush=True)
+    assert min(rs) > p + 1 - 0.5
+    assert rr[-1] < rs[-1] - 1.0
+    assert rk4[-1] > 3 * sat[-1]
+
+
+def test_rk4_rejected_where_unsupported():
+    from paper_1906_11029_amd import mtp
+    c, mm, dim, eps, mu, bc, ex, u0 = setup("cav3d_p2_rk4")
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc)
+    T = mtp.Tents(M, c["T"], 0.5)
+    S = mtp.Solver(M, T, c["p"], c["q"], c["m"], precision=mtp.MTP_MIXED_FP32)
+    with pytest.raises(mtp.MTPError) as e:
+        S.set_method(mtp.MTP_METHOD_RK4)
+    assert e.value.code == -9
+    S2 = mtp.Solver(M, T, c["p"], c["q"], c["m"])
+    S2.set_method(mtp.MTP_METHOD_RK4)
+    with pytest.raises(mtp.MTPError):
+        mtp.Batch([S2])
