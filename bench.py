@@ -208,8 +208,8 @@ def main():
     achieved = head["flops_slab"] / per_slab / kern_avg / 1e12
     peak, c32 = blended_peak(head["kernel"], head["dof_slab"], head["flops_slab"], W)
     traffic = None
-    if args.workload == "graded3d_p4" and head["kernel"] in (1, 2) and args.schedule == "layers":
-        traffic = measured_traffic("mixed" if head["kernel"] == 2 else "fp64")
+    if args.workload == "graded3d_p4" and head["kernel"] in (1, 2):
+        traffic = measured_traffic(("mixed" if head["kernel"] == 2 else "fp64") + "_" + args.schedule)
 
     compare = None
     if not args.no_compare and args.precision == "mixed":
