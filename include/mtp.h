@@ -86,6 +86,15 @@ enum { MTP_SCHEDULE_LAYERS = 0, MTP_SCHEDULE_DAG = 1 };
  *                   the order of the time stepping (for comparison studies)      */
 enum { MTP_METHOD_SAT = 0, MTP_METHOD_RK4 = 1 };
 
+/* numerical flux on the faces (section 3)
+ *   MTP_FLUX_PENALTY    the printed upwind form 1/2 A(n)(u_in + u_out) + alpha P_t(u_in - u_out),
+ *                       with no material parameters (default; alpha = 1/2 is the exact
+ *                       upwind flux for unit impedance)
+ *   MTP_FLUX_IMPEDANCE  the impedance-matched upwind flux A(n) u*, u* the interface state of
+ *                       the Riemann problem between the two media (Z = sqrt(mu/eps)); equal
+ *                       to the penalty form with alpha = 1/2 where Z = 1 on both sides   */
+enum { MTP_FLUX_PENALTY = 0, MTP_FLUX_IMPEDANCE = 1 };
+
 /* Conforming simplicial mesh (section 2).  dim = 2 (triangles, TE fields) or 3 (tets).
  * coords (nv*dim), cells (ne*(dim+1)), eps/mu (ne) per-element material constants,
  * face_bc (ne*(dim+1)) boundary kind per local face, read only where the face lies on the
@@ -227,6 +236,11 @@ mtp_status mtp_solver_set_schedule(mtp_solver solver, int32_t schedule);
  * MTP_ERR_STATE (half-done slab), MTP_ERR_UNSUPPORTED (RK4 needs the FP64 matrix-core
  * kernel, i.e. precision MTP_FP64 with the patch fitting it). */
 mtp_status mtp_solver_set_method(mtp_solver solver, int32_t method);
+
+/* Numerical flux of the solver's faces (MTP_FLUX_PENALTY by default).  Walls and
+ * plane-wave data faces take the element's own medium on both sides.  Errors: MTP_ERR_ARG,
+ * MTP_ERR_STATE (half-done slab), MTP_ERR_UNSUPPORTED (vector-ALU kernel). */
+mtp_status mtp_solver_set_flux(mtp_solver solver, int32_t flux);
 
 /* Bound (seconds, default 10) on any single wait of the persistent schedule for a tent to
  * be released.  A wait that exceeds it aborts the slab: every workgroup leaves, and the

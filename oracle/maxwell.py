@@ -108,16 +108,38 @@ class System:
         fH = -cross(Em, n3) + alpha * tang(Hi - Ho)
         return self.join_EH(fE, fH)
 
-    def flux_matrices(self, n, alpha):
-        """(B_in, B_out) with flux(u_in, u_out) = B_in u_in + B_out u_out."""
+    def flux_impedance(self, u_in, u_out, n, z_in, z_out):
+        """Impedance-matched upwind flux across a material interface: the physical flux
+        f(u*) n at the interface state u* of the one-dimensional Riemann problem along n
+        (tangential E and H continuous; the wave entering each side determined by that
+        side's state alone).  With impedances Z = sqrt(mu/eps) of the two sides:
+
+            E*_t = (Z_out E_in + Z_in E_out - Z_in Z_out n x [[H]]) / (Z_in + Z_out)
+            H*_t = (Z_in H_in + Z_out H_out + n x [[E]]) / (Z_in + Z_out),
+
+        [[u]] = u_in - u_out.  For Z_in = Z_out = 1 it is the alpha = 1/2 flux above."""
+        n3 = np.zeros(3)
+        n3[: len(n)] = n
+        Ei, Hi = self.split_EH(u_in)
+        Eo, Ho = self.split_EH(u_out)
+        s = z_in + z_out
+        Es = (z_out * Ei + z_in * Eo - z_in * z_out * cross(n3, Hi - Ho)) / s
+        Hs = (z_in * Hi + z_out * Ho + cross(n3, Ei - Eo)) / s
+        return self.join_EH(cross(Hs, n3), -cross(Es, n3))
+
+    def flux_matrices(self, n, alpha, z=None):
+        """(B_in, B_out) with flux(u_in, u_out) = B_in u_in + B_out u_out; z = (Z_in, Z_out)
+        selects the impedance-matched flux."""
         Bi = np.zeros((self.nc, self.nc))
         Bo = np.zeros((self.nc, self.nc))
-        z = np.zeros(self.nc)
+        zero = np.zeros(self.nc)
+        f = (lambda a, b: self.flux(a, b, n, alpha)) if z is None else \
+            (lambda a, b: self.flux_impedance(a, b, n, z[0], z[1]))
         for c in range(self.nc):
             e = np.zeros(self.nc)
             e[c] = 1.0
-            Bi[:, c] = self.flux(e, z, n, alpha)
-            Bo[:, c] = self.flux(z, e, n, alpha)
+            Bi[:, c] = f(e, zero)
+            Bo[:, c] = f(zero, e)
         return Bi, Bo
 
     def ghost_matrix(self, kind):

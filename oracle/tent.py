@@ -41,8 +41,9 @@ PEC, PMC, DATA = 0, 1, 2
 
 
 class TentDG:
-    def __init__(self, mesh, p, alpha=0.5, data=None):
+    def __init__(self, mesh, p, alpha=0.5, data=None, flux="penalty"):
         self.mesh, self.p, self.alpha = mesh, p, alpha
+        self.flux_kind = flux   # "penalty" (alpha-weighted, as printed) or "impedance"
         self.d = mesh.d
         self.sys = System(mesh.d)
         self.nc = self.sys.nc
@@ -147,10 +148,14 @@ class TentDG:
                 if f == k:
                     continue  # the face opposite V lies on the patch boundary: delta = 0
                 fc = self.face(e, f, k)
-                if "B" not in fc:
-                    fc["B"] = sys.flux_matrices(fc["n"], self.alpha)
-                Bi, Bo = fc["B"]
                 nb = m.nbr[e, f]
+                if "B" not in fc:
+                    z = None
+                    if self.flux_kind == "impedance":   # walls and data: the element's own medium
+                        o = nb if nb >= 0 else e
+                        z = (np.sqrt(m.mu[e] / m.eps[e]), np.sqrt(m.mu[o] / m.eps[o]))
+                    fc["B"] = sys.flux_matrices(fc["n"], self.alpha, z)
+                Bi, Bo = fc["B"]
                 if nb >= 0:
                     j = pos[int(nb)]
                     T["A"][(i, i)] = T["A"][(i, i)] - np.kron(Bi, H * fc["Fself"])

@@ -902,6 +902,21 @@ mtp_status mtp_solver_set_method(mtp_solver s, int32_t method) {
   MTP_CATCH
 }
 
+mtp_status mtp_solver_set_flux(mtp_solver s, int32_t flux) {
+  MTP_TRY
+  require(s, MTP_ERR_ARG, "null solver");
+  require(flux == MTP_FLUX_PENALTY || flux == MTP_FLUX_IMPEDANCE, MTP_ERR_ARG, "unknown flux");
+  require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  if (flux == MTP_FLUX_IMPEDANCE)
+    require(s->kernel != 0, MTP_ERR_UNSUPPORTED, "the impedance-matched flux runs on the matrix-core kernels");
+  if (flux != s->kp.flux_kind) {
+    check_hip(hipStreamSynchronize(s->stream), "sync");
+    drop_graph(s);   // the captured launches hold the old parameter block
+    s->kp.flux_kind = flux;
+  }
+  MTP_CATCH
+}
+
 mtp_status mtp_solver_set_dag_wait(mtp_solver s, double seconds) {
   MTP_TRY
   require(s, MTP_ERR_ARG, "null solver");

@@ -57,6 +57,8 @@ struct KernelParams {
   // time stepping inside a tent: 0 = SAT (q stages), 1 = classical RK4 on W (the naive
   // variant; FP64 matrix-core kernel only)
   int method;
+  // face flux: 0 = the alpha-weighted upwind flux as printed, 1 = impedance-matched
+  int flux_kind;
   // plane-wave boundary data
   int has_data;
   double pw_amp[6], pw_k[3], pw_omega, pw_phase;

@@ -113,6 +113,48 @@ __device__ __forceinline__ void flux<2>(const double* g, double alpha, const dou
   G[2] += ag * dlt[2];
 }
 
+// Impedance-matched upwind flux across a material interface: G = A(g) u* with u* the
+// interface state of the one-dimensional Riemann problem along n = g/|g| (tangential E
+// and H continuous, each side's incoming wave from its own state), impedances
+// zm = sqrt(mu/eps) of the "in" side and zp of the other:
+//   E* = (zp E_in + zm E_out - zm zp n x (H_in - H_out)) / (zm + zp)
+//   H* = (zm H_in + zp H_out + n x (E_in - E_out)) / (zm + zp)
+// (normal parts of E*, H* drop out of A(g)).  zm = zp = 1 gives the alpha = 1/2 flux.
+template <int D>
+__device__ __forceinline__ void flux_imp(const double* g, double zm, double zp, const double* um, const double* up,
+                                         double* G);
+template <>
+__device__ __forceinline__ void flux_imp<3>(const double* g, double zm, double zp, const double* um,
+                                            const double* up, double* G) {
+  const double in = 1.0 / sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  const double n[3] = {g[0] * in, g[1] * in, g[2] * in};
+  const double dE[3] = {um[0] - up[0], um[1] - up[1], um[2] - up[2]};
+  const double dH[3] = {um[3] - up[3], um[4] - up[4], um[5] - up[5]};
+  const double nxdH[3] = {n[1] * dH[2] - n[2] * dH[1], n[2] * dH[0] - n[0] * dH[2], n[0] * dH[1] - n[1] * dH[0]};
+  const double nxdE[3] = {n[1] * dE[2] - n[2] * dE[1], n[2] * dE[0] - n[0] * dE[2], n[0] * dE[1] - n[1] * dE[0]};
+  const double is = 1.0 / (zm + zp), zz = zm * zp;
+  double us[6];
+  for (int i = 0; i < 3; ++i) {
+    us[i] = (zp * um[i] + zm * up[i] - zz * nxdH[i]) * is;
+    us[3 + i] = (zm * um[3 + i] + zp * up[3 + i] + nxdE[i]) * is;
+  }
+  applyA<3>(g, us, G);
+}
+template <>
+__device__ __forceinline__ void flux_imp<2>(const double* g, double zm, double zp, const double* um,
+                                            const double* up, double* G) {
+  // TE: E in the plane, H = Hz e_z; n x (Hz e_z) = Hz (n_y, -n_x), (n x E)_z = n_x Ey - n_y Ex
+  const double in = 1.0 / sqrt(g[0] * g[0] + g[1] * g[1]);
+  const double nx = g[0] * in, ny = g[1] * in;
+  const double dHz = um[2] - up[2];
+  const double nxdE = nx * (um[1] - up[1]) - ny * (um[0] - up[0]);
+  const double is = 1.0 / (zm + zp), zz = zm * zp;
+  const double us[3] = {(zp * um[0] + zm * up[0] - zz * ny * dHz) * is,
+                        (zp * um[1] + zm * up[1] + zz * nx * dHz) * is,
+                        (zm * um[2] + zp * up[2] + nxdE) * is};
+  applyA<2>(g, us, G);
+}
+
 template <int D>
 __device__ __forceinline__ void vertex_order_dev(int k, int* order) {
   order[0] = k;

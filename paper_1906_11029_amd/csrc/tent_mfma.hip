@@ -487,7 +487,10 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
           const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
 #pragma unroll
           for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
-          flux<D>(g, kp.alpha, um, up, G);
+          if (kp.flux_kind == 1)
+            flux_imp<D>(g, sqrt(sEM[2 * e + 1] / sEM[2 * e]), sqrt(sEM[2 * pe + 1] / sEM[2 * pe]), um, up, G);
+          else
+            flux<D>(g, kp.alpha, um, up, G);
           double gg = 0.0, gn = 0.0;
 #pragma unroll
           for (int x = 0; x < D; ++x) {
@@ -504,7 +507,12 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
           }
         } else {
           ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
-          flux<D>(g, kp.alpha, um, up, G);
+          if (kp.flux_kind == 1) {   // walls and data: the element's own medium on both sides
+            const double z = sqrt(sEM[2 * e + 1] / sEM[2 * e]);
+            flux_imp<D>(g, z, z, um, up, G);
+          } else {
+            flux<D>(g, kp.alpha, um, up, G);
+          }
 #pragma unroll
           for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
         }

@@ -18,6 +18,7 @@ MTP_BC_PEC, MTP_BC_PMC, MTP_BC_DATA = 0, 1, 2
 MTP_FP64, MTP_MIXED_FP32, MTP_FP64_VALU = 0, 1, 2
 MTP_SCHEDULE_LAYERS, MTP_SCHEDULE_DAG = 0, 1
 MTP_METHOD_SAT, MTP_METHOD_RK4 = 0, 1
+MTP_FLUX_PENALTY, MTP_FLUX_IMPEDANCE = 0, 1
 
 _lib = None
 
@@ -62,6 +63,7 @@ def load():
         "mtp_solver_set_graph": [P, i32],
         "mtp_solver_set_schedule": [P, i32],
         "mtp_solver_set_method": [P, i32],
+        "mtp_solver_set_flux": [P, i32],
         "mtp_solver_set_dag_wait": [P, dbl],
         "mtp_tents_dag_size": [P, P, P],
         "mtp_tents_dag": [P, P, P, P, P, P],
@@ -253,6 +255,10 @@ def mtp_solver_set_method(solver, method):
     _check(load().mtp_solver_set_method(solver, int(method)))
 
 
+def mtp_solver_set_flux(solver, flux):
+    _check(load().mtp_solver_set_flux(solver, int(flux)))
+
+
 def mtp_solver_set_dag_wait(solver, seconds):
     _check(load().mtp_solver_set_dag_wait(solver, float(seconds)))
 
@@ -390,6 +396,9 @@ class Solver:
 
     def set_method(self, method):
         mtp_solver_set_method(self.h, method)
+
+    def set_flux(self, flux):
+        mtp_solver_set_flux(self.h, flux)
 
     def __del__(self):
         if getattr(self, "h", None):

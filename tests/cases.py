@@ -36,6 +36,17 @@ RK4_CASES = {
                               method="rk4"),
 }
 
+# the impedance-matched flux (flux="impedance") across material jumps
+IMP_CASES = {
+    "te_pec_p2_eps_imp": dict(mesh=("square", 5), p=2, q=3, m=4, T=0.4, kind=PEC, exact="pec_te", eps_split=True,
+                              flux="impedance"),
+    "cav3d_p2_pmc_eps_imp": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.2, kind=PMC, exact="pec_3d", eps_split=True,
+                                 flux="impedance"),
+    "graded3d_p3_eps_imp": dict(mesh=("kuhn_graded", 3), p=3, q=4, m=6, T=0.06, kind=PEC, exact="pulse",
+                                eps_split=True, flux="impedance"),
+    "te_planewave_p2_imp": dict(mesh=("square", 8), p=2, q=3, m=4, T=0.5, kind=DATA, exact="pw_te", flux="impedance"),
+}
+
 
 def build_mesh(spec):
     kind, n = spec
@@ -74,8 +85,9 @@ def planewave_params(ex, dim):
 
 
 def setup(name):
-    c = dict(CASES[name] if name in CASES else RK4_CASES[name])
+    c = dict(CASES.get(name) or RK4_CASES.get(name) or IMP_CASES[name])
     c.setdefault("method", "sat")
+    c.setdefault("flux", "penalty")
     c.setdefault("alpha", 0.5)
     c.setdefault("slabs", 1)
     c.setdefault("eps_split", False)

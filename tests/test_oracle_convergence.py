@@ -65,3 +65,17 @@ def test_energy_nonincreasing_pec(p):
     en = np.asarray(en)
     assert np.all(np.diff(en) <= 1e-12 * en[0])
     assert en[-1] < en[0]
+
+
+def test_energy_nonincreasing_impedance_flux_two_materials():
+    """The impedance-matched flux is dissipative across the material jump too."""
+    mm = meshes.square_tri(4)
+    eps, mu = meshes.materials_split(mm)
+    mesh = Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu,
+                face_bc=meshes.uniform_bc(len(mm["cells"]), 2, meshes.PEC))
+    tents = pitch(mesh, 0.3, sigma=0.5)
+    S = OracleSolver(mesh, 2, 3, 4, flux="impedance")
+    S.set_nodal_u(fields.CavityTE_PEC().u(meshes.equispaced_nodes(mm, 2), 0.0))
+    en = np.asarray(S.run(tents, energy_trace=True))
+    assert np.all(np.diff(en) <= 1e-12 * en[0])
+    assert en[-1] < en[0]

@@ -122,3 +122,53 @@ def test_wall_ghosts():
             assert np.allclose(np.cross(E_mean, n), 0)
         else:           # PMC: mean tangential H vanishes
             assert np.allclose(np.cross(H_mean, n), 0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_impedance_flux_is_godunov_for_unit_impedance(dim):
+    """With Z = 1 on both sides the impedance-matched flux is the alpha = 1/2 flux."""
+    sysm = System(dim)
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        n = rng.normal(size=dim)
+        n /= np.linalg.norm(n)
+        ui, uo = rng.normal(size=sysm.nc), rng.normal(size=sysm.nc)
+        assert np.allclose(sysm.flux_impedance(ui, uo, n, 1.0, 1.0), sysm.flux(ui, uo, n, 0.5), atol=1e-13)
+
+
+def _riemann_flux_by_eigenvectors(sysm, ui, uo, n, mat_in, mat_out):
+    """Interface flux of the one-dimensional Riemann problem M du/dt + A(n) du/dxi = 0
+    (xi along n) from the characteristic decomposition of each side: the waves of
+    negative speed enter the "in" medium, those of positive speed the "out" medium,
+    u*_in = u_in + sum a_k r_k, u*_out = u_out + sum b_k r_k, and the normal flux is
+    continuous, A u*_in = A u*_out."""
+    import scipy.linalg
+    A = sysm.A(n)
+
+    def eig(eps, mu):
+        lam, R = scipy.linalg.eig(A, np.diag(sysm.g_diag(eps, mu)))
+        return lam.real, R.real
+    li, Ri = eig(*mat_in)
+    lo, Ro = eig(*mat_out)
+    Rn, Rp = Ri[:, li < -1e-12], Ro[:, lo > 1e-12]
+    coef, *_ = np.linalg.lstsq(np.hstack([A @ Rn, -(A @ Rp)]), A @ (uo - ui), rcond=None)
+    ustar = ui + Rn @ coef[:Rn.shape[1]]
+    return A @ ustar
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_impedance_flux_is_the_exact_riemann_flux(dim):
+    """Against an independent construction from the generalised eigenvectors of
+    (A(n), diag(g)) on each side, for random materials, normals and states."""
+    sysm = System(dim)
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        n = rng.normal(size=dim)
+        n /= np.linalg.norm(n)
+        ui, uo = rng.normal(size=sysm.nc), rng.normal(size=sysm.nc)
+        mi, mo = rng.uniform(0.5, 3.0, size=2), rng.uniform(0.5, 3.0, size=2)
+        zi, zo = np.sqrt(mi[1] / mi[0]), np.sqrt(mo[1] / mo[0])
+        want = _riemann_flux_by_eigenvectors(sysm, ui, uo, n, mi, mo)
+        assert np.allclose(sysm.flux_impedance(ui, uo, n, zi, zo), want, atol=1e-12)
+        # both sides see the same interface state: swapping sides flips the flux
+        assert np.allclose(sysm.flux_impedance(uo, ui, -n, zo, zi), -want, atol=1e-12)

@@ -190,3 +190,13 @@ def test_brute_force_integrals_single_triangle():
             # outward normal
             mid = 0.5 * (A0 + A1)
             assert (X[f] - mid) @ fc["n"] < 0 and abs(fc["n"] @ (A1 - A0)) < 1e-14
+
+
+def test_impedance_flux_fixture_equals_godunov_fixture_for_unit_impedance():
+    """The stored oracle runs of the 2D plane wave (eps = mu = 1) with the impedance-matched
+    flux and with the alpha = 1/2 flux agree to rounding."""
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    a = np.load(os.path.join(here, "oracle_te_planewave_p2_imp.npz"))
+    b = np.load(os.path.join(here, "oracle_te_planewave_p2.npz"))
+    assert np.linalg.norm(a["w"] - b["w"]) <= 1e-12 * np.linalg.norm(b["w"])
