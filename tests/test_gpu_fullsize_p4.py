@@ -1,0 +1,86 @@
+"""Full-size checks on the benchmark workload: 32^3 x 6 Kuhn tets (196608) graded toward
+one corner, eps in {1, 2.25} split at x = 0.5, Gaussian-pulse E, P4, q = 5, m = 8, slab
+0.05.  (1) Sampled tents of a mid-slab layer against the oracle started from the GPU's
+state before that layer (FP64 <= 1e-10, mixed <= 1e-6), every element outside the layer's
+patches untouched.  (2) One whole slab in the launch configuration the benchmark times
+(persistent DAG schedule, captured slab graph) equals the per-layer launches bitwise, for
+both precisions."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+GRADE_A = 2.0 / 9.0
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _workload():
+    from mtp_inputs import fields, meshes
+    mm = meshes.cube_kuhn(32, axis_map=lambda g: GRADE_A * g + (1 - GRADE_A) * g * g)
+    eps, mu = meshes.materials_split(mm)
+    u0 = fields.GaussianPulse3D(seed=11030).u(meshes.equispaced_nodes(mm, 4), 0.0)
+    return mm, eps, mu, u0
+
+
+def _solver(mm, eps, mu, u0, precision, M=None, T=None):
+    from paper_1906_11029_amd import mtp
+    if M is None:
+        M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+        T = mtp.Tents(M, 0.05, 0.5)
+    S = mtp.Solver(M, T, 4, 5, 8, precision=precision)
+    S.set_fields(u0, 0.0)
+    return M, T, S
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+def test_full_size_p4_sampled_tents(precision, tol):
+    from oracle.mesh import Mesh as OMesh
+    from oracle.solve import OracleSolver
+    print(f"[gpu full-size P4] sampled tents, precision {precision}", flush=True)
+    mm, eps, mu, u0 = _workload()
+    M, T, S = _solver(mm, eps, mu, u0, precision)
+    L = T.n_layers // 2
+    for layer in range(L):
+        S.layer_advance(layer)
+    w_before = S.get_state()
+    S.layer_advance(L)
+    w_after = S.get_state()
+    tl = T.export()
+    tau = np.zeros(M.info["nv"])
+    sel = tl["layer"] < L
+    tau[tl["vertex"][sel]] = tl["t_top"][sel]
+    om = OMesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    O = OracleSolver(om, 4, 5, 8)
+    O.set_nodal_w(w_before)
+    O.tau[:] = tau
+    idx = np.arange(T.layer_ptr[L], T.layer_ptr[L + 1])
+    pick = np.random.default_rng(1).choice(idx, size=6, replace=False)
+    for i in pick:
+        O.run_tent(int(tl["vertex"][i]), float(tl["t_top"][i]))
+    w_or = O.nodal_w()
+    for i in pick:
+        es = om.v2e[int(tl["vertex"][i])]
+        assert rel(w_after[es], w_or[es]) <= tol
+    touched = np.unique(np.concatenate([om.v2e[int(v)] for v in tl["vertex"][idx]]))
+    mask = np.ones(len(w_after), bool)
+    mask[touched] = False
+    assert np.array_equal(w_after[mask], w_before[mask])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_p4_dag_slab_equals_layers(precision):
+    from paper_1906_11029_amd import mtp
+    print(f"[gpu full-size P4] persistent slab vs layers, precision {precision}", flush=True)
+    mm, eps, mu, u0 = _workload()
+    M, T, A = _solver(mm, eps, mu, u0, precision)
+    _, _, B = _solver(mm, eps, mu, u0, precision, M, T)
+    A.set_schedule(mtp.MTP_SCHEDULE_DAG)
+    A.advance_to(0.05)
+    B.set_graph(False)
+    for layer in range(T.n_layers):
+        B.layer_advance(layer)
+    wa, wb = A.get_state(), B.get_state()
+    assert np.all(np.isfinite(wa))
+    assert np.array_equal(wa, wb)
