@@ -62,6 +62,17 @@ enum {
 /* boundary-condition kinds of boundary faces */
 enum { MTP_BC_PEC = 0, MTP_BC_PMC = 1, MTP_BC_DATA = 2 };
 
+/* equations (the method applies to linear hyperbolic systems in conservation form
+ * d_t g(u) + div f(u) = 0; sections 1 and 3)
+ *   MTP_SYSTEM_MAXWELL   u = (E, H) (3D) or (Ex, Ey, Hz) (2D TE), g(u) = (eps E, mu H)
+ *   MTP_SYSTEM_ACOUSTIC  linear acoustics, u = (p, v), g(u) = (kappa p, rho v),
+ *                        f(u) n = (v.n, p n); the mesh's eps / mu arrays hold kappa
+ *                        (the inverse bulk modulus) and rho.  Boundary kinds: MTP_BC_PEC
+ *                        is a pressure-release wall (p = 0), MTP_BC_PMC a rigid wall
+ *                        (v.n = 0), MTP_BC_DATA a plane wave.  Matrix-core kernels, SAT,
+ *                        single solves.                                             */
+enum { MTP_SYSTEM_MAXWELL = 0, MTP_SYSTEM_ACOUSTIC = 1 };
+
 /* arithmetic of the tent kernels
  *   MTP_FP64       plain FP64; contractions on the FP64 matrix cores (falls back to the
  *                  vector-ALU kernel when a patch does not fit the matrix-core kernel)
@@ -94,6 +105,12 @@ enum { MTP_METHOD_SAT = 0, MTP_METHOD_RK4 = 1 };
  *                       the Riemann problem between the two media (Z = sqrt(mu/eps)); equal
  *                       to the penalty form with alpha = 1/2 where Z = 1 on both sides   */
 enum { MTP_FLUX_PENALTY = 0, MTP_FLUX_IMPEDANCE = 1 };
+
+/* Equations the mesh's coefficients describe (MTP_SYSTEM_MAXWELL by default); set before
+ * creating solvers (it fixes the field count nc: 6 / 3 for Maxwell, d + 1 for acoustics,
+ * and the layout of every nodal array is [element][node][component]).  Pitching is the
+ * same for both (wave speed 1/sqrt(eps mu)).  Errors: MTP_ERR_ARG. */
+mtp_status mtp_mesh_set_system(mtp_mesh mesh, int32_t system);
 
 /* Conforming simplicial mesh (section 2).  dim = 2 (triangles, TE fields) or 3 (tets).
  * coords (nv*dim), cells (ne*(dim+1)), eps/mu (ne) per-element material constants,

@@ -1,6 +1,8 @@
-"""Exact solutions and initial fields of Maxwell's equations (problem data only).
+"""Exact solutions and initial fields of Maxwell's equations and of linear acoustics
+(problem data only).
 
-Field layouts: 3D u = (Ex, Ey, Ez, Hx, Hy, Hz); 2D TE u = (Ex, Ey, Hz).
+Field layouts: Maxwell 3D u = (Ex, Ey, Ez, Hx, Hy, Hz), 2D TE u = (Ex, Ey, Hz);
+acoustics u = (p, v_1 .. v_d).
 Each exact solution is an object with
   u(x, t)        -> (..., nc) field values at points x (..., d) and time t
   dt(x, t, k)    -> k-th time derivative (plane waves only; used as boundary data)
@@ -129,3 +131,67 @@ class GaussianPulse3D:
 def nodal_fields(exact, nodes, t=0.0):
     """Nodal values u(node, t) of an exact solution, shape (ne, Np, nc)."""
     return exact.u(nodes, t)
+
+
+# ------------------------------------------------------------------ linear acoustics
+# u = (p, v):  kappa p_t + div v = 0,  rho v_t + grad p = 0  (wave speed 1/sqrt(kappa rho),
+# impedance sqrt(rho/kappa)).
+
+class AcousticPlaneWave:
+    """p = amp cos(psi), v = amp d / Z cos(psi), psi = k (d.x) - omega t + phase."""
+
+    def __init__(self, direction=(1.0, 1.0), k=2 * np.pi, amp=1.0, phase=0.0, kappa=1.0, rho=1.0):
+        dvec = np.asarray(direction, dtype=np.float64)
+        self.d = dvec / np.linalg.norm(dvec)
+        self.k, self.amp, self.phase = float(k), float(amp), float(phase)
+        self.kappa, self.rho = float(kappa), float(rho)
+        self.omega = self.k / np.sqrt(self.kappa * self.rho)
+        self.z = np.sqrt(self.rho / self.kappa)
+        self.avec = self.amp * np.concatenate([[1.0], self.d / self.z])
+
+    def dt(self, x, t, n=0):
+        x = np.asarray(x, dtype=np.float64)
+        psi = self.k * (x @ self.d) - self.omega * t + self.phase
+        s = self.omega ** n * np.cos(psi - n * np.pi / 2)
+        return s[..., None] * self.avec
+
+    def u(self, x, t):
+        return self.dt(x, t, 0)
+
+
+class AcousticCavity:
+    """Rigid-wall (v.n = 0) mode of the unit square / cube, kappa = rho = 1:
+    p = prod_i cos(pi x_i) cos(omega t),  v_i = (pi/omega) sin(pi x_i) prod_{j != i} cos(pi x_j)
+    sin(omega t),  omega = pi sqrt(d)."""
+
+    def __init__(self, dim):
+        self.dim = dim
+        self.omega = np.pi * np.sqrt(dim)
+
+    def u(self, x, t):
+        x = np.asarray(x, dtype=np.float64)
+        c, s = np.cos(np.pi * x), np.sin(np.pi * x)
+        out = np.empty(x.shape[:-1] + (self.dim + 1,))
+        out[..., 0] = np.prod(c, axis=-1) * np.cos(self.omega * t)
+        for i in range(self.dim):
+            others = np.prod(np.delete(c, i, axis=-1), axis=-1)
+            out[..., 1 + i] = np.pi / self.omega * s[..., i] * others * np.sin(self.omega * t)
+        return out
+
+
+class AcousticPulse:
+    """Gaussian pressure pulse at rest: p = exp(-|x - x0|^2 / (2 s^2)), v = 0, with x0 in
+    [0.35, 0.65]^d and s in [0.06, 0.10] drawn from the seed."""
+
+    def __init__(self, dim, seed=11031):
+        rng = np.random.default_rng(seed)
+        self.dim = dim
+        self.x0 = rng.uniform(0.35, 0.65, size=dim)
+        self.s = rng.uniform(0.06, 0.10)
+
+    def u(self, x, t=0.0):
+        x = np.asarray(x, dtype=np.float64)
+        r2 = np.sum((x - self.x0) ** 2, axis=-1)
+        out = np.zeros(x.shape[:-1] + (self.dim + 1,))
+        out[..., 0] = np.exp(-r2 / (2 * self.s ** 2))
+        return out

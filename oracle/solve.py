@@ -13,9 +13,9 @@ from .tent import TentDG
 
 
 class OracleSolver:
-    def __init__(self, mesh, p, q, m, alpha=0.5, data=None, method="sat", flux="penalty"):
+    def __init__(self, mesh, p, q, m, alpha=0.5, data=None, method="sat", flux="penalty", system="maxwell"):
         self.mesh, self.p, self.q, self.m = mesh, p, q, m
-        self.dg = TentDG(mesh, p, alpha=alpha, data=data, flux=flux)
+        self.dg = TentDG(mesh, p, alpha=alpha, data=data, flux=flux, system=system)
         self.nc, self.nb = self.dg.nc, self.dg.nb
         self.method = method
         self.tau = np.zeros(mesh.nv)

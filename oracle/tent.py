@@ -34,6 +34,7 @@ from math import factorial
 
 import numpy as np
 
+from .acoustic import AcousticSystem
 from .maxwell import System
 from .simplex import basis, quadrature, reference_nodes
 
@@ -41,11 +42,11 @@ PEC, PMC, DATA = 0, 1, 2
 
 
 class TentDG:
-    def __init__(self, mesh, p, alpha=0.5, data=None, flux="penalty"):
+    def __init__(self, mesh, p, alpha=0.5, data=None, flux="penalty", system="maxwell"):
         self.mesh, self.p, self.alpha = mesh, p, alpha
         self.flux_kind = flux   # "penalty" (alpha-weighted, as printed) or "impedance"
         self.d = mesh.d
-        self.sys = System(mesh.d)
+        self.sys = System(mesh.d) if system == "maxwell" else AcousticSystem(mesh.d)
         self.nc = self.sys.nc
         self.B = basis(self.d, p)
         self.nb = self.B.n

@@ -253,6 +253,14 @@ mtp_status mtp_mesh_create(int32_t dim, int64_t nv, const double* coords, int64_
   MTP_CATCH
 }
 
+mtp_status mtp_mesh_set_system(mtp_mesh mesh, int32_t system) {
+  MTP_TRY
+  require(mesh, MTP_ERR_ARG, "null mesh");
+  require(system == MTP_SYSTEM_MAXWELL || system == MTP_SYSTEM_ACOUSTIC, MTP_ERR_ARG, "unknown system");
+  mesh->m.system = system;
+  MTP_CATCH
+}
+
 mtp_status mtp_mesh_info(mtp_mesh mesh, int32_t* dim, int64_t* nv, int64_t* ne, int32_t* max_patch) {
   MTP_TRY
   require(mesh, MTP_ERR_ARG, "null mesh");
@@ -304,6 +312,9 @@ mtp_status mtp_tents_export(mtp_tents tents, int32_t* vertex, double* t_bot, dou
 
 void mtp_tents_destroy(mtp_tents tents) { delete tents; }
 
+// field components of the mesh's system
+static int ncomp(const Mesh& m) { return m.system == MTP_SYSTEM_ACOUSTIC ? m.d + 1 : (m.d == 3 ? 6 : 3); }
+
 // Kernel choice: 0 = vector-ALU FP64, 1 = matrix-core FP64, 2 = matrix-core FP32 (mixed).
 static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
   require(precision == MTP_FP64 || precision == MTP_MIXED_FP32 || precision == MTP_FP64_VALU,
@@ -315,6 +326,12 @@ static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
   const int np = (m.d == 2) ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
   const int block = (m.d == 2) ? 128 : 256;
   const bool valu_ok = lds_valu <= lim && m.max_patch * np <= block * 8;
+  if (m.system == MTP_SYSTEM_ACOUSTIC) {
+    require(precision != MTP_FP64_VALU, MTP_ERR_UNSUPPORTED, "acoustics runs on the matrix-core kernels");
+    require(tent_mfma_lds_bytes(m.d, p, m.max_patch, precision == MTP_MIXED_FP32, 1) <= lim, MTP_ERR_UNSUPPORTED,
+            "largest vertex patch does not fit the matrix-core kernel's LDS");
+    return precision == MTP_MIXED_FP32 ? 2 : 1;
+  }
   if (precision == MTP_MIXED_FP32) {
     require(tent_mfma_lds_bytes(m.d, p, m.max_patch, 1) <= lim, MTP_ERR_UNSUPPORTED,
             "largest vertex patch does not fit the matrix-core kernel's LDS");
@@ -331,7 +348,7 @@ mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, 
   require(mesh && tents && bytes, MTP_ERR_ARG, "null pointer");
   check_config(mesh->m, p, q, m, precision);
   RefElem R = build_refelem(mesh->m.d, p);
-  *bytes = plan(mesh->m, tents->t, R, mesh->m.d == 3 ? 6 : 3).total;
+  *bytes = plan(mesh->m, tents->t, R, ncomp(mesh->m)).total;
   MTP_CATCH
 }
 
@@ -350,7 +367,7 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     s->p = p;
     s->q = q;
     s->m = m;
-    s->nc = mesh->m.d == 3 ? 6 : 3;
+    s->nc = ncomp(mesh->m);
     s->off = plan(s->mesh, s->tents, s->ref, s->nc);
     require(bytes >= s->off.total, MTP_ERR_ARG, "workspace too small");
     s->ws = static_cast<char*>(d_workspace);
@@ -394,6 +411,7 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     kp.q = q;
     kp.m = m;
     kp.nc = s->nc;
+    kp.system = M.system;
     kp.np = s->ref.np;
     kp.nf = s->ref.nf;
     kp.alpha = alpha;
@@ -645,6 +663,7 @@ static void batch_check(const mtp_solver* solvers, int32_t n) {
     require(s->kernel == solvers[0]->kernel && s->mesh.d == solvers[0]->mesh.d && s->p == solvers[0]->p,
             MTP_ERR_UNSUPPORTED, "a batch needs one dimension, degree and precision");
     require(s->method == MTP_METHOD_SAT, MTP_ERR_UNSUPPORTED, "batches run SAT only");
+    require(s->mesh.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED, "batches run Maxwell only");
     for (int j = 0; j < i; ++j) require(solvers[j] != s, MTP_ERR_ARG, "solver listed twice");
   }
 }
@@ -892,7 +911,8 @@ mtp_status mtp_solver_set_method(mtp_solver s, int32_t method) {
   require(method == MTP_METHOD_SAT || method == MTP_METHOD_RK4, MTP_ERR_ARG, "unknown method");
   require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
   if (method == MTP_METHOD_RK4)
-    require(s->kernel == 1, MTP_ERR_UNSUPPORTED, "the RK4 variant runs on the FP64 matrix-core kernel only");
+    require(s->kernel == 1 && s->mesh.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED,
+            "the RK4 variant runs on the FP64 matrix-core kernel, Maxwell only");
   if (method != s->method) {
     check_hip(hipStreamSynchronize(s->stream), "sync");
     drop_graph(s);   // the captured launches hold the old parameter block

@@ -20,7 +20,8 @@ struct Mesh {
   int64_t nv = 0, ne = 0;
   std::vector<double> coords;    // nv*d
   std::vector<int32_t> cells;    // ne*(d+1)
-  std::vector<double> eps, mu;   // ne
+  std::vector<double> eps, mu;   // ne (acoustics: kappa, rho)
+  int system = 0;                // MTP_SYSTEM_MAXWELL or MTP_SYSTEM_ACOUSTIC
   std::vector<int32_t> face_bc;  // ne*(d+1)
   std::vector<int32_t> nbr;      // ne*(d+1): neighbour across local face j, -1 on boundary
   std::vector<int8_t> nbr_face;  // ne*(d+1): local face index of this face in the neighbour

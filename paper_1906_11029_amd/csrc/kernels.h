@@ -59,6 +59,8 @@ struct KernelParams {
   int method;
   // face flux: 0 = the alpha-weighted upwind flux as printed, 1 = impedance-matched
   int flux_kind;
+  // equations: 0 = Maxwell (E, H), 1 = linear acoustics (p, v)
+  int system;
   // plane-wave boundary data
   int has_data;
   double pw_amp[6], pw_k[3], pw_omega, pw_phase;
@@ -102,7 +104,7 @@ size_t tent_kernel_lds_bytes(int d, int p, int max_patch);
 bool tent_kernel_supported(int d, int p);
 hipError_t launch_tent_layer(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s);
 // matrix-core variant: fp32 = 0 contracts in FP64, fp32 = 1 in FP32 (mixed path)
-size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32);
+size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32, int system = 0);
 hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t count, int fp32, hipStream_t s);
 // persistent schedule: reset the DAG state for one slab, then run every tent of the slab in
 // one launch of kp.dag_grid workgroups (grid < 0: only set the kernel attributes)

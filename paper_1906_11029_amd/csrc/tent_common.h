@@ -155,6 +155,117 @@ __device__ __forceinline__ void flux_imp<2>(const double* g, double zm, double z
   applyA<2>(g, us, G);
 }
 
+// ---------------------------------------------------------------- acoustics
+// Linear acoustics kappa p_t + div v = 0, rho v_t + grad p = 0 in the same conservation form
+// d_t g(u) + div f(u) = 0: u = (p, v), g(u) = (kappa p, rho v), f(u) n = A(n) u = (v.n, p n).
+// The two per-element coefficients are (kappa, rho) in the slots of (eps, mu); the wave
+// speed is 1/sqrt(kappa rho) and the impedance Z = sqrt(rho/kappa), as for Maxwell.
+template <int D>
+__device__ __forceinline__ void applyA_ac(const double* g, const double* u, double* out) {
+  double vg = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    vg += g[i] * u[1 + i];
+    out[1 + i] = g[i] * u[0];
+  }
+  out[0] = vg;
+}
+
+// Closed-form inverse of u -> g(u) - f(u) b = (kappa p - v.b, rho v - p b):
+//   p = (rho w_p + b.w_v) / (kappa rho - |b|^2),  v = (w_v + p b) / rho.
+template <int D>
+__device__ __forceinline__ bool kinv_ac(const double* b, double kappa, double rho, const double* w, double* u) {
+  double bb = 0.0, bw = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    bb += b[i] * b[i];
+    bw += b[i] * w[1 + i];
+  }
+  const double den = kappa * rho - bb;
+  const double p = (rho * w[0] + bw) / den;
+  const double ir = 1.0 / rho;
+  u[0] = p;
+#pragma unroll
+  for (int i = 0; i < D; ++i) u[1 + i] = (w[1 + i] + p * b[i]) * ir;
+  return den > 0.0;
+}
+
+// Upwind flux times |g|:  1/2 A(g)(u_in + u_out) + alpha |g| (dp, (dv.n) n),  d = in - out
+// (alpha = 1/2: the exact upwind flux for unit impedance).
+template <int D>
+__device__ __forceinline__ void flux_ac(const double* g, double alpha, const double* um, const double* up,
+                                        double* G) {
+  double s[D + 1];
+#pragma unroll
+  for (int c = 0; c <= D; ++c) s[c] = 0.5 * (um[c] + up[c]);
+  applyA_ac<D>(g, s, G);
+  double gg = 0.0, dvg = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    gg += g[i] * g[i];
+    dvg += g[i] * (um[1 + i] - up[1 + i]);
+  }
+  const double gn = sqrt(gg);
+  G[0] += alpha * gn * (um[0] - up[0]);
+#pragma unroll
+  for (int i = 0; i < D; ++i) G[1 + i] += alpha * (dvg / gn) * g[i];
+}
+
+// Impedance-matched upwind flux: A(g) u* with the interface state of the Riemann problem
+// along n = g/|g|:  p* = (zp p_in + zm p_out + zm zp (v_in - v_out).n) / (zm + zp),
+// v*.n = (zm v_in.n + zp v_out.n + p_in - p_out) / (zm + zp).
+template <int D>
+__device__ __forceinline__ void flux_imp_ac(const double* g, double zm, double zp, const double* um,
+                                            const double* up, double* G) {
+  double gg = 0.0, vmg = 0.0, vpg = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    gg += g[i] * g[i];
+    vmg += g[i] * um[1 + i];
+    vpg += g[i] * up[1 + i];
+  }
+  const double gn = sqrt(gg), is = 1.0 / (zm + zp);
+  const double ps = (zp * um[0] + zm * up[0] + zm * zp * (vmg - vpg) / gn) * is;
+  const double vns = (zm * vmg + zp * vpg) / gn * is + (um[0] - up[0]) * is;
+  G[0] = gn * vns;
+#pragma unroll
+  for (int i = 0; i < D; ++i) G[1 + i] = ps * g[i];
+}
+
+// ---------------------------------------------------------------- physics trait
+// SYS 0: Maxwell, u = (E, H); SYS 1: acoustics, u = (p, v).  NC fields, the first NE of
+// which form the first group (E, or p: negated by a kind-0 wall, the second group by a
+// kind-1 wall); component c of A(g) u = sum over NTERM terms s g[q] u[p].
+template <int D, int SYS> struct Phys;
+template <int D> struct Phys<D, 0> {
+  static constexpr int NC = (D == 3) ? 6 : 3, NE = (D == 3) ? 3 : 2, NTERM = 2;
+  static __device__ __forceinline__ void A(const double* g, const double* u, double* o) { applyA<D>(g, u, o); }
+  static __device__ __forceinline__ bool inv(const double* b, double c1, double c2, const double* w, double* u) {
+    return kinv<D>(b, c1, c2, w, u);
+  }
+  static __device__ __forceinline__ void fl(const double* g, double a, const double* um, const double* up, double* G) {
+    flux<D>(g, a, um, up, G);
+  }
+  static __device__ __forceinline__ void fl_imp(const double* g, double zm, double zp, const double* um,
+                                                const double* up, double* G) {
+    flux_imp<D>(g, zm, zp, um, up, G);
+  }
+};
+template <int D> struct Phys<D, 1> {
+  static constexpr int NC = D + 1, NE = 1, NTERM = D;
+  static __device__ __forceinline__ void A(const double* g, const double* u, double* o) { applyA_ac<D>(g, u, o); }
+  static __device__ __forceinline__ bool inv(const double* b, double c1, double c2, const double* w, double* u) {
+    return kinv_ac<D>(b, c1, c2, w, u);
+  }
+  static __device__ __forceinline__ void fl(const double* g, double a, const double* um, const double* up, double* G) {
+    flux_ac<D>(g, a, um, up, G);
+  }
+  static __device__ __forceinline__ void fl_imp(const double* g, double zm, double zp, const double* um,
+                                                const double* up, double* G) {
+    flux_imp_ac<D>(g, zm, zp, um, up, G);
+  }
+};
+
 template <int D>
 __device__ __forceinline__ void vertex_order_dev(int k, int* order) {
   order[0] = k;
@@ -166,14 +277,15 @@ __device__ __forceinline__ void vertex_order_dev(int k, int* order) {
 
 
 
-// Ghost state on a boundary face of kind 0 (PEC mirror: E_out = -E_in, H_out = H_in),
-// 1 (PMC mirror: E_out = E_in, H_out = -H_in) or 2 (data: the plane wave
+// Ghost state on a boundary face of kind 0 (PEC mirror: E_out = -E_in, H_out = H_in;
+// acoustics: pressure release, p_out = -p_in), 1 (PMC mirror: E_out = E_in, H_out = -H_in;
+// acoustics: rigid wall, v_out = -v_in) or 2 (data: the plane wave
 // u_ex(x, phi(x, th)), whose (n-1)-th th-derivative is delta^(n-1) d_t^(n-1) u_ex with
 // delta = H lambda_V, evaluated at the face node nin of element el).
-template <int D, int P>
+template <int D, int P, int SYS = 0>
 __device__ __forceinline__ void ghost_state(const KernelParams& kp, int kind, const double* um, double* up,
                                             int el, int kloc, int nin, double H, double th, int n) {
-  constexpr int NC = (D == 3) ? 6 : 3, NV = D + 1, NE = (D == 3) ? 3 : 2;
+  constexpr int NC = Phys<D, SYS>::NC, NV = D + 1, NE = Phys<D, SYS>::NE;
   if (kind == 2 && kp.has_data) {
     int order[NV];
     vertex_order_dev<D>(kloc, order);

@@ -289,9 +289,10 @@ __global__ void __launch_bounds__(BLOCK) tent_kernel(KernelParams kp, int64_t fi
 
 // ------------------------------------------------------------------ conversions
 // set: W[e][c][node] = K(grad tau_e) u[e][node][c]   (w = g(u) - f(u) grad tau)
-template <int D>
+template <int D, int SYS>
 __global__ void set_fields_kernel(KernelParams kp, int64_t ne, const double* u) {
-  constexpr int NC = Dims<D>::NC, NV = D + 1;
+  using PH = Phys<D, SYS>;
+  constexpr int NC = PH::NC, NV = D + 1;
   const int np = kp.np;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ne * np) return;
@@ -309,18 +310,19 @@ __global__ void set_fields_kernel(KernelParams kp, int64_t ne, const double* u) 
     uu[c] = u[(e * np + a) * NC + c];
     fin &= isfinite(uu[c]);
   }
-  applyA<D>(g, uu, fu);
+  PH::A(g, uu, fu);
   const double eps = kp.eps[e], mu = kp.mu[e];
   for (int c = 0; c < NC; ++c) {
-    const double gm = (c < (D == 3 ? 3 : 2)) ? eps : mu;
+    const double gm = (c < PH::NE) ? eps : mu;
     kp.W[(e * NC + c) * np + a] = gm * uu[c] - fu[c];
   }
   if (!fin) kp.err[1] = ERRF_NONFINITE;
 }
 
-template <int D>
+template <int D, int SYS>
 __global__ void get_fields_kernel(KernelParams kp, int64_t ne, double* out, int raw) {
-  constexpr int NC = Dims<D>::NC, NV = D + 1;
+  using PH = Phys<D, SYS>;
+  constexpr int NC = PH::NC, NV = D + 1;
   const int np = kp.np;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ne * np) return;
@@ -341,7 +343,7 @@ __global__ void get_fields_kernel(KernelParams kp, int64_t ne, double* out, int 
       const double tv = kp.tau[kp.cells[e * NV + v]];
       for (int i = 0; i < D; ++i) g[i] += tv * kp.grad_lam[(e * NV + v) * D + i];
     }
-    if (!kinv<D>(g, kp.eps[e], kp.mu[e], w, u)) kp.err[0] = ERRF_CAUSALITY;
+    if (!PH::inv(g, kp.eps[e], kp.mu[e], w, u)) kp.err[0] = ERRF_CAUSALITY;
     for (int c = 0; c < NC; ++c) out[(e * np + a) * NC + c] = u[c];
   }
   if (!fin) kp.err[1] = ERRF_NONFINITE;
@@ -538,20 +540,26 @@ hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, kp.tau, nv, t0);
   const int64_t n = ne * kp.np;
   const unsigned grid = (unsigned)((n + 255) / 256);
-  if (kp.d == 2)
-    hipLaunchKernelGGL(set_fields_kernel<2>, dim3(grid), dim3(256), 0, s, kp, ne, u_nodal);
-  else
-    hipLaunchKernelGGL(set_fields_kernel<3>, dim3(grid), dim3(256), 0, s, kp, ne, u_nodal);
+  if (kp.d == 2) {
+    auto fn = kp.system ? set_fields_kernel<2, 1> : set_fields_kernel<2, 0>;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, kp, ne, u_nodal);
+  } else {
+    auto fn = kp.system ? set_fields_kernel<3, 1> : set_fields_kernel<3, 0>;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, kp, ne, u_nodal);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s) {
   const int64_t n = ne * kp.np;
   const unsigned grid = (unsigned)((n + 255) / 256);
-  if (kp.d == 2)
-    hipLaunchKernelGGL(get_fields_kernel<2>, dim3(grid), dim3(256), 0, s, kp, ne, out, raw);
-  else
-    hipLaunchKernelGGL(get_fields_kernel<3>, dim3(grid), dim3(256), 0, s, kp, ne, out, raw);
+  if (kp.d == 2) {
+    auto fn = kp.system ? get_fields_kernel<2, 1> : get_fields_kernel<2, 0>;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, kp, ne, out, raw);
+  } else {
+    auto fn = kp.system ? get_fields_kernel<3, 1> : get_fields_kernel<3, 0>;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, kp, ne, out, raw);
+  }
   return hipGetLastError();
 }
 

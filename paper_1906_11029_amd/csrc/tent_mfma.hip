@@ -49,35 +49,47 @@ template <> struct Mfma<float> {
   }
 };
 
-// component c of A(g) u = s1 g[q1] u[p1] + s2 g[q2] u[p2], from nibble tables (no branches)
-template <int D> struct ACoef;
-template <> struct ACoef<3> {
-  // g x H and -(g x E) with u = (E, H):  P1 = {4,5,3,2,0,1}, Q1 = {2,0,1,1,2,0},
+// component c of A(g) u = sum_t s[t] g[q[t]] u[p[t]] over the system's NTERM terms, from
+// nibble tables (no branches)
+template <int D, int SYS> struct ACoef;
+template <> struct ACoef<3, 0> {
+  // Maxwell, g x H and -(g x E) with u = (E, H):  P1 = {4,5,3,2,0,1}, Q1 = {2,0,1,1,2,0},
   // P2 = {5,3,4,1,2,0}, Q2 = {1,2,0,2,0,1}, s1 = +1, s2 = -1
-  static __device__ __forceinline__ void get(int c, int* p1, int* q1, double* s1, int* p2, int* q2, double* s2) {
-    *p1 = (0x102354 >> (4 * c)) & 15;
-    *q1 = (0x021102 >> (4 * c)) & 15;
-    *p2 = (0x021435 >> (4 * c)) & 15;
-    *q2 = (0x102021 >> (4 * c)) & 15;
-    *s1 = 1.0;
-    *s2 = -1.0;
+  static __device__ __forceinline__ void get(int c, int* p, int* q, double* s) {
+    p[0] = (0x102354 >> (4 * c)) & 15;
+    q[0] = (0x021102 >> (4 * c)) & 15;
+    p[1] = (0x021435 >> (4 * c)) & 15;
+    q[1] = (0x102021 >> (4 * c)) & 15;
+    s[0] = 1.0;
+    s[1] = -1.0;
   }
 };
-template <> struct ACoef<2> {
-  // (-g1 Hz, g0 Hz, g0 Ey - g1 Ex) with u = (Ex, Ey, Hz)
-  static __device__ __forceinline__ void get(int c, int* p1, int* q1, double* s1, int* p2, int* q2, double* s2) {
-    *p1 = (0x122 >> (4 * c)) & 15;
-    *q1 = (0x001 >> (4 * c)) & 15;
-    *p2 = (0x022 >> (4 * c)) & 15;
-    *q2 = (0x110 >> (4 * c)) & 15;
-    *s1 = (c == 0) ? -1.0 : 1.0;
-    *s2 = (c == 2) ? -1.0 : 0.0;
+template <> struct ACoef<2, 0> {
+  // Maxwell TE, (-g1 Hz, g0 Hz, g0 Ey - g1 Ex) with u = (Ex, Ey, Hz)
+  static __device__ __forceinline__ void get(int c, int* p, int* q, double* s) {
+    p[0] = (0x122 >> (4 * c)) & 15;
+    q[0] = (0x001 >> (4 * c)) & 15;
+    p[1] = (0x022 >> (4 * c)) & 15;
+    q[1] = (0x110 >> (4 * c)) & 15;
+    s[0] = (c == 0) ? -1.0 : 1.0;
+    s[1] = (c == 2) ? -1.0 : 0.0;
+  }
+};
+template <int D> struct ACoef<D, 1> {
+  // acoustics, (g.v, g_0 p, .., g_{D-1} p) with u = (p, v)
+  static __device__ __forceinline__ void get(int c, int* p, int* q, double* s) {
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      p[t] = (c == 0) ? 1 + t : 0;
+      q[t] = (c == 0) ? t : c - 1;
+      s[t] = (c == 0 || t == 0) ? 1.0 : 0.0;
+    }
   }
 };
 
-template <int D, int P, int NTMAX>
+template <int D, int P, int NTMAX, int SYS = 0>
 struct MShape {
-  static constexpr int NC = (D == 3) ? 6 : 3;
+  static constexpr int NC = Phys<D, SYS>::NC;
   static constexpr int NP = binom_c(P + D, D);
   static constexpr int NF = binom_c(P + D - 1, D - 1);
   static constexpr int NV = D + 1;
@@ -101,9 +113,9 @@ struct MShape {
 
 // LDS layout, identical for both variants (state, fluxes and operators stored in FP64; the
 // mixed variant only changes the precision of the products of stages n >= 2)
-template <int D, int P, typename T, int NTMAX>
+template <int D, int P, typename T, int NTMAX, int SYS = 0>
 struct MLds {
-  using SH = MShape<D, P, NTMAX>;
+  using SH = MShape<D, P, NTMAX, SYS>;
   static constexpr int OPS = SH::MP;
   static constexpr size_t op_elems = (size_t)SH::KT * OPS;
   static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
@@ -121,14 +133,15 @@ struct MLds {
 // (l = 1..D) of that block, which differ only in the coefficients of A(grad lambda_l).
 // The raw LDS operands of the next node block are loaded before the current block's
 // products are issued (register ring, no code motion across blocks).
-template <typename TM, int D, int P, int NTMAX>
+template <typename TM, int D, int P, int NTMAX, int SYS>
 __device__ __forceinline__ void tile_product(const double* sOp, const double* sU, double* sFR, const double* sGL,
                                              int wave, int lane, int ncols, int ntiles) {
-  using SH = MShape<D, P, NTMAX>;
+  using SH = MShape<D, P, NTMAX, SYS>;
+  constexpr int NT = Phys<D, SYS>::NTERM;
   using MM = Mfma<TM>;
   constexpr int NC = SH::NC, NV = SH::NV, NPK = SH::NPK, KV = SH::KV, KFP = SH::KFP, MT = SH::MT,
                 RS = SH::RS, WAVES = SH::WAVES, TPW = SH::TILES_PER_WAVE;
-  constexpr int OPS = MLds<D, P, double, NTMAX>::OPS;
+  constexpr int OPS = MLds<D, P, double, NTMAX, SYS>::OPS;
   constexpr int NB = NPK / 4;              // node blocks of the volume part
   constexpr int NG = NB + KFP / 4;         // K groups: node blocks, then lift steps
   constexpr int PDG = 2;                   // ring depth in K groups
@@ -143,32 +156,33 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       const bool live = col < ncols;
       const int e = live ? col / NC : 0;
       const int c = live ? col - e * NC : 0;
-      int p1, q1, p2, q2;
-      double s1, s2;
-      ACoef<D>::get(c, &p1, &q1, &s1, &p2, &q2, &s2);
-      TM cf1[D], cf2[D];
+      int pt[NT], qt[NT];
+      double st[NT];
+      ACoef<D, SYS>::get(c, pt, qt, st);
+      TM cf[NT][D];
 #pragma unroll
       for (int l = 0; l < D; ++l) {
         const double* gl = &sGL[(e * NV + l + 1) * D];
-        cf1[l] = (TM)(live ? s1 * gl[q1] : 0.0);
-        cf2[l] = (TM)(live ? s2 * gl[q2] : 0.0);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) cf[k][l] = (TM)(live ? st[k] * gl[qt[k]] : 0.0);
       }
       const TM fm = live ? (TM)1 : (TM)0;
       const int kq = lane >> 4;
       const double* acol = sOp + mt * 16 + (lane & 15) + kq * OPS;
-      const double* u1 = sU + kq * RS + e * NC + p1;
-      const double* u2 = sU + kq * RS + e * NC + p2;
+      const double* ut[NT];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) ut[k] = sU + kq * RS + e * NC + pt[k];
       const double* fr = sFR + kq * RS + (live ? col : 0);
-      double ra[PDG][D], r1[PDG], r2[PDG];
+      double ra[PDG][D], ru[PDG][NT];
       auto load = [&](int g, int slot) {
         if (g < NB) {
 #pragma unroll
           for (int l = 0; l < D; ++l) ra[slot][l] = acol[(l * NPK + 4 * g) * OPS];
-          r1[slot] = u1[4 * g * RS];
-          r2[slot] = u2[4 * g * RS];
+#pragma unroll
+          for (int k = 0; k < NT; ++k) ru[slot][k] = ut[k][4 * g * RS];
         } else {
           ra[slot][0] = acol[(KV + 4 * (g - NB)) * OPS];
-          r1[slot] = fr[4 * (g - NB) * RS];
+          ru[slot][0] = fr[4 * (g - NB) * RS];
         }
       };
 #pragma unroll
@@ -176,17 +190,25 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
 #pragma unroll
       for (int g = 0; g < NG; ++g) {
         const int slot = g % PDG;
-        double a[D];
+        double a[D], x[NT];
 #pragma unroll
         for (int l = 0; l < D; ++l) a[l] = ra[slot][l];
-        const double x1 = r1[slot], x2 = r2[slot];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) x[k] = ru[slot][k];
         if (g + PDG < NG) load(g + PDG, slot);
         if (g < NB) {
-          const TM v1 = (TM)x1, v2 = (TM)x2;
+          TM v[NT];
 #pragma unroll
-          for (int l = 0; l < D; ++l) accs[ts] = MM::mma((TM)a[l], cf1[l] * v1 + cf2[l] * v2, accs[ts]);
+          for (int k = 0; k < NT; ++k) v[k] = (TM)x[k];
+#pragma unroll
+          for (int l = 0; l < D; ++l) {
+            TM b = cf[0][l] * v[0];
+#pragma unroll
+            for (int k = 1; k < NT; ++k) b += cf[k][l] * v[k];
+            accs[ts] = MM::mma((TM)a[l], b, accs[ts]);
+          }
         } else {
-          accs[ts] = MM::mma((TM)a[0], fm * (TM)x1, accs[ts]);
+          accs[ts] = MM::mma((TM)a[0], fm * (TM)x[0], accs[ts]);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -351,15 +373,16 @@ struct SchedBatchDag {   // the tent DAGs of a batch of solvers, one queue of gl
 // sub-interval, whose U_{i,0} has the full size of the fields, stays FP64; the later
 // stages act on the small Taylor coefficients U_{i,n}, n >= 1, and run on the FP32 cores.
 // RK4: the classical RK4 variant instead of SAT (FP64 only).
-template <int D, int P, typename T, int NTMAX, class Sched, bool RK4 = false>
+template <int D, int P, typename T, int NTMAX, class Sched, bool RK4 = false, int SYS = 0>
 __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sched) {
-  using SH = MShape<D, P, NTMAX>;
+  using SH = MShape<D, P, NTMAX, SYS>;
+  using PH = Phys<D, SYS>;
   constexpr bool MIXED = sizeof(T) == 4;
   constexpr int NC = SH::NC, NP = SH::NP, NF = SH::NF, NV = SH::NV;
   constexpr int NPK = SH::NPK, KV = SH::KV, KF = SH::KF, KT = SH::KT, MP = SH::MP, RS = SH::RS;
-  constexpr int OPS = MLds<D, P, T, NTMAX>::OPS;
+  constexpr int OPS = MLds<D, P, T, NTMAX, SYS>::OPS;
   constexpr int MAXPAIR = SH::MAXPAIR, BLOCK = SH::BLOCK;
-  using LD = MLds<D, P, T, NTMAX>;
+  using LD = MLds<D, P, T, NTMAX, SYS>;
   extern __shared__ double lds_d[];
   double* sOp = lds_d;                            // [k][m], m fastest
   double* sU = sOp + LD::op_elems;                // [node][col]
@@ -457,7 +480,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[r][c] = Wp[c * NP];
         double u[NC];
-        ok &= kinv<D>(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
+        ok &= PH::inv(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
 #pragma unroll
         for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = u[c];
       }
@@ -488,9 +511,9 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 #pragma unroll
           for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
           if (kp.flux_kind == 1)
-            flux_imp<D>(g, sqrt(sEM[2 * e + 1] / sEM[2 * e]), sqrt(sEM[2 * pe + 1] / sEM[2 * pe]), um, up, G);
+            PH::fl_imp(g, sqrt(sEM[2 * e + 1] / sEM[2 * e]), sqrt(sEM[2 * pe + 1] / sEM[2 * pe]), um, up, G);
           else
-            flux<D>(g, kp.alpha, um, up, G);
+            PH::fl(g, kp.alpha, um, up, G);
           double gg = 0.0, gn = 0.0;
 #pragma unroll
           for (int x = 0; x < D; ++x) {
@@ -506,12 +529,12 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
             sFR[((jn - 1) * NF + s2) * RS + pe * NC + c] = ratio * G[c];
           }
         } else {
-          ghost_state<D, P>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
+          ghost_state<D, P, SYS>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
           if (kp.flux_kind == 1) {   // walls and data: the element's own medium on both sides
             const double z = sqrt(sEM[2 * e + 1] / sEM[2 * e]);
-            flux_imp<D>(g, z, z, um, up, G);
+            PH::fl_imp(g, z, z, um, up, G);
           } else {
-            flux<D>(g, kp.alpha, um, up, G);
+            PH::fl(g, kp.alpha, um, up, G);
           }
 #pragma unroll
           for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
@@ -529,7 +552,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
         for (int s = 0; s < 4; ++s) {
           const double th = (i + (s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5))) * invm;
           face_fluxes(th, 1);
-          tile_product<double, D, P, NTMAX>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<double, D, P, NTMAX, SYS>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
           const double thn = (s == 3) ? (i + 1) * invm : (i + (s == 2 ? 1.0 : 0.5)) * invm;
           const double a = (s == 2) ? invm : 0.5 * invm;   // weight of k_s in the next stage input
           const double wk = (s == 0 || s == 3) ? 1.0 : 2.0;
@@ -555,7 +578,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
                 double bi[D], un[NC];
 #pragma unroll
                 for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + thn * H * gv[x];
-                ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], wst, un);
+                ok &= PH::inv(bi, sEM[2 * e], sEM[2 * e + 1], wst, un);
 #pragma unroll
                 for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = un[c];
               }
@@ -574,9 +597,9 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 
         // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
         if (MIXED && n >= 2)
-          tile_product<float, D, P, NTMAX>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<float, D, P, NTMAX, SYS>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
         else
-          tile_product<double, D, P, NTMAX>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<double, D, P, NTMAX, SYS>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
 
         // ---- Taylor accumulation (FP64) and the next U for the owned (element, node) pairs
 #pragma unroll
@@ -602,17 +625,17 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
               }
 #pragma unroll
               for (int c = 0; c < NC; ++c) uo[c] = sU[b * RS + e * NC + c];
-              applyA<D>(bp, uo, au);
+              PH::A(bp, uo, au);
 #pragma unroll
               for (int c = 0; c < NC; ++c) rhs[c] = Y[c] + n * au[c];
-              ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], rhs, un);
+              ok &= PH::inv(bi, sEM[2 * e], sEM[2 * e + 1], rhs, un);
               write = true;
             } else if (i + 1 < kp.m) {
               double bi[D];
               const double th1 = (i + 1) * invm;
 #pragma unroll
               for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * H * gv[x];
-              ok &= kinv<D>(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], un);
+              ok &= PH::inv(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], un);
               write = true;
             }
             if (write) {
@@ -645,18 +668,18 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   }
 }
 
-template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false>
+template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false, int SYS = 0>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
-  tent_mfma_body<D, P, T, NTMAX, SchedRange, RK4>(
+  tent_mfma_body<D, P, T, NTMAX, SchedRange, RK4, SYS>(
       kp, SchedRange{&kp, first, count, (int64_t)blockIdx.x, (int64_t)gridDim.x});
 }
 
 // Persistent entry point: every tent of the slab, in DAG order, by kp.dag_grid workgroups.
-template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false>
+template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false, int SYS = 0>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_dag_kernel(KernelParams kp) {
-  tent_mfma_body<D, P, T, NTMAX, SchedDag, RK4>(kp, SchedDag{&kp});
+  tent_mfma_body<D, P, T, NTMAX, SchedDag, RK4, SYS>(kp, SchedDag{&kp});
 }
 
 // Persistent entry point of a batch: every tent of every solver's slab, in DAG order.
@@ -685,22 +708,31 @@ tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) 
 template <int D, int P, typename T, int NTMAX>
 hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
+  const size_t lds_ac = MLds<D, P, T, NTMAX, 1>::bytes;
   constexpr int WPE = 2;   // 8 waves per workgroup, one workgroup per CU
+  constexpr int BLOCK = MShape<D, P, NTMAX>::BLOCK;
   auto kfn = tent_mfma_kernel<D, P, T, NTMAX, WPE>;
   auto kfn_rk4 = tent_mfma_kernel<D, P, double, NTMAX, WPE, true>;
+  auto kfn_ac = tent_mfma_kernel<D, P, T, NTMAX, WPE, false, 1>;
   if (count < 0) {   // prepare: allow the dynamic LDS size (done once, outside graph capture)
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess && sizeof(T) == 8)
       e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn_rk4), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
+    if (e == hipSuccess && lds_ac <= 160 * 1024)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn_ac), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds_ac);
     return e;
   }
-  if (kp.method == 1) {
+  if (kp.system == 1) {
+    if (kp.method != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kfn_ac, dim3((unsigned)count), dim3(BLOCK), lds_ac, s, kp, first, count);
+  } else if (kp.method == 1) {
     if (sizeof(T) != 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
+    hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)count), dim3(BLOCK), lds, s, kp, first, count);
   } else {
-    hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, kp, first, count);
+    hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(BLOCK), lds, s, kp, first, count);
   }
   return hipGetLastError();
 }
@@ -740,7 +772,10 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   }
   auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
   auto kfn_rk4 = tent_mfma_dag_kernel<D, P, double, NTMAX, 2, true>;
-  if (resident) {   // the smaller residency of the SAT and (FP64) RK4 variants
+  auto kfn_ac = tent_mfma_dag_kernel<D, P, T, NTMAX, 2, false, 1>;
+  const size_t lds_ac = MLds<D, P, T, NTMAX, 1>::bytes;
+  if (resident) {   // the residency of the variant the solver runs (all: the smallest)
+    if (a.kp && a.kp->system == 1) return resident_grid(reinterpret_cast<const void*>(kfn_ac), BLOCK, lds_ac, resident);
     hipError_t e = resident_grid(reinterpret_cast<const void*>(kfn), BLOCK, lds, resident);
     if (e == hipSuccess && sizeof(T) == 8) {
       int r2 = 0;
@@ -751,7 +786,10 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   }
   if (a.kp->dag_n <= 0) return hipSuccess;
   if (a.kp->dag_grid <= 0) return hipErrorInvalidValue;
-  if (a.kp->method == 1) {
+  if (a.kp->system == 1) {
+    if (a.kp->method != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kfn_ac, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds_ac, s, *a.kp);
+  } else if (a.kp->method == 1) {
     if (sizeof(T) != 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds, s, *a.kp);
   } else {
@@ -841,7 +879,13 @@ hipError_t launch_mp(const KernelParams& kp, int64_t first, int64_t count, hipSt
 }
 
 template <int D, int P, typename T>
-size_t lds_mp(int max_patch) {
+size_t lds_mp(int max_patch, int system) {
+  if (system == 1) {
+    if (max_patch <= 8) return MLds<D, P, T, 8, 1>::bytes;
+    if (max_patch <= 24) return MLds<D, P, T, 24, 1>::bytes;
+    if (max_patch <= 48) return MLds<D, P, T, 48, 1>::bytes;
+    return (size_t)-1;
+  }
   if (max_patch <= 8) return MLds<D, P, T, 8>::bytes;
   if (max_patch <= 24) return MLds<D, P, T, 24>::bytes;
   if (max_patch <= 48) return MLds<D, P, T, 48>::bytes;
@@ -870,21 +914,21 @@ hipError_t launch_t(const KernelParams& kp, int64_t first, int64_t count, hipStr
 }
 
 template <typename T>
-size_t lds_t(int d, int p, int max_patch) {
+size_t lds_t(int d, int p, int max_patch, int system) {
   if (d == 2) {
     switch (p) {
-      case 1: return lds_mp<2, 1, T>(max_patch);
-      case 2: return lds_mp<2, 2, T>(max_patch);
-      case 3: return lds_mp<2, 3, T>(max_patch);
-      case 4: return lds_mp<2, 4, T>(max_patch);
-      case 5: return lds_mp<2, 5, T>(max_patch);
+      case 1: return lds_mp<2, 1, T>(max_patch, system);
+      case 2: return lds_mp<2, 2, T>(max_patch, system);
+      case 3: return lds_mp<2, 3, T>(max_patch, system);
+      case 4: return lds_mp<2, 4, T>(max_patch, system);
+      case 5: return lds_mp<2, 5, T>(max_patch, system);
     }
   } else {
     switch (p) {
-      case 1: return lds_mp<3, 1, T>(max_patch);
-      case 2: return lds_mp<3, 2, T>(max_patch);
-      case 3: return lds_mp<3, 3, T>(max_patch);
-      case 4: return lds_mp<3, 4, T>(max_patch);
+      case 1: return lds_mp<3, 1, T>(max_patch, system);
+      case 2: return lds_mp<3, 2, T>(max_patch, system);
+      case 3: return lds_mp<3, 3, T>(max_patch, system);
+      case 4: return lds_mp<3, 4, T>(max_patch, system);
     }
   }
   return (size_t)-1;
@@ -921,8 +965,8 @@ int tent_batch_dag_grid(int d, int p, int max_patch, int fp32) {
   return e == hipSuccess ? resident : 0;
 }
 
-size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32) {
-  return fp32 ? lds_t<float>(d, p, max_patch) : lds_t<double>(d, p, max_patch);
+size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32, int system) {
+  return fp32 ? lds_t<float>(d, p, max_patch, system) : lds_t<double>(d, p, max_patch, system);
 }
 
 hipError_t launch_tent_batch_mfma(const BatchLaunch& bl, int fp32, hipStream_t s) {

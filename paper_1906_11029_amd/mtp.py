@@ -19,6 +19,7 @@ MTP_FP64, MTP_MIXED_FP32, MTP_FP64_VALU = 0, 1, 2
 MTP_SCHEDULE_LAYERS, MTP_SCHEDULE_DAG = 0, 1
 MTP_METHOD_SAT, MTP_METHOD_RK4 = 0, 1
 MTP_FLUX_PENALTY, MTP_FLUX_IMPEDANCE = 0, 1
+MTP_SYSTEM_MAXWELL, MTP_SYSTEM_ACOUSTIC = 0, 1
 
 _lib = None
 
@@ -44,6 +45,7 @@ def load():
     sig = {
         "mtp_mesh_create": [i32, i64, P, i64, P, P, P, P, pp],
         "mtp_mesh_info": [P, P, P, P, P],
+        "mtp_mesh_set_system": [P, i32],
         "mtp_pitch_layers": [P, dbl, dbl, pp],
         "mtp_tents_query": [P, P, P, P],
         "mtp_tents_export": [P, P, P, P, P],
@@ -304,10 +306,19 @@ def mtp_batch_destroy(batch):
 
 
 # ----------------------------------------------------------------- thin object wrappers
+def mtp_mesh_set_system(mesh, system):
+    _check(load().mtp_mesh_set_system(mesh, int(system)))
+
+
 class Mesh:
-    def __init__(self, coords, cells, eps=None, mu=None, face_bc=None):
+    """system = MTP_SYSTEM_ACOUSTIC reads eps / mu as (kappa, rho) of linear acoustics."""
+
+    def __init__(self, coords, cells, eps=None, mu=None, face_bc=None, system=MTP_SYSTEM_MAXWELL):
         self.h = mtp_mesh_create(coords, cells, eps, mu, face_bc)
         self.info = mtp_mesh_info(self.h)
+        self.system = system
+        if system != MTP_SYSTEM_MAXWELL:
+            mtp_mesh_set_system(self.h, system)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -342,7 +353,8 @@ class Solver:
         import torch
         self.mesh, self.tents, self.p, self.q, self.m = mesh, tents, p, q, m
         d = mesh.info["dim"]
-        self.dim, self.nc = d, (6 if d == 3 else 3)
+        self.dim = d
+        self.nc = d + 1 if mesh.system == MTP_SYSTEM_ACOUSTIC else (6 if d == 3 else 3)
         self.np = (p + 1) * (p + 2) // 2 if d == 2 else (p + 1) * (p + 2) * (p + 3) // 6
         self.shape = (mesh.info["ne"], self.np, self.nc)
         nbytes = mtp_solver_workspace_size(mesh.h, tents.h, p, q, m, precision)

@@ -47,6 +47,18 @@ IMP_CASES = {
     "te_planewave_p2_imp": dict(mesh=("square", 8), p=2, q=3, m=4, T=0.5, kind=DATA, exact="pw_te", flux="impedance"),
 }
 
+# linear acoustics (system="acoustic"): kind PMC = rigid wall, PEC = pressure release;
+# eps / mu hold (kappa, rho)
+AC_CASES = {
+    "ac2d_rigid_p3": dict(mesh=("square", 4), p=3, q=4, m=6, T=0.4, kind=PMC, exact="ac_cav2", system="acoustic"),
+    "ac2d_planewave_p2": dict(mesh=("square", 6), p=2, q=3, m=4, T=0.4, kind=DATA, exact="ac_pw2", system="acoustic"),
+    "ac3d_rigid_p2": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.25, kind=PMC, exact="ac_cav3", system="acoustic"),
+    "ac3d_release_eps_p3": dict(mesh=("kuhn", 2), p=3, q=4, m=6, T=0.2, kind=PEC, exact="ac_pulse3",
+                                eps_split=True, system="acoustic"),
+    "ac3d_graded_imp_p4": dict(mesh=("kuhn_graded", 3), p=4, q=5, m=8, T=0.05, kind=PMC, exact="ac_pulse3",
+                               eps_split=True, system="acoustic", flux="impedance"),
+}
+
 
 def build_mesh(spec):
     kind, n = spec
@@ -72,12 +84,18 @@ def exact_solution(name):
             "pec_te": fields.CavityTE_PEC(),
             "pec_3d": fields.Cavity3D_PEC(),
             "pw_3d": fields.PlaneWave3D(direction=(1.0, 0.5, 0.25), k=np.pi, amp_e=(0.0, 1.0, -1.0), phase=0.3),
-            "pulse": fields.GaussianPulse3D(seed=11030)}[name]
+            "pulse": fields.GaussianPulse3D(seed=11030),
+            "ac_cav2": fields.AcousticCavity(2),
+            "ac_cav3": fields.AcousticCavity(3),
+            "ac_pw2": fields.AcousticPlaneWave(direction=(1.0, 0.6), k=2 * np.pi, phase=0.2),
+            "ac_pulse3": fields.AcousticPulse(3)}[name]
 
 
 def planewave_params(ex, dim):
     """(amp, kvec, omega, phase) of a plane-wave exact solution for the C interface."""
-    if dim == 2:
+    if hasattr(ex, "avec"):        # acoustics: amplitude of (p, v)
+        amp = ex.avec
+    elif dim == 2:
         amp = np.array([-ex.d[1] * ex.amp, ex.d[0] * ex.amp, ex.amp * np.sqrt(ex.eps / ex.mu)])
     else:
         amp = np.concatenate([ex.aE, ex.aH])
@@ -85,7 +103,8 @@ def planewave_params(ex, dim):
 
 
 def setup(name):
-    c = dict(CASES.get(name) or RK4_CASES.get(name) or IMP_CASES[name])
+    c = dict(CASES.get(name) or RK4_CASES.get(name) or IMP_CASES.get(name) or AC_CASES[name])
+    c.setdefault("system", "maxwell")
     c.setdefault("method", "sat")
     c.setdefault("flux", "penalty")
     c.setdefault("alpha", 0.5)

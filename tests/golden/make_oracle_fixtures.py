@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 sys.path.insert(0, os.path.dirname(HERE))
 
-from cases import CASES, DATA, IMP_CASES, RK4_CASES, setup  # noqa: E402
+from cases import AC_CASES, CASES, DATA, IMP_CASES, RK4_CASES, setup  # noqa: E402
 from oracle.mesh import Mesh  # noqa: E402
 from oracle.pitch import pitch  # noqa: E402
 from oracle.solve import OracleSolver  # noqa: E402
@@ -24,7 +24,7 @@ def make(name):
     mesh = Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc)
     tents = pitch(mesh, c["T"], sigma=0.5)
     S = OracleSolver(mesh, c["p"], c["q"], c["m"], alpha=c["alpha"], data=ex if c["kind"] == DATA else None,
-                     method=c["method"], flux=c["flux"])
+                     method=c["method"], flux=c["flux"], system=c["system"])
     S.set_nodal_u(u0)
     for k in range(c["slabs"]):
         S.run(tents, t_offset=k * c["T"])
@@ -35,7 +35,7 @@ def make(name):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or list(CASES) + list(RK4_CASES) + list(IMP_CASES)
+    names = sys.argv[1:] or list(CASES) + list(RK4_CASES) + list(IMP_CASES) + list(AC_CASES)
     for n in names:
         t0 = time.time()
         make(n)

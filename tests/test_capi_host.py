@@ -101,3 +101,21 @@ def test_workspace_size_and_unsupported_degree():
     with pytest.raises(mtp.MTPError) as e:
         mtp.mtp_solver_workspace_size(M.h, T.h, 2, 3, 4, precision=7)
     assert e.value.code == -9
+
+
+def test_acoustic_system_selection_errors():
+    """Host-side checks of the second system: unknown system, and the vector-ALU kernel
+    (Maxwell only) refused at the workspace query."""
+    mm = meshes.cube_kuhn(2)
+    M = mtp.Mesh(mm["coords"], mm["cells"], system=mtp.MTP_SYSTEM_ACOUSTIC)
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.mtp_mesh_set_system(M.h, 7)
+    assert e.value.code == -1
+    T = mtp.Tents(M, 0.2, 0.5)
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.mtp_solver_workspace_size(M.h, T.h, 2, 3, 4, mtp.MTP_FP64_VALU)
+    assert e.value.code == -9
+    # acoustics has d + 1 fields: a smaller workspace than Maxwell on the same mesh
+    Mm = mtp.Mesh(mm["coords"], mm["cells"])
+    Tm = mtp.Tents(Mm, 0.2, 0.5)
+    assert mtp.mtp_solver_workspace_size(M.h, T.h, 2, 3, 4) < mtp.mtp_solver_workspace_size(Mm.h, Tm.h, 2, 3, 4)

@@ -1,0 +1,98 @@
+"""GPU parity of the second system, linear acoustics u = (p, v) (the method as stated for
+linear hyperbolic systems in conservation form): the HIP path against the oracle on the
+same tents, element by element (FP64 <= 1e-10 in both schedules, mixed <= 1e-6), rigid and
+pressure-release walls, plane-wave data, two media with the impedance-matched flux; and
+the h-convergence rate p + 1 of SAT on the rigid-wall cavity at GPU sizes."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+from cases import AC_CASES, DATA, planewave_params, setup  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def fixture(name):
+    path = os.path.join(HERE, "golden", f"oracle_{name}.npz")
+    if os.path.exists(path):
+        return np.load(path)
+    pytest.skip(f"missing oracle fixture {path}")
+
+
+def run(name, precision, schedule):
+    from paper_1906_11029_amd import mtp
+    c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc, system=mtp.MTP_SYSTEM_ACOUSTIC)
+    T = mtp.Tents(M, c["T"], 0.5)
+    S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"], precision=precision)
+    if c["flux"] == "impedance":
+        S.set_flux(mtp.MTP_FLUX_IMPEDANCE)
+    S.set_schedule(schedule)
+    S.set_fields(u0, 0.0)
+    if c["kind"] == DATA:
+        S.set_planewave_bc(*planewave_params(ex, dim))
+    S.advance_to(c["slabs"] * c["T"])
+    return S, T
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("name", list(AC_CASES))
+def test_acoustic_parity_fp64(name, schedule):
+    print(f"[gpu acoustic] {name} fp64 schedule {schedule}", flush=True)
+    ref = fixture(name)
+    S, T = run(name, 0, schedule)
+    ex = T.export()
+    for k in ("vertex", "t_top", "layer"):
+        assert np.array_equal(ex[k], ref[k]), k
+    assert rel(S.get_state(), ref["w"]) <= 1e-10
+    assert rel(S.get_fields(), ref["u"]) <= 1e-10
+
+
+@pytest.mark.parametrize("name", list(AC_CASES))
+def test_acoustic_parity_mixed(name):
+    print(f"[gpu acoustic] {name} mixed", flush=True)
+    ref = fixture(name)
+    S, _ = run(name, 1, 1)
+    assert rel(S.get_state(), ref["w"]) <= 1e-6
+
+
+def test_acoustic_cavity_convergence_at_scale():
+    from mtp_inputs import fields, meshes
+    from paper_1906_11029_amd import mtp
+    p, errs = 3, []
+    for n in (8, 16, 32):
+        mm = meshes.square_tri(n)
+        M = mtp.Mesh(mm["coords"], mm["cells"], face_bc=meshes.uniform_bc(len(mm["cells"]), 2, meshes.PMC),
+                     system=mtp.MTP_SYSTEM_ACOUSTIC)
+        T = mtp.Tents(M, 0.5, 0.5)
+        S = mtp.Solver(M, T, p, p + 1, 2 * p)
+        S.set_schedule(mtp.MTP_SCHEDULE_DAG)
+        ex = fields.AcousticCavity(2)
+        nodes = meshes.equispaced_nodes(mm, p)
+        S.set_fields(ex.u(nodes, 0.0), 0.0)
+        S.advance_to(0.5)
+        errs.append(rel(S.get_fields(), ex.u(nodes, 0.5)))
+    rates = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    print(f"[gpu acoustic] P{p} rigid cavity errors {errs} rates {rates}", flush=True)
+    assert min(rates) > p + 1 - 0.5
+
+
+def test_acoustic_rejected_where_unsupported():
+    from paper_1906_11029_amd import mtp
+    c, mm, dim, eps, mu, bc, ex, u0 = setup("ac3d_rigid_p2")
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc, system=mtp.MTP_SYSTEM_ACOUSTIC)
+    T = mtp.Tents(M, c["T"], 0.5)
+    S = mtp.Solver(M, T, c["p"], c["q"], c["m"])
+    with pytest.raises(mtp.MTPError):
+        S.set_method(mtp.MTP_METHOD_RK4)
+    with pytest.raises(mtp.MTPError):
+        mtp.Batch([S])
