@@ -54,6 +54,21 @@ def workload(name):
         desc = ("3D PEC cavity mode, unit cube 32^3x6 Kuhn tets (196608) graded toward one corner "
                 "(h ratio 1:8), eps = mu = 1, P4, q=5, m=8, slab T=0.05 (equal-error certification)")
         return dict(name=name, mm=mm, p=4, q=5, m=8, T=0.05, ex=fields.Cavity3D_PEC(), desc=desc, exact=True)
+    if name in ("acoustic3d_p4", "acoustic3d_p4_cavity"):
+        grade = lambda g: GRADE_A * g + (1 - GRADE_A) * g * g  # noqa: E731
+        mm = meshes.cube_kuhn(32, axis_map=grade)
+        bc = meshes.uniform_bc(len(mm["cells"]), 3, meshes.PMC)       # rigid walls
+        if name == "acoustic3d_p4":
+            kappa, rho = meshes.materials_split(mm)
+            desc = ("3D linear acoustics, unit cube 32^3x6 Kuhn tets (196608) graded toward one corner (h ratio "
+                    "1:8), kappa in {1, 2.25} split at x=0.5, rho = 1, rigid walls, Gaussian pressure pulse, P4, "
+                    "q=5, m=8, slab T=0.05")
+            return dict(name=name, mm=mm, p=4, q=5, m=8, T=0.05, ex=fields.AcousticPulse(3), desc=desc, eps=kappa,
+                        mu=rho, bc=bc, system="acoustic", exact=False, cert="acoustic3d_p4_cavity")
+        desc = ("3D linear acoustics, rigid-wall cavity mode on the same graded mesh, kappa = rho = 1, P4, q=5, "
+                "m=8, slab T=0.05 (equal-error certification)")
+        return dict(name=name, mm=mm, p=4, q=5, m=8, T=0.05, ex=fields.AcousticCavity(3), desc=desc, bc=bc,
+                    system="acoustic", exact=True)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -67,12 +82,12 @@ def cpu_baseline(W, budget_s):
     from oracle.pitch import pitch as opitch
     from oracle.solve import OracleSolver
     with threadpool_limits(limits=1):
-        om = OMesh(W["mm"]["coords"], W["mm"]["cells"], eps=W.get("eps"), mu=W.get("mu"))
+        om = OMesh(W["mm"]["coords"], W["mm"]["cells"], eps=W.get("eps"), mu=W.get("mu"), face_bc=W.get("bc"))
         tents = opitch(om, W["T"], 0.5)
-        O = OracleSolver(om, W["p"], W["q"], W["m"])
+        O = OracleSolver(om, W["p"], W["q"], W["m"], system=W.get("system", "maxwell"))
         O.set_nodal_u(W["ex"].u(meshes.equispaced_nodes(W["mm"], W["p"]), 0.0))
         order = np.argsort(tents["layer"], kind="stable")
-        nc, npn = 6, (W["p"] + 1) * (W["p"] + 2) * (W["p"] + 3) // 6
+        nc, npn = (4 if W.get("system") == "acoustic" else 6), (W["p"] + 1) * (W["p"] + 2) * (W["p"] + 3) // 6
         dofs, done = 0.0, 0
         t0 = time.perf_counter()
         for i in order:
@@ -127,7 +142,8 @@ def run(W, precision, steps, warmup, M=None, T=None, schedule="layers"):
     from paper_1906_11029_amd import mtp
     mm = W["mm"]
     if M is None:
-        M = mtp.Mesh(mm["coords"], mm["cells"], eps=W.get("eps"), mu=W.get("mu"))
+        M = mtp.Mesh(mm["coords"], mm["cells"], eps=W.get("eps"), mu=W.get("mu"), face_bc=W.get("bc"),
+                     system=mtp.MTP_SYSTEM_ACOUSTIC if W.get("system") == "acoustic" else mtp.MTP_SYSTEM_MAXWELL)
         T = mtp.Tents(M, W["T"], 0.5)
     prec = {"fp64": mtp.MTP_FP64, "mixed": mtp.MTP_MIXED_FP32, "fp64-valu": mtp.MTP_FP64_VALU}[precision]
     S = mtp.Solver(M, T, W["p"], W["q"], W["m"], precision=prec)
