@@ -56,6 +56,7 @@ enum {
   MTP_ERR_NONFINITE = -5,   /* non-finite field values                                 */
   MTP_ERR_DEVICE = -6,      /* HIP runtime error or a device-side check failed         */
   MTP_ERR_STATE = -7,       /* call out of order (e.g. advancing past the tent table)  */
+  MTP_ERR_NOMEM = -8,       /* host memory exhausted                                   */
   MTP_ERR_UNSUPPORTED = -9  /* (dim, p) or patch size outside what the kernels cover   */
 };
 
@@ -271,6 +272,30 @@ mtp_status mtp_solver_kernel(mtp_solver solver, int32_t* kernel);
 /* Algorithmic flop count of one slab, per the kernel's arithmetic (volume and lift
  * contractions, flux, pointwise inverse, Taylor sum). */
 mtp_status mtp_slab_flops(mtp_solver solver, double* flops);
+
+/* Checkpoint of a solver's state (host file, binary): the nodal state W (the mapped
+ * variable the tents pass on, section 4), the front tau and the position in the slab
+ * sequence, with a header naming the discretisation and a checksum.  The state is
+ * copied out after the solver's stream has drained.  mtp_checkpoint_read restores it
+ * into a solver of the same mesh, tent table, p, q, m and system (errors: MTP_ERR_ARG for
+ * an unreadable, foreign, truncated or corrupted file, MTP_ERR_STATE for a checkpoint of
+ * another configuration); the device error flags are cleared and the captured slab graph
+ * stays valid.  Continuing from a restored checkpoint gives the same values bit for bit
+ * as not having stopped. */
+mtp_status mtp_checkpoint_write(mtp_solver solver, const char* path);
+mtp_status mtp_checkpoint_read(mtp_solver solver, const char* path);
+
+/* Counters and configuration of a solver (host copy; no device work). */
+typedef struct {
+  int64_t slabs_done, layers_done;   /* position of the front */
+  int64_t n_tents, n_layers;         /* per slab */
+  double front_time;                 /* time of the last flat front */
+  double dof_updates_per_slab;       /* as mtp_slab_dof_updates */
+  double flops_per_slab;             /* as mtp_slab_flops */
+  int32_t kernel, schedule, method, flux, system;
+  int32_t persistent_workgroups;     /* grid of the persistent schedule (0: not available) */
+} mtp_stats_t;
+mtp_status mtp_stats(mtp_solver solver, mtp_stats_t* out);
 
 const char* mtp_last_error(void);
 

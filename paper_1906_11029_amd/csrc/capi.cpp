@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -211,11 +213,19 @@ using namespace mtp;
     g_last_error = e.what();                             \
     return e.code;                                       \
   }                                                      \
+  catch (const std::bad_alloc& e) {                      \
+    g_last_error = "host memory exhausted";              \
+    return MTP_ERR_NOMEM;                                \
+  }                                                      \
   catch (const std::exception& e) {                      \
     g_last_error = e.what();                             \
     return MTP_ERR_ARG;                                  \
   }                                                      \
   return MTP_OK;
+
+static void check_status(mtp_status st) {
+  if (st != MTP_OK) throw Error(st, g_last_error);
+}
 
 static void require(bool c, mtp_status code, const char* msg) {
   if (!c) throw Error(code, msg);
@@ -968,6 +978,118 @@ mtp_status mtp_tents_dag(mtp_mesh mesh, mtp_tents tents, int32_t* pred_count, in
   if (succ_ptr) std::copy(sp.begin(), sp.end(), succ_ptr);
   if (succ) std::copy(sc.begin(), sc.end(), succ);
   if (n_ready) *n_ready = nr;
+  MTP_CATCH
+}
+
+// ------------------------------------------------------------------ checkpoint, stats
+namespace {
+struct CkptHeader {
+  char magic[8];
+  int32_t version, dim, system, p, q, m, nc, np;
+  int64_t ne, nv, n_tents;
+  double t_base, height;
+  int64_t slab, layers_done;
+  uint64_t checksum;
+};
+uint64_t fnv1a(const void* data, size_t n, uint64_t h) {
+  const unsigned char* b = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+const char kMagic[8] = {'M', 'T', 'P', 'C', 'K', 'P', 'T', '1'};
+}  // namespace
+
+mtp_status mtp_checkpoint_write(mtp_solver s, const char* path) {
+  MTP_TRY
+  require(s && path, MTP_ERR_ARG, "null pointer");
+  const Mesh& M = s->mesh;
+  const size_t nw = (size_t)M.ne * s->nc * s->ref.np;
+  std::vector<double> W(nw), tau(M.nv);
+  check_hip(hipStreamSynchronize(s->stream), "sync");
+  check_hip(hipMemcpy(W.data(), s->ws + s->off.W, nw * 8, hipMemcpyDeviceToHost), "copy");
+  check_hip(hipMemcpy(tau.data(), s->ws + s->off.tau, M.nv * 8, hipMemcpyDeviceToHost), "copy");
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kMagic, 8);
+  h.version = 1;
+  h.dim = M.d;
+  h.system = M.system;
+  h.p = s->p;
+  h.q = s->q;
+  h.m = s->m;
+  h.nc = s->nc;
+  h.np = s->ref.np;
+  h.ne = M.ne;
+  h.nv = M.nv;
+  h.n_tents = (int64_t)s->tents.vertex.size();
+  h.t_base = s->t_base;
+  h.height = s->tents.t_end;
+  h.slab = s->slab;
+  h.layers_done = s->layers_done;
+  h.checksum = fnv1a(tau.data(), tau.size() * 8, fnv1a(W.data(), nw * 8, 1469598103934665603ull));
+  FILE* f = std::fopen(path, "wb");
+  require(f != nullptr, MTP_ERR_ARG, "cannot open the checkpoint file for writing");
+  const bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1 && std::fwrite(W.data(), 8, nw, f) == nw &&
+                  std::fwrite(tau.data(), 8, tau.size(), f) == tau.size();
+  const bool closed = std::fclose(f) == 0;
+  require(ok && closed, MTP_ERR_ARG, "checkpoint write failed");
+  MTP_CATCH
+}
+
+mtp_status mtp_checkpoint_read(mtp_solver s, const char* path) {
+  MTP_TRY
+  require(s && path, MTP_ERR_ARG, "null pointer");
+  const Mesh& M = s->mesh;
+  FILE* f = std::fopen(path, "rb");
+  require(f != nullptr, MTP_ERR_ARG, "cannot open the checkpoint file");
+  CkptHeader h;
+  const size_t nw = (size_t)M.ne * s->nc * s->ref.np;
+  std::vector<double> W, tau;
+  bool ok = std::fread(&h, sizeof(h), 1, f) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 1;
+  const bool same = ok && h.dim == M.d && h.system == M.system && h.p == s->p && h.q == s->q && h.m == s->m &&
+                    h.nc == s->nc && h.np == s->ref.np && h.ne == M.ne && h.nv == M.nv &&
+                    h.n_tents == (int64_t)s->tents.vertex.size() && h.height == s->tents.t_end &&
+                    h.layers_done >= 0 && h.layers_done < (int64_t)s->tents.layer_ptr.size() - 1 && h.slab >= 0;
+  if (ok && same) {
+    W.resize(nw);
+    tau.resize(M.nv);
+    ok = std::fread(W.data(), 8, nw, f) == nw && std::fread(tau.data(), 8, tau.size(), f) == tau.size();
+  }
+  std::fclose(f);
+  require(ok, MTP_ERR_ARG, "not a checkpoint of this library, or truncated");
+  require(same, MTP_ERR_STATE, "checkpoint of a different mesh, tent table or discretisation");
+  require(fnv1a(tau.data(), tau.size() * 8, fnv1a(W.data(), nw * 8, 1469598103934665603ull)) == h.checksum,
+          MTP_ERR_ARG, "checkpoint checksum mismatch");
+  check_hip(hipStreamSynchronize(s->stream), "sync");
+  check_hip(hipMemcpy(s->ws + s->off.W, W.data(), nw * 8, hipMemcpyHostToDevice), "upload");
+  check_hip(hipMemcpy(s->ws + s->off.tau, tau.data(), M.nv * 8, hipMemcpyHostToDevice), "upload");
+  // device slab state: [0] bottom of the current slab, [1] height, [2] front at slab 0, [3] slabs done
+  const double slab[4] = {h.t_base + h.slab * h.height, h.height, h.t_base, (double)h.slab};
+  check_hip(hipMemcpy(s->ws + s->off.slab, slab, sizeof(slab), hipMemcpyHostToDevice), "upload");
+  check_hip(hipMemset(s->ws + s->off.err, 0, 16), "clear error flags");
+  s->t_base = h.t_base;
+  s->slab = h.slab;
+  s->layers_done = h.layers_done;
+  MTP_CATCH
+}
+
+mtp_status mtp_stats(mtp_solver s, mtp_stats_t* out) {
+  MTP_TRY
+  require(s && out, MTP_ERR_ARG, "null pointer");
+  std::memset(out, 0, sizeof(*out));
+  out->slabs_done = s->slab;
+  out->layers_done = s->layers_done;
+  out->n_tents = (int64_t)s->tents.vertex.size();
+  out->n_layers = (int64_t)s->tents.layer_ptr.size() - 1;
+  out->front_time = s->t_base + s->slab * s->tents.t_end;
+  check_status(mtp_slab_dof_updates(s, &out->dof_updates_per_slab, nullptr));
+  check_status(mtp_slab_flops(s, &out->flops_per_slab));
+  out->kernel = s->kernel;
+  out->schedule = s->schedule;
+  out->method = s->method;
+  out->flux = s->kp.flux_kind;
+  out->system = s->mesh.system;
+  out->persistent_workgroups = s->kp.dag_grid;
   MTP_CATCH
 }
 

@@ -66,6 +66,9 @@ def load():
         "mtp_solver_set_schedule": [P, i32],
         "mtp_solver_set_method": [P, i32],
         "mtp_solver_set_flux": [P, i32],
+        "mtp_checkpoint_write": [P, C.c_char_p],
+        "mtp_checkpoint_read": [P, C.c_char_p],
+        "mtp_stats": [P, P],
         "mtp_solver_set_dag_wait": [P, dbl],
         "mtp_tents_dag_size": [P, P, P],
         "mtp_tents_dag": [P, P, P, P, P, P],
@@ -261,6 +264,28 @@ def mtp_solver_set_flux(solver, flux):
     _check(load().mtp_solver_set_flux(solver, int(flux)))
 
 
+class mtp_stats_t(C.Structure):
+    _fields_ = [("slabs_done", C.c_int64), ("layers_done", C.c_int64), ("n_tents", C.c_int64),
+                ("n_layers", C.c_int64), ("front_time", C.c_double), ("dof_updates_per_slab", C.c_double),
+                ("flops_per_slab", C.c_double), ("kernel", C.c_int32), ("schedule", C.c_int32),
+                ("method", C.c_int32), ("flux", C.c_int32), ("system", C.c_int32),
+                ("persistent_workgroups", C.c_int32)]
+
+
+def mtp_stats(solver):
+    st = mtp_stats_t()
+    _check(load().mtp_stats(solver, C.byref(st)))
+    return {name: getattr(st, name) for name, _ in mtp_stats_t._fields_}
+
+
+def mtp_checkpoint_write(solver, path):
+    _check(load().mtp_checkpoint_write(solver, os.fsencode(path)))
+
+
+def mtp_checkpoint_read(solver, path):
+    _check(load().mtp_checkpoint_read(solver, os.fsencode(path)))
+
+
 def mtp_solver_set_dag_wait(solver, seconds):
     _check(load().mtp_solver_set_dag_wait(solver, float(seconds)))
 
@@ -411,6 +436,15 @@ class Solver:
 
     def set_flux(self, flux):
         mtp_solver_set_flux(self.h, flux)
+
+    def stats(self):
+        return mtp_stats(self.h)
+
+    def checkpoint_write(self, path):
+        mtp_checkpoint_write(self.h, path)
+
+    def checkpoint_read(self, path):
+        mtp_checkpoint_read(self.h, path)
 
     def __del__(self):
         if getattr(self, "h", None):
