@@ -87,6 +87,11 @@ template <int D> struct ACoef<D, 1> {
   }
 };
 
+// Threads per workgroup: 3D, 8 waves (2 per SIMD), one tent per CU; 2D tents are small
+// (a few triangles): 2 waves, so that several tents share a CU.
+template <int D>
+__host__ __device__ constexpr int tent_block() { return D == 2 ? 128 : 512; }
+
 template <int D, int P, int NTMAX, int SYS = 0>
 struct MShape {
   static constexpr int NC = Phys<D, SYS>::NC;
@@ -105,7 +110,7 @@ struct MShape {
                                         // consecutive nodes of one element hit distinct banks
   static constexpr int NTILE_MAX = NCOL / 16;
   static constexpr int FROWS = (KFP > MP) ? KFP : MP;     // F during the product, R after
-  static constexpr int BLOCK = 512;                      // 8 waves, 2 per SIMD
+  static constexpr int BLOCK = tent_block<D>();
   static constexpr int WAVES = BLOCK / 64;
   static constexpr int TILES_PER_WAVE = (MT * NTILE_MAX + WAVES - 1) / WAVES;
   static constexpr int MAXPAIR = (NTMAX * NP + BLOCK - 1) / BLOCK;
@@ -669,7 +674,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 }
 
 template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false, int SYS = 0>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+__global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
   tent_mfma_body<D, P, T, NTMAX, SchedRange, RK4, SYS>(
       kp, SchedRange{&kp, first, count, (int64_t)blockIdx.x, (int64_t)gridDim.x});
@@ -677,14 +682,14 @@ tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
 
 // Persistent entry point: every tent of the slab, in DAG order, by kp.dag_grid workgroups.
 template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false, int SYS = 0>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+__global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_dag_kernel(KernelParams kp) {
   tent_mfma_body<D, P, T, NTMAX, SchedDag, RK4, SYS>(kp, SchedDag{&kp});
 }
 
 // Persistent entry point of a batch: every tent of every solver's slab, in DAG order.
 template <int D, int P, typename T, int NTMAX, int WPE>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+__global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_batch_dag_kernel(const KernelParams* kps, BatchDag bd) {
   tent_mfma_body<D, P, T, NTMAX>(kps[0], SchedBatchDag{kps, bd, 0});
 }
@@ -692,7 +697,7 @@ tent_mfma_batch_dag_kernel(const KernelParams* kps, BatchDag bd) {
 // Batched entry point: workgroup b runs tent b - seg.block0 of segment seg, i.e. of the
 // layer slice (first, count) of solver seg.solver; all solvers share (D, P, T).
 template <int D, int P, typename T, int NTMAX, int WPE>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WPE)))
+__global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) {
   const int64_t b = blockIdx.x;
   int lo = 0, hi = nseg - 1;   // last segment with block0 <= b
