@@ -39,6 +39,14 @@ template <> struct Mfma<double> {
   static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // 4-row product on v_mfma_f64_4x4x4f64 (4 blocks of 4 columns, a quarter of the 16x16x4
+  // cycles): lane l supplies A(row l%4, k = l/16) and the same B value as for the 16x16x4
+  // shape (k = l/16, column l%16); lane l receives (row l/16, column l%16)  (measured)
+  using mini_t = double;
+  static __device__ __forceinline__ mini_t mini(double a, double b, mini_t c) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ double mini_out(mini_t c, int) { return c; }
 };
 template <> struct Mfma<float> {
   using acc_t = v4f;
@@ -46,6 +54,25 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
   static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // 4-row product on v_mfma_f32_4x4x1f32 (16 blocks of 4 x 4 x 1, a quarter of the 16x16x4
+  // cycles): block l/4 takes A(row l%4) and B from lane l, so with the 16x16x4 operands
+  // (k = l/16, column l%16) block (k, column group) accumulates the part of the sum over
+  // k = l/16 mod 4; value r of lane l is (row r, column l%16) of that part  (measured).
+  // The four parts are added across lanes l, l^16, l^32, l^48 at the end.
+  using mini_t = v4f;
+  static __device__ __forceinline__ mini_t mini(float a, float b, mini_t c) {
+    return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+  }
+  // row lane/16, column lane%16 of the 4-row product
+  static __device__ __forceinline__ double mini_out(mini_t c, int lane) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      c[r] += __shfl_xor(c[r], 16);
+      c[r] += __shfl_xor(c[r], 32);
+    }
+    const int r = lane >> 4;
+    return (double)(r == 0 ? c[0] : r == 1 ? c[1] : r == 2 ? c[2] : c[3]);
   }
 };
 
@@ -105,6 +132,10 @@ struct MShape {
   static constexpr int KT = KV + KFP;
   static constexpr int MT = (NP + 15) / 16;               // 16-row tiles of R
   static constexpr int MP = MT * 16;
+  // a last M-tile of at most 4 rows (P4 and P3 in 3D) runs on the 4-row MFMA shape, in the
+  // same pass as the last full tile of its column block (same B operand)
+  static constexpr bool MINI = NP > 16 && NP % 16 >= 1 && NP % 16 <= 4;
+  static constexpr int MTF = MINI ? NP / 16 : MT;         // 16-row tiles run as such
   static constexpr int NCOL = (NC * NTMAX + 15) / 16 * 16;  // columns (element, component)
   static constexpr int RS = NCOL + 1;   // row stride of U and F/R: odd, so that threads owning
                                         // consecutive nodes of one element hit distinct banks
@@ -112,7 +143,7 @@ struct MShape {
   static constexpr int FROWS = (KFP > MP) ? KFP : MP;     // F during the product, R after
   static constexpr int BLOCK = tent_block<D>();
   static constexpr int WAVES = BLOCK / 64;
-  static constexpr int TILES_PER_WAVE = (MT * NTILE_MAX + WAVES - 1) / WAVES;
+  static constexpr int TILES_PER_WAVE = (MTF * NTILE_MAX + WAVES - 1) / WAVES;
   static constexpr int MAXPAIR = (NTMAX * NP + BLOCK - 1) / BLOCK;
 };
 
@@ -137,26 +168,33 @@ struct MLds {
 // block major: the two U values a lane needs for node block `as` serve the D products
 // (l = 1..D) of that block, which differ only in the coefficients of A(grad lambda_l).
 // The raw LDS operands of the next node block are loaded before the current block's
-// products are issued (register ring, no code motion across blocks).
+// products are issued (register ring, no code motion across blocks).  Tiles are numbered
+// from the last full M-tile down; when the rows beyond the full tiles are at most 4, the
+// tiles of the last full M-tile also run those rows on the 4-row shape with the same B.
 template <typename TM, int D, int P, int NTMAX, int SYS>
 __device__ __forceinline__ void tile_product(const double* sOp, const double* sU, double* sFR, const double* sGL,
                                              int wave, int lane, int ncols, int ntiles) {
   using SH = MShape<D, P, NTMAX, SYS>;
   constexpr int NT = Phys<D, SYS>::NTERM;
   using MM = Mfma<TM>;
-  constexpr int NC = SH::NC, NV = SH::NV, NPK = SH::NPK, KV = SH::KV, KFP = SH::KFP, MT = SH::MT,
+  constexpr int NC = SH::NC, NV = SH::NV, NPK = SH::NPK, KV = SH::KV, KFP = SH::KFP, MTF = SH::MTF,
                 RS = SH::RS, WAVES = SH::WAVES, TPW = SH::TILES_PER_WAVE;
+  constexpr bool MINI = SH::MINI;
   constexpr int OPS = MLds<D, P, double, NTMAX, SYS>::OPS;
   constexpr int NB = NPK / 4;              // node blocks of the volume part
   constexpr int NG = NB + KFP / 4;         // K groups: node blocks, then lift steps
   constexpr int PDG = 2;                   // ring depth in K groups
   typename MM::acc_t accs[TPW];
+  typename MM::mini_t accm[TPW];
 #pragma unroll
   for (int ts = 0; ts < TPW; ++ts) {
     accs[ts] = typename MM::acc_t{0, 0, 0, 0};
+    accm[ts] = typename MM::mini_t{};
     const int tile = wave + WAVES * ts;
-    if (tile < MT * ntiles) {
-      const int mt = tile / ntiles, nt = tile - mt * ntiles;
+    if (tile < MTF * ntiles) {
+      const int mr = tile / ntiles, nt = tile - mr * ntiles;
+      const int mt = MTF - 1 - mr;
+      const bool with_mini = MINI && mr == 0;   // wave-uniform
       const int col = nt * 16 + (lane & 15);
       const bool live = col < ncols;
       const int e = live ? col / NC : 0;
@@ -174,60 +212,84 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       const TM fm = live ? (TM)1 : (TM)0;
       const int kq = lane >> 4;
       const double* acol = sOp + mt * 16 + (lane & 15) + kq * OPS;
+      const double* acolm = sOp + MTF * 16 + (lane & 3) + kq * OPS;   // rows beyond the full tiles
       const double* ut[NT];
 #pragma unroll
       for (int k = 0; k < NT; ++k) ut[k] = sU + kq * RS + e * NC + pt[k];
       const double* fr = sFR + kq * RS + (live ? col : 0);
-      double ra[PDG][D], ru[PDG][NT];
-      auto load = [&](int g, int slot) {
-        if (g < NB) {
+      // the K loop, without branches: WM (compile time) adds the 4-row product
+      auto kloop = [&](auto wm) {
+        constexpr bool WM = decltype(wm)::value;
+        constexpr int DM = WM ? D : 1;
+        double ra[PDG][D], rm[PDG][DM], ru[PDG][NT];
+        auto load = [&](int g, int slot) {
+          if (g < NB) {
 #pragma unroll
-          for (int l = 0; l < D; ++l) ra[slot][l] = acol[(l * NPK + 4 * g) * OPS];
+            for (int l = 0; l < D; ++l) ra[slot][l] = acol[(l * NPK + 4 * g) * OPS];
+            if constexpr (WM) {
 #pragma unroll
-          for (int k = 0; k < NT; ++k) ru[slot][k] = ut[k][4 * g * RS];
-        } else {
-          ra[slot][0] = acol[(KV + 4 * (g - NB)) * OPS];
-          ru[slot][0] = fr[4 * (g - NB) * RS];
+              for (int l = 0; l < D; ++l) rm[slot][l] = acolm[(l * NPK + 4 * g) * OPS];
+            }
+#pragma unroll
+            for (int k = 0; k < NT; ++k) ru[slot][k] = ut[k][4 * g * RS];
+          } else {
+            ra[slot][0] = acol[(KV + 4 * (g - NB)) * OPS];
+            if constexpr (WM) rm[slot][0] = acolm[(KV + 4 * (g - NB)) * OPS];
+            ru[slot][0] = fr[4 * (g - NB) * RS];
+          }
+        };
+#pragma unroll
+        for (int g = 0; g < PDG; ++g) load(g, g);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+          const int slot = g % PDG;
+          double a[D], am[DM], x[NT];
+#pragma unroll
+          for (int l = 0; l < D; ++l) a[l] = ra[slot][l];
+          if constexpr (WM) {
+#pragma unroll
+            for (int l = 0; l < D; ++l) am[l] = rm[slot][l];
+          }
+#pragma unroll
+          for (int k = 0; k < NT; ++k) x[k] = ru[slot][k];
+          if (g + PDG < NG) load(g + PDG, slot);
+          if (g < NB) {
+            TM v[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) v[k] = (TM)x[k];
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+              TM b = cf[0][l] * v[0];
+#pragma unroll
+              for (int k = 1; k < NT; ++k) b += cf[k][l] * v[k];
+              accs[ts] = MM::mma((TM)a[l], b, accs[ts]);
+              if constexpr (WM) accm[ts] = MM::mini((TM)am[l], b, accm[ts]);
+            }
+          } else {
+            const TM b = fm * (TM)x[0];
+            accs[ts] = MM::mma((TM)a[0], b, accs[ts]);
+            if constexpr (WM) accm[ts] = MM::mini((TM)am[0], b, accm[ts]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
       };
-#pragma unroll
-      for (int g = 0; g < PDG; ++g) load(g, g);
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        const int slot = g % PDG;
-        double a[D], x[NT];
-#pragma unroll
-        for (int l = 0; l < D; ++l) a[l] = ra[slot][l];
-#pragma unroll
-        for (int k = 0; k < NT; ++k) x[k] = ru[slot][k];
-        if (g + PDG < NG) load(g + PDG, slot);
-        if (g < NB) {
-          TM v[NT];
-#pragma unroll
-          for (int k = 0; k < NT; ++k) v[k] = (TM)x[k];
-#pragma unroll
-          for (int l = 0; l < D; ++l) {
-            TM b = cf[0][l] * v[0];
-#pragma unroll
-            for (int k = 1; k < NT; ++k) b += cf[k][l] * v[k];
-            accs[ts] = MM::mma((TM)a[l], b, accs[ts]);
-          }
-        } else {
-          accs[ts] = MM::mma((TM)a[0], fm * (TM)x[0], accs[ts]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      if (with_mini)
+        kloop(std::true_type{});
+      else
+        kloop(std::false_type{});
     }
   }
   __syncthreads();   // every wave is done reading F and U
 #pragma unroll
   for (int ts = 0; ts < TPW; ++ts) {
     const int tile = wave + WAVES * ts;
-    if (tile < MT * ntiles) {
-      const int mt = tile / ntiles, nt = tile - mt * ntiles;
+    if (tile < MTF * ntiles) {
+      const int mr = tile / ntiles, nt = tile - mr * ntiles;
+      const int mt = MTF - 1 - mr;
       const int col = nt * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) sFR[(mt * 16 + MM::row(lane, r)) * RS + col] = (double)accs[ts][r];
+      if (MINI && mr == 0) sFR[(MTF * 16 + (lane >> 4)) * RS + col] = MM::mini_out(accm[ts], lane);
     }
   }
   __syncthreads();
