@@ -171,7 +171,12 @@ struct MLds {
 // products are issued (register ring, no code motion across blocks).  Tiles are numbered
 // from the last full M-tile down; when the rows beyond the full tiles are at most 4, the
 // tiles of the last full M-tile also run those rows on the 4-row shape with the same B.
-template <typename TM, int D, int P, int NTMAX, int SYS>
+// Every wave runs the volume part of K (U only) for all its tiles, then waits for F and
+// runs the lift part.
+// SPLIT: the operator is stored as FP32 pairs (hi, lo) with hi + lo = the FP64 value to
+// 2^-48 relative (hi at [i], lo at [KT OPS + i] of the float view); FP32 products read hi
+// only (half the LDS bytes, no conversion), FP64 products use hi + lo.
+template <typename TM, int D, int P, int NTMAX, int SYS, bool SPLIT = false>
 __device__ __forceinline__ void tile_product(const double* sOp, const double* sU, double* sFR, const double* sGL,
                                              int wave, int lane, int ncols, int ntiles) {
   using SH = MShape<D, P, NTMAX, SYS>;
@@ -184,12 +189,20 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
   constexpr int NB = NPK / 4;              // node blocks of the volume part
   constexpr int NG = NB + KFP / 4;         // K groups: node blocks, then lift steps
   constexpr int PDG = 2;                   // ring depth in K groups
+  constexpr bool HL = SPLIT && sizeof(TM) == 8;   // FP64 products from hi + lo
+  constexpr int OPN = SH::KT * OPS;               // offset of the lo parts (floats)
+  using araw = std::conditional_t<SPLIT, float, double>;
   typename MM::acc_t accs[TPW];
   typename MM::mini_t accm[TPW];
 #pragma unroll
   for (int ts = 0; ts < TPW; ++ts) {
     accs[ts] = typename MM::acc_t{0, 0, 0, 0};
     accm[ts] = typename MM::mini_t{};
+  }
+  // K groups [G0, G1) of tile ts: the volume part (U only) or the lift part (F)
+  auto part = [&](int ts, auto lift) {
+    constexpr bool LIFT = decltype(lift)::value;
+    constexpr int G0 = LIFT ? NB : 0, G1 = LIFT ? NG : NB;
     const int tile = wave + WAVES * ts;
     if (tile < MTF * ntiles) {
       const int mr = tile / ntiles, nt = tile - mr * ntiles;
@@ -211,8 +224,9 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       }
       const TM fm = live ? (TM)1 : (TM)0;
       const int kq = lane >> 4;
-      const double* acol = sOp + mt * 16 + (lane & 15) + kq * OPS;
-      const double* acolm = sOp + MTF * 16 + (lane & 3) + kq * OPS;   // rows beyond the full tiles
+      const araw* opb = reinterpret_cast<const araw*>(sOp);
+      const araw* acol = opb + mt * 16 + (lane & 15) + kq * OPS;
+      const araw* acolm = opb + MTF * 16 + (lane & 3) + kq * OPS;   // rows beyond the full tiles
       const double* ut[NT];
 #pragma unroll
       for (int k = 0; k < NT; ++k) ut[k] = sU + kq * RS + e * NC + pt[k];
@@ -221,38 +235,60 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       auto kloop = [&](auto wm) {
         constexpr bool WM = decltype(wm)::value;
         constexpr int DM = WM ? D : 1;
-        double ra[PDG][D], rm[PDG][DM], ru[PDG][NT];
+        constexpr int DL = HL ? D : 1, DML = (HL && WM) ? D : 1;
+        araw ra[PDG][D], rm[PDG][DM], rl[PDG][DL], rml[PDG][DML];
+        double ru[PDG][NT];
         auto load = [&](int g, int slot) {
           if (g < NB) {
 #pragma unroll
-            for (int l = 0; l < D; ++l) ra[slot][l] = acol[(l * NPK + 4 * g) * OPS];
+            for (int l = 0; l < D; ++l) {
+              ra[slot][l] = acol[(l * NPK + 4 * g) * OPS];
+              if constexpr (HL) rl[slot][l] = acol[OPN + (l * NPK + 4 * g) * OPS];
+            }
             if constexpr (WM) {
 #pragma unroll
-              for (int l = 0; l < D; ++l) rm[slot][l] = acolm[(l * NPK + 4 * g) * OPS];
+              for (int l = 0; l < D; ++l) {
+                rm[slot][l] = acolm[(l * NPK + 4 * g) * OPS];
+                if constexpr (HL) rml[slot][l] = acolm[OPN + (l * NPK + 4 * g) * OPS];
+              }
             }
 #pragma unroll
             for (int k = 0; k < NT; ++k) ru[slot][k] = ut[k][4 * g * RS];
           } else {
             ra[slot][0] = acol[(KV + 4 * (g - NB)) * OPS];
-            if constexpr (WM) rm[slot][0] = acolm[(KV + 4 * (g - NB)) * OPS];
+            if constexpr (HL) rl[slot][0] = acol[OPN + (KV + 4 * (g - NB)) * OPS];
+            if constexpr (WM) {
+              rm[slot][0] = acolm[(KV + 4 * (g - NB)) * OPS];
+              if constexpr (HL) rml[slot][0] = acolm[OPN + (KV + 4 * (g - NB)) * OPS];
+            }
             ru[slot][0] = fr[4 * (g - NB) * RS];
           }
         };
+        // operator value of ring slot `slot`, index l, in the product precision
+        auto aval = [&](int slot, int l) -> TM {
+          if constexpr (HL) return (TM)((double)ra[slot][l] + (double)rl[slot][l]);
+          else return (TM)ra[slot][l];
+        };
+        auto amval = [&](int slot, int l) -> TM {
+          if constexpr (HL) return (TM)((double)rm[slot][l] + (double)rml[slot][l]);
+          else return (TM)rm[slot][l];
+        };
 #pragma unroll
-        for (int g = 0; g < PDG; ++g) load(g, g);
+        for (int g = G0; g < G0 + PDG && g < G1; ++g) load(g, g % PDG);
 #pragma unroll
-        for (int g = 0; g < NG; ++g) {
+        for (int g = G0; g < G1; ++g) {
           const int slot = g % PDG;
-          double a[D], am[DM], x[NT];
+          TM a[D], am[DM];
+          double x[NT];
 #pragma unroll
-          for (int l = 0; l < D; ++l) a[l] = ra[slot][l];
+          for (int l = 0; l < D; ++l) a[l] = aval(slot, l);
           if constexpr (WM) {
 #pragma unroll
-            for (int l = 0; l < D; ++l) am[l] = rm[slot][l];
+            for (int l = 0; l < D; ++l) am[l] = amval(slot, l);
           }
 #pragma unroll
           for (int k = 0; k < NT; ++k) x[k] = ru[slot][k];
-          if (g + PDG < NG) load(g + PDG, slot);
+          if (g + PDG < G1) load(g + PDG, slot);
           if (g < NB) {
             TM v[NT];
 #pragma unroll
@@ -262,13 +298,13 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
               TM b = cf[0][l] * v[0];
 #pragma unroll
               for (int k = 1; k < NT; ++k) b += cf[k][l] * v[k];
-              accs[ts] = MM::mma((TM)a[l], b, accs[ts]);
-              if constexpr (WM) accm[ts] = MM::mini((TM)am[l], b, accm[ts]);
+              accs[ts] = MM::mma(a[l], b, accs[ts]);
+              if constexpr (WM) accm[ts] = MM::mini(am[l], b, accm[ts]);
             }
           } else {
             const TM b = fm * (TM)x[0];
-            accs[ts] = MM::mma((TM)a[0], b, accs[ts]);
-            if constexpr (WM) accm[ts] = MM::mini((TM)am[0], b, accm[ts]);
+            accs[ts] = MM::mma(a[0], b, accs[ts]);
+            if constexpr (WM) accm[ts] = MM::mini(am[0], b, accm[ts]);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -278,7 +314,14 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       else
         kloop(std::false_type{});
     }
-  }
+  };
+  // every wave runs the volume part of all its tiles first: it needs U only, so it may
+  // overlap the end of the face-flux phase (the caller does not synchronise after it)
+#pragma unroll
+  for (int ts = 0; ts < TPW; ++ts) part(ts, std::false_type{});
+  __syncthreads();   // F is complete
+#pragma unroll
+  for (int ts = 0; ts < TPW; ++ts) part(ts, std::true_type{});
   __syncthreads();   // every wave is done reading F and U
 #pragma unroll
   for (int ts = 0; ts < TPW; ++ts) {
@@ -463,7 +506,8 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   int* sF = sK + NTMAX;
 
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar registers)
   // A operand [k][m]: S_l[m][a] at k = l NPK + a (a < NP), -L_j[m][s] at k = KV + j NF + s,
   // zero in the padding rows and columns
   for (int i = tid; i < KT * OPS; i += BLOCK) {
@@ -478,7 +522,14 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
         v = -kp0.L[(j * NF + s) * NP + m];
       }
     }
-    sOp[i] = v;
+    if constexpr (MIXED) {   // FP32 pairs: hi, then lo = the rounding error of hi
+      float* sOpF = reinterpret_cast<float*>(sOp);
+      const float hi = (float)v;
+      sOpF[i] = hi;
+      sOpF[KT * OPS + i] = (float)(v - (double)hi);
+    } else {
+      sOp[i] = v;
+    }
   }
   // padding rows of U and F are read by the product (times zero): keep them finite
   for (int i = tid; i < (NPK - NP) * RS; i += BLOCK) sU[NP * RS + i] = 0.0;
@@ -560,7 +611,9 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
       // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col], each face once:
       //      the other side of an interior face gets -(|grad lambda_jn| / |grad lambda_j|) G
       //      at its own face-node order (exchanged when the two orders differ)
-      for (int it = tid; it < nFace * NF; it += BLOCK) {
+      // items from the last thread down: a short last round falls on the last wave, which
+      // has the fewest product tiles and so the most slack in the product's volume part
+      for (int it = BLOCK - 1 - tid; it < nFace * NF; it += BLOCK) {
         const int fi = it / NF;
         const int s = it - fi * NF;
         const int fc = kp.pface[f0 + fi];
@@ -607,7 +660,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
           for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
         }
       }
-      __syncthreads();
+      // no barrier: the product reads F only after its volume part and a barrier
     };
 
     if constexpr (RK4) {
@@ -619,7 +672,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
         for (int s = 0; s < 4; ++s) {
           const double th = (i + (s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5))) * invm;
           face_fluxes(th, 1);
-          tile_product<double, D, P, NTMAX, SYS>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<double, D, P, NTMAX, SYS, MIXED>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
           const double thn = (s == 3) ? (i + 1) * invm : (i + (s == 2 ? 1.0 : 0.5)) * invm;
           const double a = (s == 2) ? invm : 0.5 * invm;   // weight of k_s in the next stage input
           const double wk = (s == 0 || s == 3) ? 1.0 : 2.0;
@@ -664,9 +717,9 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 
         // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
         if (MIXED && n >= 2)
-          tile_product<float, D, P, NTMAX, SYS>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<float, D, P, NTMAX, SYS, MIXED>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
         else
-          tile_product<double, D, P, NTMAX, SYS>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<double, D, P, NTMAX, SYS, MIXED>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
 
         // ---- Taylor accumulation (FP64) and the next U for the owned (element, node) pairs
 #pragma unroll
