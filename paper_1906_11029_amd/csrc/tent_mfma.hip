@@ -157,8 +157,8 @@ struct MLds {
   static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
   static constexpr size_t f_elems = (size_t)SH::FROWS * SH::RS;
   static constexpr size_t t_bytes = (op_elems + u_elems + f_elems) * 8;
-  static constexpr size_t geo_doubles = (size_t)NTMAX * (SH::NV * D + D + 2);
-  static constexpr size_t ints = (size_t)D * 2 * SH::NF + (size_t)NTMAX * (2 + D);
+  static constexpr size_t geo_doubles = (size_t)NTMAX * (SH::NV * D + D + 2) + (size_t)NTMAX * D;
+  static constexpr size_t ints = (size_t)D * 2 * SH::NF + (size_t)NTMAX * (2 + D) + (size_t)NTMAX * D + SH::NF;
   static constexpr size_t bytes = t_bytes + geo_doubles * 8 + ints * 4;
 };
 
@@ -500,10 +500,13 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   double* sGL = sFR + LD::f_elems;                // [e][v][x]
   double* sBb = sGL + NTMAX * NV * D;             // [e][x]
   double* sEM = sBb + NTMAX * D;                  // [e][2]
-  int* sFn = reinterpret_cast<int*>(sEM + NTMAX * 2);
+  double* sRat = sEM + NTMAX * 2;                 // [face]: -|grad lambda_jn| / |grad lambda_j|
+  int* sFn = reinterpret_cast<int*>(sRat + NTMAX * D);
   int* sElem = sFn + D * 2 * NF;
   int* sK = sElem + NTMAX;
   int* sF = sK + NTMAX;
+  int* sPF = sF + NTMAX * D;                      // [face]: patch face code (element << 2 | face)
+  int* sFsw = sPF + NTMAX * D;                    // [s]: face node with the two non-V vertices exchanged
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -535,6 +538,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   for (int i = tid; i < (NPK - NP) * RS; i += BLOCK) sU[NP * RS + i] = 0.0;
   for (int i = tid; i < (SH::FROWS - KF) * RS; i += BLOCK) sFR[KF * RS + i] = 0.0;
   for (int i = tid; i < D * 2 * NF; i += BLOCK) sFn[i] = kp0.fnode[i];
+  for (int i = tid; i < NF; i += BLOCK) sFsw[i] = kp0.fswap[i];
 
   __shared__ int sh_tent[2];
   for (;;) {
@@ -603,6 +607,28 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
         for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = u[c];
       }
     }
+    // per face, once per tent: the face code and, for an interior face, the factor that
+    // carries the flux to the other side
+    for (int fi = tid; fi < nFace; fi += BLOCK) {
+      const int fc = kp.pface[f0 + fi];
+      const int e = fc >> 2, j = fc & 3;
+      const int code = sF[e * D + j];
+      double ratio = 0.0;
+      if (code >= 0) {
+        const int pe = code >> 4, jn = (code >> 1) & 7;
+        double gg = 0.0, gn = 0.0;
+#pragma unroll
+        for (int x = 0; x < D; ++x) {
+          const double a = sGL[(e * NV + j + 1) * D + x];
+          gg += a * a;
+          const double h = sGL[(pe * NV + jn) * D + x];
+          gn += h * h;
+        }
+        ratio = -sqrt(gn / gg);
+      }
+      sPF[fi] = fc;
+      sRat[fi] = ratio;
+    }
     __syncthreads();
 
     // ---- face fluxes for stage input U at sub-interval time th (data ghosts: derivative
@@ -616,7 +642,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
       for (int it = BLOCK - 1 - tid; it < nFace * NF; it += BLOCK) {
         const int fi = it / NF;
         const int s = it - fi * NF;
-        const int fc = kp.pface[f0 + fi];
+        const int fc = sPF[fi];
         const int e = fc >> 2, j = fc & 3;
         const int nin = sFn[(j * 2) * NF + s];
         double um[NC], up[NC], G[NC], g[D];
@@ -634,15 +660,8 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
             PH::fl_imp(g, sqrt(sEM[2 * e + 1] / sEM[2 * e]), sqrt(sEM[2 * pe + 1] / sEM[2 * pe]), um, up, G);
           else
             PH::fl(g, kp.alpha, um, up, G);
-          double gg = 0.0, gn = 0.0;
-#pragma unroll
-          for (int x = 0; x < D; ++x) {
-            gg += g[x] * g[x];
-            const double h = sGL[(pe * NV + jn) * D + x];
-            gn += h * h;
-          }
-          const double ratio = -sqrt(gn / gg);
-          const int s2 = o ? kp.fswap[s] : s;
+          const double ratio = sRat[fi];
+          const int s2 = o ? sFsw[s] : s;
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             sFR[(j * NF + s) * RS + e * NC + c] = G[c];
