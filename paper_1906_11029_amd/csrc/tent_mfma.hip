@@ -199,11 +199,30 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
     accs[ts] = typename MM::acc_t{0, 0, 0, 0};
     accm[ts] = typename MM::mini_t{};
   }
+  // tile of slot ts of this wave: round robin, except for the full P4 patch (9 column
+  // blocks, 9 tiles with the 4-row part and 9 without), where a fixed assignment evens
+  // the matrix-core time of the four SIMDs (waves w and w + 4 share one): 5.25 / 5.25 /
+  // 5 / 4.75 tile units instead of 5.75 / 5.5 / 4.5 / 4.5 (5-bit entries, 31 = none)
+  auto tile_of = [&](int ts) -> int {
+    if constexpr (MINI && MTF == 2 && WAVES == 8 && TPW == 3) {
+      if (ntiles == 9) {
+        constexpr uint64_t T0 = 0ull | 1ull << 5 | 2ull << 10 | 4ull << 15 | 13ull << 20 | 15ull << 25 |
+                                6ull << 30 | 8ull << 35;
+        constexpr uint64_t T1 = 9ull | 11ull << 5 | 3ull << 10 | 5ull << 15 | 14ull << 20 | 16ull << 25 |
+                                7ull << 30 | 17ull << 35;
+        constexpr uint64_t T2 = 10ull | 12ull << 5 | 31ull << 10 | 31ull << 15 | 31ull << 20 | 31ull << 25 |
+                                31ull << 30 | 31ull << 35;
+        const uint64_t tab = ts == 0 ? T0 : ts == 1 ? T1 : T2;
+        return (int)((tab >> (5 * wave)) & 31);
+      }
+    }
+    return wave + WAVES * ts;
+  };
   // K groups [G0, G1) of tile ts: the volume part (U only) or the lift part (F)
   auto part = [&](int ts, auto lift) {
     constexpr bool LIFT = decltype(lift)::value;
     constexpr int G0 = LIFT ? NB : 0, G1 = LIFT ? NG : NB;
-    const int tile = wave + WAVES * ts;
+    const int tile = tile_of(ts);
     if (tile < MTF * ntiles) {
       const int mr = tile / ntiles, nt = tile - mr * ntiles;
       const int mt = MTF - 1 - mr;
@@ -325,7 +344,7 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
   __syncthreads();   // every wave is done reading F and U
 #pragma unroll
   for (int ts = 0; ts < TPW; ++ts) {
-    const int tile = wave + WAVES * ts;
+    const int tile = tile_of(ts);
     if (tile < MTF * ntiles) {
       const int mr = tile / ntiles, nt = tile - mr * ntiles;
       const int mt = MTF - 1 - mr;
