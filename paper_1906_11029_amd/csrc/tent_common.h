@@ -40,15 +40,26 @@ __device__ __forceinline__ void applyA<2>(const double* g, const double* u, doub
 // Closed-form inverse of u -> g(u) - f(u) b  (section 4):
 //   E = s (I - b b^T/(eps mu)) (mu w_E + w_H x b),  H = s (I - b b^T/(eps mu)) (eps w_H - w_E x b),
 //   s = 1/(eps mu - |b|^2).  Returns false if eps mu - |b|^2 <= 0 (causality violated).
+// The two scalars of the inverse depend only on b and the medium: f = (s, 1/(eps mu)).
+// Returns false if eps mu - |b|^2 <= 0 (causality violated).
 template <int D>
-__device__ __forceinline__ bool kinv(const double* b, double eps, double mu, const double* w, double* u);
-template <>
-__device__ __forceinline__ bool kinv<3>(const double* b, double eps, double mu, const double* w, double* u) {
+__device__ __forceinline__ bool kinv_fac(const double* b, double eps, double mu, double* f) {
   const double em = eps * mu;
-  const double bb = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  double bb = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) bb += b[i] * b[i];
   const double den = em - bb;
-  const double s = 1.0 / den;
-  const double iem = 1.0 / em;
+  f[0] = 1.0 / den;
+  f[1] = 1.0 / em;
+  return den > 0.0;
+}
+template <int D>
+__device__ __forceinline__ void kinv_apply(const double* b, double eps, double mu, const double* f, const double* w,
+                                           double* u);
+template <>
+__device__ __forceinline__ void kinv_apply<3>(const double* b, double eps, double mu, const double* f, const double* w,
+                                              double* u) {
+  const double s = f[0], iem = f[1];
   double rE[3], rH[3];
   rE[0] = mu * w[0] + (w[4] * b[2] - w[5] * b[1]);
   rE[1] = mu * w[1] + (w[5] * b[0] - w[3] * b[2]);
@@ -62,21 +73,24 @@ __device__ __forceinline__ bool kinv<3>(const double* b, double eps, double mu, 
     u[i] = s * (rE[i] - b[i] * pE);
     u[3 + i] = s * (rH[i] - b[i] * pH);
   }
-  return den > 0.0;
 }
 template <>
-__device__ __forceinline__ bool kinv<2>(const double* b, double eps, double mu, const double* w, double* u) {
-  const double em = eps * mu;
-  const double bb = b[0] * b[0] + b[1] * b[1];
-  const double den = em - bb;
-  const double s = 1.0 / den;
+__device__ __forceinline__ void kinv_apply<2>(const double* b, double eps, double mu, const double* f, const double* w,
+                                              double* u) {
+  const double s = f[0], iem = f[1];
   const double rx = mu * w[0] - w[2] * b[1];
   const double ry = mu * w[1] + w[2] * b[0];
-  const double pE = (b[0] * rx + b[1] * ry) / em;
+  const double pE = (b[0] * rx + b[1] * ry) * iem;
   u[0] = s * (rx - b[0] * pE);
   u[1] = s * (ry - b[1] * pE);
   u[2] = s * (eps * w[2] - (w[0] * b[1] - w[1] * b[0]));
-  return den > 0.0;
+}
+template <int D>
+__device__ __forceinline__ bool kinv(const double* b, double eps, double mu, const double* w, double* u) {
+  double f[2];
+  const bool ok = kinv_fac<D>(b, eps, mu, f);
+  kinv_apply<D>(b, eps, mu, f, w, u);
+  return ok;
 }
 
 // Upwind flux times |g| for the outward direction g = -grad lambda_j (unnormalised):
@@ -174,20 +188,32 @@ __device__ __forceinline__ void applyA_ac(const double* g, const double* u, doub
 // Closed-form inverse of u -> g(u) - f(u) b = (kappa p - v.b, rho v - p b):
 //   p = (rho w_p + b.w_v) / (kappa rho - |b|^2),  v = (w_v + p b) / rho.
 template <int D>
-__device__ __forceinline__ bool kinv_ac(const double* b, double kappa, double rho, const double* w, double* u) {
-  double bb = 0.0, bw = 0.0;
+__device__ __forceinline__ bool kinv_ac_fac(const double* b, double kappa, double rho, double* f) {
+  double bb = 0.0;
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    bb += b[i] * b[i];
-    bw += b[i] * w[1 + i];
-  }
+  for (int i = 0; i < D; ++i) bb += b[i] * b[i];
   const double den = kappa * rho - bb;
-  const double p = (rho * w[0] + bw) / den;
-  const double ir = 1.0 / rho;
+  f[0] = 1.0 / den;
+  f[1] = 1.0 / rho;
+  return den > 0.0;
+}
+template <int D>
+__device__ __forceinline__ void kinv_ac_apply(const double* b, double kappa, double rho, const double* f,
+                                              const double* w, double* u) {
+  double bw = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) bw += b[i] * w[1 + i];
+  const double p = (rho * w[0] + bw) * f[0];
   u[0] = p;
 #pragma unroll
-  for (int i = 0; i < D; ++i) u[1 + i] = (w[1 + i] + p * b[i]) * ir;
-  return den > 0.0;
+  for (int i = 0; i < D; ++i) u[1 + i] = (w[1 + i] + p * b[i]) * f[1];
+}
+template <int D>
+__device__ __forceinline__ bool kinv_ac(const double* b, double kappa, double rho, const double* w, double* u) {
+  double f[2];
+  const bool ok = kinv_ac_fac<D>(b, kappa, rho, f);
+  kinv_ac_apply<D>(b, kappa, rho, f, w, u);
+  return ok;
 }
 
 // Upwind flux times |g|:  1/2 A(g)(u_in + u_out) + alpha |g| (dp, (dv.n) n),  d = in - out
@@ -243,6 +269,14 @@ template <int D> struct Phys<D, 0> {
   static __device__ __forceinline__ bool inv(const double* b, double c1, double c2, const double* w, double* u) {
     return kinv<D>(b, c1, c2, w, u);
   }
+  // the inverse in two steps: its scalars at b (once per element and time), then the map
+  static __device__ __forceinline__ bool inv_fac(const double* b, double c1, double c2, double* f) {
+    return kinv_fac<D>(b, c1, c2, f);
+  }
+  static __device__ __forceinline__ void inv_apply(const double* b, double c1, double c2, const double* f,
+                                                   const double* w, double* u) {
+    kinv_apply<D>(b, c1, c2, f, w, u);
+  }
   static __device__ __forceinline__ void fl(const double* g, double a, const double* um, const double* up, double* G) {
     flux<D>(g, a, um, up, G);
   }
@@ -256,6 +290,13 @@ template <int D> struct Phys<D, 1> {
   static __device__ __forceinline__ void A(const double* g, const double* u, double* o) { applyA_ac<D>(g, u, o); }
   static __device__ __forceinline__ bool inv(const double* b, double c1, double c2, const double* w, double* u) {
     return kinv_ac<D>(b, c1, c2, w, u);
+  }
+  static __device__ __forceinline__ bool inv_fac(const double* b, double c1, double c2, double* f) {
+    return kinv_ac_fac<D>(b, c1, c2, f);
+  }
+  static __device__ __forceinline__ void inv_apply(const double* b, double c1, double c2, const double* f,
+                                                   const double* w, double* u) {
+    kinv_ac_apply<D>(b, c1, c2, f, w, u);
   }
   static __device__ __forceinline__ void fl(const double* g, double a, const double* um, const double* up, double* G) {
     flux_ac<D>(g, a, um, up, G);

@@ -157,7 +157,7 @@ struct MLds {
   static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
   static constexpr size_t f_elems = (size_t)SH::FROWS * SH::RS;
   static constexpr size_t t_bytes = (op_elems + u_elems + f_elems) * 8;
-  static constexpr size_t geo_doubles = (size_t)NTMAX * (SH::NV * D + D + 2) + (size_t)NTMAX * D;
+  static constexpr size_t geo_doubles = (size_t)NTMAX * (SH::NV * D + D + 2) + (size_t)NTMAX * D + 4 * (size_t)NTMAX;
   static constexpr size_t ints = (size_t)D * 2 * SH::NF + (size_t)NTMAX * (2 + D) + (size_t)NTMAX * D + SH::NF;
   static constexpr size_t bytes = t_bytes + geo_doubles * 8 + ints * 4;
 };
@@ -520,7 +520,8 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   double* sBb = sGL + NTMAX * NV * D;             // [e][x]
   double* sEM = sBb + NTMAX * D;                  // [e][2]
   double* sRat = sEM + NTMAX * 2;                 // [face]: -|grad lambda_jn| / |grad lambda_j|
-  int* sFn = reinterpret_cast<int*>(sRat + NTMAX * D);
+  double* sFac = sRat + NTMAX * D;                // [slot][e][2]: scalars of K(b(th))^{-1}, th = i / m
+  int* sFn = reinterpret_cast<int*>(sFac + 4 * NTMAX);
   int* sElem = sFn + D * 2 * NF;
   int* sK = sElem + NTMAX;
   int* sF = sK + NTMAX;
@@ -647,6 +648,24 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
       }
       sPF[fi] = fc;
       sRat[fi] = ratio;
+    }
+    // scalars of the inverse at th_0 and th_1 (slot i & 1 holds th_i); the recursion then
+    // computes th_{i+2} into the slot th_i leaves, in the last stage of sub-interval i.  Only
+    // th_i with i < m are used (the tent top is never inverted), and only those are formed,
+    // so that the causality flag covers exactly the inversions the method makes
+    auto fac_at = [&](int ib, int slot) {
+      for (int e = BLOCK - 1 - tid; e < nT; e += BLOCK) {
+        const double thb = ib * invm;
+        const double* gv = &sGL[(e * NV + 0) * D];
+        double bi[D];
+#pragma unroll
+        for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + thb * (H * gv[x]);
+        ok &= PH::inv_fac(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[(slot * NTMAX + e) * 2]);
+      }
+    };
+    if constexpr (!RK4) {
+      fac_at(0, 0);
+      if (kp.m > 1) fac_at(1, 1);
     }
     __syncthreads();
 
@@ -786,14 +805,14 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
               PH::A(bp, uo, au);
 #pragma unroll
               for (int c = 0; c < NC; ++c) rhs[c] = Y[c] + n * au[c];
-              ok &= PH::inv(bi, sEM[2 * e], sEM[2 * e + 1], rhs, un);
+              PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[((i & 1) * NTMAX + e) * 2], rhs, un);
               write = true;
             } else if (i + 1 < kp.m) {
               double bi[D];
               const double th1 = (i + 1) * invm;
 #pragma unroll
-              for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * H * gv[x];
-              ok &= PH::inv(bi, sEM[2 * e], sEM[2 * e + 1], acc[r], un);
+              for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * (H * gv[x]);
+              PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[(((i + 1) & 1) * NTMAX + e) * 2], acc[r], un);
               write = true;
             }
             if (write) {
@@ -802,6 +821,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
             }
           }
         }
+        if (n == kp.q && i + 2 < kp.m) fac_at(i + 2, i & 1);   // read again in sub-interval i + 1's last stage
         __syncthreads();
       }
     }
