@@ -97,14 +97,32 @@ __device__ __forceinline__ bool kinv(const double* b, double eps, double mu, con
 //   G = 1/2 A(g)(u_in + u_out) + alpha |g| P_t (u_in - u_out),   P_t = tangential part.
 template <int D>
 __device__ __forceinline__ void flux(const double* g, double alpha, const double* um, const double* up, double* G);
+// The face scalars fs = (|g|, 1/|g|^2) depend only on the face: face_scalars forms them once.
+template <int D>
+__device__ __forceinline__ void face_scalars(const double* g, double* fs) {
+  double gg = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) gg += g[i] * g[i];
+  fs[0] = sqrt(gg);
+  fs[1] = 1.0 / gg;
+}
+template <int D>
+__device__ __forceinline__ void flux_f(const double* g, const double* fs, double alpha, const double* um,
+                                       const double* up, double* G);
+template <int D>
+__device__ __forceinline__ void flux(const double* g, double alpha, const double* um, const double* up, double* G) {
+  double fs[2];
+  face_scalars<D>(g, fs);
+  flux_f<D>(g, fs, alpha, um, up, G);
+}
 template <>
-__device__ __forceinline__ void flux<3>(const double* g, double alpha, const double* um, const double* up, double* G) {
+__device__ __forceinline__ void flux_f<3>(const double* g, const double* fs, double alpha, const double* um,
+                                          const double* up, double* G) {
   double s[6], dlt[6];
   for (int c = 0; c < 6; ++c) { s[c] = 0.5 * (um[c] + up[c]); dlt[c] = um[c] - up[c]; }
   applyA<3>(g, s, G);
-  const double gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-  const double gn = sqrt(gg);
-  const double ig = 1.0 / gg;
+  const double gn = fs[0];
+  const double ig = fs[1];
   const double nE = (g[0] * dlt[0] + g[1] * dlt[1] + g[2] * dlt[2]) * ig;
   const double nH = (g[0] * dlt[3] + g[1] * dlt[4] + g[2] * dlt[5]) * ig;
   const double ag = alpha * gn;
@@ -114,13 +132,13 @@ __device__ __forceinline__ void flux<3>(const double* g, double alpha, const dou
   }
 }
 template <>
-__device__ __forceinline__ void flux<2>(const double* g, double alpha, const double* um, const double* up, double* G) {
+__device__ __forceinline__ void flux_f<2>(const double* g, const double* fs, double alpha, const double* um,
+                                          const double* up, double* G) {
   double s[3], dlt[3];
   for (int c = 0; c < 3; ++c) { s[c] = 0.5 * (um[c] + up[c]); dlt[c] = um[c] - up[c]; }
   applyA<2>(g, s, G);
-  const double gg = g[0] * g[0] + g[1] * g[1];
-  const double gn = sqrt(gg);
-  const double nE = (g[0] * dlt[0] + g[1] * dlt[1]) / gg;
+  const double gn = fs[0];
+  const double nE = (g[0] * dlt[0] + g[1] * dlt[1]) * fs[1];
   const double ag = alpha * gn;
   G[0] += ag * (dlt[0] - nE * g[0]);
   G[1] += ag * (dlt[1] - nE * g[1]);
@@ -135,12 +153,12 @@ __device__ __forceinline__ void flux<2>(const double* g, double alpha, const dou
 //   H* = (zm H_in + zp H_out + n x (E_in - E_out)) / (zm + zp)
 // (normal parts of E*, H* drop out of A(g)).  zm = zp = 1 gives the alpha = 1/2 flux.
 template <int D>
-__device__ __forceinline__ void flux_imp(const double* g, double zm, double zp, const double* um, const double* up,
-                                         double* G);
+__device__ __forceinline__ void flux_imp(const double* g, const double* fs, double zm, double zp, const double* um,
+                                         const double* up, double* G);
 template <>
-__device__ __forceinline__ void flux_imp<3>(const double* g, double zm, double zp, const double* um,
-                                            const double* up, double* G) {
-  const double in = 1.0 / sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+__device__ __forceinline__ void flux_imp<3>(const double* g, const double* fs, double zm, double zp,
+                                            const double* um, const double* up, double* G) {
+  const double in = fs[0] * fs[1];   // 1/|g|
   const double n[3] = {g[0] * in, g[1] * in, g[2] * in};
   const double dE[3] = {um[0] - up[0], um[1] - up[1], um[2] - up[2]};
   const double dH[3] = {um[3] - up[3], um[4] - up[4], um[5] - up[5]};
@@ -155,10 +173,10 @@ __device__ __forceinline__ void flux_imp<3>(const double* g, double zm, double z
   applyA<3>(g, us, G);
 }
 template <>
-__device__ __forceinline__ void flux_imp<2>(const double* g, double zm, double zp, const double* um,
-                                            const double* up, double* G) {
+__device__ __forceinline__ void flux_imp<2>(const double* g, const double* fs, double zm, double zp,
+                                            const double* um, const double* up, double* G) {
   // TE: E in the plane, H = Hz e_z; n x (Hz e_z) = Hz (n_y, -n_x), (n x E)_z = n_x Ey - n_y Ex
-  const double in = 1.0 / sqrt(g[0] * g[0] + g[1] * g[1]);
+  const double in = fs[0] * fs[1];
   const double nx = g[0] * in, ny = g[1] * in;
   const double dHz = um[2] - up[2];
   const double nxdE = nx * (um[1] - up[1]) - ny * (um[0] - up[0]);
@@ -219,40 +237,36 @@ __device__ __forceinline__ bool kinv_ac(const double* b, double kappa, double rh
 // Upwind flux times |g|:  1/2 A(g)(u_in + u_out) + alpha |g| (dp, (dv.n) n),  d = in - out
 // (alpha = 1/2: the exact upwind flux for unit impedance).
 template <int D>
-__device__ __forceinline__ void flux_ac(const double* g, double alpha, const double* um, const double* up,
-                                        double* G) {
+__device__ __forceinline__ void flux_ac(const double* g, const double* fs, double alpha, const double* um,
+                                        const double* up, double* G) {
   double s[D + 1];
 #pragma unroll
   for (int c = 0; c <= D; ++c) s[c] = 0.5 * (um[c] + up[c]);
   applyA_ac<D>(g, s, G);
-  double gg = 0.0, dvg = 0.0;
+  double dvg = 0.0;
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    gg += g[i] * g[i];
-    dvg += g[i] * (um[1 + i] - up[1 + i]);
-  }
-  const double gn = sqrt(gg);
+  for (int i = 0; i < D; ++i) dvg += g[i] * (um[1 + i] - up[1 + i]);
+  const double gn = fs[0], ign = fs[0] * fs[1];   // |g|, 1/|g|
   G[0] += alpha * gn * (um[0] - up[0]);
 #pragma unroll
-  for (int i = 0; i < D; ++i) G[1 + i] += alpha * (dvg / gn) * g[i];
+  for (int i = 0; i < D; ++i) G[1 + i] += alpha * (dvg * ign) * g[i];
 }
 
 // Impedance-matched upwind flux: A(g) u* with the interface state of the Riemann problem
 // along n = g/|g|:  p* = (zp p_in + zm p_out + zm zp (v_in - v_out).n) / (zm + zp),
 // v*.n = (zm v_in.n + zp v_out.n + p_in - p_out) / (zm + zp).
 template <int D>
-__device__ __forceinline__ void flux_imp_ac(const double* g, double zm, double zp, const double* um,
-                                            const double* up, double* G) {
-  double gg = 0.0, vmg = 0.0, vpg = 0.0;
+__device__ __forceinline__ void flux_imp_ac(const double* g, const double* fs, double zm, double zp,
+                                            const double* um, const double* up, double* G) {
+  double vmg = 0.0, vpg = 0.0;
 #pragma unroll
   for (int i = 0; i < D; ++i) {
-    gg += g[i] * g[i];
     vmg += g[i] * um[1 + i];
     vpg += g[i] * up[1 + i];
   }
-  const double gn = sqrt(gg), is = 1.0 / (zm + zp);
-  const double ps = (zp * um[0] + zm * up[0] + zm * zp * (vmg - vpg) / gn) * is;
-  const double vns = (zm * vmg + zp * vpg) / gn * is + (um[0] - up[0]) * is;
+  const double gn = fs[0], ign = fs[0] * fs[1], is = 1.0 / (zm + zp);
+  const double ps = (zp * um[0] + zm * up[0] + zm * zp * (vmg - vpg) * ign) * is;
+  const double vns = (zm * vmg + zp * vpg) * ign * is + (um[0] - up[0]) * is;
   G[0] = gn * vns;
 #pragma unroll
   for (int i = 0; i < D; ++i) G[1 + i] = ps * g[i];
@@ -277,12 +291,14 @@ template <int D> struct Phys<D, 0> {
                                                    const double* w, double* u) {
     kinv_apply<D>(b, c1, c2, f, w, u);
   }
-  static __device__ __forceinline__ void fl(const double* g, double a, const double* um, const double* up, double* G) {
-    flux<D>(g, a, um, up, G);
+  // fluxes with the face scalars fs = (|g|, 1/|g|^2) of face_scalars
+  static __device__ __forceinline__ void fl(const double* g, const double* fs, double a, const double* um,
+                                            const double* up, double* G) {
+    flux_f<D>(g, fs, a, um, up, G);
   }
-  static __device__ __forceinline__ void fl_imp(const double* g, double zm, double zp, const double* um,
-                                                const double* up, double* G) {
-    flux_imp<D>(g, zm, zp, um, up, G);
+  static __device__ __forceinline__ void fl_imp(const double* g, const double* fs, double zm, double zp,
+                                                const double* um, const double* up, double* G) {
+    flux_imp<D>(g, fs, zm, zp, um, up, G);
   }
 };
 template <int D> struct Phys<D, 1> {
@@ -298,12 +314,13 @@ template <int D> struct Phys<D, 1> {
                                                    const double* w, double* u) {
     kinv_ac_apply<D>(b, c1, c2, f, w, u);
   }
-  static __device__ __forceinline__ void fl(const double* g, double a, const double* um, const double* up, double* G) {
-    flux_ac<D>(g, a, um, up, G);
+  static __device__ __forceinline__ void fl(const double* g, const double* fs, double a, const double* um,
+                                            const double* up, double* G) {
+    flux_ac<D>(g, fs, a, um, up, G);
   }
-  static __device__ __forceinline__ void fl_imp(const double* g, double zm, double zp, const double* um,
-                                                const double* up, double* G) {
-    flux_imp_ac<D>(g, zm, zp, um, up, G);
+  static __device__ __forceinline__ void fl_imp(const double* g, const double* fs, double zm, double zp,
+                                                const double* um, const double* up, double* G) {
+    flux_imp_ac<D>(g, fs, zm, zp, um, up, G);
   }
 };
 

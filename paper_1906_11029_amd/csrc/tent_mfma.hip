@@ -140,7 +140,10 @@ struct MShape {
   static constexpr int RS = NCOL + 1;   // row stride of U and F/R: odd, so that threads owning
                                         // consecutive nodes of one element hit distinct banks
   static constexpr int NTILE_MAX = NCOL / 16;
-  static constexpr int FROWS = (KFP > MP) ? KFP : MP;     // F during the product, R after
+  // F during the product (KF rows: the lift part's last K step clamps its rows beyond KF,
+  // which meet zero operator columns), R after (up to MP rows, 16 MTF + 4 with the 4-row part)
+  static constexpr int RROWS = MINI ? MTF * 16 + 4 : MP;
+  static constexpr int FROWS = (KF > RROWS) ? KF : RROWS;
   static constexpr int BLOCK = tent_block<D>();
   static constexpr int WAVES = BLOCK / 64;
   static constexpr int TILES_PER_WAVE = (MTF * NTILE_MAX + WAVES - 1) / WAVES;
@@ -157,7 +160,8 @@ struct MLds {
   static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
   static constexpr size_t f_elems = (size_t)SH::FROWS * SH::RS;
   static constexpr size_t t_bytes = (op_elems + u_elems + f_elems) * 8;
-  static constexpr size_t geo_doubles = (size_t)NTMAX * (SH::NV * D + D + 2) + (size_t)NTMAX * D + 4 * (size_t)NTMAX;
+  static constexpr size_t geo_doubles =
+      (size_t)NTMAX * (SH::NV * D + D + 2) + 3 * (size_t)NTMAX * D + 4 * (size_t)NTMAX;
   static constexpr size_t ints = (size_t)D * 2 * SH::NF + (size_t)NTMAX * (2 + D) + (size_t)NTMAX * D + SH::NF;
   static constexpr size_t bytes = t_bytes + geo_doubles * 8 + ints * 4;
 };
@@ -182,7 +186,7 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
   using SH = MShape<D, P, NTMAX, SYS>;
   constexpr int NT = Phys<D, SYS>::NTERM;
   using MM = Mfma<TM>;
-  constexpr int NC = SH::NC, NV = SH::NV, NPK = SH::NPK, KV = SH::KV, KFP = SH::KFP, MTF = SH::MTF,
+  constexpr int NC = SH::NC, NV = SH::NV, NPK = SH::NPK, KV = SH::KV, KF = SH::KF, KFP = SH::KFP, MTF = SH::MTF,
                 RS = SH::RS, WAVES = SH::WAVES, TPW = SH::TILES_PER_WAVE;
   constexpr bool MINI = SH::MINI;
   constexpr int OPS = MLds<D, P, double, NTMAX, SYS>::OPS;
@@ -249,7 +253,8 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       const double* ut[NT];
 #pragma unroll
       for (int k = 0; k < NT; ++k) ut[k] = sU + kq * RS + e * NC + pt[k];
-      const double* fr = sFR + kq * RS + (live ? col : 0);
+      const int colp = live ? col : 0;
+      const double* fr = sFR + kq * RS + colp;
       // the K loop, without branches: WM (compile time) adds the 4-row product
       auto kloop = [&](auto wm) {
         constexpr bool WM = decltype(wm)::value;
@@ -280,7 +285,10 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
               rm[slot][0] = acolm[(KV + 4 * (g - NB)) * OPS];
               if constexpr (HL) rml[slot][0] = acolm[OPN + (KV + 4 * (g - NB)) * OPS];
             }
-            ru[slot][0] = fr[4 * (g - NB) * RS];
+            if (4 * (g - NB) + 3 < KF)
+              ru[slot][0] = fr[4 * (g - NB) * RS];
+            else   // rows beyond KF meet zero operator columns: read row KF - 1 instead
+              ru[slot][0] = sFR[min(4 * (g - NB) + kq, KF - 1) * RS + colp];
           }
         };
         // operator value of ring slot `slot`, index l, in the product precision
@@ -520,7 +528,8 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   double* sBb = sGL + NTMAX * NV * D;             // [e][x]
   double* sEM = sBb + NTMAX * D;                  // [e][2]
   double* sRat = sEM + NTMAX * 2;                 // [face]: -|grad lambda_jn| / |grad lambda_j|
-  double* sFac = sRat + NTMAX * D;                // [slot][e][2]: scalars of K(b(th))^{-1}, th = i / m
+  double* sFs = sRat + NTMAX * D;                 // [face][2]: |g|, 1/|g|^2 of the face direction g
+  double* sFac = sFs + 2 * NTMAX * D;             // [slot][e][2]: scalars of K(b(th))^{-1}, th = i / m
   int* sFn = reinterpret_cast<int*>(sFac + 4 * NTMAX);
   int* sElem = sFn + D * 2 * NF;
   int* sK = sElem + NTMAX;
@@ -633,6 +642,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
       const int fc = kp.pface[f0 + fi];
       const int e = fc >> 2, j = fc & 3;
       const int code = sF[e * D + j];
+      face_scalars<D>(&sGL[(e * NV + j + 1) * D], &sFs[2 * fi]);
       double ratio = 0.0;
       if (code >= 0) {
         const int pe = code >> 4, jn = (code >> 1) & 7;
@@ -695,9 +705,10 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 #pragma unroll
           for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
           if (kp.flux_kind == 1)
-            PH::fl_imp(g, sqrt(sEM[2 * e + 1] / sEM[2 * e]), sqrt(sEM[2 * pe + 1] / sEM[2 * pe]), um, up, G);
+            PH::fl_imp(g, &sFs[2 * fi], sqrt(sEM[2 * e + 1] / sEM[2 * e]), sqrt(sEM[2 * pe + 1] / sEM[2 * pe]), um,
+                       up, G);
           else
-            PH::fl(g, kp.alpha, um, up, G);
+            PH::fl(g, &sFs[2 * fi], kp.alpha, um, up, G);
           const double ratio = sRat[fi];
           const int s2 = o ? sFsw[s] : s;
 #pragma unroll
@@ -709,9 +720,9 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
           ghost_state<D, P, SYS>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
           if (kp.flux_kind == 1) {   // walls and data: the element's own medium on both sides
             const double z = sqrt(sEM[2 * e + 1] / sEM[2 * e]);
-            PH::fl_imp(g, z, z, um, up, G);
+            PH::fl_imp(g, &sFs[2 * fi], z, z, um, up, G);
           } else {
-            PH::fl(g, kp.alpha, um, up, G);
+            PH::fl(g, &sFs[2 * fi], kp.alpha, um, up, G);
           }
 #pragma unroll
           for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
