@@ -64,13 +64,18 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ mini_t mini(float a, float b, mini_t c) {
     return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
   }
-  // row lane/16, column lane%16 of the 4-row product
+  // row lane/16, column lane%16 of the 4-row product.  The cross-lane sums use the
+  // register swaps of gfx950 (v_permlane16_swap / v_permlane32_swap: the two results hold
+  // x[l] and x[l ^ 16], resp. x[l ^ 32], in some order; measured), not LDS permutes.
+  static __device__ __forceinline__ float xor_sum(float x, bool by32) {
+    const unsigned u = __float_as_uint(x);
+    const auto p = by32 ? __builtin_amdgcn_permlane32_swap(u, u, false, false)
+                        : __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  }
   static __device__ __forceinline__ double mini_out(mini_t c, int lane) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      c[r] += __shfl_xor(c[r], 16);
-      c[r] += __shfl_xor(c[r], 32);
-    }
+    for (int r = 0; r < 4; ++r) c[r] = xor_sum(xor_sum(c[r], false), true);
     const int r = lane >> 4;
     return (double)(r == 0 ? c[0] : r == 1 ? c[1] : r == 2 ? c[2] : c[3]);
   }
