@@ -125,6 +125,15 @@ def mtp_mesh_destroy(mesh):
     load().mtp_mesh_destroy(mesh)
 
 
+def _release(name, h):
+    """Destroy handle h with the library call `name` from a finaliser. Skipped once the
+    library is gone: at interpreter shutdown module globals are cleared, and the process
+    releases its memory anyway."""
+    lib = _lib
+    if h and lib is not None:
+        getattr(lib, name)(h)
+
+
 def mtp_pitch_layers(mesh, t_end, slope_fraction=0.5):
     h = C.c_void_p()
     _check(load().mtp_pitch_layers(mesh, float(t_end), float(slope_fraction), C.byref(h)))
@@ -345,10 +354,9 @@ class Mesh:
         if system != MTP_SYSTEM_MAXWELL:
             mtp_mesh_set_system(self.h, system)
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            mtp_mesh_destroy(self.h)
-            self.h = None
+    def __del__(self, _free=_release):   # bound at definition: safe at interpreter shutdown
+        _free("mtp_mesh_destroy", getattr(self, "h", None))
+        self.h = None
 
 
 class Tents:
@@ -364,10 +372,9 @@ class Tents:
     def dag(self):
         return mtp_tents_dag(self.mesh.h, self.h)
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            mtp_tents_destroy(self.h)
-            self.h = None
+    def __del__(self, _free=_release):   # bound at definition: safe at interpreter shutdown
+        _free("mtp_tents_destroy", getattr(self, "h", None))
+        self.h = None
 
 
 class Solver:
@@ -446,10 +453,9 @@ class Solver:
     def checkpoint_read(self, path):
         mtp_checkpoint_read(self.h, path)
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            mtp_solver_destroy(self.h)
-            self.h = None
+    def __del__(self, _free=_release):   # bound at definition: safe at interpreter shutdown
+        _free("mtp_solver_destroy", getattr(self, "h", None))
+        self.h = None
 
 
 class Batch:
@@ -472,7 +478,6 @@ class Batch:
     def set_schedule(self, schedule):
         mtp_batch_set_schedule(self.h, schedule)
 
-    def __del__(self):
-        if getattr(self, "h", None):
-            mtp_batch_destroy(self.h)
-            self.h = None
+    def __del__(self, _free=_release):   # bound at definition: safe at interpreter shutdown
+        _free("mtp_batch_destroy", getattr(self, "h", None))
+        self.h = None
