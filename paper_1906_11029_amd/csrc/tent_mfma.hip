@@ -160,8 +160,10 @@ struct MShape {
 template <int D, int P, typename T, int NTMAX, int SYS = 0>
 struct MLds {
   using SH = MShape<D, P, NTMAX, SYS>;
-  static constexpr int OPS = SH::MP;
-  static constexpr size_t op_elems = (size_t)SH::KT * OPS;
+  static constexpr int OPS = SH::RROWS;   // operator rows read by the products
+  // FP64 operator, then (mixed kernel) the FP32 copy of its volume part, in doubles
+  static constexpr size_t opf_floats = sizeof(T) == 4 ? (size_t)SH::KV * OPS : 0;
+  static constexpr size_t op_elems = (size_t)SH::KT * OPS + (opf_floats + 1) / 2;
   static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
   static constexpr size_t f_elems = (size_t)SH::FROWS * SH::RS;
   static constexpr size_t t_bytes = (op_elems + u_elems + f_elems) * 8;
@@ -182,12 +184,12 @@ struct MLds {
 // tiles of the last full M-tile also run those rows on the 4-row shape with the same B.
 // Every wave runs the volume part of K (U only) for all its tiles, then waits for F and
 // runs the lift part.
-// SPLIT: the operator is stored as FP32 pairs (hi, lo) with hi + lo = the FP64 value to
-// 2^-48 relative (hi at [i], lo at [KT OPS + i] of the float view); FP32 products read hi
-// only (half the LDS bytes, no conversion), FP64 products use hi + lo.
-template <typename TM, int D, int P, int NTMAX, int SYS, bool SPLIT = false>
-__device__ __forceinline__ void tile_product(const double* sOp, const double* sU, double* sFR, const double* sGL,
-                                             int wave, int lane, int ncols, int ntiles) {
+// sOpF (mixed kernel): an FP32 copy of the volume part of the operator (KV rows of OPS);
+// the FP32 products read their volume operands from it (half the LDS bytes, no
+// conversion), everything else reads the FP64 operator sOp.
+template <typename TM, int D, int P, int NTMAX, int SYS>
+__device__ __forceinline__ void tile_product(const double* sOp, const float* sOpF, const double* sU, double* sFR,
+                                             const double* sGL, int wave, int lane, int ncols, int ntiles) {
   using SH = MShape<D, P, NTMAX, SYS>;
   constexpr int NT = Phys<D, SYS>::NTERM;
   using MM = Mfma<TM>;
@@ -198,9 +200,7 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
   constexpr int NB = NPK / 4;              // node blocks of the volume part
   constexpr int NG = NB + KFP / 4;         // K groups: node blocks, then lift steps
   constexpr int PDG = 2;                   // ring depth in K groups
-  constexpr bool HL = SPLIT && sizeof(TM) == 8;   // FP64 products from hi + lo
-  constexpr int OPN = SH::KT * OPS;               // offset of the lo parts (floats)
-  using araw = std::conditional_t<SPLIT, float, double>;
+  constexpr bool F32 = sizeof(TM) == 4;
   typename MM::acc_t accs[TPW];
   typename MM::mini_t accm[TPW];
 #pragma unroll
@@ -252,9 +252,13 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       }
       const TM fm = live ? (TM)1 : (TM)0;
       const int kq = lane >> 4;
-      const araw* opb = reinterpret_cast<const araw*>(sOp);
+      // operand rows of this tile (lane & 15) and of the rows beyond the full tiles (lane & 3):
+      // the volume part of an FP32 product from the FP32 copy, the rest from the FP64 operator
+      using araw = std::conditional_t<F32 && !LIFT, float, double>;
+      const araw* opb;
+      if constexpr (F32 && !LIFT) opb = sOpF; else opb = sOp;
       const araw* acol = opb + mt * 16 + (lane & 15) + kq * OPS;
-      const araw* acolm = opb + MTF * 16 + (lane & 3) + kq * OPS;   // rows beyond the full tiles
+      const araw* acolm = opb + MTF * 16 + (lane & 3) + kq * OPS;
       const double* ut[NT];
 #pragma unroll
       for (int k = 0; k < NT; ++k) ut[k] = sU + kq * RS + e * NC + pt[k];
@@ -264,32 +268,21 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
       auto kloop = [&](auto wm) {
         constexpr bool WM = decltype(wm)::value;
         constexpr int DM = WM ? D : 1;
-        constexpr int DL = HL ? D : 1, DML = (HL && WM) ? D : 1;
-        araw ra[PDG][D], rm[PDG][DM], rl[PDG][DL], rml[PDG][DML];
+        araw ra[PDG][D], rm[PDG][DM];
         double ru[PDG][NT];
         auto load = [&](int g, int slot) {
           if (g < NB) {
 #pragma unroll
-            for (int l = 0; l < D; ++l) {
-              ra[slot][l] = acol[(l * NPK + 4 * g) * OPS];
-              if constexpr (HL) rl[slot][l] = acol[OPN + (l * NPK + 4 * g) * OPS];
-            }
+            for (int l = 0; l < D; ++l) ra[slot][l] = acol[(l * NPK + 4 * g) * OPS];
             if constexpr (WM) {
 #pragma unroll
-              for (int l = 0; l < D; ++l) {
-                rm[slot][l] = acolm[(l * NPK + 4 * g) * OPS];
-                if constexpr (HL) rml[slot][l] = acolm[OPN + (l * NPK + 4 * g) * OPS];
-              }
+              for (int l = 0; l < D; ++l) rm[slot][l] = acolm[(l * NPK + 4 * g) * OPS];
             }
 #pragma unroll
             for (int k = 0; k < NT; ++k) ru[slot][k] = ut[k][4 * g * RS];
           } else {
             ra[slot][0] = acol[(KV + 4 * (g - NB)) * OPS];
-            if constexpr (HL) rl[slot][0] = acol[OPN + (KV + 4 * (g - NB)) * OPS];
-            if constexpr (WM) {
-              rm[slot][0] = acolm[(KV + 4 * (g - NB)) * OPS];
-              if constexpr (HL) rml[slot][0] = acolm[OPN + (KV + 4 * (g - NB)) * OPS];
-            }
+            if constexpr (WM) rm[slot][0] = acolm[(KV + 4 * (g - NB)) * OPS];
             if (4 * (g - NB) + 3 < KF)
               ru[slot][0] = fr[4 * (g - NB) * RS];
             else   // rows beyond KF meet zero operator columns: read row KF - 1 instead
@@ -297,14 +290,8 @@ __device__ __forceinline__ void tile_product(const double* sOp, const double* sU
           }
         };
         // operator value of ring slot `slot`, index l, in the product precision
-        auto aval = [&](int slot, int l) -> TM {
-          if constexpr (HL) return (TM)((double)ra[slot][l] + (double)rl[slot][l]);
-          else return (TM)ra[slot][l];
-        };
-        auto amval = [&](int slot, int l) -> TM {
-          if constexpr (HL) return (TM)((double)rm[slot][l] + (double)rml[slot][l]);
-          else return (TM)rm[slot][l];
-        };
+        auto aval = [&](int slot, int l) -> TM { return (TM)ra[slot][l]; };
+        auto amval = [&](int slot, int l) -> TM { return (TM)rm[slot][l]; };
 #pragma unroll
         for (int g = G0; g < G0 + PDG && g < G1; ++g) load(g, g % PDG);
 #pragma unroll
@@ -527,6 +514,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   using LD = MLds<D, P, T, NTMAX, SYS>;
   extern __shared__ double lds_d[];
   double* sOp = lds_d;                            // [k][m], m fastest
+  float* sOpF = reinterpret_cast<float*>(sOp + KT * OPS);   // mixed: FP32 copy of the volume rows k < KV
   double* sU = sOp + LD::op_elems;                // [node][col]
   double* sFR = sU + LD::u_elems;                 // [row][col]: F, then R
   double* sGL = sFR + LD::f_elems;                // [e][v][x]
@@ -559,13 +547,9 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
         v = -kp0.L[(j * NF + s) * NP + m];
       }
     }
-    if constexpr (MIXED) {   // FP32 pairs: hi, then lo = the rounding error of hi
-      float* sOpF = reinterpret_cast<float*>(sOp);
-      const float hi = (float)v;
-      sOpF[i] = hi;
-      sOpF[KT * OPS + i] = (float)(v - (double)hi);
-    } else {
-      sOp[i] = v;
+    sOp[i] = v;
+    if constexpr (MIXED) {
+      if (k < KV) sOpF[i] = (float)v;
     }
   }
   // padding rows of U and F are read by the product (times zero): keep them finite
@@ -745,7 +729,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
         for (int s = 0; s < 4; ++s) {
           const double th = (i + (s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5))) * invm;
           face_fluxes(th, 1);
-          tile_product<double, D, P, NTMAX, SYS, MIXED>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
           const double thn = (s == 3) ? (i + 1) * invm : (i + (s == 2 ? 1.0 : 0.5)) * invm;
           const double a = (s == 2) ? invm : 0.5 * invm;   // weight of k_s in the next stage input
           const double wk = (s == 0 || s == 3) ? 1.0 : 2.0;
@@ -790,9 +774,9 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 
         // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
         if (MIXED && n >= 2)
-          tile_product<float, D, P, NTMAX, SYS, MIXED>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<float, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
         else
-          tile_product<double, D, P, NTMAX, SYS, MIXED>(sOp, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
 
         // ---- Taylor accumulation (FP64) and the next U for the owned (element, node) pairs
 #pragma unroll
