@@ -11,10 +11,12 @@
 // loading the B operand (two LDS reads and two multiply-adds per value: A(g) is a cross
 // product), so only U and F are stored.  Accumulators stay in registers until every wave
 // has finished reading F, then R overwrites F in LDS.  The plain path (T = double) runs
-// every product on v_mfma_f64_16x16x4f64.  The mixed path (T = float) keeps the same FP64
-// storage and FP64 first stage of every sub-interval, and runs the products of the later
-// stages, which act on the small Taylor coefficients U_{i,n} (n >= 1), on
-// v_mfma_f32_16x16x4f32; the closed-form inverses, fluxes and the Taylor sum stay FP64.
+// every product on v_mfma_f64_16x16x4f64, and at most 4 rows beyond the full 16-row tiles
+// on v_mfma_f64_4x4x4f64.  The mixed path (T = float) keeps the same FP64 storage (plus an
+// FP32 copy of the operator's volume part) and FP64 first stage of every sub-interval,
+// and runs the products of the later stages, which act on the small Taylor coefficients
+// U_{i,n} (n >= 1), on v_mfma_f32_16x16x4f32 / v_mfma_f32_4x4x1f32; the closed-form
+// inverses, fluxes and the Taylor sum stay FP64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
