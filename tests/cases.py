@@ -25,6 +25,11 @@ CASES = {
     "single_tri_p2": dict(mesh=("tri1", 1), p=2, q=3, m=4, T=0.5, kind=PEC, exact="pec_te"),
     "single_tet_p3": dict(mesh=("tet1", 1), p=3, q=4, m=6, T=0.3, kind=PMC, exact="pec_3d"),
     "te_pmc_p2_two_slabs": dict(mesh=("square_pi", 4), p=2, q=3, m=4, T=0.25, kind=PMC, exact="pmc_te", slabs=2),
+    # sub-interval edge cases: one sub-interval (the tent top is never inverted), odd m with
+    # the 4-row tiles (P3 in 3D), and first-order Taylor (q = 1: no recursion step)
+    "te_pmc_p2_m1": dict(mesh=("square_pi", 4), p=2, q=3, m=1, T=0.1, kind=PMC, exact="pmc_te"),
+    "cav3d_p3_m5": dict(mesh=("kuhn", 2), p=3, q=4, m=5, T=0.25, kind=PEC, exact="pec_3d"),
+    "cav3d_p2_q1_m3": dict(mesh=("kuhn", 2), p=2, q=1, m=3, T=0.1, kind=PEC, exact="pec_3d"),
 }
 
 # the classical RK4 variant (method="rk4"): same inputs, RK4 on the tent ODE
