@@ -52,13 +52,16 @@ enum {
   MTP_ERR_ARG = -1,         /* invalid argument (null pointer, size, range)            */
   MTP_ERR_MESH = -2,        /* non-conforming mesh, degenerate element, bad face kind  */
   MTP_ERR_CAUSALITY = -3,   /* slope fraction outside (0,1): tents would not be causal */
-  MTP_ERR_PITCH = -4,       /* pitching made no progress                               */
+  MTP_ERR_PITCH = -4,       /* pitching made no progress (also: a tent table that is   */
+                            /* not one mtp_pitch_layers made)                          */
   MTP_ERR_NONFINITE = -5,   /* non-finite field values                                 */
   MTP_ERR_DEVICE = -6,      /* HIP runtime error or a device-side check failed         */
   MTP_ERR_STATE = -7,       /* call out of order (e.g. advancing past the tent table)  */
   MTP_ERR_NOMEM = -8,       /* host memory exhausted                                   */
   MTP_ERR_UNSUPPORTED = -9  /* (dim, p) or patch size outside what the kernels cover   */
 };
+/* the name of the pitching status in the boundary sketch this interface follows */
+enum { MTP_ERR_PITCH_STALL = MTP_ERR_PITCH };
 
 /* boundary-condition kinds of boundary faces */
 enum { MTP_BC_PEC = 0, MTP_BC_PMC = 1, MTP_BC_DATA = 2 };
@@ -74,15 +77,19 @@ enum { MTP_BC_PEC = 0, MTP_BC_PMC = 1, MTP_BC_DATA = 2 };
  *                        single solves.                                             */
 enum { MTP_SYSTEM_MAXWELL = 0, MTP_SYSTEM_ACOUSTIC = 1 };
 
-/* arithmetic of the tent kernels
+/* arithmetic of the tent kernels (section 4's recursion Y_{i,n} = A U_{i,n-1}: the
+ * contractions; the pointwise inverse and the Taylor sum of eq. taylor_pol)
  *   MTP_FP64       plain FP64; contractions on the FP64 matrix cores (falls back to the
  *                  vector-ALU kernel when a patch does not fit the matrix-core kernel)
  *   MTP_MIXED_FP32 the contractions of SAT stages n >= 2, which act on the small Taylor
  *                  coefficients U_{i,n-1}, n-1 >= 1, run on the FP32 matrix cores; the first
  *                  stage of every sub-interval (acting on U_{i,0}, the size of the fields),
  *                  the closed-form inversions, fluxes and the Taylor sum stay FP64
- *   MTP_FP64_VALU  plain FP64 on the vector ALUs (reference kernel)                    */
-enum { MTP_FP64 = 0, MTP_MIXED_FP32 = 1, MTP_FP64_VALU = 2 };
+ *   MTP_FP64_VALU  plain FP64 on the vector ALUs (reference kernel)
+ *   MTP_BF16X3     reserved for split-BF16 contractions of the stages n >= 2 (three BF16
+ *                  products per FP32 product, FP32 accumulation); not built: solvers
+ *                  asking for it get MTP_ERR_UNSUPPORTED                                */
+enum { MTP_FP64 = 0, MTP_MIXED_FP32 = 1, MTP_FP64_VALU = 2, MTP_BF16X3 = 3 };
 
 /* how a slab's tents are scheduled on the device
  *   MTP_SCHEDULE_LAYERS  one launch per layer (stream order is the layer barrier)
@@ -114,10 +121,13 @@ enum { MTP_FLUX_PENALTY = 0, MTP_FLUX_IMPEDANCE = 1 };
 mtp_status mtp_mesh_set_system(mtp_mesh mesh, int32_t system);
 
 /* Conforming simplicial mesh (section 2).  dim = 2 (triangles, TE fields) or 3 (tets).
- * coords (nv*dim), cells (ne*(dim+1)), eps/mu (ne) per-element material constants,
- * face_bc (ne*(dim+1)) boundary kind per local face, read only where the face lies on the
- * domain boundary; NULL means PEC everywhere.  Errors: MTP_ERR_ARG, MTP_ERR_MESH
- * (zero-volume element, a face shared by more than two elements, eps or mu <= 0). */
+ * coords (nv*dim), cells (ne*(dim+1), int32: meshes up to 2^31 - 1 vertices and elements),
+ * eps/mu (ne) per-element material constants, face_bc (ne*(dim+1)) boundary kind per local
+ * face, read only where the face lies on the domain boundary; NULL means PEC everywhere.
+ * (The boundary is given per local face, not as a separate list of boundary faces: every
+ * element's kinds sit beside its cell, and faces need not be matched on the host.)  All
+ * arrays are copied.  Errors: MTP_ERR_ARG, MTP_ERR_MESH (zero-volume element, a face
+ * shared by more than two elements, eps or mu <= 0). */
 mtp_status mtp_mesh_create(int32_t dim, int64_t nv, const double* coords, int64_t ne,
                            const int32_t* cells, const double* eps, const double* mu,
                            const int32_t* face_bc, mtp_mesh* out);
@@ -125,21 +135,32 @@ mtp_status mtp_mesh_info(mtp_mesh mesh, int32_t* dim, int64_t* nv, int64_t* ne,
                          int32_t* max_patch);
 void mtp_mesh_destroy(mtp_mesh mesh);
 
-/* Tent pitching on the host (section 2), from the flat front t = 0 to the flat front
- * t = t_end.  Rule (the paper defers the algorithm to earlier work; this is the
- * library's documented choice): per element k_T = slope_fraction*sqrt(eps mu) /
- * min_i sum_{j!=i} |grad lambda_j|, per edge k_vw = min over its elements; repeatedly
- * the vertex with the smallest (time, id) moves to min(t_end, Q floor((min over
- * neighbours w of tau_w + k_vw)/Q - 1e-3)), Q = 2^-24, in layer 1 + the largest layer
- * of itself and its neighbours.  Keeps |grad tau| <= slope_fraction*sqrt(eps mu) on every
- * element (the paper's experiments use 1/2).  Errors: MTP_ERR_ARG (t_end <= 0),
- * MTP_ERR_CAUSALITY (slope_fraction not in (0,1)), MTP_ERR_PITCH. */
-mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_end, double slope_fraction, mtp_tents* out);
-/* n_tents, n_layers; layer_ptr (n_layers+1 entries, may be NULL) receives the start of
- * each layer in the layer-sorted tent order used by mtp_tents_export. */
+/* Tent pitching on the host (section 2: the front is advanced one vertex at a time,
+ * each step limited by causality; section 5 bounds the front slope by 1/(2c)), from the
+ * flat front t = t_start to the flat front t = t_end.  Rule (the paper defers the
+ * algorithm to earlier work; this is the library's documented choice): per element
+ * k_T = slope_fraction*sqrt(eps mu) / min_i sum_{j!=i} |grad lambda_j|, per edge
+ * k_vw = min over its elements; repeatedly the vertex with the smallest (time, id) moves
+ * to min(H, Q floor((min over neighbours w of tau_w + k_vw)/Q - 1e-3)), Q = 2^-24,
+ * H = t_end - t_start, times measured from t_start, in layer 1 + the largest layer of
+ * itself and its neighbours.  Keeps |grad tau| <= slope_fraction*sqrt(eps mu) on every
+ * element (the paper's experiments use 1/2).  The table is a slab of height H: a solver
+ * applies it from its current flat front (mtp_set_fields' t0) and repeats it slab after
+ * slab (mtp_advance_to), so one table serves every slab bit for bit.  Errors:
+ * MTP_ERR_ARG (t_end <= t_start or not finite), MTP_ERR_CAUSALITY (slope_fraction not in
+ * (0,1)), MTP_ERR_PITCH. */
+mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_start, double t_end, double slope_fraction,
+                            mtp_tents* out);
+/* Size of a tent table (section 2: tents whose vertices are at graph distance >= 2 are
+ * independent; a layer is a set of such tents).  n_tents, n_layers; layer_ptr
+ * (n_layers+1 entries, may be NULL) receives the start of each layer in the layer-sorted
+ * tent order used by mtp_tents_export.  Host only.  Errors: MTP_ERR_ARG. */
 mtp_status mtp_tents_query(mtp_tents tents, int64_t* n_tents, int64_t* n_layers, int64_t* layer_ptr);
-/* Tent list sorted by layer (stable in pitching order): central vertex, bottom and top
- * time, layer.  Any pointer may be NULL. */
+/* The tent table itself (section 2: a tent is the vertex that moves, the front time at
+ * that vertex below and above it; its spatial extent is the vertex patch), sorted by
+ * layer (stable in pitching order): central vertex, bottom and top time (absolute:
+ * t_start plus the relative time), layer.  Arrays of n_tents entries owned by the caller;
+ * any pointer may be NULL.  Host only.  Errors: MTP_ERR_ARG. */
 mtp_status mtp_tents_export(mtp_tents tents, int32_t* vertex, double* t_bot, double* t_top,
                             int32_t* layer);
 void mtp_tents_destroy(mtp_tents tents);
@@ -159,24 +180,39 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
                              void* hip_stream, mtp_solver* out);
 void mtp_solver_destroy(mtp_solver solver);
 
-/* Physical coordinates of the interchange nodes, host array (ne*Np*dim). */
+/* Physical coordinates of the interchange nodes (the equispaced nodes of the degree-p
+ * Lagrange basis described above; section 3 discretises each tent by DG of degree p):
+ * host array of ne*Np*dim doubles owned by the caller.  Host only.  Errors: MTP_ERR_ARG. */
 mtp_status mtp_node_coords(mtp_solver solver, double* xyz);
 
-/* Set the fields u on the flat front t0 (must be a multiple of the slab height times an
- * integer, normally 0).  nodal: (ne, Np, nc) doubles, host pointer if on_device == 0,
- * else a device pointer.  Stores w = g(u) (section 4: Y = MU continuous across tents).
+/* Set the fields u on the flat front t0 (normally the t_start of the tent table).
+ * nodal: exactly ne*Np*nc doubles in the interchange layout (ne, Np, nc), a host pointer if
+ * on_device == 0, else a device pointer on the solver's device; the library reads that many
+ * values and no more (a shorter array is read past its end: the binding checks the shape).
+ * Stores w = g(u) (section 4: Y = MU passes unchanged from one tent to the next).
  * Errors: MTP_ERR_ARG, MTP_ERR_NONFINITE (host input), MTP_ERR_DEVICE. */
 mtp_status mtp_set_fields(mtp_solver solver, const double* nodal, int32_t on_device, double t0);
 
-/* Boundary data for MTP_BC_DATA faces: the plane wave
- * u(x,t) = amp * cos(k.x - omega t + phase), amp = (E amplitude, H amplitude) with nc
- * entries, kvec (dim entries), omega.  The ghost state on a data face of a tent is
- * u(x, phi(x,t)), entering the SAT recursion through its t-derivatives
- * delta^n d_t^n u (chain rule of the tent map), interpolated at the face nodes. */
+/* Boundary data for MTP_BC_DATA faces (section 5.1 prescribes initial and boundary values
+ * from the exact solution): the plane wave u(x,t) = amp * cos(k.x - omega t + phase).
+ * amp: nc doubles, the amplitude of every field component (Maxwell 3D: E then H; 2D TE:
+ * Ex, Ey, Hz; acoustics: p then v), kvec: dim doubles, omega: angular frequency.  The
+ * caller states the full field amplitude, so any medium and system is covered; for a
+ * Maxwell wave in a uniform medium with direction d and wave number k (the boundary
+ * sketch's (dir, k, amp_E, phase)) pass kvec = k d, omega = k/sqrt(eps mu) and
+ * amp = (amp_E, sqrt(eps/mu) d x amp_E).  The ghost state on a data face of a tent is
+ * u(x, phi(x,t)), entering the SAT recursion through its t-derivatives delta^n d_t^n u
+ * (chain rule of the tent map), interpolated at the face nodes.  Takes effect for work
+ * enqueued after the call (synchronises the solver's stream and drops the captured slab
+ * graph, which holds the old data).  Errors: MTP_ERR_ARG (null or non-finite values). */
 mtp_status mtp_set_planewave_bc(mtp_solver solver, const double* amp, const double* kvec,
                                 double omega, double phase);
 
-/* Enqueue the tents of one layer of the current slab (stream ordered, asynchronous). */
+/* Enqueue the tents of one layer of the current slab (section 2: the tents of a layer are
+ * causally independent and run concurrently; layers run in order).  Stream ordered,
+ * asynchronous; layer must be the next one of the slab.  Errors: MTP_ERR_ARG,
+ * MTP_ERR_STATE (out of order, or data faces without mtp_set_planewave_bc),
+ * MTP_ERR_DEVICE. */
 mtp_status mtp_layer_advance(mtp_solver solver, int64_t layer);
 /* Enqueue whole slabs until the flat front reaches T (T must be the current front time
  * plus a whole number of slab heights).  Asynchronous.  By default the first call captures
@@ -184,15 +220,18 @@ mtp_status mtp_layer_advance(mtp_solver solver, int64_t layer);
  * stream and every slab replays it on the solver's stream; the slab's time offset lives in
  * device memory, so one graph serves all slabs. */
 mtp_status mtp_advance_to(mtp_solver solver, double T);
-/* Current front time (flat) and number of layers done in the current slab. */
+/* Current front time (flat) and number of layers done in the current slab.  Host only. */
 mtp_status mtp_front(mtp_solver solver, double* t_front, int64_t* layers_done);
 
-/* Read-out on the current flat front: u = K(grad tau)^{-1} w node by node, written in the
- * interchange format to a host (on_device == 0, synchronises the stream) or device
- * pointer.  Also surfaces device-side error flags (MTP_ERR_DEVICE: a tent met
- * eps*mu - |grad phi|^2 <= 0; MTP_ERR_NONFINITE). */
+/* Read-out (section 4: on a flat front the mass form is diagonal in the materials, and
+ * in general u = K(grad tau)^{-1} w node by node): writes ne*Np*nc doubles in the
+ * interchange format to a host (on_device == 0) or device pointer owned by the caller.
+ * Synchronises the solver's stream and surfaces device-side error flags (MTP_ERR_DEVICE:
+ * a tent met eps*mu - |grad phi|^2 <= 0, or a persistent-schedule wait exceeded its
+ * bound; MTP_ERR_NONFINITE). */
 mtp_status mtp_get_fields(mtp_solver solver, double* nodal, int32_t on_device);
-/* Raw state w (interchange layout), host or device pointer. */
+/* Raw state w = g(u) - f(u) grad tau (the variable tents pass on, section 4), same layout,
+ * ownership and errors as mtp_get_fields. */
 mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
 
 /* Batches of independent solves (section 2: tents on different meshes are independent).

@@ -140,3 +140,29 @@ def equispaced_nodes(mesh, p):
     X = mesh["coords"][mesh["cells"]]  # (ne, d+1, d)
     J = X[:, 1:, :] - X[:, :1, :]      # rows = v_l - v0
     return X[:, :1, :] + np.einsum("nl,eld->end", ref, J)
+
+
+def fan_disk(nfan, radius=1.0, rings=2):
+    """Disk of the given radius around a centre vertex of valence nfan: `rings` rings of
+    nfan vertices (ring r at radius r/rings, every other ring rotated by half a sector),
+    the centre joined to the first ring, neighbouring rings joined by strips of 2 nfan
+    triangles.  The centre's patch holds nfan triangles."""
+    coords = [(0.0, 0.0)]
+    for r in range(1, rings + 1):
+        off = 0.5 * (r % 2 == 0)
+        for i in range(nfan):
+            a = 2.0 * np.pi * (i + off) / nfan
+            coords.append((radius * r / rings * np.cos(a), radius * r / rings * np.sin(a)))
+    coords = np.asarray(coords)
+    vid = lambda r, i: 1 + (r - 1) * nfan + (i % nfan)  # noqa: E731
+    cells = [(0, vid(1, i), vid(1, i + 1)) for i in range(nfan)]
+    for r in range(1, rings):
+        for i in range(nfan):
+            if r % 2 == 1:   # outer ring r+1 is rotated forward by half a sector
+                cells.append((vid(r, i), vid(r + 1, i), vid(r, i + 1)))
+                cells.append((vid(r, i + 1), vid(r + 1, i), vid(r + 1, i + 1)))
+            else:            # outer ring r+1 is aligned with ring r - 1, behind ring r
+                cells.append((vid(r, i), vid(r + 1, i + 1), vid(r, i + 1)))
+                cells.append((vid(r, i), vid(r + 1, i), vid(r + 1, i + 1)))
+    cells = np.asarray(cells, dtype=np.int32)
+    return {"coords": coords, "cells": _orient(coords, cells)}

@@ -283,14 +283,18 @@ mtp_status mtp_mesh_info(mtp_mesh mesh, int32_t* dim, int64_t* nv, int64_t* ne, 
 
 void mtp_mesh_destroy(mtp_mesh mesh) { delete mesh; }
 
-mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_end, double slope_fraction, mtp_tents* out) {
+mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_start, double t_end, double slope_fraction, mtp_tents* out) {
   MTP_TRY
   require(mesh && out, MTP_ERR_ARG, "null pointer");
-  require(t_end > 0 && std::isfinite(t_end), MTP_ERR_ARG, "t_end must be positive");
+  require(std::isfinite(t_start) && std::isfinite(t_end) && t_end > t_start, MTP_ERR_ARG,
+          "need finite t_start < t_end");
   require(slope_fraction > 0 && slope_fraction < 1, MTP_ERR_CAUSALITY, "slope fraction must be in (0,1)");
   auto* h = new mtp_tents_s();
   try {
-    pitch(mesh->m, t_end, slope_fraction, h->t);
+    // times relative to t_start: the table is a slab pattern that solvers apply from their
+    // current flat front, and one table serves every slab bit for bit
+    pitch(mesh->m, t_end - t_start, slope_fraction, h->t);
+    h->t.t_start = t_start;
   } catch (...) {
     delete h;
     throw;
@@ -314,8 +318,8 @@ mtp_status mtp_tents_export(mtp_tents tents, int32_t* vertex, double* t_bot, dou
   require(tents, MTP_ERR_ARG, "null tents");
   const Tents& t = tents->t;
   if (vertex) std::copy(t.vertex.begin(), t.vertex.end(), vertex);
-  if (t_bot) std::copy(t.t_bot.begin(), t.t_bot.end(), t_bot);
-  if (t_top) std::copy(t.t_top.begin(), t.t_top.end(), t_top);
+  if (t_bot) for (size_t i = 0; i < t.t_bot.size(); ++i) t_bot[i] = t.t_start + t.t_bot[i];
+  if (t_top) for (size_t i = 0; i < t.t_top.size(); ++i) t_top[i] = t.t_start + t.t_top[i];
   if (layer) std::copy(t.layer.begin(), t.layer.end(), layer);
   MTP_CATCH
 }
@@ -327,6 +331,7 @@ static int ncomp(const Mesh& m) { return m.system == MTP_SYSTEM_ACOUSTIC ? m.d +
 
 // Kernel choice: 0 = vector-ALU FP64, 1 = matrix-core FP64, 2 = matrix-core FP32 (mixed).
 static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
+  require(precision != MTP_BF16X3, MTP_ERR_UNSUPPORTED, "split-BF16 contractions are not built");
   require(precision == MTP_FP64 || precision == MTP_MIXED_FP32 || precision == MTP_FP64_VALU,
           MTP_ERR_UNSUPPORTED, "unknown precision");
   require(q >= 1 && q <= 32 && mm >= 1 && mm <= 1024, MTP_ERR_ARG, "q must be in 1..32 and m in 1..1024");
@@ -537,6 +542,13 @@ mtp_status mtp_set_fields(mtp_solver s, const double* nodal, int32_t on_device, 
 mtp_status mtp_set_planewave_bc(mtp_solver s, const double* amp, const double* kvec, double omega, double phase) {
   MTP_TRY
   require(s && amp && kvec, MTP_ERR_ARG, "null pointer");
+  for (int c = 0; c < s->nc; ++c) require(std::isfinite(amp[c]), MTP_ERR_ARG, "non-finite amplitude");
+  for (int i = 0; i < s->mesh.d; ++i) require(std::isfinite(kvec[i]), MTP_ERR_ARG, "non-finite wave vector");
+  require(std::isfinite(omega) && std::isfinite(phase), MTP_ERR_ARG, "non-finite omega or phase");
+  // the captured slab graph holds the kernel parameter block by value: drop it so that the
+  // next advance_to captures the new boundary data (work already enqueued keeps the old)
+  check_hip(hipStreamSynchronize(s->stream), "sync");
+  drop_graph(s);
   for (int c = 0; c < s->nc; ++c) s->kp.pw_amp[c] = amp[c];
   for (int i = 0; i < s->mesh.d; ++i) s->kp.pw_k[i] = kvec[i];
   s->kp.pw_omega = omega;

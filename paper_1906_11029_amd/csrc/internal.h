@@ -37,7 +37,8 @@ struct Mesh {
 
 // Tents sorted by layer (stable in pitching order).
 struct Tents {
-  double t_end = 0.0;
+  double t_start = 0.0;             // front time the table starts from (times below are relative to it)
+  double t_end = 0.0;               // slab height: the table runs from relative time 0 to t_end
   double slope = 0.5;
   std::vector<int32_t> vertex;
   std::vector<double> t_bot, t_top;

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmtp.so")
 
 MTP_OK = 0
 MTP_BC_PEC, MTP_BC_PMC, MTP_BC_DATA = 0, 1, 2
-MTP_FP64, MTP_MIXED_FP32, MTP_FP64_VALU = 0, 1, 2
+MTP_FP64, MTP_MIXED_FP32, MTP_FP64_VALU, MTP_BF16X3 = 0, 1, 2, 3
 MTP_SCHEDULE_LAYERS, MTP_SCHEDULE_DAG = 0, 1
 MTP_METHOD_SAT, MTP_METHOD_RK4 = 0, 1
 MTP_FLUX_PENALTY, MTP_FLUX_IMPEDANCE = 0, 1
@@ -46,7 +46,7 @@ def load():
         "mtp_mesh_create": [i32, i64, P, i64, P, P, P, P, pp],
         "mtp_mesh_info": [P, P, P, P, P],
         "mtp_mesh_set_system": [P, i32],
-        "mtp_pitch_layers": [P, dbl, dbl, pp],
+        "mtp_pitch_layers": [P, dbl, dbl, dbl, pp],
         "mtp_tents_query": [P, P, P, P],
         "mtp_tents_export": [P, P, P, P, P],
         "mtp_solver_workspace_size": [P, P, i32, i32, i32, i32, P],
@@ -134,9 +134,9 @@ def _release(name, h):
         getattr(lib, name)(h)
 
 
-def mtp_pitch_layers(mesh, t_end, slope_fraction=0.5):
+def mtp_pitch_layers(mesh, t_start, t_end, slope_fraction=0.5):
     h = C.c_void_p()
-    _check(load().mtp_pitch_layers(mesh, float(t_end), float(slope_fraction), C.byref(h)))
+    _check(load().mtp_pitch_layers(mesh, float(t_start), float(t_end), float(slope_fraction), C.byref(h)))
     return h
 
 
@@ -197,19 +197,29 @@ def mtp_node_coords(solver, ne, np_, dim):
     return out
 
 
-def mtp_set_fields(solver, nodal, t0=0.0):
-    """nodal: numpy array (host) or torch CUDA tensor (device), shape (ne, Np, nc), float64."""
+def mtp_set_fields(solver, nodal, shape, t0=0.0):
+    """nodal: numpy array (host) or torch CUDA tensor (device) of exactly `shape` =
+    (ne, Np, nc) float64 values (the library reads that many)."""
+    shape = tuple(int(x) for x in shape)
     if isinstance(nodal, np.ndarray):
+        if tuple(nodal.shape) != shape:
+            raise ValueError(f"nodal fields must have shape {shape}, got {tuple(nodal.shape)}")
         a = np.ascontiguousarray(nodal, dtype=np.float64)
         _check(load().mtp_set_fields(solver, _ptr(a), 0, float(t0)))
     else:
-        assert nodal.is_cuda and nodal.is_contiguous() and str(nodal.dtype) == "torch.float64"
+        if not (nodal.is_cuda and nodal.is_contiguous() and str(nodal.dtype) == "torch.float64"):
+            raise ValueError("device fields must be a contiguous float64 CUDA tensor")
+        if tuple(nodal.shape) != shape:
+            raise ValueError(f"nodal fields must have shape {shape}, got {tuple(nodal.shape)}")
         _check(load().mtp_set_fields(solver, C.c_void_p(nodal.data_ptr()), 1, float(t0)))
 
 
-def mtp_set_planewave_bc(solver, amp, kvec, omega, phase):
-    a = np.ascontiguousarray(amp, dtype=np.float64)
-    k = np.ascontiguousarray(kvec, dtype=np.float64)
+def mtp_set_planewave_bc(solver, amp, kvec, omega, phase, nc, dim):
+    """amp: nc field amplitudes, kvec: dim wave-vector components."""
+    a = np.ascontiguousarray(amp, dtype=np.float64).ravel()
+    k = np.ascontiguousarray(kvec, dtype=np.float64).ravel()
+    if a.size != nc or k.size != dim:
+        raise ValueError(f"need {nc} amplitudes and {dim} wave-vector components, got {a.size} and {k.size}")
     _check(load().mtp_set_planewave_bc(solver, _ptr(a), _ptr(k), float(omega), float(phase)))
 
 
@@ -360,9 +370,9 @@ class Mesh:
 
 
 class Tents:
-    def __init__(self, mesh, t_end, slope_fraction=0.5):
+    def __init__(self, mesh, t_end, slope_fraction=0.5, t_start=0.0):
         self.mesh = mesh
-        self.h = mtp_pitch_layers(mesh.h, t_end, slope_fraction)
+        self.h = mtp_pitch_layers(mesh.h, t_start, t_end, slope_fraction)
         self.n_tents, self.n_layers, self.layer_ptr = mtp_tents_query(self.h)
         self.t_end = t_end
 
@@ -400,10 +410,10 @@ class Solver:
         return mtp_node_coords(self.h, self.shape[0], self.np, self.dim)
 
     def set_fields(self, nodal, t0=0.0):
-        mtp_set_fields(self.h, nodal, t0)
+        mtp_set_fields(self.h, nodal, self.shape, t0)
 
     def set_planewave_bc(self, amp, kvec, omega, phase):
-        mtp_set_planewave_bc(self.h, amp, kvec, omega, phase)
+        mtp_set_planewave_bc(self.h, amp, kvec, omega, phase, self.nc, self.dim)
 
     def layer_advance(self, layer):
         mtp_layer_advance(self.h, layer)

@@ -30,6 +30,15 @@ CASES = {
     "te_pmc_p2_m1": dict(mesh=("square_pi", 4), p=2, q=3, m=1, T=0.1, kind=PMC, exact="pmc_te"),
     "cav3d_p3_m5": dict(mesh=("kuhn", 2), p=3, q=4, m=5, T=0.25, kind=PEC, exact="pec_3d"),
     "cav3d_p2_q1_m3": dict(mesh=("kuhn", 2), p=2, q=1, m=3, T=0.1, kind=PEC, exact="pec_3d"),
+    # patches beyond 8 and 24 elements (the kernels' 24- and 48-element instantiations):
+    # 2D fans around a centre vertex of valence 12 and 32, and a jittered Delaunay cube
+    # whose vertex patches hold up to 36 tets
+    "te_fan12_p3": dict(mesh=("fan", 12), p=3, q=4, m=6, T=0.2, kind=PMC, exact="pec_te"),
+    "te_fan32_p2_data": dict(mesh=("fan", 32), p=2, q=3, m=4, T=0.2, kind=DATA, exact="pw_te"),
+    "te_fan32_p5": dict(mesh=("fan", 32), p=5, q=6, m=10, T=0.1, kind=PEC, exact="pec_te"),
+    "delaunay3d_p2": dict(mesh=("delaunay", 3), p=2, q=3, m=4, T=0.1, kind=PEC, exact="pec_3d"),
+    "delaunay3d_p3_eps": dict(mesh=("delaunay", 3), p=3, q=4, m=6, T=0.1, kind=PMC, exact="pec_3d",
+                              eps_split=True),
 }
 
 # the classical RK4 variant (method="rk4"): same inputs, RK4 on the tent ODE
@@ -75,6 +84,10 @@ def build_mesh(spec):
         return meshes.cube_kuhn(n)
     if kind == "kuhn_graded":
         return meshes.cube_kuhn(n, axis_map=lambda g: 0.25 * g + 0.75 * g * g)
+    if kind == "fan":
+        return meshes.fan_disk(n)
+    if kind == "delaunay":   # 4^3 lattice on the unit cube, jitter 0.3 h, 179 tets, patches up to 36
+        return meshes.graded_delaunay_cube(n=n, a=1.0, jitter=0.3, seed=3)
     if kind == "tri1":
         return {"coords": np.array([[0.1, 0.0], [1.0, 0.2], [0.3, 0.9]]), "cells": np.array([[0, 1, 2]], np.int32)}
     if kind == "tet1":

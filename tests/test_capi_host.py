@@ -119,3 +119,38 @@ def test_acoustic_system_selection_errors():
     Mm = mtp.Mesh(mm["coords"], mm["cells"])
     Tm = mtp.Tents(Mm, 0.2, 0.5)
     assert mtp.mtp_solver_workspace_size(M.h, T.h, 2, 3, 4) < mtp.mtp_solver_workspace_size(Mm.h, Tm.h, 2, 3, 4)
+
+
+def test_pitch_from_t_start():
+    """A table pitched from the flat front t_start holds the same tents as one pitched from
+    0, shifted by t_start (times are kept relative to t_start, so the slab pattern is the
+    same bit for bit); t_end <= t_start is refused."""
+    mm = meshes.square_tri(4)
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    a = mtp.Tents(M, 0.3, 0.5).export()
+    b = mtp.Tents(M, 2.3, 0.5, t_start=2.0).export()
+    assert np.array_equal(a["vertex"], b["vertex"]) and np.array_equal(a["layer"], b["layer"])
+    assert np.array_equal(b["t_top"], 2.0 + a["t_top"]) and np.array_equal(b["t_bot"], 2.0 + a["t_bot"])
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.Tents(M, 1.0, 0.5, t_start=1.0)
+    assert e.value.code == -1
+
+
+def test_binding_checks_array_sizes_before_calling_the_library():
+    """The library reads ne*Np*nc field values and nc amplitudes / dim wave-vector entries:
+    the binding refuses arrays of another shape before any call is made (handle None)."""
+    with pytest.raises(ValueError, match="shape"):
+        mtp.mtp_set_fields(None, np.zeros((4, 6, 3)), (4, 10, 3))
+    with pytest.raises(ValueError, match="amplitudes"):
+        mtp.mtp_set_planewave_bc(None, np.zeros(3), np.zeros(2), 1.0, 0.0, nc=6, dim=3)
+    with pytest.raises(ValueError, match="amplitudes"):
+        mtp.mtp_set_planewave_bc(None, np.zeros(3), np.zeros(3), 1.0, 0.0, nc=3, dim=2)
+
+
+def test_split_bf16_precision_is_reserved():
+    mm = meshes.cube_kuhn(2)
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    T = mtp.Tents(M, 0.2, 0.5)
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.mtp_solver_workspace_size(M.h, T.h, 2, 3, 4, mtp.MTP_BF16X3)
+    assert e.value.code == -9

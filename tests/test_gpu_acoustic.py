@@ -12,13 +12,12 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
+from parity import assert_parity, rel  # noqa: E402
 from cases import AC_CASES, DATA, planewave_params, setup  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def fixture(name):
@@ -53,8 +52,8 @@ def test_acoustic_parity_fp64(name, schedule):
     ex = T.export()
     for k in ("vertex", "t_top", "layer"):
         assert np.array_equal(ex[k], ref[k]), k
-    assert rel(S.get_state(), ref["w"]) <= 1e-10
-    assert rel(S.get_fields(), ref["u"]) <= 1e-10
+    assert_parity(S.get_state(), ref["w"], 1e-10, name)
+    assert_parity(S.get_fields(), ref["u"], 1e-10, name)
 
 
 @pytest.mark.parametrize("name", list(AC_CASES))
@@ -62,7 +61,7 @@ def test_acoustic_parity_mixed(name):
     print(f"[gpu acoustic] {name} mixed", flush=True)
     ref = fixture(name)
     S, _ = run(name, 1, 1)
-    assert rel(S.get_state(), ref["w"]) <= 1e-6
+    assert_parity(S.get_state(), ref["w"], 1e-6, name)
 
 
 def test_acoustic_cavity_convergence_at_scale():

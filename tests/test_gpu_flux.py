@@ -10,13 +10,12 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
+from parity import assert_parity, rel  # noqa: E402
 from cases import DATA, IMP_CASES, planewave_params, setup  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def fixture(name):
@@ -47,8 +46,8 @@ def test_impedance_flux_parity_fp64(name, schedule):
     print(f"[gpu flux] {name} fp64 schedule {schedule}", flush=True)
     ref = fixture(name)
     S = run(name, 0, schedule)
-    assert rel(S.get_state(), ref["w"]) <= 1e-10
-    assert rel(S.get_fields(), ref["u"]) <= 1e-10
+    assert_parity(S.get_state(), ref["w"], 1e-10, name)
+    assert_parity(S.get_fields(), ref["u"], 1e-10, name)
 
 
 @pytest.mark.parametrize("name", list(IMP_CASES))
@@ -56,7 +55,7 @@ def test_impedance_flux_parity_mixed(name):
     print(f"[gpu flux] {name} mixed", flush=True)
     ref = fixture(name)
     S = run(name, 1, 1)
-    assert rel(S.get_state(), ref["w"]) <= 1e-6
+    assert_parity(S.get_state(), ref["w"], 1e-6, name)
 
 
 def test_impedance_flux_rejected_on_vector_alu_kernel():

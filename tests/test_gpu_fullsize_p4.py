@@ -5,15 +5,17 @@ state before that layer (FP64 <= 1e-10, mixed <= 1e-6), every element outside th
 patches untouched.  (2) One whole slab in the launch configuration the benchmark times
 (persistent DAG schedule, captured slab graph) equals the per-layer launches bitwise, for
 both precisions."""
+import os
+import sys
+
 import numpy as np
 import pytest
 
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from parity import assert_parity  # noqa: E402
+
 pytestmark = pytest.mark.gpu
 GRADE_A = 2.0 / 9.0
-
-
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def _workload():
@@ -56,13 +58,21 @@ def test_full_size_p4_sampled_tents(precision, tol):
     O.set_nodal_w(w_before)
     O.tau[:] = tau
     idx = np.arange(T.layer_ptr[L], T.layer_ptr[L + 1])
-    pick = np.random.default_rng(1).choice(idx, size=6, replace=False)
+    # 6 random tents of the layer, plus the first two whose patch has a PEC wall face
+    # (their vertex lies on the boundary) and the first whose patch holds both media
+    rng = np.random.default_rng(1)
+    pick = list(rng.choice(idx, size=6, replace=False))
+    xv = mm["coords"][tl["vertex"][idx]]
+    on_wall = idx[np.any((xv < 1e-12) | (xv > 1 - 1e-12), axis=1)]
+    on_jump = idx[[len(np.unique(eps[om.v2e[int(tl["vertex"][i])]])) == 2 for i in idx]]
+    pick += [i for i in on_wall[:2] if i not in pick] + [i for i in on_jump[:1] if i not in pick]
+    assert len(on_wall) >= 2 and len(on_jump) >= 1
     for i in pick:
         O.run_tent(int(tl["vertex"][i]), float(tl["t_top"][i]))
     w_or = O.nodal_w()
     for i in pick:
         es = om.v2e[int(tl["vertex"][i])]
-        assert rel(w_after[es], w_or[es]) <= tol
+        assert_parity(w_after[es], w_or[es], tol, f"tent {i}")
     touched = np.unique(np.concatenate([om.v2e[int(v)] for v in tl["vertex"][idx]]))
     mask = np.ones(len(w_after), bool)
     mask[touched] = False

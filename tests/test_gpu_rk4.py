@@ -12,14 +12,13 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
+from parity import assert_parity, rel  # noqa: E402
 from cases import DATA, RK4_CASES, planewave_params, setup  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def fixture(name):
@@ -45,8 +44,8 @@ def test_rk4_parity_against_oracle(name, schedule):
     if c["kind"] == DATA:
         S.set_planewave_bc(*planewave_params(ex, dim))
     S.advance_to(c["slabs"] * c["T"])
-    assert rel(S.get_state(), ref["w"]) <= TOL
-    assert rel(S.get_fields(), ref["u"]) <= TOL
+    assert_parity(S.get_state(), ref["w"], TOL, name)
+    assert_parity(S.get_fields(), ref["u"], TOL, name)
 
 
 def _cavity_error(n, p, method):

@@ -41,10 +41,13 @@ def test_sat_optimal_order_2d(case, p, ns):
     assert rate(e0, e1) > p + 1 - 0.3, (e0, e1)
 
 
-def test_sat_order_3d_cavity():
-    e0, _ = run("pec3", 2, 1, T=0.25)
-    e1, _ = run("pec3", 4, 1, T=0.25)
-    assert rate(e0, e1) > 1.6, (e0, e1)
+@pytest.mark.parametrize("p", [1, 2])
+def test_sat_order_3d_cavity(p):
+    """3D PEC cavity mode on 2^3 and 4^3 Kuhn cubes: rate > p + 1 - 0.3 (measured 1.80
+    at p = 1, 3.21 at p = 2)."""
+    e0, _ = run("pec3", 2, p, T=0.25)
+    e1, _ = run("pec3", 4, p, T=0.25)
+    assert rate(e0, e1) > p + 1 - 0.3, (e0, e1)
 
 
 def test_rk4_loses_order():

@@ -59,3 +59,86 @@ def test_jittered_mesh_terminates():
     mesh = Mesh(mm["coords"], mm["cells"])
     tents = pitch(mesh, 0.3, sigma=0.5)
     assert validate(mesh, tents, 0.3, sigma=0.5)
+
+
+def _valid(mm, T=0.3):
+    mesh = Mesh(mm["coords"], mm["cells"])
+    tents = pitch(mesh, T, sigma=0.5)
+    assert validate(mesh, tents, T)
+    return mesh, {k: v.copy() for k, v in tents.items()}, T
+
+
+def _last_tent_of(tents, v):
+    return int(np.where(tents["vertex"] == v)[0][-1])
+
+
+def test_validate_rejects_over_tall_tent():
+    """A tent raised to 2.5x its height breaks the slope bound (the vertex's later tents
+    shifted with it, so only the slope can fail)."""
+    mesh, t, T = _valid(meshes.square_tri(4))
+    v = 12                                        # an interior vertex
+    i = int(np.where(t["vertex"] == v)[0][0])     # its first tent
+    dh = 1.5 * (t["t_top"][i] - t["t_bot"][i])
+    later = np.where((t["vertex"] == v) & (np.arange(len(t["vertex"])) > i))[0]
+    t["t_top"][i] += dh
+    t["t_bot"][later[0]] += dh
+    with pytest.raises(AssertionError, match="slope bound"):
+        validate(mesh, t, T)
+
+
+def test_validate_rejects_overlapping_patches_in_a_layer():
+    """Two neighbouring vertices' tents put in one layer: their patches share elements."""
+    mesh, t, T = _valid(meshes.square_tri(4))
+    a = int(np.where(t["vertex"] == 12)[0][0])
+    b = int(np.where(t["vertex"] == 13)[0][0])
+    assert 13 in mesh.adj[12]
+    t["layer"][b] = t["layer"][a]
+    with pytest.raises(AssertionError):
+        validate(mesh, t, T)
+
+
+def test_validate_rejects_wrong_layer_order():
+    """A tent moved to a layer before one it depends on (its own vertex's previous tent)."""
+    mesh, t, T = _valid(meshes.square_tri(4))
+    idx = np.where(t["vertex"] == 12)[0]
+    t["layer"][idx[1]] = t["layer"][idx[0]] - 1
+    with pytest.raises(AssertionError):
+        validate(mesh, t, T)
+
+
+def test_validate_rejects_non_flat_final_front():
+    """The last tent of one vertex dropped: the final front is not flat at T."""
+    mesh, t, T = _valid(meshes.square_tri(4))
+    keep = np.ones(len(t["vertex"]), bool)
+    keep[_last_tent_of(t, 5)] = False
+    t = {k: v[keep] for k, v in t.items()}
+    with pytest.raises(AssertionError, match="flat"):
+        validate(mesh, t, T)
+
+
+def test_validate_rejects_non_positive_height_and_bottom_mismatch():
+    mesh, t, T = _valid(meshes.square_tri(4))
+    i = int(np.where(t["vertex"] == 7)[0][0])
+    bad = {k: v.copy() for k, v in t.items()}
+    bad["t_top"][i] = bad["t_bot"][i]
+    with pytest.raises(AssertionError, match="height"):
+        validate(mesh, bad, T)
+    bad = {k: v.copy() for k, v in t.items()}
+    bad["t_bot"][i] += 1e-3
+    with pytest.raises(AssertionError, match="bottom"):
+        validate(mesh, bad, T)
+
+
+def test_validate_rejects_steep_front_on_a_graded_two_material_mesh():
+    """The slope bound is sigma sqrt(eps mu) (slope 1/(2c)): a table pitched for eps = 16
+    on half of a graded mesh (waves 4x slower, fronts 4x steeper allowed there) is valid for
+    that mesh and fails the slope bound when validated against eps = 1 everywhere.  (The
+    edge rule stays well inside the bound, so a factor 2.25 would not show.)"""
+    mm = meshes.cube_kuhn(3, axis_map=lambda g: 0.3 * g + 0.7 * g * g)
+    eps, mu = meshes.materials_split(mm, eps_right=16.0)
+    slow = Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    unit = Mesh(mm["coords"], mm["cells"])
+    t = pitch(slow, 0.2, sigma=0.5)
+    assert validate(slow, t, 0.2)
+    with pytest.raises(AssertionError, match="slope bound"):
+        validate(unit, t, 0.2)

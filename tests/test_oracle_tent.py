@@ -171,7 +171,6 @@ def test_brute_force_integrals_single_triangle():
         lam_xy = lam[k]  # lambda_k as a function of (s, t)
         D = dg.vol(0, k)
         for j, var in enumerate((x, y)):
-            exact = tri_int(sp.diff(P, var) * Q * 1) if False else None
             G = (sp.diff(P, var) * Q).subs({x: xm, y: ym}, simultaneous=True) * lam_xy
             exact = float(sp.integrate(sp.integrate(G * detJ, (t, 0, 1 - s)), (s, 0, 1)))
             assert np.isclose(cP @ D[j] @ cQ, exact, rtol=1e-12)
@@ -200,3 +199,68 @@ def test_impedance_flux_fixture_equals_godunov_fixture_for_unit_impedance():
     a = np.load(os.path.join(here, "oracle_te_planewave_p2_imp.npz"))
     b = np.load(os.path.join(here, "oracle_te_planewave_p2.npz"))
     assert np.linalg.norm(a["w"] - b["w"]) <= 1e-12 * np.linalg.norm(b["w"])
+
+
+def test_brute_force_integrals_single_tet_and_shared_face():
+    """Every integral the oracle assembles in 3D, checked on a generic tetrahedron (and a
+    second one sharing its face 0) against exact sympy integration of polynomials: the
+    mass, the lambda_k-weighted derivative terms D_j, the lambda_k-weighted face terms with
+    the element's own basis on both sides and with the neighbour's basis as trial
+    functions, and the outward unit normals."""
+    sp = pytest.importorskip("sympy")
+    x, y, z, s, t, r = sp.symbols("x y z s t r")
+    X = np.array([[0.1, -0.2, 0.0], [1.3, 0.2, 0.1], [0.2, 1.1, -0.1], [0.3, 0.1, 0.9], [1.2, 1.0, 0.8]])
+    cells = np.array([[0, 1, 2, 3], [4, 3, 2, 1]])
+    mesh = Mesh(X, cells)
+    assert mesh.nbr[0, 0] == 1 and np.all(mesh.detJ > 0)
+    p = 2
+    dg = TentDG(mesh, p)
+    P = 1 + 2 * x - x * y + 0.5 * z ** 2 - y * z
+    Q = 3 - x + 0.25 * y ** 2 + z + x * z
+
+    def coef(F, e):
+        nodes = X[cells[e, 0]] + reference_nodes(3, p) @ (X[cells[e, 1:]] - X[cells[e, 0]])
+        V = basis(3, p).eval(reference_nodes(3, p))
+        return np.linalg.solve(V, np.array([float(F.subs({x: a, y: b, z: c})) for a, b, c in nodes]))
+
+    R = lambda v: sp.Rational(str(v))  # noqa: E731
+    V0, V1, V2, V3 = [[R(c) for c in X[i]] for i in cells[0]]
+    xm = [V0[i] + s * (V1[i] - V0[i]) + t * (V2[i] - V0[i]) + r * (V3[i] - V0[i]) for i in range(3)]
+    detJ = abs(sp.Matrix([[V1[i] - V0[i] for i in range(3)], [V2[i] - V0[i] for i in range(3)],
+                          [V3[i] - V0[i] for i in range(3)]]).det())
+    lam = [1 - s - t - r, s, t, r]
+
+    def tet_int(F):
+        G = sp.expand(F.subs({x: xm[0], y: xm[1], z: xm[2]}, simultaneous=True) * detJ)
+        return float(sp.integrate(G, (r, 0, 1 - s - t), (t, 0, 1 - s), (s, 0, 1)))
+
+    cP, cQ = coef(P, 0), coef(Q, 0)
+    cQn = coef(Q, 1)
+    assert np.isclose(cP @ dg.mass(0) @ cQ, tet_int(P * Q), rtol=1e-12)
+    for k in range(4):
+        D = dg.vol(0, k)
+        for j, var in enumerate((x, y, z)):
+            assert np.isclose(cP @ D[j] @ cQ, tet_int(sp.diff(P, var) * Q * lam[k]), rtol=1e-12), (k, j)
+        for f in range(4):
+            if f == k:
+                continue
+            ids = [i for i in range(4) if i != f]
+            A0, A1, A2 = ([R(c) for c in X[cells[0, i]]] for i in ids)
+            xf = [A0[i] + s * (A1[i] - A0[i]) + t * (A2[i] - A0[i]) for i in range(3)]
+            e1 = sp.Matrix([A1[i] - A0[i] for i in range(3)])
+            e2 = sp.Matrix([A2[i] - A0[i] for i in range(3)])
+            area2 = sp.sqrt(e1.cross(e2).dot(e1.cross(e2)))
+            lam_f = {ids[0]: 1 - s - t, ids[1]: s, ids[2]: t}[k]
+
+            def face_int(F):
+                G = sp.expand(F.subs({x: xf[0], y: xf[1], z: xf[2]}, simultaneous=True) * lam_f)
+                return float(sp.integrate(G, (t, 0, 1 - s), (s, 0, 1)) * area2)
+
+            fc = dg.face(0, f, k)
+            assert np.isclose(cP @ fc["Fself"] @ cQ, face_int(P * Q), rtol=1e-12), (k, f)
+            if f == 0:   # the face shared with element 1: neighbour's basis as trial functions
+                assert np.isclose(cP @ fc["Fcross"] @ cQn, face_int(P * Q), rtol=1e-12), (k, f)
+            nrm = np.array([float(v) for v in e1.cross(e2)])
+            nrm /= np.linalg.norm(nrm)
+            mid = X[cells[0, ids]].mean(axis=0)
+            assert abs(abs(fc["n"] @ nrm) - 1) < 1e-14 and (X[cells[0, f]] - mid) @ fc["n"] < 0
