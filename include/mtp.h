@@ -220,6 +220,22 @@ mtp_status mtp_layer_advance(mtp_solver solver, int64_t layer);
  * stream and every slab replays it on the solver's stream; the slab's time offset lives in
  * device memory, so one graph serves all slabs. */
 mtp_status mtp_advance_to(mtp_solver solver, double T);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): mtp_advance_to on the persistent
+ * schedule (MTP_SCHEDULE_DAG, whatever the solver's setting), launched eagerly on the
+ * solver's stream with no graph or stream creation, its per-slab scratch (working
+ * predecessor counts, ready queue, control words: 8 bytes per tent of the slab + 16,
+ * rounded to 256-byte blocks) taken from a static device array of MTP_STATIC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends, instead of from
+ * the solver's workspace.  It calls no allocating routine.  Every call on one GPU shares
+ * that GPU's array and each slab re-initialises what it reads, so calls that run one after
+ * the other are independent; calls whose work overlaps on one GPU (solvers advanced on
+ * different streams at once) race on the array and must be serialised by the caller.
+ * Results equal mtp_advance_to's bit for bit.  Errors: MTP_ERR_ARG, MTP_ERR_STATE (as
+ * mtp_advance_to), MTP_ERR_UNSUPPORTED (a slab with more tents than the array holds,
+ * about 1.05 million, or the vector-ALU kernel), MTP_ERR_DEVICE. */
+#define MTP_STATIC_SCRATCH_BYTES (8u << 20)
+mtp_status mtp_advance_to_static(mtp_solver solver, double T);
 /* Current front time (flat) and number of layers done in the current slab.  Host only. */
 mtp_status mtp_front(mtp_solver solver, double* t_front, int64_t* layers_done);
 

@@ -178,6 +178,7 @@ struct mtp_solver_s {
   int kernel = 0;            // 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32
   int schedule = MTP_SCHEDULE_LAYERS;
   int method = MTP_METHOD_SAT;
+  int device = 0;            // HIP device current at creation (the workspace's)
   // one slab (slab begin, every layer or the persistent DAG launch, slab end) captured once
   // and replayed per slab
   bool use_graph = true;
@@ -471,6 +472,7 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
       kp.dag_nready = nready;
       int dev = 0, khz = 0;
       check_hip(hipGetDevice(&dev), "device");
+      s->device = dev;
       check_hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
       kp.dag_wait_ticks = (int64_t)khz * 1000 * 10;   // 10 s
       kp.dag_grid = s->kernel == 0 ? 0 : tent_dag_grid(kp, s->kernel == 2);
@@ -1135,3 +1137,49 @@ mtp_status mtp_slab_flops(mtp_solver s, double* flops) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free advance
+namespace mtp {
+
+void set_last_error(const char* msg) { g_last_error = msg; }
+
+int solver_device(mtp_solver s) { return s->device; }
+
+// mtp_advance_to on the persistent schedule with its per-slab scratch (working predecessor
+// counts, ready queue, control words) at d_scratch (cap bytes) instead of the solver's
+// workspace; eager launches on the solver's stream, no graph, nothing allocated.
+void advance_to_dag_scratch(mtp_solver s, double T, char* d_scratch, size_t cap) {
+  require(s != nullptr, MTP_ERR_ARG, "null solver");
+  require(s->kernel != 0 && s->kp.dag_grid > 0, MTP_ERR_UNSUPPORTED,
+          "the persistent schedule needs the matrix-core kernel resident on the device");
+  require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
+  const double h = s->tents.t_end;
+  const double now = s->t_base + s->slab * h;
+  const double k = (T - now) / h;
+  const int64_t nslab = (int64_t)std::llround(k);
+  require(std::fabs(k - (double)nslab) < 1e-9 && nslab >= 0, MTP_ERR_STATE,
+          "T must be the front time plus a whole number of slabs");
+  const size_t n = (size_t)std::max(1, s->kp.dag_n);
+  Layout L;
+  const size_t o_indeg = L.add(4 * n), o_queue = L.add(4 * n), o_ctl = L.add(16);
+  if (L.off > cap) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "a slab of %d tents needs %zu bytes of scratch; the static array holds %zu",
+                  s->kp.dag_n, L.off, cap);
+    throw Error(MTP_ERR_UNSUPPORTED, msg);
+  }
+  KernelParams kp = s->kp;
+  kp.dag_indeg = reinterpret_cast<int32_t*>(d_scratch + o_indeg);
+  kp.dag_queue = reinterpret_cast<int32_t*>(d_scratch + o_queue);
+  kp.dag_ctl = reinterpret_cast<int32_t*>(d_scratch + o_ctl);
+  for (int64_t j = 0; j < nslab; ++j) {
+    check_hip(launch_slab_begin(kp, s->stream), "slab begin");
+    check_hip(launch_dag_reset(kp, s->stream), "dag reset");   // clears every scratch word the slab reads
+    check_hip(launch_tent_dag_mfma(kp, s->kernel == 2, s->stream), "persistent tent kernel");
+    check_hip(launch_slab_end(kp, s->stream), "slab end");
+    s->slab++;
+  }
+}
+
+}  // namespace mtp

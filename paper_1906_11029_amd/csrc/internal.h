@@ -72,4 +72,10 @@ void tent_dag(const Mesh& m, const Tents& t, std::vector<int32_t>& pred_count, s
               std::vector<int32_t>& succ, int32_t& nready);
 int64_t tent_dag_edges(const Mesh& m, const Tents& t);
 
+// allocation-free advance (capi.cpp): the thread's error message, the solver's device, and
+// mtp_advance_to on the persistent schedule with its scratch at a given device address
+void set_last_error(const char* msg);
+int solver_device(mtp_solver s);
+void advance_to_dag_scratch(mtp_solver s, double T, char* d_scratch, size_t cap);
+
 }  // namespace mtp

@@ -56,6 +56,7 @@ def load():
         "mtp_set_planewave_bc": [P, P, P, dbl, dbl],
         "mtp_layer_advance": [P, i64],
         "mtp_advance_to": [P, dbl],
+        "mtp_advance_to_static": [P, dbl],
         "mtp_front": [P, P, P],
         "mtp_get_fields": [P, P, i32],
         "mtp_get_state": [P, P, i32],
@@ -229,6 +230,10 @@ def mtp_layer_advance(solver, layer):
 
 def mtp_advance_to(solver, T):
     _check(load().mtp_advance_to(solver, float(T)))
+
+
+def mtp_advance_to_static(solver, T):
+    _check(load().mtp_advance_to_static(solver, float(T)))
 
 
 def mtp_front(solver):
@@ -420,6 +425,9 @@ class Solver:
 
     def advance_to(self, T):
         mtp_advance_to(self.h, T)
+
+    def advance_to_static(self, T):
+        mtp_advance_to_static(self.h, T)
 
     def front(self):
         return mtp_front(self.h)
