@@ -9,8 +9,11 @@ graded toward one corner (h ratio 1:8), eps in {1, 2.25} split at x = 0.5, Gauss
 initial E, P4 DG, q = 5 Taylor stages, m = 8 sub-intervals, slab height 0.05, mixed
 precision (FP64 first stage of every sub-interval, FP32 matrix cores for the later stages).
 Beside it, in the same run: the plain FP64 path on the same workload (DOF-updates/s,
-speedup, relative L2 difference of the fields) and the equal-error check, one slab of
-the graded mesh with a closed-form PEC cavity mode in both precisions.
+speedup, relative L2 difference of the fields), the equal-error check (the graded mesh
+with a closed-form PEC cavity mode, in both precisions, for as many slabs as the timed run
+plus its warm-up), the roofline fraction against the FP32 matrix peak (and a blended
+FP64/FP32 peak beside it), the tents' use of the slope bound, and the oracle timed on the
+host's cores.
 """
 import argparse
 import json
@@ -72,39 +75,116 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(W, budget_s):
-    """The oracle as it stands, on the first tents of the same workload (layer order),
-    until budget_s of CPU time; one thread."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+_ORACLE = {}   # set by cpu_baseline before the worker processes fork
+
+
+def _oracle_worker(args):
+    """Tents w, w + P, w + 2P, ... of the layer-ordered list, one numpy thread, on this
+    worker's copy of the oracle state, until `budget` seconds: (DOF-updates, seconds, tents)."""
+    w, P, budget = args
     from threadpoolctl import threadpool_limits
+    G = _ORACLE
+    with threadpool_limits(limits=1):
+        dofs, done, t0 = 0.0, 0, time.perf_counter()
+        for i in G["order"][w::P]:
+            v = int(G["tents"]["vertex"][i])
+            G["O"].run_tent(v, float(G["tents"]["t_top"][i]))
+            dofs += G["per_elem"] * len(G["om"].v2e[v])
+            done += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return dofs, time.perf_counter() - t0, done
+
+
+def cpu_baseline(W, budget_s):
+    """The oracle as it stands on the host's cores: the same workload (mesh, tents, fields),
+    its tents taken in layer order and dealt round robin to one process per core in the
+    affinity mask (at most 16), each with its own copy of the oracle state and one numpy
+    thread, for budget_s seconds; then the same with one process.  The value is the
+    all-core rate; the tents of a layer are independent, so the work per tent is that of a
+    sequential run."""
+    import multiprocessing as mp
 
     from mtp_inputs import meshes
     from oracle.mesh import Mesh as OMesh
     from oracle.pitch import pitch as opitch
     from oracle.solve import OracleSolver
-    with threadpool_limits(limits=1):
-        om = OMesh(W["mm"]["coords"], W["mm"]["cells"], eps=W.get("eps"), mu=W.get("mu"), face_bc=W.get("bc"))
-        tents = opitch(om, W["T"], 0.5)
-        O = OracleSolver(om, W["p"], W["q"], W["m"], system=W.get("system", "maxwell"))
-        O.set_nodal_u(W["ex"].u(meshes.equispaced_nodes(W["mm"], W["p"]), 0.0))
-        order = np.argsort(tents["layer"], kind="stable")
-        nc, npn = (4 if W.get("system") == "acoustic" else 6), (W["p"] + 1) * (W["p"] + 2) * (W["p"] + 3) // 6
-        dofs, done = 0.0, 0
-        t0 = time.perf_counter()
-        for i in order:
-            v = int(tents["vertex"][i])
-            O.run_tent(v, float(tents["t_top"][i]))
-            dofs += nc * npn * len(om.v2e[v]) * W["m"] * W["q"]
-            done += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
-        el = time.perf_counter() - t0
-    return {"value": dofs / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} tents (layer order) of the same workload, {el:.1f} s, numpy FP64, 1 thread"}
+    om = OMesh(W["mm"]["coords"], W["mm"]["cells"], eps=W.get("eps"), mu=W.get("mu"), face_bc=W.get("bc"))
+    tents = opitch(om, W["T"], 0.5)
+    O = OracleSolver(om, W["p"], W["q"], W["m"], system=W.get("system", "maxwell"))
+    O.set_nodal_u(W["ex"].u(meshes.equispaced_nodes(W["mm"], W["p"]), 0.0))
+    nc = 4 if W.get("system") == "acoustic" else 6
+    npn = (W["p"] + 1) * (W["p"] + 2) * (W["p"] + 3) // 6
+    _ORACLE.update(O=O, om=om, tents=tents, order=np.argsort(tents["layer"], kind="stable"),
+                   per_elem=nc * npn * W["m"] * W["q"])
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    out = {}
+    for P in (cores, 1):
+        with mp.get_context("fork").Pool(P) as pool:
+            res = pool.map(_oracle_worker, [(w, P, budget_s) for w in range(P)])
+        dofs = sum(r[0] for r in res)
+        el = max(r[1] for r in res)
+        out[P] = (dofs / el, sum(r[2] for r in res), el)
+    _ORACLE.clear()
+    v, n, el = out[cores]
+    v1, n1, el1 = out[1]
+    return {"value": v, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} tents in layer order of the same workload ({cores} processes x 1 numpy thread, "
+                      f"{el:.1f} s); one process: {n1} tents in {el1:.1f} s",
+            "value_1_core": v1, "cpu_model": _cpu_model(), "host_cores_in_mask": len(os.sched_getaffinity(0))}
+
+
+def slope_use(mm, eps, mu, tents, sigma=0.5):
+    """Mean over tents of max over the tent's patch of |grad tau| / (sigma sqrt(eps mu))
+    just after the tent (1 = every tent as tall as the slope bound allows), and tents per
+    vertex per slab.  Tents of a layer have element-disjoint patches whose vertices no other
+    tent of the layer moves, so the slopes after a whole layer are those after each tent."""
+    X = mm["coords"][mm["cells"]]
+    d = X.shape[2]
+    J = np.transpose(X[:, 1:, :] - X[:, :1, :], (0, 2, 1))
+    Ji = np.linalg.inv(J)
+    gl = np.concatenate([-Ji.sum(axis=1, keepdims=True), Ji], axis=1)   # (ne, d+1, d)
+    ne, nv = len(mm["cells"]), len(mm["coords"])
+    eps = np.ones(ne) if eps is None else np.asarray(eps)
+    mu = np.ones(ne) if mu is None else np.asarray(mu)
+    bound = sigma * np.sqrt(eps * mu)
+    cells = mm["cells"].astype(np.int64)
+    order = np.argsort(cells.ravel(), kind="stable")
+    v2e = order // (d + 1)
+    ptr = np.searchsorted(cells.ravel()[order], np.arange(nv + 1))
+    tau = np.zeros(nv)
+    lay = np.asarray(tents["layer"])
+    vert = np.asarray(tents["vertex"])
+    ttop = np.asarray(tents["t_top"])
+    cuts = np.flatnonzero(np.diff(lay)) + 1
+    tot = 0.0
+    for sl in np.split(np.arange(len(lay)), cuts):
+        vs = vert[sl]
+        tau[vs] = ttop[sl]
+        idx = np.concatenate([v2e[ptr[v]:ptr[v + 1]] for v in vs])
+        g = np.einsum("ek,ekx->ex", tau[cells[idx]], gl[idx])
+        r = np.linalg.norm(g, axis=1) / bound[idx]
+        cnt = ptr[vs + 1] - ptr[vs]
+        tot += np.maximum.reduceat(r, np.concatenate([[0], np.cumsum(cnt)[:-1]])).sum()
+    return {"mean_slope_over_bound": tot / len(lay), "tents_per_vertex_per_slab": len(lay) / nv}
 
 
 def blended_peak(prec_kernel, dof_slab, flops_slab, W):
     """Peak for the kernel's mix of units: FP64 (vector or matrix, 78.6) for everything
-    except, in the mixed kernel, the contractions of stages n >= 2 (FP32 matrix, 157.3)."""
+    except, in the mixed kernel, the contractions of stages n >= 2 (FP32 matrix, 157.3).
+    Returns (peak, FP32 contraction flops per slab)."""
     if prec_kernel != 2:
         return PEAK_FP64, 0.0
     d, p, q = 3, W["p"], W["q"]
@@ -257,7 +337,9 @@ def batch2d(args):
            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
            "config": {"workload": "64 independent 2D TE plane-wave solves (seed 4), n in 23..158, p in 2..5, "
-                                  "q = p+1, m = 2p, data faces, slab 0.1; one persistent batch launch per degree",
+                                  "q = p+1, m = 2p, data faces, slab 0.1; one batch per degree, "
+                                  + ("one persistent launch per slab" if args.schedule == "dag"
+                                     else "one launch per global layer index"),
                       "solves": 64, "tents_per_step": int(tents), "precision": args.precision,
                       "schedule": args.schedule,
                       "rel_l2_error_vs_exact": {"max": max(errs), "median": float(np.median(errs))},
@@ -278,7 +360,8 @@ def main():
                          "persistent schedule's device-scope fences than they gain)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 run of the same workload and the equal-error check")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work per measurement (all cores, then one core)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 512 MiB device-to-device copy (HBM counter calibration)")
@@ -315,25 +398,34 @@ def main():
     launches = args.steps * per_slab
     kern_avg = head["gpu_s"] / launches
     achieved = head["flops_slab"] / per_slab / kern_avg / 1e12
-    peak, c32 = blended_peak(head["kernel"], head["dof_slab"], head["flops_slab"], W)
+    peak_bl, c32 = blended_peak(head["kernel"], head["dof_slab"], head["flops_slab"], W)
+    # the bulk contraction's pipe: FP32 matrix cores for the mixed kernel, FP64 otherwise
+    peak = PEAK_FP32 if head["kernel"] == 2 else PEAK_FP64
     traffic = None
     if args.workload == "graded3d_p4" and head["kernel"] in (1, 2):
         traffic = measured_traffic(("mixed" if head["kernel"] == 2 else "fp64") + "_" + args.schedule)
+    slopes = slope_use(W["mm"], W.get("eps"), W.get("mu"), T.export())
 
     compare = None
     if not args.no_compare and args.precision == "mixed":
         # the plain FP64 path on the same workload and inputs, and the equal-error check on
-        # the same graded mesh with a closed-form solution
+        # the same graded mesh with a closed-form solution over as many slabs as above
         ref = run(W, "fp64", args.steps, args.warmup, M=M, T=T, schedule=args.schedule)
         diff = float(np.linalg.norm(head["u"] - ref["u"]) / np.linalg.norm(ref["u"]))
         del ref["S"]
         cert = {}
         if W.get("cert"):
             Wc = workload(W["cert"])
+            nsl = args.steps + args.warmup
             for prec in ("fp64", "mixed"):
-                rc = run(Wc, prec, 1, 0, schedule=args.schedule)
+                rc = run(Wc, prec, nsl, 0, schedule=args.schedule)
                 cert[prec + "_rel_l2_error_vs_exact"] = rc["err"]
                 del rc
+            cert["slabs"] = nsl
+            cert["final_time"] = nsl * Wc["T"]
+            e64, emx = cert["fp64_rel_l2_error_vs_exact"], cert["mixed_rel_l2_error_vs_exact"]
+            cert["mixed_over_fp64_error"] = emx / e64
+            cert["equal_within_5pct"] = bool(abs(emx / e64 - 1) <= 0.05)
             cert["workload"] = Wc["desc"]
         compare = {"fp64_dof_updates_per_s": ref["value"], "speedup_vs_fp64": head["value"] / ref["value"],
                    "mixed_vs_fp64_rel_l2": diff, "equal_error_check": cert or None}
@@ -346,6 +438,8 @@ def main():
         "dtype": "f32+f64" if head["kernel"] == 2 else "f64", "data": "synthetic",
         "config": {"workload": W["desc"], "tets": int(M.info["ne"]), "p": W["p"], "q": W["q"], "m": W["m"],
                    "tents_per_step": int(head["n_tents"]), "layers_per_step": int(nl), "slope_fraction": 0.5,
+                   "mean_slope_over_bound": round(float(slopes["mean_slope_over_bound"]), 4),
+                   "tents_per_vertex_per_slab": round(float(slopes["tents_per_vertex_per_slab"]), 3),
                    "precision": args.precision, "schedule": args.schedule,
                    "nodal_rel_error_vs_exact": head["err"],
                    "tent_dof_updates_per_s": head["value"] / (W["m"] * W["q"])},
@@ -356,6 +450,8 @@ def main():
                                               if args.schedule == "dag" else ", one launch per layer")
                                + ", slab captured in a HIP graph",
                      "avg_launch_ms": kern_avg * 1e3, "launches": int(launches),
+                     "flop_per_spacetime_dof": head["flops_slab"] / head["dof_slab"],
+                     "peak_blended": peak_bl, "frac_blended": achieved / peak_bl,
                      "fp32_mfma_flop_share": c32 / head["flops_slab"]},
     }
     if compare:

@@ -324,8 +324,13 @@ mtp_status mtp_solver_set_dag_wait(mtp_solver solver, double seconds);
 /* Kernel the solver runs: 0 vector-ALU FP64, 1 matrix-core FP64, 2 matrix-core FP32. */
 mtp_status mtp_solver_kernel(mtp_solver solver, int32_t* kernel);
 
-/* Algorithmic flop count of one slab, per the kernel's arithmetic (volume and lift
- * contractions, flux, pointwise inverse, Taylor sum). */
+/* Algorithmic flop count of one slab (section 5 counts the work in spacetime DOF,
+ * sum over tents of N_dof m q; this counts the arithmetic behind them): per element of a
+ * tent's patch and per stage, the volume contraction 2 Np (d Np) nc, the face lift
+ * 2 Np Nf nc d, the face flux 30 d Nf (2D: 12 d Nf), the reference-direction flux formation
+ * 54 Np (2D: 12 Np), the pointwise correction and inverse 100 Np (2D: 30 Np) and the Taylor
+ * sum 2 nc Np, times m q (RK4: 4 m).  3D P4 Maxwell: 70,160 flop per element-stage, 334 per
+ * spacetime DOF.  Host only.  Errors: MTP_ERR_ARG. */
 mtp_status mtp_slab_flops(mtp_solver solver, double* flops);
 
 /* Checkpoint of a solver's state (host file, binary): the nodal state W (the mapped

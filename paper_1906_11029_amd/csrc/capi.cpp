@@ -1119,20 +1119,20 @@ mtp_status mtp_slab_flops(mtp_solver s, double* flops) {
   require(s && flops, MTP_ERR_ARG, "null pointer");
   const Mesh& M = s->mesh;
   const int d = M.d, np = s->ref.np, nf = s->ref.nf, nc = s->nc;
-  // per element and stage: volume 2 d np^2 nc, lift 2 d np nf nc, A(grad lambda) on d
-  // directions (2 nc flops each per node), flux (about 40 flops per face node in 3D,
-  // 20 in 2D), pointwise inverse with the M' correction (about 60 flops per node in 3D,
-  // 25 in 2D), Taylor update 2 nc per node
-  const double vol = 2.0 * d * np * np * nc;
-  const double lift = 2.0 * d * np * nf * nc;
-  const double adir = 2.0 * d * nc * np;
-  const double flx = (d == 3 ? 40.0 : 20.0) * d * nf;
-  const double kin = (d == 3 ? 60.0 : 25.0) * np;
+  // algorithmic work per element and stage: volume contraction 2 np (d np) nc, face lift
+  // 2 np nf nc d, face flux about 30 d nf (3D) / 12 d nf (2D), reference-direction flux
+  // formation about 54 np (3D) / 12 np (2D), pointwise M' correction and inverse about
+  // 100 np (3D) / 30 np (2D), Taylor sum 2 nc np (3D P4: 70,160 flop, 334 per spacetime DOF)
+  const double vol = 2.0 * np * (d * np) * nc;
+  const double lift = 2.0 * np * nf * nc * d;
+  const double flx = (d == 3 ? 30.0 : 12.0) * d * nf;
+  const double adir = (d == 3 ? 54.0 : 12.0) * np;
+  const double kin = (d == 3 ? 100.0 : 30.0) * np;
   const double tay = 2.0 * nc * np;
   double elem_tents = 0.0;
   for (int32_t v : s->tents.vertex) elem_tents += (double)(M.v2e_ptr[v + 1] - M.v2e_ptr[v]);
   const int stages = s->method == MTP_METHOD_RK4 ? 4 : s->q;
-  *flops = elem_tents * s->m * stages * (vol + lift + adir + flx + kin + tay);
+  *flops = elem_tents * s->m * stages * (vol + lift + flx + adir + kin + tay);
   MTP_CATCH
 }
 
