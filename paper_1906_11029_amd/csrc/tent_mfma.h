@@ -366,8 +366,10 @@ __device__ __forceinline__ void tile_product(const double* sOp, const float* sOp
 // ---- persistent schedule over the tent DAG
 // Claim the next queue slot and wait (bounded) until a released tent fills it.  Returns the
 // tent, or -1 when every slot is claimed, on abort, or when the wait bound is exceeded
-// (which sets ERRF_DAG_WAIT and the abort word, so that every workgroup leaves).  The
-// acquire fence after the claim makes the predecessors' W and tau visible to this CU.
+// (which sets ERRF_DAG_WAIT and the abort word, so that every workgroup leaves).  Thread 0's
+// acquire fence after the claim makes the predecessors' W and tau visible: it invalidates the
+// CU's L1 and its XCD's L2, which every wave of the workgroup reads through after the
+// barrier, so one fence per workgroup suffices.
 __device__ __forceinline__ int dag_claim(const KernelParams& kp, int* sh, int tid) {
   if (tid == 0) {
     int t = -1;
@@ -388,55 +390,77 @@ __device__ __forceinline__ int dag_claim(const KernelParams& kp, int* sh, int ti
         }
       }
     }
+    if (t >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *sh = t;
   }
   __syncthreads();
-  const int t = *sh;
-  if (t >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return t;
+  return *sh;
 }
 
-// Tent t is done: make its W and tau visible device-wide, then count down its successors;
-// a successor whose count reaches zero goes into the next queue slot.
-__device__ __forceinline__ void dag_release(const KernelParams& kp, int t, int tid) {
+// Wave 0 of a workgroup whose tent is done: after the release fence, one lane per successor
+// counts its predecessor count down (in parallel, not one round trip after another); the
+// successors that reach zero get consecutive queue slots from one reservation, ranked by lane.
+// Queue entries are base + successor (base: the solver's first global id in a batch).
+__device__ __forceinline__ void dag_push_successors(const int32_t* succ, int nsucc, int32_t* indeg, int32_t* queue,
+                                                    int32_t* ctl, int base, int lane) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (tid == 0) {
-    const int b = kp.dag_succ_ptr[t], e = kp.dag_succ_ptr[t + 1];
-    for (int i = b; i < e; ++i) {
-      const int s = kp.dag_succ[i];
-      if (__hip_atomic_fetch_add(&kp.dag_indeg[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
-        const int slot = __hip_atomic_fetch_add(&kp.dag_ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&kp.dag_queue[slot], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i0 = 0; i0 < nsucc; i0 += 64) {
+    const int i = i0 + lane;
+    int s = -1;
+    bool ready = false;
+    if (i < nsucc) {
+      s = succ[i];
+      ready = __hip_atomic_fetch_add(&indeg[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1;
+    }
+    const unsigned long long mask = __ballot(ready);
+    if (mask) {
+      const int leader = __ffsll((long long)mask) - 1;
+      int slot0 = 0;
+      if (lane == leader)
+        slot0 = __hip_atomic_fetch_add(&ctl[1], __popcll(mask), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      slot0 = __shfl(slot0, leader);
+      if (ready) {
+        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+        __hip_atomic_store(&queue[slot0 + rank], base + s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }
 }
 
-// Tent sources of the body: next() yields the next tent and its solver's parameter block
-// (false: the workgroup is done), done() runs after the tent's scatter.
+// Tent t is done: make its W and tau visible device-wide, then count down its successors;
+// a successor whose count reaches zero goes into the next queue slot.  The caller's barrier
+// has completed every wave's stores (they sit in the XCD's L2); wave 0's release fence
+// writes the L2 back for the other XCDs, one fence per workgroup.
+__device__ __forceinline__ void dag_release(const KernelParams& kp, int t, int tid) {
+  if (tid < 64) dag_push_successors(kp.dag_succ + kp.dag_succ_ptr[t], kp.dag_succ_ptr[t + 1] - kp.dag_succ_ptr[t],
+                                     kp.dag_indeg, kp.dag_queue, kp.dag_ctl, 0, tid);
+}
+
+// Tent sources of the body: next() yields the next tent (false: the workgroup is done),
+// params() the parameter block of its solver (kp0, the kernel's own block, for a single
+// solve: the body reads it through a reference to the kernel argument, which the compiler
+// lowers to scalar loads of the argument segment; a batch's blocks live in device memory),
+// done() runs after the tent's scatter.
 struct SchedRange {   // tents first + it, it = begin, begin + step, ... < count
-  const KernelParams* kp;
   int64_t first, count, it, step;
-  __device__ bool next(int*, int, const KernelParams*& k, int64_t& t) {
+  __device__ bool next(const KernelParams&, int*, int, int64_t& t) {
     if (it >= count) return false;
-    k = kp;
     t = first + it;
     it += step;
     return true;
   }
+  __device__ const KernelParams& params(const KernelParams& kp0) const { return kp0; }
   __device__ void done(const KernelParams&, int64_t, int) {}
 };
 
 struct SchedDag {     // one solver's tent DAG
-  const KernelParams* kp;
-  __device__ bool next(int* sh, int tid, const KernelParams*& k, int64_t& t) {
-    const int c = dag_claim(*kp, sh, tid);
+  __device__ bool next(const KernelParams& kp0, int* sh, int tid, int64_t& t) {
+    const int c = dag_claim(kp0, sh, tid);
     if (c < 0) return false;
-    k = kp;
     t = c;
     return true;
   }
+  __device__ const KernelParams& params(const KernelParams& kp0) const { return kp0; }
   __device__ void done(const KernelParams& k, int64_t t, int tid) { dag_release(k, (int)t, tid); }
 };
 
@@ -444,7 +468,7 @@ struct SchedBatchDag {   // the tent DAGs of a batch of solvers, one queue of gl
   const KernelParams* kps;
   BatchDag bd;
   int solver;
-  __device__ bool next(int* sh, int tid, const KernelParams*& k, int64_t& t) {
+  __device__ bool next(const KernelParams&, int* sh, int tid, int64_t& t) {
     if (tid == 0) {
       int g = -1;
       if (__hip_atomic_load(&bd.ctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
@@ -473,6 +497,7 @@ struct SchedBatchDag {   // the tent DAGs of a batch of solvers, one queue of gl
         }
         s = lo;
       }
+      if (g >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // once per workgroup, as dag_claim
       sh[0] = g;
       sh[1] = s;
     }
@@ -480,25 +505,14 @@ struct SchedBatchDag {   // the tent DAGs of a batch of solvers, one queue of gl
     const int g = sh[0];
     solver = sh[1];
     if (g < 0) return false;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    k = &kps[solver];
     t = g - bd.off[solver];
     return true;
   }
-  __device__ void done(const KernelParams& k, int64_t t, int tid) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0) {
-      const int b = k.dag_succ_ptr[t], e = k.dag_succ_ptr[t + 1];
-      const int base = bd.off[solver];
-      for (int i = b; i < e; ++i) {
-        const int s = k.dag_succ[i];
-        if (__hip_atomic_fetch_add(&k.dag_indeg[s], -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == 1) {
-          const int slot = __hip_atomic_fetch_add(&bd.ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&bd.queue[slot], base + s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-      }
-    }
+  __device__ const KernelParams& params(const KernelParams&) const { return kps[solver]; }
+  __device__ void done(const KernelParams& k, int64_t t, int tid) {   // after the body's barrier, as dag_release
+    if (tid < 64)
+      dag_push_successors(k.dag_succ + k.dag_succ_ptr[t], k.dag_succ_ptr[t + 1] - k.dag_succ_ptr[t], k.dag_indeg,
+                          bd.queue, bd.ctl, bd.off[solver], tid);
   }
 };
 
@@ -566,10 +580,9 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 
   __shared__ int sh_tent[2];
   for (;;) {
-    const KernelParams* kpp;
     int64_t t;
-    if (!sched.next(sh_tent, tid, kpp, t)) break;
-    const KernelParams& kp = *kpp;
+    if (!sched.next(kp0, sh_tent, tid, t)) break;
+    const KernelParams& kp = sched.params(kp0);
     const double invm = 1.0 / kp.m;
     const int32_t V = kp.tent_vertex[t];
     const double t_top = kp.slab[0] + kp.tent_top[t];
@@ -856,14 +869,14 @@ template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false, int SY
 __global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_kernel(KernelParams kp, int64_t first, int64_t count) {
   tent_mfma_body<D, P, T, NTMAX, SchedRange, RK4, SYS>(
-      kp, SchedRange{&kp, first, count, (int64_t)blockIdx.x, (int64_t)gridDim.x});
+      kp, SchedRange{first, count, (int64_t)blockIdx.x, (int64_t)gridDim.x});
 }
 
 // Persistent entry point: every tent of the slab, in DAG order, by kp.dag_grid workgroups.
 template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false, int SYS = 0>
 __global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_dag_kernel(KernelParams kp) {
-  tent_mfma_body<D, P, T, NTMAX, SchedDag, RK4, SYS>(kp, SchedDag{&kp});
+  tent_mfma_body<D, P, T, NTMAX, SchedDag, RK4, SYS>(kp, SchedDag{});
 }
 
 // Persistent entry point of a batch: every tent of every solver's slab, in DAG order.
@@ -886,7 +899,7 @@ tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) 
   }
   const BatchSeg sg = segs[lo];
   tent_mfma_body<D, P, T, NTMAX>(kps[sg.solver],
-                                 SchedRange{&kps[sg.solver], sg.first, sg.count, b - sg.block0, (int64_t)1 << 62});
+                                 SchedRange{sg.first, sg.count, b - sg.block0, (int64_t)1 << 62});
 }
 
 template <int D, int P, typename T, int NTMAX>
