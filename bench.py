@@ -262,10 +262,10 @@ def run(W, precision, steps, warmup, M=None, T=None, schedule="layers"):
 def batch2d(args):
     """64 independent 2D TE plane-wave solves (seed 4): n ~ U{23..158} (2n^2 triangles),
     p ~ U{2..5}, q = p + 1, m = 2p, direction, k ~ U[pi, 4pi] and phase drawn from the seed,
-    data faces on the whole boundary, slab 0.1 (ten slabs reach T = 1).  Solves of one
-    degree form one batch; every batch runs one persistent launch per slab.  Beside it,
-    the same solves one by one with per-layer launches, and every solve's error against
-    its exact plane wave."""
+    data faces on the whole boundary, slab 0.1 (ten slabs reach T = 1).  All 64 solves form
+    one batch, which groups them by degree: one launch per (global layer index, degree), or
+    one persistent launch per degree and slab.  Beside it, the same solves one by one
+    with per-layer launches, and every solve's error against its exact plane wave."""
     import torch
 
     from mtp_inputs import fields, meshes
@@ -293,14 +293,9 @@ def batch2d(args):
     t0 = time.perf_counter()
     solves = make()
     log(f"batch2d: 64 solves set up in {time.perf_counter() - t0:.1f}s")
-    groups = {}
-    for i, sp in enumerate(specs):
-        groups.setdefault(sp["p"], []).append(solves[i][0])
-    batches = []
-    for p in sorted(groups):
-        B = mtp.Batch(groups[p])
-        B.set_schedule(mtp.MTP_SCHEDULE_DAG if args.schedule == "dag" else mtp.MTP_SCHEDULE_LAYERS)
-        batches.append(B)
+    B = mtp.Batch([S for S, _, _ in solves])
+    B.set_schedule(mtp.MTP_SCHEDULE_DAG if args.schedule == "dag" else mtp.MTP_SCHEDULE_LAYERS)
+    batches = [B]
     dof = sum(S.slab_dof_updates()[0] for S, _, _ in solves)
     tents = sum(S.slab_dof_updates()[1] for S, _, _ in solves)
     for B in batches:
@@ -337,9 +332,9 @@ def batch2d(args):
            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
            "config": {"workload": "64 independent 2D TE plane-wave solves (seed 4), n in 23..158, p in 2..5, "
-                                  "q = p+1, m = 2p, data faces, slab 0.1; one batch per degree, "
-                                  + ("one persistent launch per slab" if args.schedule == "dag"
-                                     else "one launch per global layer index"),
+                                  "q = p+1, m = 2p, data faces, slab 0.1; one batch grouped by degree, "
+                                  + ("one persistent launch per degree and slab" if args.schedule == "dag"
+                                     else "one launch per global layer index and degree"),
                       "solves": 64, "tents_per_step": int(tents), "precision": args.precision,
                       "schedule": args.schedule,
                       "rel_l2_error_vs_exact": {"max": max(errs), "median": float(np.median(errs))},

@@ -252,8 +252,10 @@ mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
 
 /* Batches of independent solves (section 2: tents on different meshes are independent).
  * Every launch of a batch runs layer l of every solver in it, so small solves share the
- * GPU: solvers must use the matrix-core kernels with one dimension, degree and precision
- * (q, m, meshes, materials and boundary data may differ).  mtp_batch_advance moves every
+ * GPU: solvers must use the matrix-core kernels with one dimension and precision; degrees
+ * may differ (solvers of one degree form a group, and each layer index is one launch per
+ * group, or each group one persistent launch).  q, m, meshes, materials and boundary
+ * data may differ too.  mtp_batch_advance moves every
  * solver forward by n_slabs of its own slab height; the first call captures one batched
  * slab into a HIP graph that later calls replay.  Solvers keep their handles and state;
  * a solver must not be advanced on its own while a batch call is in flight.
@@ -264,9 +266,10 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
 mtp_status mtp_batch_advance(mtp_batch batch, int64_t n_slabs);
 mtp_status mtp_batch_set_graph(mtp_batch batch, int32_t on);
 /* Schedule of the batch's slabs: MTP_SCHEDULE_LAYERS (one launch per global layer index,
- * the default) or MTP_SCHEDULE_DAG (one persistent launch per slab draining one queue of
- * ready tents of every solver; tents of different solves and of uneven patch size share
- * the workgroups; the wait bound is the largest of the solvers').  Results are identical.
+ * and degree group, the default) or MTP_SCHEDULE_DAG (per slab, one persistent launch per
+ * degree group draining one queue of ready tents of the group's solvers; tents of different
+ * solves and of uneven patch size share the workgroups; the wait bound is the largest of
+ * the group's solvers').  Results are identical.
  * Errors: MTP_ERR_ARG, MTP_ERR_UNSUPPORTED (kernel cannot be resident). */
 mtp_status mtp_batch_set_schedule(mtp_batch batch, int32_t schedule);
 void mtp_batch_destroy(mtp_batch batch);

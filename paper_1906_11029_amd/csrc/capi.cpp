@@ -188,17 +188,29 @@ struct mtp_solver_s {
 };
 
 struct mtp_batch_s {
-  std::vector<mtp_solver> solvers;
-  int kernel = 0, d = 0, p = 0, max_patch = 0;
+  // Solvers of one degree run together: the batch keeps its kernel parameters sorted by
+  // degree (internal index j holds solver order[j]), so each degree group is a contiguous
+  // range [s0, s1) served by the single-degree kernels.
+  struct Group {
+    int p = 0, max_patch = 0, s0 = 0, s1 = 0;
+    mtp::BatchDag bd{};           // persistent schedule over the group's tent DAGs
+  };
+  struct Launch {                 // one layer of one degree group
+    int64_t seg0 = 0, blocks = 0;
+    int nseg = 0, group = 0;
+  };
+  std::vector<mtp_solver> solvers;   // in the caller's order
+  std::vector<int> order;
+  std::vector<Group> groups;
+  std::vector<Launch> launches;
+  int kernel = 0, d = 0;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   mtp::KernelParams* d_kps = nullptr;
   mtp::BatchSeg* d_segs = nullptr;
   std::vector<mtp::KernelParams> h_kps;
-  std::vector<int64_t> seg_ptr;   // per global layer: first segment
-  std::vector<int64_t> blocks;    // per global layer: workgroups
   int schedule = MTP_SCHEDULE_LAYERS;
-  mtp::BatchDag bd{};             // persistent schedule over every solver's tent DAG
+  bool dag_ok = true;             // every group's persistent kernel can be resident
   bool use_graph = true;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -684,8 +696,8 @@ static void batch_check(const mtp_solver* solvers, int32_t n) {
     const mtp_solver s = solvers[i];
     require(s != nullptr, MTP_ERR_ARG, "null solver in batch");
     require(s->kernel == 1 || s->kernel == 2, MTP_ERR_UNSUPPORTED, "batches need the matrix-core kernels");
-    require(s->kernel == solvers[0]->kernel && s->mesh.d == solvers[0]->mesh.d && s->p == solvers[0]->p,
-            MTP_ERR_UNSUPPORTED, "a batch needs one dimension, degree and precision");
+    require(s->kernel == solvers[0]->kernel && s->mesh.d == solvers[0]->mesh.d, MTP_ERR_UNSUPPORTED,
+            "a batch needs one dimension and precision");
     require(s->method == MTP_METHOD_SAT, MTP_ERR_UNSUPPORTED, "batches run SAT only");
     require(s->mesh.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED, "batches run Maxwell only");
     for (int j = 0; j < i; ++j) require(solvers[j] != s, MTP_ERR_ARG, "solver listed twice");
@@ -704,6 +716,9 @@ static int64_t batch_tents(const mtp_solver* solvers, int32_t n) {
   return tot;
 }
 
+// At most one group per degree.
+constexpr int kMaxBatchGroups = 8;
+
 struct BatchLayout {
   size_t kps, segs, queue, ctl, off, roff, total;
 };
@@ -714,8 +729,8 @@ static BatchLayout batch_layout(const mtp_solver* solvers, int32_t n) {
   o.segs = L.add(sizeof(BatchSeg) * batch_segments(solvers, n));
   o.queue = L.add(sizeof(int32_t) * std::max<int64_t>(1, batch_tents(solvers, n)));
   o.ctl = L.add(sizeof(int32_t) * 4);
-  o.off = L.add(sizeof(int32_t) * (n + 1));
-  o.roff = L.add(sizeof(int32_t) * (n + 1));
+  o.off = L.add(sizeof(int32_t) * (n + kMaxBatchGroups));    // per group: n_g + 1 entries
+  o.roff = L.add(sizeof(int32_t) * (n + kMaxBatchGroups));
   o.total = L.off;
   return o;
 }
@@ -738,10 +753,26 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     b->solvers.assign(solvers, solvers + n);
     b->kernel = solvers[0]->kernel;
     b->d = solvers[0]->mesh.d;
-    b->p = solvers[0]->p;
-    for (int i = 0; i < n; ++i) b->max_patch = std::max(b->max_patch, solvers[i]->mesh.max_patch);
-    require(tent_mfma_lds_bytes(b->d, b->p, b->max_patch, b->kernel == 2) <= 160 * 1024, MTP_ERR_UNSUPPORTED,
-            "largest vertex patch of the batch does not fit the matrix-core kernel's LDS");
+    // degree groups: stable sort by degree
+    b->order.resize(n);
+    for (int i = 0; i < n; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int x, int y) { return solvers[x]->p < solvers[y]->p; });
+    for (int j = 0; j < n; ++j) {
+      const mtp_solver s = solvers[b->order[j]];
+      if (b->groups.empty() || b->groups.back().p != s->p) {
+        mtp_batch_s::Group g;
+        g.p = s->p;
+        g.s0 = j;
+        b->groups.push_back(g);
+      }
+      auto& g = b->groups.back();
+      g.s1 = j + 1;
+      g.max_patch = std::max(g.max_patch, s->mesh.max_patch);
+    }
+    for (const auto& g : b->groups)
+      require(tent_mfma_lds_bytes(b->d, g.p, g.max_patch, b->kernel == 2) <= 160 * 1024, MTP_ERR_UNSUPPORTED,
+              "largest vertex patch of the batch does not fit the matrix-core kernel's LDS");
     const BatchLayout lo = batch_layout(solvers, n);
     require(bytes >= lo.total, MTP_ERR_ARG, "workspace too small");
     require(batch_tents(solvers, n) < (int64_t)1 << 31, MTP_ERR_UNSUPPORTED, "more than 2^31 - 1 tents per batch slab");
@@ -749,54 +780,66 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->d_kps = reinterpret_cast<KernelParams*>(b->ws + lo.kps);
     b->d_segs = reinterpret_cast<BatchSeg*>(b->ws + lo.segs);
-    // persistent schedule: global tent ids solver by solver, first-layer tents first
+    // persistent schedule, per group: tent ids solver by solver, first-layer tents first in the queue
     {
-      std::vector<int32_t> off(n + 1, 0), roff(n + 1, 0);
-      for (int i = 0; i < n; ++i) {
-        off[i + 1] = off[i] + (int32_t)solvers[i]->tents.vertex.size();
-        roff[i + 1] = roff[i] + solvers[i]->kp.dag_nready;
+      std::vector<int32_t> off(n + kMaxBatchGroups, 0), roff(n + kMaxBatchGroups, 0);
+      for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        auto& g = b->groups[gi];
+        const int base = g.s0 + (int)gi;   // the group's arrays start here
+        int64_t ticks = 0;
+        for (int j = g.s0; j < g.s1; ++j) {
+          const mtp_solver s = solvers[b->order[j]];
+          off[base + j - g.s0 + 1] = off[base + j - g.s0] + (int32_t)s->tents.vertex.size();
+          roff[base + j - g.s0 + 1] = roff[base + j - g.s0] + s->kp.dag_nready;
+          ticks = std::max(ticks, s->kp.dag_wait_ticks);
+        }
+        g.bd.queue = reinterpret_cast<int32_t*>(b->ws + lo.queue);   // shared: the groups run one after another
+        g.bd.ctl = reinterpret_cast<int32_t*>(b->ws + lo.ctl);
+        g.bd.off = reinterpret_cast<const int32_t*>(b->ws + lo.off) + base;
+        g.bd.roff = reinterpret_cast<const int32_t*>(b->ws + lo.roff) + base;
+        g.bd.nsolv = g.s1 - g.s0;
+        g.bd.n = off[base + g.s1 - g.s0];
+        g.bd.wait_ticks = ticks;
+        g.bd.grid = tent_batch_dag_grid(b->d, g.p, g.max_patch, b->kernel == 2);
+        if (g.bd.grid <= 0) b->dag_ok = false;
       }
       check_hip(hipMemcpyAsync(b->ws + lo.off, off.data(), off.size() * 4, hipMemcpyHostToDevice, b->stream),
                 "upload");
       check_hip(hipMemcpyAsync(b->ws + lo.roff, roff.data(), roff.size() * 4, hipMemcpyHostToDevice, b->stream),
                 "upload");
-      b->bd.queue = reinterpret_cast<int32_t*>(b->ws + lo.queue);
-      b->bd.ctl = reinterpret_cast<int32_t*>(b->ws + lo.ctl);
-      b->bd.off = reinterpret_cast<const int32_t*>(b->ws + lo.off);
-      b->bd.roff = reinterpret_cast<const int32_t*>(b->ws + lo.roff);
-      b->bd.nsolv = n;
-      b->bd.n = off[n];
-      int64_t ticks = 0;
-      for (int i = 0; i < n; ++i) ticks = std::max(ticks, solvers[i]->kp.dag_wait_ticks);
-      b->bd.wait_ticks = ticks;
-      b->bd.grid = tent_batch_dag_grid(b->d, b->p, b->max_patch, b->kernel == 2);
     }
-    // global layer l runs layer l of every solver that has it
+    // layer schedule: global layer l runs layer l of every solver that has it, one launch per group
     int64_t nl = 0;
     for (int i = 0; i < n; ++i) nl = std::max<int64_t>(nl, (int64_t)solvers[i]->tents.layer_ptr.size() - 1);
     std::vector<BatchSeg> segs;
     for (int64_t l = 0; l < nl; ++l) {
-      b->seg_ptr.push_back((int64_t)segs.size());
-      int64_t blk = 0;
-      for (int i = 0; i < n; ++i) {
-        const Tents& T = solvers[i]->tents;
-        if (l + 1 >= (int64_t)T.layer_ptr.size()) continue;
-        BatchSeg sg;
-        sg.block0 = blk;
-        sg.first = T.layer_ptr[l];
-        sg.count = T.layer_ptr[l + 1] - T.layer_ptr[l];
-        sg.solver = i;
-        sg.pad = 0;
-        segs.push_back(sg);
-        blk += sg.count;
+      for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const auto& g = b->groups[gi];
+        mtp_batch_s::Launch la;
+        la.seg0 = (int64_t)segs.size();
+        la.group = (int)gi;
+        for (int j = g.s0; j < g.s1; ++j) {
+          const Tents& T = solvers[b->order[j]]->tents;
+          if (l + 1 >= (int64_t)T.layer_ptr.size()) continue;
+          BatchSeg sg;
+          sg.block0 = la.blocks;
+          sg.first = T.layer_ptr[l];
+          sg.count = T.layer_ptr[l + 1] - T.layer_ptr[l];
+          sg.solver = j;
+          sg.pad = 0;
+          segs.push_back(sg);
+          la.blocks += sg.count;
+        }
+        la.nseg = (int)((int64_t)segs.size() - la.seg0);
+        if (la.nseg > 0) b->launches.push_back(la);
       }
-      b->blocks.push_back(blk);
     }
-    b->seg_ptr.push_back((int64_t)segs.size());
     check_hip(hipMemcpyAsync(b->d_segs, segs.data(), segs.size() * sizeof(BatchSeg), hipMemcpyHostToDevice,
                              b->stream), "upload");
-    BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, b->p, b->max_patch};
-    check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, nullptr), "batch kernel attributes");
+    for (const auto& g : b->groups) {
+      BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, g.p, g.max_patch};
+      check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, nullptr), "batch kernel attributes");
+    }
     check_hip(hipStreamSynchronize(b->stream), "sync");
   } catch (...) {
     delete b;
@@ -810,13 +853,15 @@ static void batch_slab(mtp_batch b, hipStream_t st) {
   const int n = (int)b->solvers.size();
   check_hip(launch_batch_slab(b->d_kps, n, 0, st), "batch slab begin");
   if (b->schedule == MTP_SCHEDULE_DAG) {
-    check_hip(launch_batch_dag_reset(b->d_kps, b->bd, st), "batch dag reset");
-    check_hip(launch_tent_batch_dag_mfma(b->d_kps, b->bd, b->d, b->p, b->max_patch, b->kernel == 2, st),
-              "persistent batched tent kernel");
+    for (const auto& g : b->groups) {
+      check_hip(launch_batch_dag_reset(b->d_kps + g.s0, g.bd, st), "batch dag reset");
+      check_hip(launch_tent_batch_dag_mfma(b->d_kps + g.s0, g.bd, b->d, g.p, g.max_patch, b->kernel == 2, st),
+                "persistent batched tent kernel");
+    }
   } else {
-    for (size_t l = 0; l + 1 < b->seg_ptr.size(); ++l) {
-      BatchLaunch bl{b->d_kps, b->d_segs + b->seg_ptr[l], (int)(b->seg_ptr[l + 1] - b->seg_ptr[l]), b->blocks[l],
-                     b->d, b->p, b->max_patch};
+    for (const auto& la : b->launches) {
+      const auto& g = b->groups[la.group];
+      BatchLaunch bl{b->d_kps, b->d_segs + la.seg0, la.nseg, la.blocks, b->d, g.p, g.max_patch};
       check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, st), "batched tent kernel");
     }
   }
@@ -838,11 +883,11 @@ mtp_status mtp_batch_advance(mtp_batch b, int64_t n_slabs) {
   require(n_slabs >= 0, MTP_ERR_ARG, "negative slab count");
   const int n = (int)b->solvers.size();
   b->h_kps.resize(n);
-  for (int i = 0; i < n; ++i) {
-    mtp_solver s = b->solvers[i];
+  for (int j = 0; j < n; ++j) {
+    mtp_solver s = b->solvers[b->order[j]];
     require(s->layers_done == 0, MTP_ERR_STATE, "a solver of the batch is in the middle of a slab");
     require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
-    b->h_kps[i] = s->kp;
+    b->h_kps[j] = s->kp;
     // work the solvers enqueued on their own streams comes first
     if (s->stream != b->stream) check_hip(hipStreamSynchronize(s->stream), "sync solver stream");
   }
@@ -883,7 +928,7 @@ mtp_status mtp_batch_set_schedule(mtp_batch b, int32_t schedule) {
   require(b, MTP_ERR_ARG, "null batch");
   require(schedule == MTP_SCHEDULE_LAYERS || schedule == MTP_SCHEDULE_DAG, MTP_ERR_ARG, "unknown schedule");
   if (schedule == MTP_SCHEDULE_DAG)
-    require(b->bd.grid > 0, MTP_ERR_UNSUPPORTED, "the persistent batched kernel cannot be resident");
+    require(b->dag_ok, MTP_ERR_UNSUPPORTED, "the persistent batched kernel cannot be resident");
   if (schedule != b->schedule) {
     check_hip(hipStreamSynchronize(b->stream), "sync");
     drop_batch_graph(b);

@@ -162,7 +162,9 @@ struct MShape {
 };
 
 // LDS layout, identical for both variants (state, fluxes and operators stored in FP64; the
-// mixed variant only changes the precision of the products of stages n >= 2)
+// mixed variant only changes the precision of the products of stages n >= 2): an operator
+// block (FP64 operator, in the mixed kernel the FP32 copy of its volume part, the face-node
+// tables), which depends on the degree only, then the region of one tent (U, F/R, geometry).
 template <int D, int P, typename T, int NTMAX, int SYS = 0>
 struct MLds {
   using SH = MShape<D, P, NTMAX, SYS>;
@@ -170,14 +172,91 @@ struct MLds {
   // FP64 operator, then (mixed kernel) the FP32 copy of its volume part, in doubles
   static constexpr size_t opf_floats = sizeof(T) == 4 ? (size_t)SH::KV * OPS : 0;
   static constexpr size_t op_elems = (size_t)SH::KT * OPS + (opf_floats + 1) / 2;
+  static constexpr size_t face_ints = (size_t)D * 2 * SH::NF + SH::NF;
+  static constexpr size_t op_block = op_elems + (face_ints + 1) / 2;   // doubles
   static constexpr size_t u_elems = (size_t)SH::NPK * SH::RS;
   static constexpr size_t f_elems = (size_t)SH::FROWS * SH::RS;
-  static constexpr size_t t_bytes = (op_elems + u_elems + f_elems) * 8;
   static constexpr size_t geo_doubles =
       (size_t)NTMAX * (SH::NV * D + D + 2) + 3 * (size_t)NTMAX * D + 4 * (size_t)NTMAX;
-  static constexpr size_t ints = (size_t)D * 2 * SH::NF + (size_t)NTMAX * (2 + D) + (size_t)NTMAX * D + SH::NF;
-  static constexpr size_t bytes = t_bytes + geo_doubles * 8 + ints * 4;
+  static constexpr size_t tent_ints = (size_t)NTMAX * (2 + D) + (size_t)NTMAX * D;
+  static constexpr size_t common = u_elems + f_elems + geo_doubles + (tent_ints + 1) / 2;   // doubles
+  static constexpr size_t bytes = (op_block + common) * 8;
 };
+
+// LDS pointers of one degree's operator block and of the tent region
+struct TentLds {
+  double* sOp;     // [k][m], m fastest
+  float* sOpF;     // mixed: FP32 copy of the volume rows k < KV
+  int* sFn;        // face node -> volume node, [j][o][s]
+  int* sFsw;       // [s]: face node with the two non-V vertices exchanged
+  double* sU;      // [node][col]
+  double* sFR;     // [row][col]: F, then R
+  double* sGL;     // [e][v][x]
+  double* sBb;     // [e][x]
+  double* sEM;     // [e][2]
+  double* sRat;    // [face]: -|grad lambda_jn| / |grad lambda_j|
+  double* sFs;     // [face][2]: |g|, 1/|g|^2 of the face direction g
+  double* sFac;    // [slot][e][2]: scalars of K(b(th))^{-1}, th = i / m
+  int* sElem;
+  int* sK;
+  int* sF;
+  int* sPF;        // [face]: patch face code (element << 2 | face)
+};
+
+template <int D, int P, typename T, int NTMAX, int SYS>
+__device__ __forceinline__ TentLds tent_lds(double* op, double* common) {
+  using SH = MShape<D, P, NTMAX, SYS>;
+  using LD = MLds<D, P, T, NTMAX, SYS>;
+  constexpr int NV = SH::NV;
+  TentLds L;
+  L.sOp = op;
+  L.sOpF = reinterpret_cast<float*>(op + SH::KT * LD::OPS);
+  L.sFn = reinterpret_cast<int*>(op + LD::op_elems);
+  L.sFsw = L.sFn + D * 2 * SH::NF;
+  L.sU = common;
+  L.sFR = L.sU + LD::u_elems;
+  L.sGL = L.sFR + LD::f_elems;
+  L.sBb = L.sGL + NTMAX * NV * D;
+  L.sEM = L.sBb + NTMAX * D;
+  L.sRat = L.sEM + NTMAX * 2;
+  L.sFs = L.sRat + NTMAX * D;
+  L.sFac = L.sFs + 2 * NTMAX * D;
+  L.sElem = reinterpret_cast<int*>(L.sFac + 4 * NTMAX);
+  L.sK = L.sElem + NTMAX;
+  L.sF = L.sK + NTMAX;
+  L.sPF = L.sF + NTMAX * D;
+  return L;
+}
+
+// The operator block of degree P: A operand [k][m] with S_l[m][a] at k = l NPK + a (a < NP),
+// -L_j[m][s] at k = KV + j NF + s, zero in the padding rows and columns; the face-node tables.
+template <int D, int P, typename T, int NTMAX, int SYS>
+__device__ __forceinline__ void stage_operator(const KernelParams& kp0, const TentLds& L, int tid) {
+  using SH = MShape<D, P, NTMAX, SYS>;
+  constexpr bool MIXED = sizeof(T) == 4;
+  constexpr int NP = SH::NP, NF = SH::NF, NPK = SH::NPK, KV = SH::KV, KF = SH::KF, KT = SH::KT;
+  constexpr int OPS = MLds<D, P, T, NTMAX, SYS>::OPS, BLOCK = SH::BLOCK;
+  for (int i = tid; i < KT * OPS; i += BLOCK) {
+    const int k = i / OPS, m = i - k * OPS;
+    double v = 0.0;
+    if (m < NP) {
+      if (k < KV) {
+        const int l = k / NPK, a = k - l * NPK;
+        if (a < NP) v = kp0.S[(l * NP + a) * NP + m];
+      } else if (k < KV + KF) {
+        const int j = (k - KV) / NF, s = (k - KV) - j * NF;
+        v = -kp0.L[(j * NF + s) * NP + m];
+      }
+    }
+    L.sOp[i] = v;
+    if constexpr (MIXED) {
+      if (k < KV) L.sOpF[i] = (float)v;
+    }
+  }
+  for (int i = tid; i < D * 2 * NF; i += BLOCK) L.sFn[i] = kp0.fnode[i];
+  for (int i = tid; i < NF; i += BLOCK) L.sFsw[i] = kp0.fswap[i];
+}
+
 
 // R = [S | -L] [A(grad lambda) U ; F] for this wave's tiles with TM-precision products
 // (operands converted from the FP64 LDS values as they are loaded), written back to
@@ -522,345 +601,339 @@ struct SchedBatchDag {   // the tent DAGs of a batch of solvers, one queue of gl
 // sub-interval, whose U_{i,0} has the full size of the fields, stays FP64; the later
 // stages act on the small Taylor coefficients U_{i,n}, n >= 1, and run on the FP32 cores.
 // RK4: the classical RK4 variant instead of SAT (FP64 only).
-template <int D, int P, typename T, int NTMAX, class Sched, bool RK4 = false, int SYS = 0>
-__device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sched) {
+// One tent of degree P in the LDS regions L: gather, m sub-intervals of the SAT recursion
+// (or classical RK4), scatter, and the tent vertex's new time.
+template <int D, int P, typename T, int NTMAX, bool RK4, int SYS>
+__device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, const TentLds& L, int tid, int lane,
+                                         int wave) {
   using SH = MShape<D, P, NTMAX, SYS>;
   using PH = Phys<D, SYS>;
   constexpr bool MIXED = sizeof(T) == 4;
   constexpr int NC = SH::NC, NP = SH::NP, NF = SH::NF, NV = SH::NV;
-  constexpr int NPK = SH::NPK, KV = SH::KV, KF = SH::KF, KT = SH::KT, MP = SH::MP, RS = SH::RS;
-  constexpr int OPS = MLds<D, P, T, NTMAX, SYS>::OPS;
+  constexpr int RS = SH::RS;
   constexpr int MAXPAIR = SH::MAXPAIR, BLOCK = SH::BLOCK;
-  using LD = MLds<D, P, T, NTMAX, SYS>;
-  extern __shared__ double lds_d[];
-  double* sOp = lds_d;                            // [k][m], m fastest
-  float* sOpF = reinterpret_cast<float*>(sOp + KT * OPS);   // mixed: FP32 copy of the volume rows k < KV
-  double* sU = sOp + LD::op_elems;                // [node][col]
-  double* sFR = sU + LD::u_elems;                 // [row][col]: F, then R
-  double* sGL = sFR + LD::f_elems;                // [e][v][x]
-  double* sBb = sGL + NTMAX * NV * D;             // [e][x]
-  double* sEM = sBb + NTMAX * D;                  // [e][2]
-  double* sRat = sEM + NTMAX * 2;                 // [face]: -|grad lambda_jn| / |grad lambda_j|
-  double* sFs = sRat + NTMAX * D;                 // [face][2]: |g|, 1/|g|^2 of the face direction g
-  double* sFac = sFs + 2 * NTMAX * D;             // [slot][e][2]: scalars of K(b(th))^{-1}, th = i / m
-  int* sFn = reinterpret_cast<int*>(sFac + 4 * NTMAX);
-  int* sElem = sFn + D * 2 * NF;
-  int* sK = sElem + NTMAX;
-  int* sF = sK + NTMAX;
-  int* sPF = sF + NTMAX * D;                      // [face]: patch face code (element << 2 | face)
-  int* sFsw = sPF + NTMAX * D;                    // [s]: face node with the two non-V vertices exchanged
+  double* const sOp = L.sOp;
+  float* const sOpF = L.sOpF;
+  double* const sU = L.sU;
+  double* const sFR = L.sFR;
+  double* const sGL = L.sGL;
+  double* const sBb = L.sBb;
+  double* const sEM = L.sEM;
+  double* const sRat = L.sRat;
+  double* const sFs = L.sFs;
+  double* const sFac = L.sFac;
+  const int* const sFn = L.sFn;
+  const int* const sFsw = L.sFsw;
+  int* const sElem = L.sElem;
+  int* const sK = L.sK;
+  int* const sF = L.sF;
+  int* const sPF = L.sPF;
+  const double invm = 1.0 / kp.m;
+  const int32_t V = kp.tent_vertex[t];
+  const double t_top = kp.slab[0] + kp.tent_top[t];
+  const int32_t p0 = kp.patch_ptr[V];
+  const int nT = kp.patch_ptr[V + 1] - p0;
+  const double H = t_top - kp.tau[V];
+  const int ncols = nT * NC;
+  const int ntiles = (ncols + 15) / 16;
+  const int32_t f0 = kp.pface_ptr[V];
+  const int nFace = kp.pface_ptr[V + 1] - f0;
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar registers)
-  // A operand [k][m]: S_l[m][a] at k = l NPK + a (a < NP), -L_j[m][s] at k = KV + j NF + s,
-  // zero in the padding rows and columns
-  for (int i = tid; i < KT * OPS; i += BLOCK) {
-    const int k = i / OPS, m = i - k * OPS;
-    double v = 0.0;
-    if (m < NP) {
-      if (k < KV) {
-        const int l = k / NPK, a = k - l * NPK;
-        if (a < NP) v = kp0.S[(l * NP + a) * NP + m];
-      } else if (k < KV + KF) {
-        const int j = (k - KV) / NF, s = (k - KV) - j * NF;
-        v = -kp0.L[(j * NF + s) * NP + m];
-      }
+  for (int e = tid; e < nT; e += BLOCK) {
+    const int el = kp.patch_elem[p0 + e];
+    const int32_t* info = kp.patch_info + (size_t)(p0 + e) * (1 + D);
+    const int k = info[0];
+    int order[NV];
+    vertex_order_dev<D>(k, order);
+    const double* gl = kp.grad_lam + (size_t)el * NV * D;
+    double gb[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) gb[i] = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double tv = kp.tau[kp.cells[(size_t)el * NV + v]];
+#pragma unroll
+      for (int i = 0; i < D; ++i) gb[i] += tv * gl[v * D + i];
     }
-    sOp[i] = v;
-    if constexpr (MIXED) {
-      if (k < KV) sOpF[i] = (float)v;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int i = 0; i < D; ++i) sGL[(e * NV + v) * D + i] = gl[order[v] * D + i];
+#pragma unroll
+    for (int i = 0; i < D; ++i) sBb[e * D + i] = gb[i];
+    sEM[2 * e] = kp.eps[el];
+    sEM[2 * e + 1] = kp.mu[el];
+    sElem[e] = el;
+    sK[e] = k;
+#pragma unroll
+    for (int j = 0; j < D; ++j) sF[e * D + j] = info[1 + j];
+  }
+  __syncthreads();
+
+  // gather W (FP64, registers) and U_{0,0} = K(b_0)^{-1} W (closed form in FP64)
+  const int npairs = nT * NP;
+  double acc[MAXPAIR][NC];
+  bool ok = true;
+#pragma unroll
+  for (int r = 0; r < MAXPAIR; ++r) {
+    const int P_ = tid + r * BLOCK;
+    if (P_ < npairs) {
+      const int e = P_ / NP, b = P_ - e * NP;
+      const int nold = kp.perm[sK[e] * NP + b];
+      const double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[r][c] = Wp[c * NP];
+      double u[NC];
+      ok &= PH::inv(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = u[c];
     }
   }
-  // padding rows of U and F are read by the product (times zero): keep them finite
-  for (int i = tid; i < (NPK - NP) * RS; i += BLOCK) sU[NP * RS + i] = 0.0;
-  for (int i = tid; i < (SH::FROWS - KF) * RS; i += BLOCK) sFR[KF * RS + i] = 0.0;
-  for (int i = tid; i < D * 2 * NF; i += BLOCK) sFn[i] = kp0.fnode[i];
-  for (int i = tid; i < NF; i += BLOCK) sFsw[i] = kp0.fswap[i];
-
-  __shared__ int sh_tent[2];
-  for (;;) {
-    int64_t t;
-    if (!sched.next(kp0, sh_tent, tid, t)) break;
-    const KernelParams& kp = sched.params(kp0);
-    const double invm = 1.0 / kp.m;
-    const int32_t V = kp.tent_vertex[t];
-    const double t_top = kp.slab[0] + kp.tent_top[t];
-    const int32_t p0 = kp.patch_ptr[V];
-    const int nT = kp.patch_ptr[V + 1] - p0;
-    const double H = t_top - kp.tau[V];
-    const int ncols = nT * NC;
-    const int ntiles = (ncols + 15) / 16;
-    const int32_t f0 = kp.pface_ptr[V];
-    const int nFace = kp.pface_ptr[V + 1] - f0;
-
-    for (int e = tid; e < nT; e += BLOCK) {
-      const int el = kp.patch_elem[p0 + e];
-      const int32_t* info = kp.patch_info + (size_t)(p0 + e) * (1 + D);
-      const int k = info[0];
-      int order[NV];
-      vertex_order_dev<D>(k, order);
-      const double* gl = kp.grad_lam + (size_t)el * NV * D;
-      double gb[D];
+  // per face, once per tent: the face code and, for an interior face, the factor that
+  // carries the flux to the other side
+  for (int fi = tid; fi < nFace; fi += BLOCK) {
+    const int fc = kp.pface[f0 + fi];
+    const int e = fc >> 2, j = fc & 3;
+    const int code = sF[e * D + j];
+    face_scalars<D>(&sGL[(e * NV + j + 1) * D], &sFs[2 * fi]);
+    double ratio = 0.0;
+    if (code >= 0) {
+      const int pe = code >> 4, jn = (code >> 1) & 7;
+      double gg = 0.0, gn = 0.0;
 #pragma unroll
-      for (int i = 0; i < D; ++i) gb[i] = 0.0;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double tv = kp.tau[kp.cells[(size_t)el * NV + v]];
-#pragma unroll
-        for (int i = 0; i < D; ++i) gb[i] += tv * gl[v * D + i];
+      for (int x = 0; x < D; ++x) {
+        const double a = sGL[(e * NV + j + 1) * D + x];
+        gg += a * a;
+        const double h = sGL[(pe * NV + jn) * D + x];
+        gn += h * h;
       }
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int i = 0; i < D; ++i) sGL[(e * NV + v) * D + i] = gl[order[v] * D + i];
-#pragma unroll
-      for (int i = 0; i < D; ++i) sBb[e * D + i] = gb[i];
-      sEM[2 * e] = kp.eps[el];
-      sEM[2 * e + 1] = kp.mu[el];
-      sElem[e] = el;
-      sK[e] = k;
-#pragma unroll
-      for (int j = 0; j < D; ++j) sF[e * D + j] = info[1 + j];
+      ratio = -sqrt(gn / gg);
     }
-    __syncthreads();
+    sPF[fi] = fc;
+    sRat[fi] = ratio;
+  }
+  // scalars of the inverse at th_0 and th_1 (slot i & 1 holds th_i); the recursion then
+  // computes th_{i+2} into the slot th_i leaves, in the last stage of sub-interval i.  Only
+  // th_i with i < m are used (the tent top is never inverted), and only those are formed,
+  // so that the causality flag covers exactly the inversions the method makes
+  auto fac_at = [&](int ib, int slot) {
+    for (int e = BLOCK - 1 - tid; e < nT; e += BLOCK) {
+      const double thb = ib * invm;
+      const double* gv = &sGL[(e * NV + 0) * D];
+      double bi[D];
+#pragma unroll
+      for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + thb * (H * gv[x]);
+      ok &= PH::inv_fac(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[(slot * NTMAX + e) * 2]);
+    }
+  };
+  if constexpr (!RK4) {
+    fac_at(0, 0);
+    if (kp.m > 1) fac_at(1, 1);
+  }
+  __syncthreads();
 
-    // gather W (FP64, registers) and U_{0,0} = K(b_0)^{-1} W (closed form in FP64)
-    const int npairs = nT * NP;
-    double acc[MAXPAIR][NC];
-    bool ok = true;
-#pragma unroll
-    for (int r = 0; r < MAXPAIR; ++r) {
-      const int P_ = tid + r * BLOCK;
-      if (P_ < npairs) {
-        const int e = P_ / NP, b = P_ - e * NP;
-        const int nold = kp.perm[sK[e] * NP + b];
-        const double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) acc[r][c] = Wp[c * NP];
-        double u[NC];
-        ok &= PH::inv(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = u[c];
-      }
-    }
-    // per face, once per tent: the face code and, for an interior face, the factor that
-    // carries the flux to the other side
-    for (int fi = tid; fi < nFace; fi += BLOCK) {
-      const int fc = kp.pface[f0 + fi];
+  // ---- face fluxes for stage input U at sub-interval time th (data ghosts: derivative
+  //      n - 1 of the boundary data)
+  auto face_fluxes = [&](double th, int n) {
+    // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col], each face once:
+    //      the other side of an interior face gets -(|grad lambda_jn| / |grad lambda_j|) G
+    //      at its own face-node order (exchanged when the two orders differ)
+    // items from the last thread down: a short last round falls on the last wave, which
+    // has the fewest product tiles and so the most slack in the product's volume part
+    for (int it = BLOCK - 1 - tid; it < nFace * NF; it += BLOCK) {
+      const int fi = it / NF;
+      const int s = it - fi * NF;
+      const int fc = sPF[fi];
       const int e = fc >> 2, j = fc & 3;
+      const int nin = sFn[(j * 2) * NF + s];
+      double um[NC], up[NC], G[NC], g[D];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) um[c] = sU[nin * RS + e * NC + c];
+#pragma unroll
+      for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
       const int code = sF[e * D + j];
-      face_scalars<D>(&sGL[(e * NV + j + 1) * D], &sFs[2 * fi]);
-      double ratio = 0.0;
       if (code >= 0) {
-        const int pe = code >> 4, jn = (code >> 1) & 7;
-        double gg = 0.0, gn = 0.0;
+        const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
+        const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
 #pragma unroll
-        for (int x = 0; x < D; ++x) {
-          const double a = sGL[(e * NV + j + 1) * D + x];
-          gg += a * a;
-          const double h = sGL[(pe * NV + jn) * D + x];
-          gn += h * h;
-        }
-        ratio = -sqrt(gn / gg);
-      }
-      sPF[fi] = fc;
-      sRat[fi] = ratio;
-    }
-    // scalars of the inverse at th_0 and th_1 (slot i & 1 holds th_i); the recursion then
-    // computes th_{i+2} into the slot th_i leaves, in the last stage of sub-interval i.  Only
-    // th_i with i < m are used (the tent top is never inverted), and only those are formed,
-    // so that the causality flag covers exactly the inversions the method makes
-    auto fac_at = [&](int ib, int slot) {
-      for (int e = BLOCK - 1 - tid; e < nT; e += BLOCK) {
-        const double thb = ib * invm;
-        const double* gv = &sGL[(e * NV + 0) * D];
-        double bi[D];
-#pragma unroll
-        for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + thb * (H * gv[x]);
-        ok &= PH::inv_fac(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[(slot * NTMAX + e) * 2]);
-      }
-    };
-    if constexpr (!RK4) {
-      fac_at(0, 0);
-      if (kp.m > 1) fac_at(1, 1);
-    }
-    __syncthreads();
-
-    // ---- face fluxes for stage input U at sub-interval time th (data ghosts: derivative
-    //      n - 1 of the boundary data)
-    auto face_fluxes = [&](double th, int n) {
-      // ---- face fluxes (times |grad lambda_j|) into F[j nf + s][col], each face once:
-      //      the other side of an interior face gets -(|grad lambda_jn| / |grad lambda_j|) G
-      //      at its own face-node order (exchanged when the two orders differ)
-      // items from the last thread down: a short last round falls on the last wave, which
-      // has the fewest product tiles and so the most slack in the product's volume part
-      for (int it = BLOCK - 1 - tid; it < nFace * NF; it += BLOCK) {
-        const int fi = it / NF;
-        const int s = it - fi * NF;
-        const int fc = sPF[fi];
-        const int e = fc >> 2, j = fc & 3;
-        const int nin = sFn[(j * 2) * NF + s];
-        double um[NC], up[NC], G[NC], g[D];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) um[c] = sU[nin * RS + e * NC + c];
-#pragma unroll
-        for (int x = 0; x < D; ++x) g[x] = -sGL[(e * NV + j + 1) * D + x];
-        const int code = sF[e * D + j];
-        if (code >= 0) {
-          const int pe = code >> 4, jn = (code >> 1) & 7, o = code & 1;
-          const int nout = sFn[((jn - 1) * 2 + o) * NF + s];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
-          if (kp.flux_kind == 1)
-            PH::fl_imp(g, &sFs[2 * fi], sqrt(sEM[2 * e + 1] / sEM[2 * e]), sqrt(sEM[2 * pe + 1] / sEM[2 * pe]), um,
-                       up, G);
-          else
-            PH::fl(g, &sFs[2 * fi], kp.alpha, um, up, G);
-          const double ratio = sRat[fi];
-          const int s2 = o ? sFsw[s] : s;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            sFR[(j * NF + s) * RS + e * NC + c] = G[c];
-            sFR[((jn - 1) * NF + s2) * RS + pe * NC + c] = ratio * G[c];
-          }
-        } else {
-          ghost_state<D, P, SYS>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
-          if (kp.flux_kind == 1) {   // walls and data: the element's own medium on both sides
-            const double z = sqrt(sEM[2 * e + 1] / sEM[2 * e]);
-            PH::fl_imp(g, &sFs[2 * fi], z, z, um, up, G);
-          } else {
-            PH::fl(g, &sFs[2 * fi], kp.alpha, um, up, G);
-          }
-#pragma unroll
-          for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
-        }
-      }
-      // no barrier: the product reads F only after its volume part and a barrier
-    };
-
-    if constexpr (RK4) {
-      // classical RK4 on dW/dth = H R(K(b(th))^{-1} W) + data source, the naive variant the
-      // paper contrasts with SAT: four evaluations per sub-interval, each with the pointwise
-      // inverse at its own time; FP64 step-start state (acc) and stage sum (ks)
-      double ks[MAXPAIR][NC];
-      for (int i = 0; i < kp.m; ++i) {
-        for (int s = 0; s < 4; ++s) {
-          const double th = (i + (s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5))) * invm;
-          face_fluxes(th, 1);
-          tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
-          const double thn = (s == 3) ? (i + 1) * invm : (i + (s == 2 ? 1.0 : 0.5)) * invm;
-          const double a = (s == 2) ? invm : 0.5 * invm;   // weight of k_s in the next stage input
-          const double wk = (s == 0 || s == 3) ? 1.0 : 2.0;
-#pragma unroll
-          for (int r = 0; r < MAXPAIR; ++r) {
-            const int P_ = tid + r * BLOCK;
-            if (P_ < npairs) {
-              const int e = P_ / NP, b = P_ - e * NP;
-              double wst[NC];
-#pragma unroll
-              for (int c = 0; c < NC; ++c) {
-                const double k = H * sFR[b * RS + e * NC + c];
-                ks[r][c] = (s == 0) ? k : fma(wk, k, ks[r][c]);
-                if (s < 3) {
-                  wst[c] = fma(a, k, acc[r][c]);
-                } else {
-                  acc[r][c] = fma(invm / 6.0, ks[r][c], acc[r][c]);
-                  wst[c] = acc[r][c];
-                }
-              }
-              if (s < 3 || i + 1 < kp.m) {
-                const double* gv = &sGL[(e * NV + 0) * D];
-                double bi[D], un[NC];
-#pragma unroll
-                for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + thn * H * gv[x];
-                ok &= PH::inv(bi, sEM[2 * e], sEM[2 * e + 1], wst, un);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = un[c];
-              }
-            }
-          }
-          __syncthreads();
-        }
-      }
-    } else
-    for (int i = 0; i < kp.m; ++i) {
-      const double th = i * invm;
-      double coef = 1.0;
-      for (int n = 1; n <= kp.q; ++n) {
-        coef *= invm / n;
-        face_fluxes(th, n);
-
-        // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
-        if (MIXED && n >= 2)
-          tile_product<float, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
+        for (int c = 0; c < NC; ++c) up[c] = sU[nout * RS + pe * NC + c];
+        if (kp.flux_kind == 1)
+          PH::fl_imp(g, &sFs[2 * fi], sqrt(sEM[2 * e + 1] / sEM[2 * e]), sqrt(sEM[2 * pe + 1] / sEM[2 * pe]), um,
+                     up, G);
         else
-          tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
+          PH::fl(g, &sFs[2 * fi], kp.alpha, um, up, G);
+        const double ratio = sRat[fi];
+        const int s2 = o ? sFsw[s] : s;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          sFR[(j * NF + s) * RS + e * NC + c] = G[c];
+          sFR[((jn - 1) * NF + s2) * RS + pe * NC + c] = ratio * G[c];
+        }
+      } else {
+        ghost_state<D, P, SYS>(kp, -1 - code, um, up, sElem[e], sK[e], nin, H, th, n);
+        if (kp.flux_kind == 1) {   // walls and data: the element's own medium on both sides
+          const double z = sqrt(sEM[2 * e + 1] / sEM[2 * e]);
+          PH::fl_imp(g, &sFs[2 * fi], z, z, um, up, G);
+        } else {
+          PH::fl(g, &sFs[2 * fi], kp.alpha, um, up, G);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sFR[(j * NF + s) * RS + e * NC + c] = G[c];
+      }
+    }
+    // no barrier: the product reads F only after its volume part and a barrier
+  };
 
-        // ---- Taylor accumulation (FP64) and the next U for the owned (element, node) pairs
+  if constexpr (RK4) {
+    // classical RK4 on dW/dth = H R(K(b(th))^{-1} W) + data source, the naive variant the
+    // paper contrasts with SAT: four evaluations per sub-interval, each with the pointwise
+    // inverse at its own time; FP64 step-start state (acc) and stage sum (ks)
+    double ks[MAXPAIR][NC];
+    for (int i = 0; i < kp.m; ++i) {
+      for (int s = 0; s < 4; ++s) {
+        const double th = (i + (s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5))) * invm;
+        face_fluxes(th, 1);
+        tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
+        const double thn = (s == 3) ? (i + 1) * invm : (i + (s == 2 ? 1.0 : 0.5)) * invm;
+        const double a = (s == 2) ? invm : 0.5 * invm;   // weight of k_s in the next stage input
+        const double wk = (s == 0 || s == 3) ? 1.0 : 2.0;
 #pragma unroll
         for (int r = 0; r < MAXPAIR; ++r) {
           const int P_ = tid + r * BLOCK;
           if (P_ < npairs) {
             const int e = P_ / NP, b = P_ - e * NP;
-            double Y[NC];
+            double wst[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-              Y[c] = H * sFR[b * RS + e * NC + c];
-              acc[r][c] = fma(coef, Y[c], acc[r][c]);
-            }
-            const double* gv = &sGL[(e * NV + 0) * D];
-            double un[NC];
-            bool write = false;
-            if (n < kp.q) {
-              double bi[D], bp[D], uo[NC], au[NC], rhs[NC];
-#pragma unroll
-              for (int x = 0; x < D; ++x) {
-                bp[x] = H * gv[x];
-                bi[x] = sBb[e * D + x] + th * bp[x];
+              const double k = H * sFR[b * RS + e * NC + c];
+              ks[r][c] = (s == 0) ? k : fma(wk, k, ks[r][c]);
+              if (s < 3) {
+                wst[c] = fma(a, k, acc[r][c]);
+              } else {
+                acc[r][c] = fma(invm / 6.0, ks[r][c], acc[r][c]);
+                wst[c] = acc[r][c];
               }
-#pragma unroll
-              for (int c = 0; c < NC; ++c) uo[c] = sU[b * RS + e * NC + c];
-              PH::A(bp, uo, au);
-#pragma unroll
-              for (int c = 0; c < NC; ++c) rhs[c] = Y[c] + n * au[c];
-              PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[((i & 1) * NTMAX + e) * 2], rhs, un);
-              write = true;
-            } else if (i + 1 < kp.m) {
-              double bi[D];
-              const double th1 = (i + 1) * invm;
-#pragma unroll
-              for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * (H * gv[x]);
-              PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[(((i + 1) & 1) * NTMAX + e) * 2], acc[r], un);
-              write = true;
             }
-            if (write) {
+            if (s < 3 || i + 1 < kp.m) {
+              const double* gv = &sGL[(e * NV + 0) * D];
+              double bi[D], un[NC];
+#pragma unroll
+              for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + thn * H * gv[x];
+              ok &= PH::inv(bi, sEM[2 * e], sEM[2 * e + 1], wst, un);
 #pragma unroll
               for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = un[c];
             }
           }
         }
-        if (n == kp.q && i + 2 < kp.m) fac_at(i + 2, i & 1);   // read again in sub-interval i + 1's last stage
         __syncthreads();
       }
     }
+  } else
+  for (int i = 0; i < kp.m; ++i) {
+    const double th = i * invm;
+    double coef = 1.0;
+    for (int n = 1; n <= kp.q; ++n) {
+      coef *= invm / n;
+      face_fluxes(th, n);
 
-    // scatter the tent top
+      // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
+      if (MIXED && n >= 2)
+        tile_product<float, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
+      else
+        tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles);
+
+      // ---- Taylor accumulation (FP64) and the next U for the owned (element, node) pairs
 #pragma unroll
-    for (int r = 0; r < MAXPAIR; ++r) {
-      const int P_ = tid + r * BLOCK;
-      if (P_ < npairs) {
-        const int e = P_ / NP, b = P_ - e * NP;
-        const int nold = kp.perm[sK[e] * NP + b];
-        double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+      for (int r = 0; r < MAXPAIR; ++r) {
+        const int P_ = tid + r * BLOCK;
+        if (P_ < npairs) {
+          const int e = P_ / NP, b = P_ - e * NP;
+          double Y[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) Wp[c * NP] = acc[r][c];
+          for (int c = 0; c < NC; ++c) {
+            Y[c] = H * sFR[b * RS + e * NC + c];
+            acc[r][c] = fma(coef, Y[c], acc[r][c]);
+          }
+          const double* gv = &sGL[(e * NV + 0) * D];
+          double un[NC];
+          bool write = false;
+          if (n < kp.q) {
+            double bi[D], bp[D], uo[NC], au[NC], rhs[NC];
+#pragma unroll
+            for (int x = 0; x < D; ++x) {
+              bp[x] = H * gv[x];
+              bi[x] = sBb[e * D + x] + th * bp[x];
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) uo[c] = sU[b * RS + e * NC + c];
+            PH::A(bp, uo, au);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) rhs[c] = Y[c] + n * au[c];
+            PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[((i & 1) * NTMAX + e) * 2], rhs, un);
+            write = true;
+          } else if (i + 1 < kp.m) {
+            double bi[D];
+            const double th1 = (i + 1) * invm;
+#pragma unroll
+            for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * (H * gv[x]);
+            PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[(((i + 1) & 1) * NTMAX + e) * 2], acc[r], un);
+            write = true;
+          }
+          if (write) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = un[c];
+          }
+        }
       }
+      if (n == kp.q && i + 2 < kp.m) fac_at(i + 2, i & 1);   // read again in sub-interval i + 1's last stage
+      __syncthreads();
     }
-    if (!ok) kp.err[0] = ERRF_CAUSALITY;
-    __syncthreads();
-    if (tid == 0) kp.tau[V] = t_top;
-    __syncthreads();
+  }
+
+  // scatter the tent top
+#pragma unroll
+  for (int r = 0; r < MAXPAIR; ++r) {
+    const int P_ = tid + r * BLOCK;
+    if (P_ < npairs) {
+      const int e = P_ / NP, b = P_ - e * NP;
+      const int nold = kp.perm[sK[e] * NP + b];
+      double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) Wp[c * NP] = acc[r][c];
+    }
+  }
+  if (!ok) kp.err[0] = ERRF_CAUSALITY;
+  __syncthreads();
+  if (tid == 0) kp.tau[V] = t_top;
+  __syncthreads();
+}
+
+// Body shared by every single-degree entry point: the operator of degree P staged once,
+// then tents from the Sched source (all solvers of a batch share dimension and degree).
+// T = double: every product in FP64.  T = float (mixed): the first stage of every
+// sub-interval, whose U_{i,0} has the full size of the fields, stays FP64; the later
+// stages act on the small Taylor coefficients U_{i,n}, n >= 1, and run on the FP32 cores.
+// RK4: the classical RK4 variant instead of SAT (FP64 only).
+template <int D, int P, typename T, int NTMAX, class Sched, bool RK4 = false, int SYS = 0>
+__device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sched) {
+  using SH = MShape<D, P, NTMAX, SYS>;
+  using LD = MLds<D, P, T, NTMAX, SYS>;
+  extern __shared__ double lds_d[];
+  const TentLds L = tent_lds<D, P, T, NTMAX, SYS>(lds_d, lds_d + LD::op_block);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar registers)
+  stage_operator<D, P, T, NTMAX, SYS>(kp0, L, tid);
+  // padding rows of U and F are read by the product (times zero): keep them finite
+  for (int i = tid; i < (SH::NPK - SH::NP) * SH::RS; i += SH::BLOCK) L.sU[SH::NP * SH::RS + i] = 0.0;
+  for (int i = tid; i < (SH::FROWS - SH::KF) * SH::RS; i += SH::BLOCK) L.sFR[SH::KF * SH::RS + i] = 0.0;
+  __syncthreads();
+  __shared__ int sh_tent[2];
+  for (;;) {
+    int64_t t;
+    if (!sched.next(kp0, sh_tent, tid, t)) break;
+    const KernelParams& kp = sched.params(kp0);
+    tent_run<D, P, T, NTMAX, RK4, SYS>(kp, t, L, tid, lane, wave);
     sched.done(kp, t, tid);
   }
 }

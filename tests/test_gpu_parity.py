@@ -305,3 +305,34 @@ def test_planewave_change_between_graph_replays():
     wa, wb, wk = A.get_state(), B.get_state(), K.get_state()
     assert np.array_equal(wa, wb)
     assert rel(wa, wk) > 1e-3
+
+
+MIXED_DEGREE = {
+    2: ["te_pmc_p1", "te_planewave_p2", "te_pmc_p3", "te_pec_p4_alpha025", "te_pmc_p5", "te_fan32_p2_data",
+        "te_fan12_p3"],
+    3: ["cav3d_p1", "cav3d_p3", "planewave3d_p2", "cav3d_p2", "delaunay3d_p3_eps", "cav3d_p4"],
+}
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("precision,tol", [(0, TOL), (1, MIXED_TOL)])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_batch_mixed_degrees_against_oracle(dim, precision, tol, schedule):
+    """Solves of several degrees (listed out of degree order; cavities, plane-wave data
+    faces, fans and a Delaunay patch) in one batch: the batch groups its solvers by degree,
+    one launch per (global layer index, degree) or one persistent launch per degree; against
+    the oracle's fixtures element by element, and bitwise equal to the same solves advanced
+    one by one."""
+    from paper_1906_11029_amd import mtp
+    names = MIXED_DEGREE[dim]
+    print(f"[gpu parity] {dim}D mixed-degree batch precision {precision} schedule {schedule}", flush=True)
+    batched = [gpu_solver(nm, precision)[1] for nm in names]
+    single = [gpu_solver(nm, precision) for nm in names]
+    B = mtp.Batch(batched)
+    B.set_schedule(schedule)
+    B.advance(1)
+    for S, (c, S1, _), nm in zip(batched, single, names):
+        S1.advance_to(c["T"])
+        w = S.get_state()
+        assert_parity(w, fixture(nm)["w"], tol, f"batch {nm}")
+        assert np.array_equal(w, S1.get_state()), nm
