@@ -213,9 +213,21 @@ def measured_traffic(tag):
         return None
 
 
-def run(W, precision, steps, warmup, M=None, T=None, schedule="layers"):
+SCHEDULES = {"layers": 0, "dag": 1}
+TILE_ORDERS = {0: "default", 1: "round-robin", 2: "blocked", 3: "column-major"}
+
+
+def describe_tuning(t):
+    return {"schedule": {0: "layers", 1: "dag"}[t["schedule"]], "tile_order": TILE_ORDERS[t["tile_order"]],
+            "grid_frac": t["grid_frac"], "from_tuning_table": t.get("from_table", False)}
+
+
+def run(W, precision, steps, warmup, M=None, T=None, schedule="auto", tune=0):
     """Set up one solver on workload W, advance `warmup` untimed and `steps` timed slabs
-    (each a replay of the captured slab graph); returns timings and the final fields."""
+    (each a replay of the captured slab graph); returns timings and the final fields.
+    schedule "auto": the launch choice the tuning table gives at creation (the default
+    choice without an entry); tune > 0: run the tuner (tune timed slabs per candidate)
+    after the warm-up and time the choice it applies."""
     import torch
 
     from mtp_inputs import meshes
@@ -227,13 +239,19 @@ def run(W, precision, steps, warmup, M=None, T=None, schedule="layers"):
         T = mtp.Tents(M, W["T"], 0.5)
     prec = {"fp64": mtp.MTP_FP64, "mixed": mtp.MTP_MIXED_FP32, "fp64-valu": mtp.MTP_FP64_VALU}[precision]
     S = mtp.Solver(M, T, W["p"], W["q"], W["m"], precision=prec)
-    S.set_schedule({"layers": mtp.MTP_SCHEDULE_LAYERS, "dag": mtp.MTP_SCHEDULE_DAG}[schedule])
+    if schedule != "auto":
+        S.set_tuning(SCHEDULES[schedule])
     S.set_fields(W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), 0.0), 0.0)
     dof_slab, n_tents = S.slab_dof_updates()
     front = 0.0
     for _ in range(warmup):
         front += W["T"]
         S.advance_to(front)
+    tuned = None
+    if tune > 0:
+        tuned = S.tune(tune)
+        log(f"tuner: {tuned}")
+    tuning = S.tuning()
     stream = torch.cuda.current_stream()   # the solver's stream: graphs replay on it
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -253,10 +271,34 @@ def run(W, precision, steps, warmup, M=None, T=None, schedule="layers"):
         uex = W["ex"].u(meshes.equispaced_nodes(mm, W["p"]), front)
         err = float(np.linalg.norm(u - uex) / np.linalg.norm(uex))
     r = dict(S=S, M=M, T=T, wall=wall, gpu_s=gpu_s, u=u, err=err, dof_slab=dof_slab, n_tents=n_tents,
-             flops_slab=S.slab_flops(), kernel=S.kernel(), layers=T.n_layers, value=dof_slab * steps / wall)
-    log(f"{precision:6s} {schedule:6s} {W['name']}: {steps} slabs in {wall:.3f}s (events {gpu_s:.3f}s), "
-        f"{r['value']:.4e} DOF-updates/s, error vs exact {err}")
+             flops_slab=S.slab_flops(), kernel=S.kernel(), layers=T.n_layers, value=dof_slab * steps / wall,
+             tuning=tuning, tuned=tuned, front=front)
+    log(f"{precision:6s} {describe_tuning(tuning)} {W['name']}: {steps} slabs in {wall:.3f}s "
+        f"(events {gpu_s:.3f}s), {r['value']:.4e} DOF-updates/s, error vs exact {err}")
     return r
+
+
+def default_choice_ms(r, W, steps):
+    """Time per slab of the same solver with the default launch choice (layer schedule,
+    default tiles, full grid), continuing from where run() stopped; None if the applied
+    choice is the default."""
+    import torch
+    t = r["tuning"]
+    if t["schedule"] == 0 and t["tile_order"] == 0 and t["grid_frac"] == 1.0:
+        return None
+    S, front = r["S"], r["front"]
+    S.set_tuning(0)
+    front += W["T"]
+    S.advance_to(front)   # captures the default choice's slab graph
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(steps):
+        front += W["T"]
+        S.advance_to(front)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - w0) / steps * 1e3
+    S.set_tuning(t["schedule"], t["tile_order"], t["grid_frac"])
+    return ms
 
 
 def batch2d(args):
@@ -294,28 +336,32 @@ def batch2d(args):
     solves = make()
     log(f"batch2d: 64 solves set up in {time.perf_counter() - t0:.1f}s")
     B = mtp.Batch([S for S, _, _ in solves])
-    B.set_schedule(mtp.MTP_SCHEDULE_DAG if args.schedule == "dag" else mtp.MTP_SCHEDULE_LAYERS)
-    batches = [B]
+    if args.schedule != "auto":
+        B.set_tuning(SCHEDULES[args.schedule])
     dof = sum(S.slab_dof_updates()[0] for S, _, _ in solves)
     tents = sum(S.slab_dof_updates()[1] for S, _, _ in solves)
-    for B in batches:
-        B.advance(args.warmup)
+    B.advance(args.warmup)
+    tuned = B.tune(args.tune) if args.tune > 0 else None
+    if tuned:
+        log(f"tuner: {tuned}")
+    tuning = describe_tuning(B.tuning())
+    if tuned:
+        tuning["tuner"] = tuned
     torch.cuda.synchronize()
     w0 = time.perf_counter()
-    for B in batches:
-        B.advance(args.steps)
+    B.advance(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     value = dof * args.steps / wall
     tf = H * (args.warmup + args.steps)
     errs = [float(np.linalg.norm(S.get_fields() - ex.u(nodes, tf)) / np.linalg.norm(ex.u(nodes, tf)))
             for S, ex, nodes in solves]
-    log(f"batched ({args.schedule}): {args.steps} slabs in {wall:.3f}s, {value:.4e} DOF-updates/s; errors max {max(errs):.2e}")
+    log(f"batched ({tuning}): {args.steps} slabs in {wall:.3f}s, {value:.4e} DOF-updates/s; errors max {max(errs):.2e}")
     compare = None
     if not args.no_compare:
         seq = make()
         for S, _, _ in seq:
-            S.set_schedule(mtp.MTP_SCHEDULE_LAYERS)
+            S.set_tuning(mtp.MTP_SCHEDULE_LAYERS)
             S.advance_to(H * args.warmup)
         torch.cuda.synchronize()
         w1 = time.perf_counter()
@@ -333,10 +379,10 @@ def batch2d(args):
            "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
            "config": {"workload": "64 independent 2D TE plane-wave solves (seed 4), n in 23..158, p in 2..5, "
                                   "q = p+1, m = 2p, data faces, slab 0.1; one batch grouped by degree, "
-                                  + ("one persistent launch per degree and slab" if args.schedule == "dag"
+                                  + ("one persistent launch per degree and slab" if tuning["schedule"] == "dag"
                                      else "one launch per global layer index and degree"),
                       "solves": 64, "tents_per_step": int(tents), "precision": args.precision,
-                      "schedule": args.schedule,
+                      "schedule": tuning["schedule"], "tuning": tuning,
                       "rel_l2_error_vs_exact": {"max": max(errs), "median": float(np.median(errs))},
                       "compare": compare}}
     print(json.dumps(out), flush=True)
@@ -349,10 +395,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="graded3d_p4")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "fp64-valu"])
-    ap.add_argument("--schedule", default=None, choices=["layers", "dag"],
-                    help="one launch per layer, or one persistent launch per slab over the tent DAG "
-                         "(default: dag; layers for batch2d, whose tiny 2D tents pay more for the "
-                         "persistent schedule's device-scope fences than they gain)")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "layers", "dag"],
+                    help="one launch per layer, one persistent launch per slab over the tent DAG, or "
+                         "auto (default): the launch choice of the package's tuning table")
+    ap.add_argument("--tune", type=int, default=0,
+                    help="run the tuner (this many timed slabs per candidate) before timing")
+    ap.add_argument("--tune-out", default=None, help="write the tuning table here at the end")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 run of the same workload and the equal-error check")
     ap.add_argument("--cpu-budget", type=float, default=12.0,
@@ -377,15 +425,22 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": x.numel() * 8, "copies": 3}))
         return
 
+    from paper_1906_11029_amd import mtp
     if args.workload == "batch2d":
-        args.schedule = args.schedule or "layers"
         batch2d(args)
+        if args.tune_out:
+            mtp.mtp_tune_save(args.tune_out)
         return
-    args.schedule = args.schedule or "dag"
     W = workload(args.workload)
-    head = run(W, args.precision, args.steps, args.warmup, schedule=args.schedule)
-    M, T, S = head["M"], head["T"], head["S"]
+    head = run(W, args.precision, args.steps, args.warmup, schedule=args.schedule, tune=args.tune)
+    M, T = head["M"], head["T"]
     log(f"mesh {M.info} tents {head['n_tents']} layers {head['layers']}")
+    tuning = describe_tuning(head["tuning"])
+    if head["tuned"]:
+        tuning["tuner"] = head["tuned"]
+    tuning["default_choice_ms_per_step"] = default_choice_ms(head, W, min(args.steps, 5))
+    del head["S"]
+    args.schedule = tuning["schedule"]
     kernel_name = {0: "tent_kernel (vector-ALU FP64)", 1: "tent_mfma_kernel<double> (FP64 MFMA)",
                    2: "tent_mfma_kernel<float> (FP64 first stage, FP32 MFMA later stages)"}[head["kernel"]]
     nl = head["layers"]
@@ -405,7 +460,7 @@ def main():
     if not args.no_compare and args.precision == "mixed":
         # the plain FP64 path on the same workload and inputs, and the equal-error check on
         # the same graded mesh with a closed-form solution over as many slabs as above
-        ref = run(W, "fp64", args.steps, args.warmup, M=M, T=T, schedule=args.schedule)
+        ref = run(W, "fp64", args.steps, args.warmup, M=M, T=T, schedule="auto", tune=args.tune)
         diff = float(np.linalg.norm(head["u"] - ref["u"]) / np.linalg.norm(ref["u"]))
         del ref["S"]
         cert = {}
@@ -413,7 +468,7 @@ def main():
             Wc = workload(W["cert"])
             nsl = args.steps + args.warmup
             for prec in ("fp64", "mixed"):
-                rc = run(Wc, prec, nsl, 0, schedule=args.schedule)
+                rc = run(Wc, prec, nsl, 0, schedule="auto")
                 cert[prec + "_rel_l2_error_vs_exact"] = rc["err"]
                 del rc
             cert["slabs"] = nsl
@@ -423,6 +478,7 @@ def main():
             cert["equal_within_5pct"] = bool(abs(emx / e64 - 1) <= 0.05)
             cert["workload"] = Wc["desc"]
         compare = {"fp64_dof_updates_per_s": ref["value"], "speedup_vs_fp64": head["value"] / ref["value"],
+                   "fp64_tuning": describe_tuning(ref["tuning"]),
                    "mixed_vs_fp64_rel_l2": diff, "equal_error_check": cert or None}
 
     out = {
@@ -435,7 +491,7 @@ def main():
                    "tents_per_step": int(head["n_tents"]), "layers_per_step": int(nl), "slope_fraction": 0.5,
                    "mean_slope_over_bound": round(float(slopes["mean_slope_over_bound"]), 4),
                    "tents_per_vertex_per_slab": round(float(slopes["tents_per_vertex_per_slab"]), 3),
-                   "precision": args.precision, "schedule": args.schedule,
+                   "precision": args.precision, "schedule": args.schedule, "tuning": tuning,
                    "nodal_rel_error_vs_exact": head["err"],
                    "tent_dof_updates_per_s": head["value"] / (W["m"] * W["q"])},
         "roofline": {"bound": "alu" if head["kernel"] == 0 else "mfma", "achieved": achieved, "peak": peak,
@@ -453,6 +509,8 @@ def main():
         out["config"]["compare"] = compare
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, args.cpu_budget)
+    if args.tune_out:
+        mtp.mtp_tune_save(args.tune_out)
     print(json.dumps(out), flush=True)
 
 

@@ -360,6 +360,65 @@ typedef struct {
 } mtp_stats_t;
 mtp_status mtp_stats(mtp_solver solver, mtp_stats_t* out);
 
+/* Tuning of launch choices that leave the results unchanged bit for bit: the schedule
+ * (MTP_SCHEDULE_LAYERS or MTP_SCHEDULE_DAG), the assignment of the matrix-core product's
+ * tiles to the waves of a tent's workgroup, and the number of workgroups of the
+ * persistent schedule as a fraction of the resident maximum.  Every tent computes the same
+ * values under any choice, so tuning changes the time only.  (The paper fixes none of
+ * these: they are choices of this implementation.) */
+enum {
+  MTP_TILES_DEFAULT = 0,        /* round robin; fixed balanced table for full 3D P4 patches */
+  MTP_TILES_ROUND_ROBIN = 1,    /* round robin over the tiles numbered row block first */
+  MTP_TILES_BLOCKED = 2,        /* each wave a run of consecutive tiles */
+  MTP_TILES_COLUMN_MAJOR = 3    /* round robin over the tiles numbered column block first */
+};
+typedef struct {
+  int32_t schedule;     /* MTP_SCHEDULE_* */
+  int32_t tile_order;   /* MTP_TILES_* */
+  double grid_frac;     /* persistent workgroups / resident maximum, in (0, 1] */
+} mtp_tuning;
+typedef struct {
+  mtp_tuning best;           /* the choice applied */
+  double ms_best;            /* its time per slab */
+  double ms_default;         /* time per slab of {LAYERS, DEFAULT, 1} */
+  int32_t candidates;        /* choices timed */
+} mtp_tune_result;
+
+/* Apply a choice to a solver or batch (drops the captured slab graph).  Errors:
+ * MTP_ERR_ARG (unknown value, grid_frac outside (0, 1]), MTP_ERR_STATE (half-done slab),
+ * MTP_ERR_UNSUPPORTED (persistent schedule not available, or a non-default choice on the
+ * vector-ALU kernel). */
+mtp_status mtp_solver_set_tuning(mtp_solver solver, const mtp_tuning* choice);
+mtp_status mtp_solver_get_tuning(mtp_solver solver, mtp_tuning* choice, int32_t* from_table);
+mtp_status mtp_batch_set_tuning(mtp_batch batch, const mtp_tuning* choice);
+mtp_status mtp_batch_get_tuning(mtp_batch batch, mtp_tuning* choice, int32_t* from_table);
+
+/* Time the candidate choices on the solver's (batch's) own slabs and apply the fastest:
+ * the tile assignments on the layer schedule, then the persistent schedule with the best
+ * of them, then (if that wins) smaller persistent grids.  Each candidate runs one untimed
+ * slab and slabs_per_trial (>= 1) timed ones (HIP events on the solver's stream), starting
+ * from the state at the call; the state is restored afterwards, so the solve continues as
+ * if the call had not happened.  The first slab of every candidate is checked to give the
+ * same state bit for bit as the default's (MTP_ERR_DEVICE otherwise).  A choice replaces
+ * the default only if it is at least 2 % faster.  The result is also recorded in the
+ * process-wide tuning table under the configuration's key (device, dimension, system,
+ * degree(s), kernel, method, patch-size class and tents-per-slab class), from which later
+ * mtp_solver_create / mtp_batch_create calls of the same key take their initial choice.
+ * Allocates a temporary device copy of the state (hipMalloc; not for callers that cannot
+ * allocate).  Synchronous.  Errors: MTP_ERR_ARG, MTP_ERR_STATE (half-done slab, or data
+ * faces without boundary data), MTP_ERR_NOMEM, MTP_ERR_DEVICE. */
+mtp_status mtp_solver_tune(mtp_solver solver, int32_t slabs_per_trial, mtp_tune_result* out);
+mtp_status mtp_batch_tune(mtp_batch batch, int32_t slabs_per_trial, mtp_tune_result* out);
+
+/* The process-wide tuning table as a JSON file (host): mtp_tune_save writes every entry,
+ * mtp_tune_load merges a file's entries into the table (later entries replace earlier ones
+ * of the same key), mtp_tune_clear empties it, mtp_tune_size counts its entries.
+ * Thread-safe.  Errors: MTP_ERR_ARG (unreadable or malformed file, write failure). */
+mtp_status mtp_tune_save(const char* path);
+mtp_status mtp_tune_load(const char* path);
+mtp_status mtp_tune_clear(void);
+mtp_status mtp_tune_size(int32_t* n_entries);
+
 const char* mtp_last_error(void);
 
 #ifdef __cplusplus

@@ -179,6 +179,11 @@ struct mtp_solver_s {
   int schedule = MTP_SCHEDULE_LAYERS;
   int method = MTP_METHOD_SAT;
   int device = 0;            // HIP device current at creation (the workspace's)
+  // tuned launch choices (results do not depend on them): persistent grid as a fraction of
+  // the resident maximum dag_grid_max, tile assignment in kp.tile_order, schedule above
+  int dag_grid_max = 0;
+  double grid_frac = 1.0;
+  bool tuned_from_table = false;
   // one slab (slab begin, every layer or the persistent DAG launch, slab end) captured once
   // and replayed per slab
   bool use_graph = true;
@@ -193,6 +198,7 @@ struct mtp_batch_s {
   // range [s0, s1) served by the single-degree kernels.
   struct Group {
     int p = 0, max_patch = 0, s0 = 0, s1 = 0;
+    int grid_max = 0;             // resident maximum of the group's persistent kernel
     mtp::BatchDag bd{};           // persistent schedule over the group's tent DAGs
   };
   struct Launch {                 // one layer of one degree group
@@ -210,6 +216,9 @@ struct mtp_batch_s {
   mtp::BatchSeg* d_segs = nullptr;
   std::vector<mtp::KernelParams> h_kps;
   int schedule = MTP_SCHEDULE_LAYERS;
+  int tile_order = 0;             // tuned tile assignment of every solver's tents in the batch
+  double grid_frac = 1.0;         // tuned persistent grid, fraction of each group's maximum
+  bool tuned_from_table = false;
   bool dag_ok = true;             // every group's persistent kernel can be resident
   bool use_graph = true;
   hipStream_t cap = nullptr;
@@ -380,6 +389,44 @@ mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, 
   MTP_CATCH
 }
 
+// ------------------------------------------------------------------ tuning keys and choices
+// "<arch>x<compute units>" of a device, e.g. gfx950x256
+static std::string device_tag(int dev) {
+  hipDeviceProp_t pr;
+  check_hip(hipGetDeviceProperties(&pr, dev), "device properties");
+  std::string arch = pr.gcnArchName;
+  const size_t c = arch.find(':');
+  if (c != std::string::npos) arch.resize(c);
+  return arch + "x" + std::to_string(pr.multiProcessorCount);
+}
+static int patch_class(int max_patch) { return max_patch <= 8 ? 8 : max_patch <= 24 ? 24 : 48; }
+static int log2_class(int64_t n) {
+  int c = 0;
+  while (c < 62 && ((int64_t)1 << (c + 1)) <= n) ++c;
+  return c;
+}
+static std::string solver_key(mtp_solver s) {
+  return "solver|" + device_tag(s->device) + "|d" + std::to_string(s->mesh.d) + "|sys" +
+         std::to_string(s->mesh.system) + "|p" + std::to_string(s->p) + "|k" + std::to_string(s->kernel) + "|m" +
+         std::to_string(s->method) + "|nt" + std::to_string(patch_class(s->mesh.max_patch)) + "|t" +
+         std::to_string(log2_class((int64_t)s->tents.vertex.size()));
+}
+static void drop_graph(mtp_solver s);
+static void validate_choice(int schedule, int tile_order, double grid_frac) {
+  require(schedule == MTP_SCHEDULE_LAYERS || schedule == MTP_SCHEDULE_DAG, MTP_ERR_ARG, "unknown schedule");
+  require(tile_order >= MTP_TILES_DEFAULT && tile_order <= MTP_TILES_COLUMN_MAJOR, MTP_ERR_ARG,
+          "unknown tile order");
+  require(grid_frac > 0.0 && grid_frac <= 1.0, MTP_ERR_ARG, "grid_frac must lie in (0, 1]");
+}
+// the solver's stream must be idle (or the solver new); drops the captured slab graph
+static void solver_apply(mtp_solver s, int schedule, int tile_order, double grid_frac) {
+  drop_graph(s);
+  s->schedule = schedule;
+  s->kp.tile_order = tile_order;
+  s->grid_frac = grid_frac;
+  s->kp.dag_grid = s->dag_grid_max > 0 ? std::max(1, (int)std::lround(grid_frac * s->dag_grid_max)) : 0;
+}
+
 mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q, int32_t m, int32_t precision,
                              double alpha, void* d_workspace, size_t bytes, void* hip_stream, mtp_solver* out) {
   MTP_TRY
@@ -492,6 +539,13 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     check_hip(prepare_tent_kernel(kp, s->kernel), "tent kernel attributes");
     check_hip(launch_slab_reset(kp, 0.0, s->tents.t_end, s->stream), "slab state");
     check_hip(hipStreamSynchronize(s->stream), "upload sync");
+    s->dag_grid_max = kp.dag_grid;
+    TuneEntry te;
+    if (s->kernel != 0 && tune_find(solver_key(s), &te)) {
+      if (te.schedule == MTP_SCHEDULE_DAG && s->dag_grid_max <= 0) te.schedule = MTP_SCHEDULE_LAYERS;
+      solver_apply(s, te.schedule, te.tile_order, te.grid_frac);
+      s->tuned_from_table = true;
+    }
   } catch (...) {
     delete s;
     throw;
@@ -609,6 +663,18 @@ static void build_graph(mtp_solver s) {
   check_hip(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0), "graph instantiate");
 }
 
+// n whole slabs from a flat front: replays of the captured slab graph, or eager launches
+static void solver_slabs(mtp_solver s, int64_t n) {
+  if (n > 0 && s->use_graph && !s->gexec) build_graph(s);
+  for (int64_t j = 0; j < n; ++j) {
+    if (s->use_graph)
+      check_hip(hipGraphLaunch(s->gexec, s->stream), "graph launch");
+    else
+      run_slab(s, s->stream);
+    s->slab++;
+  }
+}
+
 mtp_status mtp_layer_advance(mtp_solver s, int64_t layer) {
   MTP_TRY
   require(s, MTP_ERR_ARG, "null solver");
@@ -637,14 +703,7 @@ mtp_status mtp_advance_to(mtp_solver s, double T) {
   const int64_t nslab = (int64_t)std::llround(k);
   require(std::fabs(k - (double)nslab) < 1e-9 && nslab >= 0, MTP_ERR_STATE,
           "T must be the front time plus a whole number of slabs");
-  if (nslab > 0 && s->use_graph && !s->gexec) build_graph(s);
-  for (int64_t j = 0; j < nslab; ++j) {
-    if (s->use_graph)
-      check_hip(hipGraphLaunch(s->gexec, s->stream), "graph launch");
-    else
-      run_slab(s, s->stream);
-    s->slab++;
-  }
+  solver_slabs(s, nslab);
   MTP_CATCH
 }
 
@@ -743,6 +802,29 @@ mtp_status mtp_batch_workspace_size(const mtp_solver* solvers, int32_t n, size_t
   MTP_CATCH
 }
 
+static std::string batch_key(mtp_batch b) {
+  std::string degs;
+  int mp = 0;
+  int64_t tents = 0;
+  for (const auto& g : b->groups) {
+    degs += std::to_string(g.p);
+    mp = std::max(mp, g.max_patch);
+  }
+  for (mtp_solver s : b->solvers) tents += (int64_t)s->tents.vertex.size();
+  return "batch|" + device_tag(b->solvers[0]->device) + "|d" + std::to_string(b->d) + "|sys0|p" + degs + "|k" +
+         std::to_string(b->kernel) + "|nt" + std::to_string(patch_class(mp)) + "|t" + std::to_string(log2_class(tents)) +
+         "|n" + std::to_string(log2_class((int64_t)b->solvers.size()));
+}
+static void drop_batch_graph(mtp_batch b);
+// the batch's stream must be idle (or the batch new); drops the captured slab graph
+static void batch_apply(mtp_batch b, int schedule, int tile_order, double grid_frac) {
+  drop_batch_graph(b);
+  b->schedule = schedule;
+  b->tile_order = tile_order;
+  b->grid_frac = grid_frac;
+  for (auto& g : b->groups) g.bd.grid = g.grid_max > 0 ? std::max(1, (int)std::lround(grid_frac * g.grid_max)) : 0;
+}
+
 mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_workspace, size_t bytes, void* hip_stream,
                             mtp_batch* out) {
   MTP_TRY
@@ -800,8 +882,9 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
         g.bd.nsolv = g.s1 - g.s0;
         g.bd.n = off[base + g.s1 - g.s0];
         g.bd.wait_ticks = ticks;
-        g.bd.grid = tent_batch_dag_grid(b->d, g.p, g.max_patch, b->kernel == 2);
-        if (g.bd.grid <= 0) b->dag_ok = false;
+        g.grid_max = tent_batch_dag_grid(b->d, g.p, g.max_patch, b->kernel == 2);
+        g.bd.grid = g.grid_max;
+        if (g.grid_max <= 0) b->dag_ok = false;
       }
       check_hip(hipMemcpyAsync(b->ws + lo.off, off.data(), off.size() * 4, hipMemcpyHostToDevice, b->stream),
                 "upload");
@@ -841,6 +924,12 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
       check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, nullptr), "batch kernel attributes");
     }
     check_hip(hipStreamSynchronize(b->stream), "sync");
+    TuneEntry te;
+    if (tune_find(batch_key(b), &te)) {
+      if (te.schedule == MTP_SCHEDULE_DAG && !b->dag_ok) te.schedule = MTP_SCHEDULE_LAYERS;
+      batch_apply(b, te.schedule, te.tile_order, te.grid_frac);
+      b->tuned_from_table = true;
+    }
   } catch (...) {
     delete b;
     throw;
@@ -888,6 +977,7 @@ mtp_status mtp_batch_advance(mtp_batch b, int64_t n_slabs) {
     require(s->layers_done == 0, MTP_ERR_STATE, "a solver of the batch is in the middle of a slab");
     require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
     b->h_kps[j] = s->kp;
+    b->h_kps[j].tile_order = b->tile_order;
     // work the solvers enqueued on their own streams comes first
     if (s->stream != b->stream) check_hip(hipStreamSynchronize(s->stream), "sync solver stream");
   }
@@ -964,7 +1054,7 @@ mtp_status mtp_solver_set_schedule(mtp_solver s, int32_t schedule) {
   require(schedule == MTP_SCHEDULE_LAYERS || schedule == MTP_SCHEDULE_DAG, MTP_ERR_ARG, "unknown schedule");
   require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
   if (schedule == MTP_SCHEDULE_DAG)
-    require(s->kernel != 0 && s->kp.dag_grid > 0, MTP_ERR_UNSUPPORTED,
+    require(s->kernel != 0 && s->dag_grid_max > 0, MTP_ERR_UNSUPPORTED,
             "the persistent schedule needs the matrix-core kernel resident on the device");
   if (schedule != s->schedule) {
     check_hip(hipStreamSynchronize(s->stream), "sync");
@@ -1178,6 +1268,357 @@ mtp_status mtp_slab_flops(mtp_solver s, double* flops) {
   for (int32_t v : s->tents.vertex) elem_tents += (double)(M.v2e_ptr[v + 1] - M.v2e_ptr[v]);
   const int stages = s->method == MTP_METHOD_RK4 ? 4 : s->q;
   *flops = elem_tents * s->m * stages * (vol + lift + flx + adir + kin + tay);
+  MTP_CATCH
+}
+
+// ------------------------------------------------------------------ tuning
+mtp_status mtp_solver_set_tuning(mtp_solver s, const mtp_tuning* c) {
+  MTP_TRY
+  require(s && c, MTP_ERR_ARG, "null pointer");
+  validate_choice(c->schedule, c->tile_order, c->grid_frac);
+  require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  if (c->schedule == MTP_SCHEDULE_DAG)
+    require(s->kernel != 0 && s->dag_grid_max > 0, MTP_ERR_UNSUPPORTED,
+            "the persistent schedule needs the matrix-core kernel resident on the device");
+  require(s->kernel != 0 || (c->tile_order == MTP_TILES_DEFAULT && c->grid_frac == 1.0), MTP_ERR_UNSUPPORTED,
+          "the vector-ALU kernel has no tiles and no persistent grid");
+  check_hip(hipStreamSynchronize(s->stream), "sync");
+  solver_apply(s, c->schedule, c->tile_order, c->grid_frac);
+  s->tuned_from_table = false;
+  MTP_CATCH
+}
+
+mtp_status mtp_solver_get_tuning(mtp_solver s, mtp_tuning* c, int32_t* from_table) {
+  MTP_TRY
+  require(s && c, MTP_ERR_ARG, "null pointer");
+  c->schedule = s->schedule;
+  c->tile_order = s->kp.tile_order;
+  c->grid_frac = s->grid_frac;
+  if (from_table) *from_table = s->tuned_from_table ? 1 : 0;
+  MTP_CATCH
+}
+
+mtp_status mtp_batch_set_tuning(mtp_batch b, const mtp_tuning* c) {
+  MTP_TRY
+  require(b && c, MTP_ERR_ARG, "null pointer");
+  validate_choice(c->schedule, c->tile_order, c->grid_frac);
+  if (c->schedule == MTP_SCHEDULE_DAG)
+    require(b->dag_ok, MTP_ERR_UNSUPPORTED, "the persistent batched kernel cannot be resident");
+  check_hip(hipStreamSynchronize(b->stream), "sync");
+  batch_apply(b, c->schedule, c->tile_order, c->grid_frac);
+  b->tuned_from_table = false;
+  MTP_CATCH
+}
+
+mtp_status mtp_batch_get_tuning(mtp_batch b, mtp_tuning* c, int32_t* from_table) {
+  MTP_TRY
+  require(b && c, MTP_ERR_ARG, "null pointer");
+  c->schedule = b->schedule;
+  c->tile_order = b->tile_order;
+  c->grid_frac = b->grid_frac;
+  if (from_table) *from_table = b->tuned_from_table ? 1 : 0;
+  MTP_CATCH
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device copy of the mutable state of a set of solvers (W, front, slab state, error flags)
+// and their host slab counters, for running trial slabs and putting everything back.
+class StateSnapshot {
+ public:
+  StateSnapshot(const std::vector<mtp_solver>& ss, hipStream_t st) : ss_(ss), st_(st) {
+    size_t tot = 0;
+    for (mtp_solver s : ss_) {
+      Part p;
+      p.nw = (size_t)s->mesh.ne * s->nc * s->ref.np;
+      p.nv = (size_t)s->mesh.nv;
+      p.off = tot;
+      p.slab = s->slab;
+      p.t_base = s->t_base;
+      tot += (p.nw + p.nv + 4) * 8 + 16;
+      parts_.push_back(p);
+    }
+    if (hipMalloc(&buf_, std::max<size_t>(tot, 8)) != hipSuccess) {
+      (void)hipGetLastError();
+      buf_ = nullptr;
+      throw Error(MTP_ERR_NOMEM, "device memory for the tuning snapshot");
+    }
+    copy(true);
+  }
+  ~StateSnapshot() {
+    (void)hipStreamSynchronize(st_);
+    if (buf_) (void)hipFree(buf_);
+  }
+  void restore() {
+    copy(false);
+    for (size_t i = 0; i < ss_.size(); ++i) {
+      ss_[i]->slab = parts_[i].slab;
+      ss_[i]->t_base = parts_[i].t_base;
+      ss_[i]->layers_done = 0;
+    }
+  }
+
+ private:
+  struct Part {
+    size_t nw = 0, nv = 0, off = 0;
+    int64_t slab = 0;
+    double t_base = 0.0;
+  };
+  void copy(bool save) {
+    for (size_t i = 0; i < ss_.size(); ++i) {
+      mtp_solver s = ss_[i];
+      const Part& p = parts_[i];
+      char* b = buf_ + p.off;
+      const std::pair<char*, size_t> regs[4] = {{s->ws + s->off.W, p.nw * 8},
+                                                {s->ws + s->off.tau, p.nv * 8},
+                                                {s->ws + s->off.slab, 32},
+                                                {s->ws + s->off.err, 16}};
+      size_t o = 0;
+      for (const auto& r : regs) {
+        if (save)
+          check_hip(hipMemcpyAsync(b + o, r.first, r.second, hipMemcpyDeviceToDevice, st_), "snapshot");
+        else
+          check_hip(hipMemcpyAsync(r.first, b + o, r.second, hipMemcpyDeviceToDevice, st_), "restore");
+        o += r.second;
+      }
+    }
+    check_hip(hipStreamSynchronize(st_), "sync");
+  }
+  std::vector<mtp_solver> ss_;
+  hipStream_t st_;
+  std::vector<Part> parts_;
+  char* buf_ = nullptr;
+};
+
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EventPair() {
+    check_hip(hipEventCreate(&a), "event");
+    check_hip(hipEventCreate(&b), "event");
+  }
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+// the solvers' states (W, then the error words) in one host vector
+void read_states(const std::vector<mtp_solver>& ss, std::vector<double>& w, int32_t* err_or) {
+  size_t tot = 0;
+  for (mtp_solver s : ss) tot += (size_t)s->mesh.ne * s->nc * s->ref.np;
+  w.resize(tot);
+  size_t o = 0;
+  *err_or = 0;
+  for (mtp_solver s : ss) {
+    const size_t nw = (size_t)s->mesh.ne * s->nc * s->ref.np;
+    int32_t err[4] = {0, 0, 0, 0};
+    check_hip(hipStreamSynchronize(s->stream), "sync");
+    check_hip(hipMemcpy(w.data() + o, s->ws + s->off.W, nw * 8, hipMemcpyDeviceToHost), "copy");
+    check_hip(hipMemcpy(err, s->ws + s->off.err, 16, hipMemcpyDeviceToHost), "copy");
+    *err_or |= err[0] | err[1] | err[2] | err[3];
+    o += nw;
+  }
+}
+
+struct Choice {
+  int schedule = MTP_SCHEDULE_LAYERS, order = MTP_TILES_DEFAULT;
+  double frac = 1.0, ms = 0.0;
+};
+
+// The search shared by solvers and batches: tile orders on the layer schedule, then the
+// persistent schedule with the best order, then smaller persistent grids if it wins.
+// run(c, n) applies c and runs n slabs on the stream; trial() wraps it with the state
+// restore, the bit-for-bit check of the first slab and the event timing.
+template <class Apply, class Run>
+Choice search(const std::vector<mtp_solver>& ss, hipStream_t st, bool has_tiles, bool dag_ok, int slabs,
+              Apply apply, Run run, int* ncand, double* ms_default) {
+  StateSnapshot snap(ss, st);
+  EventPair ev;
+  std::vector<double> ref, cur;
+  auto trial = [&](Choice c) -> Choice {
+    snap.restore();
+    apply(c);
+    run(1);
+    int32_t err = 0;
+    read_states(ss, cur, &err);
+    if (err != 0) throw Error(MTP_ERR_DEVICE, "a tuning candidate set the device error flags");
+    if (ref.empty())
+      ref.swap(cur);
+    else if (std::memcmp(ref.data(), cur.data(), ref.size() * 8) != 0)
+      throw Error(MTP_ERR_DEVICE, "a tuning candidate changed the results");
+    check_hip(hipEventRecord(ev.a, st), "event");
+    run(slabs);
+    check_hip(hipEventRecord(ev.b, st), "event");
+    check_hip(hipEventSynchronize(ev.b), "event sync");
+    float ms = 0.0f;
+    check_hip(hipEventElapsedTime(&ms, ev.a, ev.b), "event time");
+    read_states(ss, cur, &err);
+    if (err != 0) throw Error(MTP_ERR_DEVICE, "a tuning candidate set the device error flags");
+    c.ms = ms / slabs;
+    ++*ncand;
+    return c;
+  };
+  Choice dflt;
+  Choice best;
+  try {
+    dflt = trial(Choice{});
+    best = dflt;
+    if (has_tiles) {
+      for (int o = MTP_TILES_ROUND_ROBIN; o <= MTP_TILES_COLUMN_MAJOR; ++o) {
+        Choice c;
+        c.order = o;
+        c = trial(c);
+        if (c.ms < best.ms) best = c;
+      }
+      if (dag_ok) {
+        Choice c;
+        c.schedule = MTP_SCHEDULE_DAG;
+        c.order = best.order;
+        c = trial(c);
+        if (c.ms < best.ms) {
+          best = c;
+          for (double f : {0.75, 0.5}) {
+            Choice g = best;
+            g.frac = f;
+            g = trial(g);
+            if (g.ms < best.ms) best = g;
+          }
+        }
+      }
+    }
+  } catch (...) {
+    snap.restore();
+    throw;
+  }
+  snap.restore();
+  if (best.ms > 0.98 * dflt.ms) best = dflt;
+  *ms_default = dflt.ms;
+  return best;
+}
+
+}  // namespace
+
+extern "C" {
+
+mtp_status mtp_solver_tune(mtp_solver s, int32_t slabs, mtp_tune_result* out) {
+  MTP_TRY
+  require(s && out, MTP_ERR_ARG, "null pointer");
+  require(slabs >= 1, MTP_ERR_ARG, "slabs_per_trial must be >= 1");
+  require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
+  check_hip(hipStreamSynchronize(s->stream), "sync");
+  int32_t err[4] = {0, 0, 0, 0};
+  check_hip(hipMemcpy(err, s->ws + s->off.err, 16, hipMemcpyDeviceToHost), "copy");
+  require((err[0] | err[1] | err[2] | err[3]) == 0, MTP_ERR_STATE,
+          "the solver has pending device errors (read them with mtp_get_fields first)");
+  const Choice orig{s->schedule, s->kp.tile_order, s->grid_frac, 0.0};
+  const bool orig_table = s->tuned_from_table;
+  int ncand = 0;
+  double ms_default = 0.0;
+  Choice best;
+  try {
+    best = search(
+        {s}, s->stream, s->kernel != 0, s->kernel != 0 && s->dag_grid_max > 0, slabs,
+        [&](const Choice& c) { solver_apply(s, c.schedule, c.order, c.frac); },
+        [&](int64_t n) { solver_slabs(s, n); }, &ncand, &ms_default);
+  } catch (...) {
+    solver_apply(s, orig.schedule, orig.order, orig.frac);
+    s->tuned_from_table = orig_table;
+    throw;
+  }
+  solver_apply(s, best.schedule, best.order, best.frac);
+  s->tuned_from_table = false;
+  TuneEntry te;
+  te.schedule = best.schedule;
+  te.tile_order = best.order;
+  te.grid_frac = best.frac;
+  te.ms_best = best.ms;
+  te.ms_default = ms_default;
+  te.candidates = ncand;
+  if (s->kernel != 0) tune_put(solver_key(s), te);
+  out->best.schedule = best.schedule;
+  out->best.tile_order = best.order;
+  out->best.grid_frac = best.frac;
+  out->ms_best = best.ms;
+  out->ms_default = ms_default;
+  out->candidates = ncand;
+  MTP_CATCH
+}
+
+mtp_status mtp_batch_tune(mtp_batch b, int32_t slabs, mtp_tune_result* out) {
+  MTP_TRY
+  require(b && out, MTP_ERR_ARG, "null pointer");
+  require(slabs >= 1, MTP_ERR_ARG, "slabs_per_trial must be >= 1");
+  for (mtp_solver s : b->solvers) {
+    require(s->layers_done == 0, MTP_ERR_STATE, "a solver of the batch is in the middle of a slab");
+    require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
+    check_hip(hipStreamSynchronize(s->stream), "sync");
+    int32_t err[4] = {0, 0, 0, 0};
+    check_hip(hipMemcpy(err, s->ws + s->off.err, 16, hipMemcpyDeviceToHost), "copy");
+    require((err[0] | err[1] | err[2] | err[3]) == 0, MTP_ERR_STATE,
+            "a solver of the batch has pending device errors (read them with mtp_get_fields first)");
+  }
+  check_hip(hipStreamSynchronize(b->stream), "sync");
+  const Choice orig{b->schedule, b->tile_order, b->grid_frac, 0.0};
+  const bool orig_table = b->tuned_from_table;
+  int ncand = 0;
+  double ms_default = 0.0;
+  Choice best;
+  try {
+    best = search(
+        b->solvers, b->stream, true, b->dag_ok, slabs,
+        [&](const Choice& c) { batch_apply(b, c.schedule, c.order, c.frac); },
+        [&](int64_t n) { check_status(mtp_batch_advance(b, n)); }, &ncand, &ms_default);
+  } catch (...) {
+    batch_apply(b, orig.schedule, orig.order, orig.frac);
+    b->tuned_from_table = orig_table;
+    throw;
+  }
+  batch_apply(b, best.schedule, best.order, best.frac);
+  b->tuned_from_table = false;
+  TuneEntry te;
+  te.schedule = best.schedule;
+  te.tile_order = best.order;
+  te.grid_frac = best.frac;
+  te.ms_best = best.ms;
+  te.ms_default = ms_default;
+  te.candidates = ncand;
+  tune_put(batch_key(b), te);
+  out->best.schedule = best.schedule;
+  out->best.tile_order = best.order;
+  out->best.grid_frac = best.frac;
+  out->ms_best = best.ms;
+  out->ms_default = ms_default;
+  out->candidates = ncand;
+  MTP_CATCH
+}
+
+mtp_status mtp_tune_save(const char* path) {
+  MTP_TRY
+  require(path != nullptr, MTP_ERR_ARG, "null path");
+  tune_save_file(path);
+  MTP_CATCH
+}
+
+mtp_status mtp_tune_load(const char* path) {
+  MTP_TRY
+  require(path != nullptr, MTP_ERR_ARG, "null path");
+  tune_load_file(path);
+  MTP_CATCH
+}
+
+mtp_status mtp_tune_clear(void) {
+  MTP_TRY
+  tune_clear_all();
+  MTP_CATCH
+}
+
+mtp_status mtp_tune_size(int32_t* n) {
+  MTP_TRY
+  require(n != nullptr, MTP_ERR_ARG, "null pointer");
+  *n = tune_count();
   MTP_CATCH
 }
 

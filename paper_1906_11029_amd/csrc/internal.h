@@ -78,4 +78,18 @@ void set_last_error(const char* msg);
 int solver_device(mtp_solver s);
 void advance_to_dag_scratch(mtp_solver s, double T, char* d_scratch, size_t cap);
 
+// tuning table (tune.cpp): launch choices by configuration key
+struct TuneEntry {
+  int schedule = 0, tile_order = 0;
+  double grid_frac = 1.0;
+  double ms_best = 0.0, ms_default = 0.0;
+  int candidates = 0;
+};
+bool tune_find(const std::string& key, TuneEntry* out);
+void tune_put(const std::string& key, const TuneEntry& e);
+void tune_clear_all();
+int tune_count();
+void tune_save_file(const char* path);   // throws Error
+void tune_load_file(const char* path);   // throws Error; merges
+
 }  // namespace mtp

@@ -65,6 +65,8 @@ struct KernelParams {
   int has_data;
   double pw_amp[6], pw_k[3], pw_omega, pw_phase;
   int max_patch;
+  // assignment of the product's tiles to waves (tuned; results do not depend on it)
+  int tile_order;
 };
 
 // One segment of a batched launch: layer slice (first, count) of solver `solver`, run by

@@ -20,6 +20,11 @@ MTP_SCHEDULE_LAYERS, MTP_SCHEDULE_DAG = 0, 1
 MTP_METHOD_SAT, MTP_METHOD_RK4 = 0, 1
 MTP_FLUX_PENALTY, MTP_FLUX_IMPEDANCE = 0, 1
 MTP_SYSTEM_MAXWELL, MTP_SYSTEM_ACOUSTIC = 0, 1
+MTP_TILES_DEFAULT, MTP_TILES_ROUND_ROBIN, MTP_TILES_BLOCKED, MTP_TILES_COLUMN_MAJOR = 0, 1, 2, 3
+
+# tuning table shipped with the package (measured on MI355X); MTP_TUNE_FILE names another
+# file to load instead, or, set to the empty string, disables loading one
+TUNE_FILE = os.path.join(_HERE, "tuning", "mi355x.json")
 
 _lib = None
 
@@ -78,6 +83,16 @@ def load():
         "mtp_batch_advance": [P, i64],
         "mtp_batch_set_graph": [P, i32],
         "mtp_batch_set_schedule": [P, i32],
+        "mtp_solver_set_tuning": [P, P],
+        "mtp_solver_get_tuning": [P, P, P],
+        "mtp_batch_set_tuning": [P, P],
+        "mtp_batch_get_tuning": [P, P, P],
+        "mtp_solver_tune": [P, i32, P],
+        "mtp_batch_tune": [P, i32, P],
+        "mtp_tune_save": [C.c_char_p],
+        "mtp_tune_load": [C.c_char_p],
+        "mtp_tune_clear": [],
+        "mtp_tune_size": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -90,6 +105,9 @@ def load():
     L.mtp_last_error.argtypes = []
     L.mtp_last_error.restype = C.c_char_p
     _lib = L
+    path = os.environ.get("MTP_TUNE_FILE", TUNE_FILE)
+    if path and os.path.exists(path):
+        _check(L.mtp_tune_load(os.fsencode(path)))
     return L
 
 
@@ -354,6 +372,80 @@ def mtp_batch_destroy(batch):
     load().mtp_batch_destroy(batch)
 
 
+class mtp_tuning(C.Structure):
+    _fields_ = [("schedule", C.c_int32), ("tile_order", C.c_int32), ("grid_frac", C.c_double)]
+
+
+class mtp_tune_result(C.Structure):
+    _fields_ = [("best", mtp_tuning), ("ms_best", C.c_double), ("ms_default", C.c_double),
+                ("candidates", C.c_int32)]
+
+
+def _tuning_dict(t):
+    return {"schedule": t.schedule, "tile_order": t.tile_order, "grid_frac": t.grid_frac}
+
+
+def _set_tuning(fn, h, schedule, tile_order, grid_frac):
+    _check(fn(h, C.byref(mtp_tuning(int(schedule), int(tile_order), float(grid_frac)))))
+
+
+def _get_tuning(fn, h):
+    t, f = mtp_tuning(), C.c_int32()
+    _check(fn(h, C.byref(t), C.byref(f)))
+    out = _tuning_dict(t)
+    out["from_table"] = bool(f.value)
+    return out
+
+
+def _tune(fn, h, slabs_per_trial):
+    r = mtp_tune_result()
+    _check(fn(h, int(slabs_per_trial), C.byref(r)))
+    return {"best": _tuning_dict(r.best), "ms_best": r.ms_best, "ms_default": r.ms_default,
+            "candidates": r.candidates}
+
+
+def mtp_solver_set_tuning(solver, schedule, tile_order=MTP_TILES_DEFAULT, grid_frac=1.0):
+    _set_tuning(load().mtp_solver_set_tuning, solver, schedule, tile_order, grid_frac)
+
+
+def mtp_solver_get_tuning(solver):
+    return _get_tuning(load().mtp_solver_get_tuning, solver)
+
+
+def mtp_batch_set_tuning(batch, schedule, tile_order=MTP_TILES_DEFAULT, grid_frac=1.0):
+    _set_tuning(load().mtp_batch_set_tuning, batch, schedule, tile_order, grid_frac)
+
+
+def mtp_batch_get_tuning(batch):
+    return _get_tuning(load().mtp_batch_get_tuning, batch)
+
+
+def mtp_solver_tune(solver, slabs_per_trial=2):
+    return _tune(load().mtp_solver_tune, solver, slabs_per_trial)
+
+
+def mtp_batch_tune(batch, slabs_per_trial=2):
+    return _tune(load().mtp_batch_tune, batch, slabs_per_trial)
+
+
+def mtp_tune_save(path):
+    _check(load().mtp_tune_save(os.fsencode(path)))
+
+
+def mtp_tune_load(path):
+    _check(load().mtp_tune_load(os.fsencode(path)))
+
+
+def mtp_tune_clear():
+    _check(load().mtp_tune_clear())
+
+
+def mtp_tune_size():
+    n = C.c_int32()
+    _check(load().mtp_tune_size(C.byref(n)))
+    return n.value
+
+
 # ----------------------------------------------------------------- thin object wrappers
 def mtp_mesh_set_system(mesh, system):
     _check(load().mtp_mesh_set_system(mesh, int(system)))
@@ -471,6 +563,15 @@ class Solver:
     def checkpoint_read(self, path):
         mtp_checkpoint_read(self.h, path)
 
+    def set_tuning(self, schedule, tile_order=MTP_TILES_DEFAULT, grid_frac=1.0):
+        mtp_solver_set_tuning(self.h, schedule, tile_order, grid_frac)
+
+    def tuning(self):
+        return mtp_solver_get_tuning(self.h)
+
+    def tune(self, slabs_per_trial=2):
+        return mtp_solver_tune(self.h, slabs_per_trial)
+
     def __del__(self, _free=_release):   # bound at definition: safe at interpreter shutdown
         _free("mtp_solver_destroy", getattr(self, "h", None))
         self.h = None
@@ -495,6 +596,15 @@ class Batch:
 
     def set_schedule(self, schedule):
         mtp_batch_set_schedule(self.h, schedule)
+
+    def set_tuning(self, schedule, tile_order=MTP_TILES_DEFAULT, grid_frac=1.0):
+        mtp_batch_set_tuning(self.h, schedule, tile_order, grid_frac)
+
+    def tuning(self):
+        return mtp_batch_get_tuning(self.h)
+
+    def tune(self, slabs_per_trial=2):
+        return mtp_batch_tune(self.h, slabs_per_trial)
 
     def __del__(self, _free=_release):   # bound at definition: safe at interpreter shutdown
         _free("mtp_batch_destroy", getattr(self, "h", None))

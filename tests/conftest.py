@@ -9,3 +9,7 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long CPU test (oracle on larger meshes)")
+
+# Tests run with the default launch choices unless they load a tuning table themselves;
+# an explicitly set MTP_TUNE_FILE is kept.
+os.environ.setdefault("MTP_TUNE_FILE", "")
