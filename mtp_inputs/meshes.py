@@ -166,3 +166,58 @@ def fan_disk(nfan, radius=1.0, rings=2):
                 cells.append((vid(r, i), vid(r + 1, i), vid(r + 1, i + 1)))
     cells = np.asarray(cells, dtype=np.int32)
     return {"coords": coords, "cells": _orient(coords, cells)}
+
+
+def disk_tri(n, radius=1.0):
+    """Disk of the given radius: the centre and n rings, ring k (k = 1..n) holding 6k vertices
+    at radius k/n * radius (angles 2 pi j / (6k)); consecutive rings are joined by walking
+    both by angle and closing, at every step, the triangle whose new vertex comes first.
+    6 n^2 triangles, 3 n (n + 1) + 1 vertices; boundary = ring n."""
+    coords = [(0.0, 0.0)]
+    start = [0]
+    for k in range(1, n + 1):
+        start.append(len(coords))
+        for j in range(6 * k):
+            a = 2.0 * np.pi * j / (6 * k)
+            coords.append((radius * k / n * np.cos(a), radius * k / n * np.sin(a)))
+    coords = np.asarray(coords)
+    cells = []
+    # centre fan
+    for j in range(6):
+        cells.append((0, start[1] + j, start[1] + (j + 1) % 6))
+    for k in range(1, n):
+        ni, no = 6 * k, 6 * (k + 1)
+        i = o = 0
+        while i < ni or o < no:
+            ai = (i + 1) / ni   # angle (in turns) of the next inner vertex
+            ao = (o + 1) / no
+            vi, vo = start[k] + i % ni, start[k + 1] + o % no
+            if o < no and (i >= ni or ao <= ai):
+                cells.append((vi, vo, start[k + 1] + (o + 1) % no))
+                o += 1
+            else:
+                cells.append((vi, vo, start[k] + (i + 1) % ni))
+                i += 1
+    cells = np.asarray(cells, dtype=np.int32)
+    return {"coords": coords, "cells": _orient(coords, cells)}
+
+
+def p2_geometry(mesh, on_circle=None):
+    """Quadratic (P2) geometry nodes per triangle, shape (ne, 6, 2): the three vertices in
+    cell order, then the midpoints of edges (0,1), (1,2), (0,2).  With on_circle = R, the
+    midpoint of every edge whose two vertices lie on the circle |x| = R is moved onto the
+    circle (at the mean angle of its ends), which curves the elements along the boundary;
+    every other midpoint stays straight.  Without it, every element is affine."""
+    X = mesh["coords"][mesh["cells"]]
+    mids = [(0, 1), (1, 2), (0, 2)]
+    geo = np.zeros((len(X), 6, 2))
+    geo[:, :3] = X
+    for s, (a, b) in enumerate(mids):
+        m = 0.5 * (X[:, a] + X[:, b])
+        if on_circle is not None:
+            ra = np.linalg.norm(X[:, a], axis=1)
+            rb = np.linalg.norm(X[:, b], axis=1)
+            bnd = (np.abs(ra - on_circle) < 1e-12 * on_circle) & (np.abs(rb - on_circle) < 1e-12 * on_circle)
+            m[bnd] = on_circle * m[bnd] / np.linalg.norm(m[bnd], axis=1)[:, None]
+        geo[:, 3 + s] = m
+    return geo
