@@ -272,10 +272,54 @@ __device__ __forceinline__ void stage_operator(const KernelParams& kp0, const Te
 // sOpF (mixed kernel): an FP32 copy of the volume part of the operator (KV rows of OPS);
 // the FP32 products read their volume operands from it (half the LDS bytes, no
 // conversion), everything else reads the FP64 operator sOp.
+// The product's tiles (row block mr, column block nt) = mr * ntiles + nt run by this wave,
+// slot by slot (MTF * ntiles, or more, for an empty slot), by the tuned assignment `order`
+// (wave-uniform, worked out once per tent; results do not depend on it):
+//   0: round robin, except for the full P4 patch (9 column blocks, 9 tiles with the 4-row
+//      part and 9 without), where a fixed assignment evens the matrix-core time of the
+//      four SIMDs (waves w and w + 4 share one): 5.25 / 5.25 / 5 / 4.75 tile units
+//      instead of 5.75 / 5.5 / 4.5 / 4.5 (5-bit entries, 31 = none)
+//   1: round robin over the tiles numbered row block first
+//   2: blocked, each wave a run of consecutive tiles of that numbering
+//   3: round robin over the tiles numbered column block first
+template <int D, int P, int NTMAX, int SYS>
+__device__ __forceinline__ void tile_assign(int order, int wave, int ntiles,
+                                            int (&tiles)[MShape<D, P, NTMAX, SYS>::TILES_PER_WAVE]) {
+  using SH = MShape<D, P, NTMAX, SYS>;
+  constexpr int MTF = SH::MTF, WAVES = SH::WAVES, TPW = SH::TILES_PER_WAVE;
+  constexpr bool MINI = SH::MINI;
+  const int ntot = MTF * ntiles;
+#pragma unroll
+  for (int ts = 0; ts < TPW; ++ts) {
+    int t = wave + WAVES * ts;
+    if (order == 2) {
+      const int per = (ntot + WAVES - 1) / WAVES;
+      t = ts < per ? wave * per + ts : ntot;
+    } else if (order == 3) {
+      const int j = wave + WAVES * ts;
+      t = j < ntot ? (j % MTF) * ntiles + j / MTF : ntot;
+    } else if (order == 0) {
+      if constexpr (MINI && MTF == 2 && WAVES == 8 && TPW == 3) {
+        if (ntiles == 9) {
+          constexpr uint64_t T0 = 0ull | 1ull << 5 | 2ull << 10 | 4ull << 15 | 13ull << 20 | 15ull << 25 |
+                                  6ull << 30 | 8ull << 35;
+          constexpr uint64_t T1 = 9ull | 11ull << 5 | 3ull << 10 | 5ull << 15 | 14ull << 20 | 16ull << 25 |
+                                  7ull << 30 | 17ull << 35;
+          constexpr uint64_t T2 = 10ull | 12ull << 5 | 31ull << 10 | 31ull << 15 | 31ull << 20 | 31ull << 25 |
+                                  31ull << 30 | 31ull << 35;
+          const uint64_t tab = ts == 0 ? T0 : ts == 1 ? T1 : T2;
+          t = (int)((tab >> (5 * wave)) & 31);
+        }
+      }
+    }
+    tiles[ts] = __builtin_amdgcn_readfirstlane(t);
+  }
+}
+
 template <typename TM, int D, int P, int NTMAX, int SYS>
 __device__ __forceinline__ void tile_product(const double* sOp, const float* sOpF, const double* sU, double* sFR,
                                              const double* sGL, int wave, int lane, int ncols, int ntiles,
-                                             int order) {
+                                             const int (&tiles)[MShape<D, P, NTMAX, SYS>::TILES_PER_WAVE]) {
   using SH = MShape<D, P, NTMAX, SYS>;
   constexpr int NT = Phys<D, SYS>::NTERM;
   using MM = Mfma<TM>;
@@ -294,39 +338,7 @@ __device__ __forceinline__ void tile_product(const double* sOp, const float* sOp
     accs[ts] = typename MM::acc_t{0, 0, 0, 0};
     accm[ts] = typename MM::mini_t{};
   }
-  // tile (row block mr, column block nt) = mr * ntiles + nt of slot ts of this wave, by the
-  // tuned assignment `order` (wave-uniform; results do not depend on it):
-  //   0: round robin, except for the full P4 patch (9 column blocks, 9 tiles with the 4-row
-  //      part and 9 without), where a fixed assignment evens the matrix-core time of the
-  //      four SIMDs (waves w and w + 4 share one): 5.25 / 5.25 / 5 / 4.75 tile units
-  //      instead of 5.75 / 5.5 / 4.5 / 4.5 (5-bit entries, 31 = none)
-  //   1: round robin over the tiles numbered row block first
-  //   2: blocked, each wave a run of consecutive tiles of that numbering
-  //   3: round robin over the tiles numbered column block first
-  auto tile_of = [&](int ts) -> int {
-    const int ntot = MTF * ntiles;
-    if (order == 2) {
-      const int per = (ntot + WAVES - 1) / WAVES;
-      return ts < per ? wave * per + ts : ntot;
-    }
-    if (order == 3) {
-      const int j = wave + WAVES * ts;
-      return j < ntot ? (j % MTF) * ntiles + j / MTF : ntot;
-    }
-    if constexpr (MINI && MTF == 2 && WAVES == 8 && TPW == 3) {
-      if (order == 0 && ntiles == 9) {
-        constexpr uint64_t T0 = 0ull | 1ull << 5 | 2ull << 10 | 4ull << 15 | 13ull << 20 | 15ull << 25 |
-                                6ull << 30 | 8ull << 35;
-        constexpr uint64_t T1 = 9ull | 11ull << 5 | 3ull << 10 | 5ull << 15 | 14ull << 20 | 16ull << 25 |
-                                7ull << 30 | 17ull << 35;
-        constexpr uint64_t T2 = 10ull | 12ull << 5 | 31ull << 10 | 31ull << 15 | 31ull << 20 | 31ull << 25 |
-                                31ull << 30 | 31ull << 35;
-        const uint64_t tab = ts == 0 ? T0 : ts == 1 ? T1 : T2;
-        return (int)((tab >> (5 * wave)) & 31);
-      }
-    }
-    return wave + WAVES * ts;
-  };
+  auto tile_of = [&](int ts) -> int { return tiles[ts]; };
   // K groups [G0, G1) of tile ts: the volume part (U only) or the lift part (F)
   auto part = [&](int ts, auto lift) {
     constexpr bool LIFT = decltype(lift)::value;
@@ -651,6 +663,8 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
   const double H = t_top - kp.tau[V];
   const int ncols = nT * NC;
   const int ntiles = (ncols + 15) / 16;
+  int tiles[SH::TILES_PER_WAVE];
+  tile_assign<D, P, NTMAX, SYS>(kp.tile_order, wave, ntiles, tiles);
   const int32_t f0 = kp.pface_ptr[V];
   const int nFace = kp.pface_ptr[V + 1] - f0;
 
@@ -808,7 +822,7 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
       for (int s = 0; s < 4; ++s) {
         const double th = (i + (s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5))) * invm;
         face_fluxes(th, 1);
-        tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles, kp.tile_order);
+        tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles, tiles);
         const double thn = (s == 3) ? (i + 1) * invm : (i + (s == 2 ? 1.0 : 0.5)) * invm;
         const double a = (s == 2) ? invm : 0.5 * invm;   // weight of k_s in the next stage input
         const double wk = (s == 0 || s == 3) ? 1.0 : 2.0;
@@ -853,9 +867,9 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
 
       // ---- R = [S | -L] [A(grad lambda) U ; F] on the matrix cores
       if (MIXED && n >= 2)
-        tile_product<float, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles, kp.tile_order);
+        tile_product<float, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles, tiles);
       else
-        tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles, kp.tile_order);
+        tile_product<double, D, P, NTMAX, SYS>(sOp, sOpF, sU, sFR, sGL, wave, lane, ncols, ntiles, tiles);
 
       // ---- Taylor accumulation (FP64) and the next U for the owned (element, node) pairs
 #pragma unroll
