@@ -468,7 +468,7 @@ def main():
             Wc = workload(W["cert"])
             nsl = args.steps + args.warmup
             for prec in ("fp64", "mixed"):
-                rc = run(Wc, prec, nsl, 0, schedule="auto")
+                rc = run(Wc, prec, nsl, 0, schedule="auto", tune=args.tune)
                 cert[prec + "_rel_l2_error_vs_exact"] = rc["err"]
                 del rc
             cert["slabs"] = nsl

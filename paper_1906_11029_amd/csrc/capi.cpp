@@ -405,11 +405,14 @@ static int log2_class(int64_t n) {
   while (c < 62 && ((int64_t)1 << (c + 1)) <= n) ++c;
   return c;
 }
+// tents per slab in factors of 4 (a slab's tent count moves with the materials and the
+// mesh grading; the launch choice does not change within such a band)
+static int tents_class(int64_t n) { return log2_class(n) / 2; }
 static std::string solver_key(mtp_solver s) {
   return "solver|" + device_tag(s->device) + "|d" + std::to_string(s->mesh.d) + "|sys" +
          std::to_string(s->mesh.system) + "|p" + std::to_string(s->p) + "|k" + std::to_string(s->kernel) + "|m" +
          std::to_string(s->method) + "|nt" + std::to_string(patch_class(s->mesh.max_patch)) + "|t" +
-         std::to_string(log2_class((int64_t)s->tents.vertex.size()));
+         std::to_string(tents_class((int64_t)s->tents.vertex.size()));
 }
 static void drop_graph(mtp_solver s);
 static void validate_choice(int schedule, int tile_order, double grid_frac) {
@@ -812,7 +815,7 @@ static std::string batch_key(mtp_batch b) {
   }
   for (mtp_solver s : b->solvers) tents += (int64_t)s->tents.vertex.size();
   return "batch|" + device_tag(b->solvers[0]->device) + "|d" + std::to_string(b->d) + "|sys0|p" + degs + "|k" +
-         std::to_string(b->kernel) + "|nt" + std::to_string(patch_class(mp)) + "|t" + std::to_string(log2_class(tents)) +
+         std::to_string(b->kernel) + "|nt" + std::to_string(patch_class(mp)) + "|t" + std::to_string(tents_class(tents)) +
          "|n" + std::to_string(log2_class((int64_t)b->solvers.size()));
 }
 static void drop_batch_graph(mtp_batch b);
