@@ -345,6 +345,9 @@ __device__ __forceinline__ void ghost_state(const KernelParams& kp, int kind, co
                                             int el, int kloc, int nin, double H, double th, int n) {
   constexpr int NC = Phys<D, SYS>::NC, NV = D + 1, NE = Phys<D, SYS>::NE;
   if (kind == 2 && kp.has_data) {
+    // every multiply-add written as an explicit fma and no other contraction, so that the
+    // data do not depend on how a kernel instantiation schedules this code
+#pragma clang fp contract(off)
     int order[NV];
     vertex_order_dev<D>(kloc, order);
     double x[D], phib = 0.0;
@@ -355,19 +358,20 @@ __device__ __forceinline__ void ghost_state(const KernelParams& kp, int kind, co
     for (int v = 0; v < NV; ++v) {
       const int gv = kp.cells[(size_t)el * NV + order[v]];
       const double lam = (double)alpha[v] / P;
-      phib += lam * kp.tau[gv];
+      phib = fma(lam, kp.tau[gv], phib);
 #pragma unroll
-      for (int xx = 0; xx < D; ++xx) x[xx] += lam * kp.coords[(size_t)gv * D + xx];
+      for (int xx = 0; xx < D; ++xx) x[xx] = fma(lam, kp.coords[(size_t)gv * D + xx], x[xx]);
     }
-    const double delta = H * (double)alpha[0] / P;
-    const double phi = phib + th * delta;
-    double psi = kp.pw_phase - kp.pw_omega * phi;
+    const double delta = H * ((double)alpha[0] / P);
+    const double phi = fma(th, delta, phib);
+    double psi = fma(-kp.pw_omega, phi, kp.pw_phase);
 #pragma unroll
-    for (int xx = 0; xx < D; ++xx) psi += kp.pw_k[xx] * x[xx];
+    for (int xx = 0; xx < D; ++xx) psi = fma(kp.pw_k[xx], x[xx], psi);
     const int kd = n - 1;
     double scale = 1.0;
     for (int z = 0; z < kd; ++z) scale *= delta * kp.pw_omega;
-    const double val = scale * cos(psi - kd * 1.5707963267948966);  // d_t^k cos = omega^k cos(. - k pi/2)
+    // d_t^k cos = omega^k cos(. - k pi/2)
+    const double val = scale * cos(fma(-(double)kd, 1.5707963267948966, psi));
 #pragma unroll
     for (int c = 0; c < NC; ++c) up[c] = kp.pw_amp[c] * val;
   } else if (kind == 1) {

@@ -321,8 +321,11 @@ def test_batch_mixed_degrees_against_oracle(dim, precision, tol, schedule):
     """Solves of several degrees (listed out of degree order; cavities, plane-wave data
     faces, fans and a Delaunay patch) in one batch: the batch groups its solvers by degree,
     one launch per (global layer index, degree) or one persistent launch per degree; against
-    the oracle's fixtures element by element, and bitwise equal to the same solves advanced
-    one by one."""
+    the oracle's fixtures element by element, and equal to the same solves advanced one by
+    one: bitwise where the batch runs a solve with the kernel of the same patch capacity
+    (the group's largest patch falls in the same class as the solve's own), else to
+    rounding (a kernel of another capacity is another instantiation, which the compiler
+    may contract differently)."""
     from paper_1906_11029_amd import mtp
     names = MIXED_DEGREE[dim]
     print(f"[gpu parity] {dim}D mixed-degree batch precision {precision} schedule {schedule}", flush=True)
@@ -331,8 +334,15 @@ def test_batch_mixed_degrees_against_oracle(dim, precision, tol, schedule):
     B = mtp.Batch(batched)
     B.set_schedule(schedule)
     B.advance(1)
+    cap = lambda mp: 8 if mp <= 8 else 24 if mp <= 24 else 48   # noqa: E731
+    group = {}
+    for S in batched:
+        group[S.p] = max(group.get(S.p, 0), S.mesh.info["max_patch"])
     for S, (c, S1, _), nm in zip(batched, single, names):
         S1.advance_to(c["T"])
-        w = S.get_state()
+        w, w1 = S.get_state(), S1.get_state()
         assert_parity(w, fixture(nm)["w"], tol, f"batch {nm}")
-        assert np.array_equal(w, S1.get_state()), nm
+        if cap(group[S.p]) == cap(S.mesh.info["max_patch"]):
+            assert np.array_equal(w, w1), nm
+        else:
+            assert np.abs(w - w1).max() <= (1e-13 if precision == 0 else 1e-9) * np.abs(w1).max(), nm
