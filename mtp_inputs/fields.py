@@ -195,3 +195,43 @@ class AcousticPulse:
         out = np.zeros(x.shape[:-1] + (self.dim + 1,))
         out[..., 0] = np.exp(-r2 / (2 * self.s ** 2))
         return out
+
+
+class CircularCavityTE:
+    """TE mode of the circular PEC cavity of radius R (eps = mu = 1):
+    Hz = J_m(k r) cos(m theta) cos(k t) with J_m'(k R) = 0 (tangential E vanishes on the
+    wall), E = (d_y Hz, -d_x Hz) sin(k t) / k; u = (Ex, Ey, Hz).  Default: m = 1 and the
+    first root, k R = 1.8412."""
+
+    def __init__(self, m=1, root=1, radius=1.0):
+        from scipy.special import jnp_zeros
+        self.m, self.R = m, radius
+        self.k = float(jnp_zeros(m, root)[-1]) / radius
+
+    def _hz_grad(self, x):
+        from scipy.special import jv, jvp
+        x = np.asarray(x, dtype=np.float64)
+        r = np.hypot(x[..., 0], x[..., 1])
+        th = np.arctan2(x[..., 1], x[..., 0])
+        k, m = self.k, self.m
+        rs = np.maximum(r, 1e-300)
+        J, Jp = jv(m, k * r), k * jvp(m, k * r)
+        c, s = np.cos(m * th), np.sin(m * th)
+        hz = J * c
+        dr, dth = Jp * c, -m * J * s / rs            # d/dr and (1/r) d/dtheta
+        gx = dr * np.cos(th) - dth * np.sin(th)
+        gy = dr * np.sin(th) + dth * np.cos(th)
+        if m == 1:   # at the centre J_1(kr)/r -> k/2: grad Hz = (k/2, 0)
+            z = r < 1e-12
+            gx = np.where(z, k / 2.0, gx)
+            gy = np.where(z, 0.0, gy)
+        return hz, gx, gy
+
+    def u(self, x, t):
+        hz, gx, gy = self._hz_grad(x)
+        k = self.k
+        out = np.empty(np.shape(x)[:-1] + (3,))
+        out[..., 0] = gy * np.sin(k * t) / k
+        out[..., 1] = -gx * np.sin(k * t) / k
+        out[..., 2] = hz * np.cos(k * t)
+        return out

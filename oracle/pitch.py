@@ -34,11 +34,16 @@ QUANTUM = 2.0 ** -24
 SAFETY = 1e-3
 
 
-def edge_steps(mesh, sigma):
-    """k_vw per vertex: list of (neighbour ids, k values) aligned with mesh.adj."""
-    norms = np.linalg.norm(mesh.grad_lam, axis=2)              # (ne, d+1)
-    sums = norms.sum(axis=1, keepdims=True) - norms             # sum over j != i
-    k_T = sigma * np.sqrt(mesh.eps * mesh.mu) / sums.min(axis=1)
+def edge_steps(mesh, sigma, k_elem=None):
+    """k_vw per vertex: list of (neighbour ids, k values) aligned with mesh.adj.  k_elem,
+    if given, replaces the affine per-element step k_T (curved elements bound the gradient
+    of their hat functions over the element, oracle/curved.py)."""
+    if k_elem is None:
+        norms = np.linalg.norm(mesh.grad_lam, axis=2)              # (ne, d+1)
+        sums = norms.sum(axis=1, keepdims=True) - norms             # sum over j != i
+        k_T = sigma * np.sqrt(mesh.eps * mesh.mu) / sums.min(axis=1)
+    else:
+        k_T = np.asarray(k_elem, dtype=np.float64)
     kv = []
     for v in range(mesh.nv):
         nb = mesh.adj[v]
@@ -53,14 +58,14 @@ def edge_steps(mesh, sigma):
     return kv
 
 
-def pitch(mesh, t_end, sigma=0.5):
+def pitch(mesh, t_end, sigma=0.5, k_elem=None):
     """Pitch tents from the flat front 0 to the flat front t_end.
 
     Returns dict with int arrays vertex, layer and float arrays t_bot, t_top, in
-    emission order."""
+    emission order.  k_elem: per-element steps replacing the affine rule's k_T."""
     nv = mesh.nv
     tau = np.zeros(nv)
-    kv = edge_steps(mesh, sigma)
+    kv = edge_steps(mesh, sigma, k_elem)
     last_layer = -np.ones(nv, dtype=np.int64)
     heap = [(0.0, v) for v in range(nv)]
     heapq.heapify(heap)
