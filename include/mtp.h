@@ -135,6 +135,29 @@ mtp_status mtp_mesh_info(mtp_mesh mesh, int32_t* dim, int64_t* nv, int64_t* ne,
                          int32_t* max_patch);
 void mtp_mesh_destroy(mtp_mesh mesh);
 
+/* Curved elements (section 4: on the few curved elements the projection that follows the
+ * pointwise closed-form inverse uses an approximation of the inverse mass matrix).  2D
+ * only.  nodes (ne*6*2): six geometry nodes per triangle, the three vertices in cell order
+ * (equal to the mesh's coordinates), then the midpoints of the edges (0,1), (1,2), (0,2);
+ * the element map is the quadratic isoparametric one, x = sum_i nodes_i N_i(xhat).  An
+ * element whose midpoint nodes are the straight midpoints stays affine; a shared edge must
+ * carry one midpoint node.  The pitcher then bounds a curved element's hat-function
+ * gradients over the element (the largest min_i sum_{j != i} |grad lambda_j| over the
+ * barycentric lattice i/12, j/12), so call this before mtp_pitch_layers, and before
+ * mtp_solver_create.  Solvers then run the tents whose patch holds a curved element on a
+ * separate FP64 vector-ALU path, after the layer's other tents: every patch element by
+ * quadrature (collapsed Gauss-Jacobi rule, p + 4 points per direction) with the element
+ * map's Jacobian at the points, grad phi = J^{-T} sum_k tau_k gradhat lambdahat_k varying
+ * inside the element, the closed-form inverse at the points, and the weight-adjusted
+ * inverse mass Mhat^{-1} M_{1/J} Mhat^{-1} (M_{1/J} = int phi_a phi_b / |det J|, p + 8
+ * points) for every projection.  Scope of such solvers: 2D Maxwell, p = 1..4, MTP_FP64 or
+ * MTP_FP64_VALU (the other tents' kernel), SAT, the penalty flux, the layer schedule, walls
+ * (PEC/PMC) next to curved elements; no batches.  mtp_node_coords maps a curved element's
+ * nodes through its quadratic map.  Errors: MTP_ERR_ARG (null, dim != 2, the first three
+ * nodes not the element's vertices, non-finite nodes), MTP_ERR_MESH (a shared edge with two
+ * midpoint nodes, a curved element with a non-positive Jacobian on the lattice). */
+mtp_status mtp_mesh_set_curved_p2(mtp_mesh mesh, const double* nodes);
+
 /* Tent pitching on the host (section 2: the front is advanced one vertex at a time,
  * each step limited by causality; section 5 bounds the front slope by 1/(2c)), from the
  * flat front t = t_start to the flat front t = t_end.  Rule (the paper defers the

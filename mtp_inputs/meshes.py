@@ -221,3 +221,15 @@ def p2_geometry(mesh, on_circle=None):
             m[bnd] = on_circle * m[bnd] / np.linalg.norm(m[bnd], axis=1)[:, None]
         geo[:, 3 + s] = m
     return geo
+
+
+def equispaced_nodes_p2(geo, p):
+    """Physical coordinates of the documented equispaced nodes on quadratic triangles
+    (geo from p2_geometry), shape (ne, Np, 2): the reference nodes (i/p, j/p), i fastest,
+    mapped by x = sum_i G_i N_i with the P2 Lagrange shape functions (vertices
+    l_v (2 l_v - 1), edge midpoints 4 l_a l_b, l the barycentric coordinates)."""
+    pts = np.array([(i / p, j / p) for j in range(p + 1) for i in range(p + 1 - j)])
+    L = np.stack([1.0 - pts[:, 0] - pts[:, 1], pts[:, 0], pts[:, 1]], axis=1)
+    N = np.stack([L[:, 0] * (2 * L[:, 0] - 1), L[:, 1] * (2 * L[:, 1] - 1), L[:, 2] * (2 * L[:, 2] - 1),
+                  4 * L[:, 0] * L[:, 1], 4 * L[:, 1] * L[:, 2], 4 * L[:, 0] * L[:, 2]], axis=1)
+    return np.einsum("ni,eix->enx", N, np.asarray(geo, dtype=np.float64))

@@ -212,15 +212,21 @@ class CurvedMesh:
         geo = np.asarray(geo, dtype=np.float64)
         assert np.allclose(geo[:, :3], b.X, atol=1e-14), "geometry vertices must follow the cells"
         self.el = [CurvedTriangle(G) for G in geo]
+        # curved: some midpoint node differs from the straight edge midpoint
+        mids = 0.5 * (b.X[:, [0, 1, 0]] + b.X[:, [1, 2, 2]])
+        scale = np.abs(b.X).max(axis=(1, 2))[:, None, None] + 1.0
+        self.curved = np.any(np.abs(geo[:, 3:] - mids) > 1e-14 * scale, axis=(1, 2))
 
-    def step_bounds(self, sigma, n=8):
-        """Per-element pitching step: sigma sqrt(eps mu) / max over sample points x of
-        min_i sum_{j != i} |grad lambda_j(x)| (the affine rule's bound taken pointwise; the
-        samples are a degree-n collapsed Gauss rule plus the six geometry nodes)."""
-        pts = np.concatenate([quadrature(2, n)[0], REF_NODES6])
-        k = np.empty(self.ne)
-        for e, el in enumerate(self.el):
-            nrm = np.linalg.norm(el.grad_lambda(pts), axis=2)          # (q, 3)
+    def step_bounds(self, sigma, n=12):
+        """Per-element pitching step.  Straight elements: the affine rule's k_T.  Curved
+        elements: sigma sqrt(eps mu) / max over the barycentric lattice (i/n, j/n), i + j <= n,
+        of min_i sum_{j != i} |grad lambda_j(x)| (the affine bound taken pointwise)."""
+        b = self.base
+        norms = np.linalg.norm(b.grad_lam, axis=2)
+        k = sigma * np.sqrt(self.eps * self.mu) / (norms.sum(axis=1, keepdims=True) - norms).min(axis=1)
+        pts = np.array([(i / n, j / n) for j in range(n + 1) for i in range(n + 1 - j)])
+        for e in np.nonzero(self.curved)[0]:
+            nrm = np.linalg.norm(self.el[e].grad_lambda(pts), axis=2)   # (q, 3)
             s = (nrm.sum(axis=1, keepdims=True) - nrm).min(axis=1)      # min_i sum_{j!=i}
             k[e] = sigma * np.sqrt(self.eps[e] * self.mu[e]) / s.max()
         return k
@@ -452,6 +458,24 @@ class CurvedSolver:
             fun = lambda xh: exact.u(el.map(xh), t0) * g[None, :]   # noqa: E731
             U = project(el, self.p, fun, "wadg" if dg.recovery == "wadg" else "exact")
             self.cw[e] = U.T.reshape(-1)
+
+    def set_nodal_u(self, u_nodal, t0=0.0):
+        """Fields u on a flat front as nodal values (ne, Np, nc) at the documented equispaced
+        nodes mapped through each element's map: w = g(u) interpolated there."""
+        from .simplex import reference_nodes
+        self.tau[:] = t0
+        V = self.dg.B.eval(reference_nodes(2, self.p))
+        Vinv = np.linalg.inv(V)
+        for e in range(self.mesh.ne):
+            g = self.dg.sys.g_diag(self.mesh.eps[e], self.mesh.mu[e])
+            w = np.asarray(u_nodal[e], dtype=np.float64) * g[None, :]
+            self.cw[e] = (Vinv @ w).T.reshape(-1)
+
+    def nodal_w(self):
+        from .simplex import reference_nodes
+        V = self.dg.B.eval(reference_nodes(2, self.p))
+        c = self.cw.reshape(self.mesh.ne, self.nc, self.nb)
+        return np.einsum("ab,ecb->eac", V, c)
 
     def run_tent(self, v, t_top):
         dg = self.dg

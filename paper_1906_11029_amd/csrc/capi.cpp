@@ -36,7 +36,8 @@ struct Layout {
 
 struct Offsets {
   size_t W, tau, stage, grad_lam, cells, eps, mu, coords, pptr, pelem, pinfo, fptr, face, tv, tt, S, L,
-      fnode, fswap, perm, mi, err, slab, dag_indeg, dag_indeg0, dag_sptr, dag_succ, dag_queue, dag_ctl, total;
+      fnode, fswap, perm, mi, err, slab, dag_indeg, dag_indeg0, dag_sptr, dag_succ, dag_queue, dag_ctl,
+      cref, cgeo, cnbr, czone, total;
 };
 
 static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
@@ -74,6 +75,13 @@ static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
   o.dag_succ = L.add(sizeof(int32_t) * std::max<int64_t>(1, tent_dag_edges(m, t)));
   o.dag_queue = L.add(sizeof(int32_t) * nt);
   o.dag_ctl = L.add(sizeof(int32_t) * 4);
+  // curved-element tent path (empty for an all-affine mesh)
+  const CurvedPlan cp = curved_plan(m, t, R.p);
+  const bool cur = !cp.zone_elem.empty();
+  o.cref = L.add(cur ? sizeof(double) * cp.n_ref() : 0);
+  o.cgeo = L.add(cur ? sizeof(double) * cp.n_geo() : 0);
+  o.cnbr = L.add(cur ? sizeof(int32_t) * cp.zone_elem.size() * 6 : 0);
+  o.czone = L.add(cur ? sizeof(int32_t) * m.ne : 0);
   o.total = L.off;
   return o;
 }
@@ -184,6 +192,11 @@ struct mtp_solver_s {
   int dag_grid_max = 0;
   double grid_frac = 1.0;
   bool tuned_from_table = false;
+  // curved-element path: within each layer the affine tents come first (layer_na of them),
+  // then the tents whose patch holds a curved element
+  bool curved = false;
+  std::vector<int64_t> layer_na;
+  mtp::CurvedParams cparams{};
   // one slab (slab begin, every layer or the persistent DAG launch, slab end) captured once
   // and replayed per slab
   bool use_graph = true;
@@ -285,6 +298,13 @@ mtp_status mtp_mesh_create(int32_t dim, int64_t nv, const double* coords, int64_
   MTP_CATCH
 }
 
+mtp_status mtp_mesh_set_curved_p2(mtp_mesh mesh, const double* nodes) {
+  MTP_TRY
+  require(mesh && nodes, MTP_ERR_ARG, "null pointer");
+  set_curved_p2(mesh->m, nodes);
+  MTP_CATCH
+}
+
 mtp_status mtp_mesh_set_system(mtp_mesh mesh, int32_t system) {
   MTP_TRY
   require(mesh, MTP_ERR_ARG, "null mesh");
@@ -359,6 +379,24 @@ static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
   require(q >= 1 && q <= 32 && mm >= 1 && mm <= 1024, MTP_ERR_ARG, "q must be in 1..32 and m in 1..1024");
   require(tent_kernel_supported(m.d, p), MTP_ERR_UNSUPPORTED, "degree p not covered for this dimension");
   const size_t lim = 160 * 1024;
+  if (m.n_curved > 0) {
+    require(m.d == 2 && m.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED, "curved elements: 2D Maxwell only");
+    require(p >= 1 && p <= 4, MTP_ERR_UNSUPPORTED, "curved elements: degrees 1..4");
+    require(precision == MTP_FP64 || precision == MTP_FP64_VALU, MTP_ERR_UNSUPPORTED,
+            "curved elements run in FP64");
+    require(tent_curved_lds_bytes(p, m.max_patch) <= lim, MTP_ERR_UNSUPPORTED,
+            "largest vertex patch does not fit the curved-element kernel's LDS");
+    for (int64_t e = 0; e < m.ne; ++e)
+      for (int f = 0; f < 3; ++f) {
+        bool near = false;   // a data face of an element that shares a vertex with a curved one
+        for (int v = 0; v < 3 && !near; ++v) {
+          const int32_t V = m.cells[e * 3 + v];
+          for (int64_t k = m.v2e_ptr[V]; k < m.v2e_ptr[V + 1]; ++k) near = near || m.curved[m.v2e[k]];
+        }
+        require(!(near && m.nbr[e * 3 + f] < 0 && m.face_bc[e * 3 + f] == MTP_BC_DATA), MTP_ERR_UNSUPPORTED,
+                "curved elements: walls only (no data faces next to a curved element)");
+      }
+  }
   const size_t lds_valu = tent_kernel_lds_bytes(m.d, p, m.max_patch);
   const int np = (m.d == 2) ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
   const int block = (m.d == 2) ? 128 : 256;
@@ -441,6 +479,35 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
   try {
     s->mesh = mesh->m;
     s->tents = tents->t;
+    CurvedPlan cplan = curved_plan(mesh->m, s->tents, p);
+    s->curved = !cplan.zone_elem.empty();
+    if (s->curved) {   // affine tents first within each layer, then the curved ones
+      Tents& T = s->tents;
+      const int64_t nl = (int64_t)T.layer_ptr.size() - 1;
+      std::vector<size_t> ord;
+      std::vector<uint8_t> flag;
+      for (int64_t l = 0; l < nl; ++l) {
+        int64_t na = 0;
+        for (int pass = 0; pass < 2; ++pass)
+          for (int64_t i = T.layer_ptr[l]; i < T.layer_ptr[l + 1]; ++i)
+            if (cplan.tent_curved[i] == pass) {
+              ord.push_back((size_t)i);
+              flag.push_back((uint8_t)pass);
+              na += pass == 0;
+            }
+        s->layer_na.push_back(na);
+      }
+      auto perm = [&](auto& v) {
+        auto o = v;
+        for (size_t i = 0; i < ord.size(); ++i) o[i] = v[ord[i]];
+        v.swap(o);
+      };
+      perm(T.vertex);
+      perm(T.t_bot);
+      perm(T.t_top);
+      perm(T.layer);
+      cplan = curved_plan(mesh->m, T, p);   // zone numbering of the reordered table
+    }
     s->ref = build_refelem(mesh->m.d, p);
     s->p = p;
     s->q = q;
@@ -540,6 +607,26 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
       kp.dag_grid = s->kernel == 0 ? 0 : tent_dag_grid(kp, s->kernel == 2);
     }
     check_hip(prepare_tent_kernel(kp, s->kernel), "tent kernel attributes");
+    if (s->curved) {
+      // tables of the curved-element path; the persistent schedule does not cover it
+      std::vector<double> cref, cgeo;
+      std::vector<int32_t> cnbr;
+      curved_tables(M, cplan, s->ref.mi, cref, cgeo, cnbr);
+      up(s->off.cref, cref.data(), cref.size() * 8);
+      up(s->off.cgeo, cgeo.data(), cgeo.size() * 8);
+      up(s->off.cnbr, cnbr.data(), cnbr.size() * 4);
+      up(s->off.czone, cplan.zone.data(), cplan.zone.size() * 4);
+      CurvedParams& c = s->cparams;
+      c.ref = reinterpret_cast<const double*>(s->ws + s->off.cref);
+      c.geo = reinterpret_cast<const double*>(s->ws + s->off.cgeo);
+      c.nbr = reinterpret_cast<const int32_t*>(s->ws + s->off.cnbr);
+      c.zone = reinterpret_cast<const int32_t*>(s->ws + s->off.czone);
+      c.p = p;
+      c.max_patch = cplan.max_patch;
+      c.lds = tent_curved_lds_bytes(p, cplan.max_patch);
+      check_hip(launch_tent_curved(kp, c, 0, -1, nullptr), "curved kernel attributes");
+      kp.dag_grid = 0;
+    }
     check_hip(launch_slab_reset(kp, 0.0, s->tents.t_end, s->stream), "slab state");
     check_hip(hipStreamSynchronize(s->stream), "upload sync");
     s->dag_grid_max = kp.dag_grid;
@@ -578,7 +665,14 @@ mtp_status mtp_node_coords(mtp_solver s, double* xyz) {
   require(s && xyz, MTP_ERR_ARG, "null pointer");
   const Mesh& M = s->mesh;
   const int d = M.d, np = s->ref.np, p = s->p;
-  for (int64_t e = 0; e < M.ne; ++e)
+  for (int64_t e = 0; e < M.ne; ++e) {
+    if (M.n_curved > 0 && M.curved[e]) {   // the quadratic map of the reference node
+      for (int a = 0; a < np; ++a) {
+        const double xh[2] = {(double)s->ref.mi[a * 3 + 1] / p, (double)s->ref.mi[a * 3 + 2] / p};
+        curved_node(M, e, xh, &xyz[(e * np + a) * 2]);
+      }
+      continue;
+    }
     for (int a = 0; a < np; ++a)
       for (int i = 0; i < d; ++i) {
         double x = 0.0;
@@ -586,6 +680,7 @@ mtp_status mtp_node_coords(mtp_solver s, double* xyz) {
           x += (double)s->ref.mi[a * (d + 1) + v] / p * M.coords[M.cells[e * (d + 1) + v] * d + i];
         xyz[(e * np + a) * d + i] = x;
       }
+  }
   MTP_CATCH
 }
 
@@ -630,7 +725,14 @@ mtp_status mtp_set_planewave_bc(mtp_solver s, const double* amp, const double* k
 
 static void run_layer(mtp_solver s, int64_t layer, hipStream_t st) {
   const Tents& T = s->tents;
-  const int64_t first = T.layer_ptr[layer], count = T.layer_ptr[layer + 1] - first;
+  const int64_t first = T.layer_ptr[layer];
+  int64_t count = T.layer_ptr[layer + 1] - first;
+  if (s->curved) {   // the layer's tents with a curved element in their patch, after the others
+    const int64_t na = s->layer_na[layer];
+    if (count > na) check_hip(launch_tent_curved(s->kp, s->cparams, first + na, count - na, st), "curved tent kernel");
+    count = na;
+    if (count == 0) return;
+  }
   if (s->kernel == 0)
     check_hip(launch_tent_layer(s->kp, first, count, st), "tent kernel");
   else
@@ -762,6 +864,7 @@ static void batch_check(const mtp_solver* solvers, int32_t n) {
             "a batch needs one dimension and precision");
     require(s->method == MTP_METHOD_SAT, MTP_ERR_UNSUPPORTED, "batches run SAT only");
     require(s->mesh.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED, "batches run Maxwell only");
+    require(!s->curved, MTP_ERR_UNSUPPORTED, "batches do not run curved elements");
     for (int j = 0; j < i; ++j) require(solvers[j] != s, MTP_ERR_ARG, "solver listed twice");
   }
 }
@@ -1072,6 +1175,7 @@ mtp_status mtp_solver_set_method(mtp_solver s, int32_t method) {
   require(s, MTP_ERR_ARG, "null solver");
   require(method == MTP_METHOD_SAT || method == MTP_METHOD_RK4, MTP_ERR_ARG, "unknown method");
   require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  require(method == MTP_METHOD_SAT || !s->curved, MTP_ERR_UNSUPPORTED, "curved elements run SAT only");
   if (method == MTP_METHOD_RK4)
     require(s->kernel == 1 && s->mesh.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED,
             "the RK4 variant runs on the FP64 matrix-core kernel, Maxwell only");
@@ -1089,6 +1193,7 @@ mtp_status mtp_solver_set_flux(mtp_solver s, int32_t flux) {
   require(s, MTP_ERR_ARG, "null solver");
   require(flux == MTP_FLUX_PENALTY || flux == MTP_FLUX_IMPEDANCE, MTP_ERR_ARG, "unknown flux");
   require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
+  require(flux == MTP_FLUX_PENALTY || !s->curved, MTP_ERR_UNSUPPORTED, "curved elements use the penalty flux");
   if (flux == MTP_FLUX_IMPEDANCE)
     require(s->kernel != 0, MTP_ERR_UNSUPPORTED, "the impedance-matched flux runs on the matrix-core kernels");
   if (flux != s->kp.flux_kind) {

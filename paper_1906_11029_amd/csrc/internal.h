@@ -33,6 +33,12 @@ struct Mesh {
   std::vector<int64_t> adj_ptr;  // nv+1 : vertex neighbours
   std::vector<int32_t> adj;
   int max_patch = 0;
+  // quadratic (curved) triangles, 2D only: geo = ne*6*2 geometry nodes (vertices in cell
+  // order, then the midpoints of edges (0,1), (1,2), (0,2)); curved[e] != 0 where a
+  // midpoint node is not the straight midpoint.  Empty for an all-affine mesh.
+  std::vector<double> geo;
+  std::vector<uint8_t> curved;
+  int64_t n_curved = 0;
 };
 
 // Tents sorted by layer (stable in pitching order).
@@ -77,6 +83,33 @@ int64_t tent_dag_edges(const Mesh& m, const Tents& t);
 void set_last_error(const char* msg);
 int solver_device(mtp_solver s);
 void advance_to_dag_scratch(mtp_solver s, double T, char* d_scratch, size_t cap);
+
+// curved quadratic triangles (curved.cpp)
+void set_curved_p2(Mesh& m, const double* nodes);            // validates; throws Error
+double curved_step(const Mesh& m, int64_t e, double slope);  // pitcher step of a curved element
+void curved_node(const Mesh& m, int64_t e, const double* xh, double* x);   // x = map_e(xh)
+
+// The curved-element tent path of one solver: which tents run on it (those whose patch
+// holds a curved element), the zone of elements their patches cover, and the tables its
+// kernel reads (quadrature rules, reference basis at the points, per zone element the
+// geometry at the points and the weight-adjusted inverse mass).
+struct CurvedPlan {
+  int p = 0, np = 0, nq = 0, nfq = 0;      // nq = (p + 4)^2 volume points, nfq = p + 4 face points
+  std::vector<uint8_t> tent_curved;        // per tent of the table
+  std::vector<int32_t> zone;               // ne: zone index or -1
+  std::vector<int32_t> zone_elem;          // nz: element of each zone index
+  int max_patch = 0;                       // largest patch of a curved tent
+  // table sizes (doubles / ints)
+  size_t n_ref() const { return (size_t)nq * np * 3 + (size_t)nq * 3 + 3 * (size_t)nfq * (np + 3); }
+  size_t n_geo() const { return zone_elem.size() * ((size_t)nq * 5 + (size_t)np * np + 3 * (size_t)nfq * 3); }
+};
+CurvedPlan curved_plan(const Mesh& m, const Tents& t, int p);
+// ref: V[q][a], Gr[q][a][l], Lam[q][k], then per face f: Vf[f][q][a], Lamf[f][q][k];
+// geo per zone element z: Q[z][q][5] (w |det J|, J^{-1}[l][r]), Minv[z][a][b], F[z][f][q][3]
+// (w |dx/ds|, outward unit normal); nbr per zone element and face: neighbour element or
+// -1 - boundary kind, and (neighbour face | reversed << 2)
+void curved_tables(const Mesh& m, const CurvedPlan& cp, const std::vector<int32_t>& mi, std::vector<double>& ref,
+                   std::vector<double>& geo, std::vector<int32_t>& nbr);
 
 // tuning table (tune.cpp): launch choices by configuration key
 struct TuneEntry {

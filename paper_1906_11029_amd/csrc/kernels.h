@@ -99,6 +99,17 @@ struct BatchLaunch {
   int d, p, max_patch;
 };
 
+// The curved-element tent path: reference tables, per zone element tables and neighbours,
+// the zone map (see CurvedPlan), and the launch shape.
+struct CurvedParams {
+  const double* ref;
+  const double* geo;
+  const int32_t* nbr;
+  const int32_t* zone;
+  int p, max_patch;
+  size_t lds;
+};
+
 // error flag bits
 enum { ERRF_CAUSALITY = 1, ERRF_NONFINITE = 2, ERRF_DAG_WAIT = 4 };
 
@@ -124,6 +135,11 @@ hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);
 hipError_t launch_tent_batch_mfma(const BatchLaunch& bl, int fp32, hipStream_t s);
 hipError_t launch_batch_slab(const KernelParams* kps, int n, int end, hipStream_t s);
+// tents [first, first + count) of the table on the curved-element path (2D TE, P1..P4);
+// count < 0: only set the kernel attributes
+hipError_t launch_tent_curved(const KernelParams& kp, const CurvedParams& cp, int64_t first, int64_t count,
+                              hipStream_t s);
+size_t tent_curved_lds_bytes(int p, int max_patch);
 // slab bookkeeping on the device (graph-safe: kernels, no memsets)
 hipError_t launch_slab_reset(const KernelParams& kp, double t0, double height, hipStream_t s);
 hipError_t launch_slab_begin(const KernelParams& kp, hipStream_t s);

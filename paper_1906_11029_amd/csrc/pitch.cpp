@@ -6,7 +6,9 @@
 // to min(t_end, Q floor((min_w tau_w + k_vw)/Q - 1e-3)), Q = 2^-24.  Every edge then keeps
 // |tau_v - tau_w| <= k_vw, so on every element
 //   |grad phi| = |sum_{j != i} (tau_j - tau_i) grad lambda_j| <= slope*sqrt(eps mu),
-// and the minimum vertex always advances (no stalls).  Times are multiples of Q.
+// and the minimum vertex always advances (no stalls).  Times are multiples of Q.  On a curved
+// (quadratic) triangle grad lambda_j varies; its k_T takes the largest value of
+// min_i sum_{j != i} |grad lambda_j(x)| over the barycentric lattice (i/12, j/12).
 #include <algorithm>
 #include <cmath>
 #include <functional>
@@ -34,6 +36,8 @@ void pitch(const Mesh& m, double t_end, double slope, Tents& out) {
     double best = 1e300;
     for (int i = 0; i < nvert; ++i) best = std::min(best, tot - nrm[i]);
     kT[e] = slope * std::sqrt(m.eps[e] * m.mu[e]) / best;
+    // a curved element: the same bound taken pointwise, at its worst point of the lattice
+    if (m.n_curved > 0 && m.curved[e]) kT[e] = curved_step(m, e, slope);
   }
   // edge steps aligned with the adjacency CSR
   std::vector<double> kvw(m.adj.size(), 1e300);

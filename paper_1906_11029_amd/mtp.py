@@ -51,6 +51,7 @@ def load():
         "mtp_mesh_create": [i32, i64, P, i64, P, P, P, P, pp],
         "mtp_mesh_info": [P, P, P, P, P],
         "mtp_mesh_set_system": [P, i32],
+        "mtp_mesh_set_curved_p2": [P, P],
         "mtp_pitch_layers": [P, dbl, dbl, dbl, pp],
         "mtp_tents_query": [P, P, P, P],
         "mtp_tents_export": [P, P, P, P, P],
@@ -451,15 +452,25 @@ def mtp_mesh_set_system(mesh, system):
     _check(load().mtp_mesh_set_system(mesh, int(system)))
 
 
+def mtp_mesh_set_curved_p2(mesh, nodes, ne):
+    a = np.ascontiguousarray(nodes, dtype=np.float64)
+    if a.shape != (ne, 6, 2):
+        raise ValueError(f"curved nodes must have shape ({ne}, 6, 2), got {a.shape}")
+    _check(load().mtp_mesh_set_curved_p2(mesh, _ptr(a)))
+
+
 class Mesh:
     """system = MTP_SYSTEM_ACOUSTIC reads eps / mu as (kappa, rho) of linear acoustics."""
 
-    def __init__(self, coords, cells, eps=None, mu=None, face_bc=None, system=MTP_SYSTEM_MAXWELL):
+    def __init__(self, coords, cells, eps=None, mu=None, face_bc=None, system=MTP_SYSTEM_MAXWELL, curved=None):
+        """curved: (ne, 6, 2) quadratic geometry nodes per triangle (mtp_mesh_set_curved_p2)."""
         self.h = mtp_mesh_create(coords, cells, eps, mu, face_bc)
         self.info = mtp_mesh_info(self.h)
         self.system = system
         if system != MTP_SYSTEM_MAXWELL:
             mtp_mesh_set_system(self.h, system)
+        if curved is not None:
+            mtp_mesh_set_curved_p2(self.h, curved, self.info["ne"])
 
     def __del__(self, _free=_release):   # bound at definition: safe at interpreter shutdown
         _free("mtp_mesh_destroy", getattr(self, "h", None))

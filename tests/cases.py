@@ -74,6 +74,18 @@ AC_CASES = {
 }
 
 
+# Curved cases: the disk with quadratic boundary triangles (oracle/curved.py, weight-adjusted
+# scheme), against the circular-cavity TE mode's initial data.
+CURVED_CASES = {
+    "disk_curved_p2": dict(mesh=("disk", 3), p=2, q=3, m=4, T=0.2, kind=PEC, exact="disk_te", curved=True),
+    "disk_curved_p3_pmc": dict(mesh=("disk", 2), p=3, q=4, m=6, T=0.15, kind=PMC, exact="disk_te", curved=True),
+    "disk_curved_p4_eps": dict(mesh=("disk", 2), p=4, q=5, m=8, T=0.1, kind=PEC, exact="disk_te", curved=True,
+                               eps_split=True),
+    "disk_curved_p1_two_slabs": dict(mesh=("disk", 3), p=1, q=2, m=2, T=0.1, kind=PEC, exact="disk_te",
+                                     curved=True, slabs=2),
+}
+
+
 def build_mesh(spec):
     kind, n = spec
     if kind == "square":
@@ -88,6 +100,8 @@ def build_mesh(spec):
         return meshes.fan_disk(n)
     if kind == "delaunay":   # 4^3 lattice on the unit cube, jitter 0.3 h, 179 tets, patches up to 36
         return meshes.graded_delaunay_cube(n=n, a=1.0, jitter=0.3, seed=3)
+    if kind == "disk":
+        return meshes.disk_tri(n)
     if kind == "tri1":
         return {"coords": np.array([[0.1, 0.0], [1.0, 0.2], [0.3, 0.9]]), "cells": np.array([[0, 1, 2]], np.int32)}
     if kind == "tet1":
@@ -106,7 +120,8 @@ def exact_solution(name):
             "ac_cav2": fields.AcousticCavity(2),
             "ac_cav3": fields.AcousticCavity(3),
             "ac_pw2": fields.AcousticPlaneWave(direction=(1.0, 0.6), k=2 * np.pi, phase=0.2),
-            "ac_pulse3": fields.AcousticPulse(3)}[name]
+            "ac_pulse3": fields.AcousticPulse(3),
+            "disk_te": fields.CircularCavityTE()}[name]
 
 
 def planewave_params(ex, dim):
@@ -121,7 +136,9 @@ def planewave_params(ex, dim):
 
 
 def setup(name):
-    c = dict(CASES.get(name) or RK4_CASES.get(name) or IMP_CASES.get(name) or AC_CASES[name])
+    c = dict(CASES.get(name) or RK4_CASES.get(name) or IMP_CASES.get(name) or CURVED_CASES.get(name)
+             or AC_CASES[name])
+    c.setdefault("curved", False)
     c.setdefault("system", "maxwell")
     c.setdefault("method", "sat")
     c.setdefault("flux", "penalty")
@@ -136,5 +153,9 @@ def setup(name):
     else:
         eps, mu = np.ones(ne), np.ones(ne)
     ex = exact_solution(c["exact"])
-    u0 = ex.u(meshes.equispaced_nodes(mm, c["p"]), 0.0)
+    if c["curved"]:
+        mm["geo"] = meshes.p2_geometry(mm, on_circle=1.0)
+        u0 = ex.u(meshes.equispaced_nodes_p2(mm["geo"], c["p"]), 0.0)
+    else:
+        u0 = ex.u(meshes.equispaced_nodes(mm, c["p"]), 0.0)
     return c, mm, dim, eps, mu, meshes.uniform_bc(ne, dim, c["kind"]), ex, u0

@@ -13,13 +13,31 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 sys.path.insert(0, os.path.dirname(HERE))
 
-from cases import AC_CASES, CASES, DATA, IMP_CASES, RK4_CASES, setup  # noqa: E402
+from cases import AC_CASES, CASES, CURVED_CASES, DATA, IMP_CASES, RK4_CASES, setup  # noqa: E402
+from oracle import curved  # noqa: E402
 from oracle.mesh import Mesh  # noqa: E402
 from oracle.pitch import pitch  # noqa: E402
 from oracle.solve import OracleSolver  # noqa: E402
 
 
+def make_curved(name):
+    """Quadratic boundary triangles: the oracle's weight-adjusted curved tent solve."""
+    c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
+    cm = curved.CurvedMesh(mm["coords"], mm["cells"], mm["geo"], eps=eps, mu=mu, face_bc=bc)
+    tents = pitch(cm.base, c["T"], 0.5, k_elem=cm.step_bounds(0.5))
+    S = curved.CurvedSolver(cm, c["p"], c["q"], c["m"], alpha=c["alpha"], recovery="wadg")
+    S.set_nodal_u(u0)
+    for k in range(c["slabs"]):
+        S.run({**tents, "t_top": tents["t_top"] + k * c["T"]})
+    order = np.argsort(tents["layer"], kind="stable")
+    np.savez_compressed(os.path.join(HERE, f"oracle_{name}.npz"), w=S.nodal_w(),
+                        vertex=tents["vertex"][order].astype(np.int32), t_top=tents["t_top"][order],
+                        layer=tents["layer"][order].astype(np.int32))
+
+
 def make(name):
+    if name in CURVED_CASES:
+        return make_curved(name)
     c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
     mesh = Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc)
     tents = pitch(mesh, c["T"], sigma=0.5)
@@ -35,7 +53,7 @@ def make(name):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or list(CASES) + list(RK4_CASES) + list(IMP_CASES) + list(AC_CASES)
+    names = sys.argv[1:] or list(CASES) + list(RK4_CASES) + list(IMP_CASES) + list(AC_CASES) + list(CURVED_CASES)
     for n in names:
         t0 = time.time()
         make(n)
