@@ -214,6 +214,7 @@ def measured_traffic(tag):
 
 
 SCHEDULES = {"layers": 0, "dag": 1}
+PITCH = {"min-vertex": 0, "colour": 1}   # tent pitching rules
 TILE_ORDERS = {0: "default", 1: "round-robin", 2: "blocked", 3: "column-major"}
 
 
@@ -222,7 +223,7 @@ def describe_tuning(t):
             "grid_frac": t["grid_frac"], "from_tuning_table": t.get("from_table", False)}
 
 
-def run(W, precision, steps, warmup, M=None, T=None, schedule="auto", tune=0):
+def run(W, precision, steps, warmup, M=None, T=None, schedule="auto", tune=0, pitch=0):
     """Set up one solver on workload W, advance `warmup` untimed and `steps` timed slabs
     (each a replay of the captured slab graph); returns timings and the final fields.
     schedule "auto": the launch choice the tuning table gives at creation (the default
@@ -236,7 +237,7 @@ def run(W, precision, steps, warmup, M=None, T=None, schedule="auto", tune=0):
     if M is None:
         M = mtp.Mesh(mm["coords"], mm["cells"], eps=W.get("eps"), mu=W.get("mu"), face_bc=W.get("bc"),
                      system=mtp.MTP_SYSTEM_ACOUSTIC if W.get("system") == "acoustic" else mtp.MTP_SYSTEM_MAXWELL)
-        T = mtp.Tents(M, W["T"], 0.5)
+        T = mtp.Tents(M, W["T"], 0.5, rule=pitch)
     prec = {"fp64": mtp.MTP_FP64, "mixed": mtp.MTP_MIXED_FP32, "fp64-valu": mtp.MTP_FP64_VALU}[precision]
     S = mtp.Solver(M, T, W["p"], W["q"], W["m"], precision=prec)
     if schedule != "auto":
@@ -324,7 +325,7 @@ def batch2d(args):
             mm = meshes.square_tri(sp["n"])
             ex = fields.PlaneWaveTE(direction=(np.cos(sp["theta"]), np.sin(sp["theta"])), k=sp["k"], phase=sp["phase"])
             M = mtp.Mesh(mm["coords"], mm["cells"], face_bc=meshes.uniform_bc(len(mm["cells"]), 2, meshes.DATA))
-            T = mtp.Tents(M, H, 0.5)
+            T = mtp.Tents(M, H, 0.5, rule=PITCH[args.pitch])
             S = mtp.Solver(M, T, sp["p"], sp["p"] + 1, 2 * sp["p"], precision=prec)
             nodes = meshes.equispaced_nodes(mm, sp["p"])
             S.set_fields(ex.u(nodes, 0.0), 0.0)
@@ -381,7 +382,7 @@ def batch2d(args):
                                   "q = p+1, m = 2p, data faces, slab 0.1; one batch grouped by degree, "
                                   + ("one persistent launch per degree and slab" if tuning["schedule"] == "dag"
                                      else "one launch per global layer index and degree"),
-                      "solves": 64, "tents_per_step": int(tents), "precision": args.precision,
+                      "solves": 64, "tents_per_step": int(tents), "precision": args.precision, "pitch": args.pitch,
                       "schedule": tuning["schedule"], "tuning": tuning,
                       "rel_l2_error_vs_exact": {"max": max(errs), "median": float(np.median(errs))},
                       "compare": compare}}
@@ -395,7 +396,7 @@ def curved2d(args):
     The tents whose patch holds a curved triangle run on the curved-element path (FP64 vector
     ALU, quadrature, weight-adjusted inverse mass), the others on the FP64 matrix-core kernel.
     Beside it: the same vertices with straight edges (every tent on the matrix-core kernel),
-    and both runs' errors against the exact mode."""
+    the curved disk pitched by the other rule, and every run's error against the exact mode."""
     import torch
 
     from mtp_inputs import fields, meshes
@@ -404,10 +405,14 @@ def curved2d(args):
     mm = meshes.disk_tri(96)
     geo = meshes.p2_geometry(mm, on_circle=1.0)
     p, q, m, H = 3, 4, 6, 0.05
+    other = "min-vertex" if args.pitch == "colour" else "colour"
+    runs = [("curved", geo, args.pitch), ("straight", None, args.pitch)]
+    if not args.no_compare:
+        runs.append(("curved_" + other.replace("-", "_") + "_pitch", geo, other))
     res = {}
-    for label, g in (("curved", geo), ("straight", None)):
+    for label, g, rule in runs:
         M = mtp.Mesh(mm["coords"], mm["cells"], curved=g)
-        T = mtp.Tents(M, H, 0.5)
+        T = mtp.Tents(M, H, 0.5, rule=PITCH[rule])
         S = mtp.Solver(M, T, p, q, m, precision=mtp.MTP_FP64)
         nodes = meshes.equispaced_nodes_p2(geo if g is not None else meshes.p2_geometry(mm), p)
         S.set_fields(ex.u(nodes, 0.0), 0.0)
@@ -420,9 +425,10 @@ def curved2d(args):
         dof, nt = S.slab_dof_updates()
         tf = H * (args.warmup + args.steps)
         u, ue = S.get_fields(), ex.u(nodes, tf)
-        res[label] = {"dof_updates_per_s": dof * args.steps / wall, "ms_per_step": wall / args.steps * 1e3,
-                      "tents_per_step": int(nt), "rel_l2_nodal_error_vs_exact": float(np.linalg.norm(u - ue) /
-                                                                                       np.linalg.norm(ue))}
+        res[label] = {"pitch": rule, "dof_updates_per_s": dof * args.steps / wall,
+                      "ms_per_step": wall / args.steps * 1e3, "tents_per_step": int(nt),
+                      "layers_per_step": int(T.n_layers),
+                      "rel_l2_nodal_error_vs_exact": float(np.linalg.norm(u - ue) / np.linalg.norm(ue))}
         log(f"{label}: {args.steps} slabs in {wall:.3f}s, {res[label]['dof_updates_per_s']:.4e} DOF-updates/s, "
             f"error vs exact {res[label]['rel_l2_nodal_error_vs_exact']:.3e}")
     curved_elems = int(sum(1 for e in range(len(mm["cells"]))
@@ -434,7 +440,9 @@ def curved2d(args):
            "config": {"workload": "2D TE circular PEC cavity, disk of 96 rings (55296 triangles, 576 quadratic on "
                                   "the circle), P3, q=4, m=6, slab 0.05, TE mode J_1(kr) cos(theta); curved-element "
                                   "path for the tents whose patch holds a curved triangle",
-                      "curved_elements": curved_elems, "curved": res["curved"], "straight_edges": res["straight"],
+                      "curved_elements": curved_elems, "pitch": args.pitch, "curved": res["curved"],
+                      "straight_edges": res["straight"],
+                      "curved_other_pitch": res[runs[2][0]] if len(runs) > 2 else None,
                       "curved_over_straight_time": res["curved"]["ms_per_step"] / res["straight"]["ms_per_step"]}}
     print(json.dumps(out), flush=True)
 
@@ -449,6 +457,9 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "layers", "dag"],
                     help="one launch per layer, one persistent launch per slab over the tent DAG, or "
                          "auto (default): the launch choice of the package's tuning table")
+    ap.add_argument("--pitch", default=None, choices=list(PITCH),
+                    help="tent pitching rule: the minimum vertex moves, or the colour classes take turns "
+                         "(default: colour for the 2D disk and batch workloads, minimum vertex otherwise)")
     ap.add_argument("--tune", type=int, default=0,
                     help="run the tuner (this many timed slabs per candidate) before timing")
     ap.add_argument("--tune-out", default=None, help="write the tuning table here at the end")
@@ -461,9 +472,13 @@ def main():
                     help="only run a plain 512 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(sharding is described in the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.pitch is None:
+        # the colour rule widens the layers of irregular 2D meshes (the disk: 47 layers per slab
+        # instead of 28,069) and of the batch's squares; on the graded 3D mesh it makes more tents
+        args.pitch = "colour" if args.workload in ("curved2d", "batch2d") else "min-vertex"
 
     import torch
 
@@ -486,7 +501,8 @@ def main():
             mtp.mtp_tune_save(args.tune_out)
         return
     W = workload(args.workload)
-    head = run(W, args.precision, args.steps, args.warmup, schedule=args.schedule, tune=args.tune)
+    pitch = PITCH[args.pitch]
+    head = run(W, args.precision, args.steps, args.warmup, schedule=args.schedule, tune=args.tune, pitch=pitch)
     M, T = head["M"], head["T"]
     log(f"mesh {M.info} tents {head['n_tents']} layers {head['layers']}")
     tuning = describe_tuning(head["tuning"])
@@ -522,7 +538,7 @@ def main():
             Wc = workload(W["cert"])
             nsl = args.steps + args.warmup
             for prec in ("fp64", "mixed"):
-                rc = run(Wc, prec, nsl, 0, schedule="auto", tune=args.tune)
+                rc = run(Wc, prec, nsl, 0, schedule="auto", tune=args.tune, pitch=pitch)
                 cert[prec + "_rel_l2_error_vs_exact"] = rc["err"]
                 del rc
             cert["slabs"] = nsl
@@ -543,6 +559,7 @@ def main():
         "dtype": "f32+f64" if head["kernel"] == 2 else "f64", "data": "synthetic",
         "config": {"workload": W["desc"], "tets": int(M.info["ne"]), "p": W["p"], "q": W["q"], "m": W["m"],
                    "tents_per_step": int(head["n_tents"]), "layers_per_step": int(nl), "slope_fraction": 0.5,
+                   "pitch": args.pitch,
                    "mean_slope_over_bound": round(float(slopes["mean_slope_over_bound"]), 4),
                    "tents_per_vertex_per_slab": round(float(slopes["tents_per_vertex_per_slab"]), 3),
                    "precision": args.precision, "schedule": args.schedule, "tuning": tuning,

@@ -174,6 +174,30 @@ mtp_status mtp_mesh_set_curved_p2(mtp_mesh mesh, const double* nodes);
  * (0,1)), MTP_ERR_PITCH. */
 mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_start, double t_end, double slope_fraction,
                             mtp_tents* out);
+
+/* Pitching rules (section 2 leaves the order in which vertices move open: any order that
+ * keeps the causality bound yields a valid tent table). */
+enum {
+  MTP_PITCH_MIN_VERTEX = 0,   /* mtp_pitch_layers' rule: the (time, id)-smallest vertex moves   */
+  MTP_PITCH_COLOUR = 1        /* the vertex graph is coloured greedily (ids ascending, smallest */
+                              /* colour no neighbour holds); the colours take turns, and at its */
+                              /* turn every vertex of the colour below H moves (ids ascending)  */
+                              /* to the target above, capped at tau_v + 1.5 min_w k_vw, if that */
+                              /* lies above its time.                                           */
+};
+/* mtp_pitch_layers with a choice of rule.  Both rules keep the slope bound and put a tent
+ * in layer 1 + the largest layer of itself and its neighbours, so both make tables that
+ * solvers, batches and mtp_tents_dag take alike.  They differ in order: the minimum-vertex
+ * rule advances the front in time order, which on irregular meshes serialises it (a disk of
+ * triangles gets a few tents per layer); the colour rule advances a whole independent set
+ * per turn and gives layers as wide as a colour class, at the price of more layers (and, on
+ * graded 3D meshes with material jumps, more tents) where the minimum-vertex rule already
+ * fills them.  The cap bounds the pole height, which the pseudo-time operator scales with:
+ * a vertex that waited while its neighbours rose would otherwise make poles of two edge
+ * steps.  The table is the same for the same mesh and arguments on every call.  Errors: as
+ * mtp_pitch_layers, and MTP_ERR_ARG for an unknown rule. */
+mtp_status mtp_pitch_layers_rule(mtp_mesh mesh, double t_start, double t_end, double slope_fraction,
+                                 int32_t rule, mtp_tents* out);
 /* Size of a tent table (section 2: tents whose vertices are at graph distance >= 2 are
  * independent; a layer is a set of such tents).  n_tents, n_layers; layer_ptr
  * (n_layers+1 entries, may be NULL) receives the start of each layer in the layer-sorted

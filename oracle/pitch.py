@@ -15,6 +15,21 @@ implementations follow:
           emit tent (v, tau_v, t_new) in layer 1 + max(last layer of v and of its
           neighbours); tau_v = t_new.
 
+A second ordering ("colour") moves the vertices in another order, which the paper allows
+(any order that keeps causality gives valid tents):
+  colour the vertex graph greedily (ids ascending, each vertex takes the smallest colour
+  none of its already coloured neighbours holds); the colours take turns 0, 1, ..., C-1,
+  0, ...; at its turn every vertex of the colour still below t_end computes
+      t_new = min(t_end, Q floor(min(t_plus, tau_v + 1.5 min_w k_vw) / Q - 1e-3))
+  and, if t_new > tau_v, emits its tent (ids ascending) with the same layer rule.
+A colour class is an independent set, so within a turn no move changes another's target.
+The cap on the pole height (1.5 times the vertex's smallest edge step) is a reading: the
+paper states no pseudo-time step condition beyond causality, but a vertex that waited
+while its neighbours rose would make poles of up to two edge steps, and such tents next to a
+material jump made the SAT recursion grow without bound; the cap keeps every pole at most
+1.5 edge steps.  The vertex holding the global minimum moves at its colour's turn by at
+least its smallest edge step (times quantised), so no C consecutive turns are idle.
+
 Invariant: |tau_v - tau_w| <= k_vw on every edge, hence on every element
 grad phi = sum_{j != i} (tau_j - tau_i) grad lambda_j has |grad phi| <= sigma sqrt(eps mu)
 (the slope bound 1/(2c) for sigma = 1/2).  The minimum vertex always advances by at least
@@ -32,6 +47,7 @@ import numpy as np
 
 QUANTUM = 2.0 ** -24
 SAFETY = 1e-3
+POLE_CAP = 1.5     # colour rule: pole height <= POLE_CAP * min_w k_vw
 
 
 def edge_steps(mesh, sigma, k_elem=None):
@@ -58,11 +74,28 @@ def edge_steps(mesh, sigma, k_elem=None):
     return kv
 
 
-def pitch(mesh, t_end, sigma=0.5, k_elem=None):
+def greedy_colouring(mesh):
+    """Colour of every vertex: ids ascending, the smallest colour no earlier neighbour holds."""
+    colour = -np.ones(mesh.nv, dtype=np.int64)
+    for v in range(mesh.nv):
+        taken = {int(colour[w]) for w in mesh.adj[v]}
+        c = 0
+        while c in taken:
+            c += 1
+        colour[v] = c
+    return colour
+
+
+def pitch(mesh, t_end, sigma=0.5, k_elem=None, rule="min_vertex"):
     """Pitch tents from the flat front 0 to the flat front t_end.
 
     Returns dict with int arrays vertex, layer and float arrays t_bot, t_top, in
-    emission order.  k_elem: per-element steps replacing the affine rule's k_T."""
+    emission order.  k_elem: per-element steps replacing the affine rule's k_T.
+    rule: "min_vertex" or "colour" (module docstring)."""
+    if rule == "colour":
+        return _pitch_colour(mesh, t_end, sigma, k_elem)
+    if rule != "min_vertex":
+        raise ValueError(f"unknown pitching rule {rule}")
     nv = mesh.nv
     tau = np.zeros(nv)
     kv = edge_steps(mesh, sigma, k_elem)
@@ -88,6 +121,40 @@ def pitch(mesh, t_end, sigma=0.5, k_elem=None):
         tau[v] = t_new
         if t_new < t_end:
             heapq.heappush(heap, (t_new, v))
+    return {"vertex": np.asarray(V, dtype=np.int64), "t_bot": np.asarray(TB),
+            "t_top": np.asarray(TT), "layer": np.asarray(L, dtype=np.int64)}
+
+
+def _pitch_colour(mesh, t_end, sigma, k_elem):
+    tau = np.zeros(mesh.nv)
+    kv = edge_steps(mesh, sigma, k_elem)
+    cap = np.array([POLE_CAP * np.min(k) for k in kv])
+    colour = greedy_colouring(mesh)
+    n_colours = int(colour.max()) + 1
+    last_layer = -np.ones(mesh.nv, dtype=np.int64)
+    V, TB, TT, L = [], [], [], []
+    turn, idle = 0, 0
+    while np.any(tau < t_end):
+        moved = False
+        for v in np.nonzero(colour == turn)[0]:
+            if tau[v] >= t_end:
+                continue
+            nb = mesh.adj[v]
+            t_plus = min(np.min(tau[nb] + kv[v]), tau[v] + cap[v])
+            t_new = min(t_end, QUANTUM * np.floor(t_plus / QUANTUM - SAFETY))
+            if t_new > tau[v]:
+                lay = 1 + max(last_layer[v], int(np.max(last_layer[nb])))
+                last_layer[v] = lay
+                V.append(int(v))
+                TB.append(tau[v])
+                TT.append(t_new)
+                L.append(lay)
+                tau[v] = t_new
+                moved = True
+        idle = 0 if moved else idle + 1
+        if idle > n_colours:
+            raise RuntimeError("colour pitching made no progress")
+        turn = (turn + 1) % n_colours
     return {"vertex": np.asarray(V, dtype=np.int64), "t_bot": np.asarray(TB),
             "t_top": np.asarray(TT), "layer": np.asarray(L, dtype=np.int64)}
 

@@ -326,16 +326,22 @@ mtp_status mtp_mesh_info(mtp_mesh mesh, int32_t* dim, int64_t* nv, int64_t* ne, 
 void mtp_mesh_destroy(mtp_mesh mesh) { delete mesh; }
 
 mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_start, double t_end, double slope_fraction, mtp_tents* out) {
+  return mtp_pitch_layers_rule(mesh, t_start, t_end, slope_fraction, MTP_PITCH_MIN_VERTEX, out);
+}
+
+mtp_status mtp_pitch_layers_rule(mtp_mesh mesh, double t_start, double t_end, double slope_fraction, int32_t rule,
+                                 mtp_tents* out) {
   MTP_TRY
   require(mesh && out, MTP_ERR_ARG, "null pointer");
   require(std::isfinite(t_start) && std::isfinite(t_end) && t_end > t_start, MTP_ERR_ARG,
           "need finite t_start < t_end");
   require(slope_fraction > 0 && slope_fraction < 1, MTP_ERR_CAUSALITY, "slope fraction must be in (0,1)");
+  require(rule == MTP_PITCH_MIN_VERTEX || rule == MTP_PITCH_COLOUR, MTP_ERR_ARG, "unknown pitching rule");
   auto* h = new mtp_tents_s();
   try {
     // times relative to t_start: the table is a slab pattern that solvers apply from their
     // current flat front, and one table serves every slab bit for bit
-    pitch(mesh->m, t_end - t_start, slope_fraction, h->t);
+    pitch(mesh->m, t_end - t_start, slope_fraction, rule, h->t);
     h->t.t_start = t_start;
   } catch (...) {
     delete h;

@@ -46,6 +46,7 @@ struct Tents {
   double t_start = 0.0;             // front time the table starts from (times below are relative to it)
   double t_end = 0.0;               // slab height: the table runs from relative time 0 to t_end
   double slope = 0.5;
+  int rule = 0;                     // MTP_PITCH_*
   std::vector<int32_t> vertex;
   std::vector<double> t_bot, t_top;
   std::vector<int32_t> layer;
@@ -71,7 +72,7 @@ RefElem build_refelem(int d, int p);
 void vertex_order(int d, int k, int* order);
 
 void build_topology(Mesh& m);
-void pitch(const Mesh& m, double t_end, double slope, Tents& out);
+void pitch(const Mesh& m, double t_end, double slope, int rule, Tents& out);
 // dependency graph of the tents (table order): predecessor counts, successors (CSR) and the
 // number of leading tents without predecessor
 void tent_dag(const Mesh& m, const Tents& t, std::vector<int32_t>& pred_count, std::vector<int32_t>& succ_ptr,

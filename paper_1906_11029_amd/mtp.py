@@ -21,6 +21,7 @@ MTP_METHOD_SAT, MTP_METHOD_RK4 = 0, 1
 MTP_FLUX_PENALTY, MTP_FLUX_IMPEDANCE = 0, 1
 MTP_SYSTEM_MAXWELL, MTP_SYSTEM_ACOUSTIC = 0, 1
 MTP_TILES_DEFAULT, MTP_TILES_ROUND_ROBIN, MTP_TILES_BLOCKED, MTP_TILES_COLUMN_MAJOR = 0, 1, 2, 3
+MTP_PITCH_MIN_VERTEX, MTP_PITCH_COLOUR = 0, 1
 
 # tuning table shipped with the package (measured on MI355X); MTP_TUNE_FILE names another
 # file to load instead, or, set to the empty string, disables loading one
@@ -53,6 +54,7 @@ def load():
         "mtp_mesh_set_system": [P, i32],
         "mtp_mesh_set_curved_p2": [P, P],
         "mtp_pitch_layers": [P, dbl, dbl, dbl, pp],
+        "mtp_pitch_layers_rule": [P, dbl, dbl, dbl, i32, pp],
         "mtp_tents_query": [P, P, P, P],
         "mtp_tents_export": [P, P, P, P, P],
         "mtp_solver_workspace_size": [P, P, i32, i32, i32, i32, P],
@@ -157,6 +159,13 @@ def _release(name, h):
 def mtp_pitch_layers(mesh, t_start, t_end, slope_fraction=0.5):
     h = C.c_void_p()
     _check(load().mtp_pitch_layers(mesh, float(t_start), float(t_end), float(slope_fraction), C.byref(h)))
+    return h
+
+
+def mtp_pitch_layers_rule(mesh, t_start, t_end, slope_fraction=0.5, rule=0):
+    h = C.c_void_p()
+    _check(load().mtp_pitch_layers_rule(mesh, float(t_start), float(t_end), float(slope_fraction), int(rule),
+                                        C.byref(h)))
     return h
 
 
@@ -478,9 +487,13 @@ class Mesh:
 
 
 class Tents:
-    def __init__(self, mesh, t_end, slope_fraction=0.5, t_start=0.0):
+    def __init__(self, mesh, t_end, slope_fraction=0.5, t_start=0.0, rule=None):
         self.mesh = mesh
-        self.h = mtp_pitch_layers(mesh.h, t_start, t_end, slope_fraction)
+        if rule is None:
+            self.h = mtp_pitch_layers(mesh.h, t_start, t_end, slope_fraction)
+        else:
+            self.h = mtp_pitch_layers_rule(mesh.h, t_start, t_end, slope_fraction, rule)
+        self.rule = MTP_PITCH_MIN_VERTEX if rule is None else rule
         self.n_tents, self.n_layers, self.layer_ptr = mtp_tents_query(self.h)
         self.t_end = t_end
 

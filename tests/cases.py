@@ -85,6 +85,20 @@ CURVED_CASES = {
                                      curved=True, slabs=2),
 }
 
+# The colour pitching rule (rule="colour"): the same problems pitched by colour turns
+# instead of the minimum vertex: wide layers on the irregular disk and fan, the Kuhn
+# cube's eight colours, data faces, and the curved disk.
+COLOUR_CASES = {
+    "disk_colour_p2": dict(mesh=("disk", 4), p=2, q=3, m=4, T=0.2, kind=PEC, exact="disk_te", rule="colour"),
+    "te_fan32_p3_colour": dict(mesh=("fan", 32), p=3, q=4, m=6, T=0.1, kind=PMC, exact="pec_te", rule="colour"),
+    "cav3d_p3_colour": dict(mesh=("kuhn", 2), p=3, q=4, m=6, T=0.25, kind=PEC, exact="pec_3d", rule="colour",
+                            eps_split=True),
+    "te_planewave_p2_colour": dict(mesh=("square", 8), p=2, q=3, m=4, T=0.5, kind=DATA, exact="pw_te",
+                                   rule="colour"),
+    "disk_curved_p3_colour": dict(mesh=("disk", 3), p=3, q=4, m=6, T=0.15, kind=PMC, exact="disk_te", curved=True,
+                                  rule="colour", slabs=2),
+}
+
 
 def build_mesh(spec):
     kind, n = spec
@@ -137,8 +151,9 @@ def planewave_params(ex, dim):
 
 def setup(name):
     c = dict(CASES.get(name) or RK4_CASES.get(name) or IMP_CASES.get(name) or CURVED_CASES.get(name)
-             or AC_CASES[name])
+             or COLOUR_CASES.get(name) or AC_CASES[name])
     c.setdefault("curved", False)
+    c.setdefault("rule", "min_vertex")
     c.setdefault("system", "maxwell")
     c.setdefault("method", "sat")
     c.setdefault("flux", "penalty")

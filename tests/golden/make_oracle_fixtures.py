@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 sys.path.insert(0, os.path.dirname(HERE))
 
-from cases import AC_CASES, CASES, CURVED_CASES, DATA, IMP_CASES, RK4_CASES, setup  # noqa: E402
+from cases import AC_CASES, CASES, COLOUR_CASES, CURVED_CASES, DATA, IMP_CASES, RK4_CASES, setup  # noqa: E402
 from oracle import curved  # noqa: E402
 from oracle.mesh import Mesh  # noqa: E402
 from oracle.pitch import pitch  # noqa: E402
@@ -24,7 +24,7 @@ def make_curved(name):
     """Quadratic boundary triangles: the oracle's weight-adjusted curved tent solve."""
     c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
     cm = curved.CurvedMesh(mm["coords"], mm["cells"], mm["geo"], eps=eps, mu=mu, face_bc=bc)
-    tents = pitch(cm.base, c["T"], 0.5, k_elem=cm.step_bounds(0.5))
+    tents = pitch(cm.base, c["T"], 0.5, k_elem=cm.step_bounds(0.5), rule=c["rule"])
     S = curved.CurvedSolver(cm, c["p"], c["q"], c["m"], alpha=c["alpha"], recovery="wadg")
     S.set_nodal_u(u0)
     for k in range(c["slabs"]):
@@ -36,11 +36,11 @@ def make_curved(name):
 
 
 def make(name):
-    if name in CURVED_CASES:
+    if setup(name)[0]["curved"]:
         return make_curved(name)
     c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
     mesh = Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc)
-    tents = pitch(mesh, c["T"], sigma=0.5)
+    tents = pitch(mesh, c["T"], sigma=0.5, rule=c["rule"])
     S = OracleSolver(mesh, c["p"], c["q"], c["m"], alpha=c["alpha"], data=ex if c["kind"] == DATA else None,
                      method=c["method"], flux=c["flux"], system=c["system"])
     S.set_nodal_u(u0)
@@ -53,7 +53,8 @@ def make(name):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or list(CASES) + list(RK4_CASES) + list(IMP_CASES) + list(AC_CASES) + list(CURVED_CASES)
+    names = sys.argv[1:] or (list(CASES) + list(RK4_CASES) + list(IMP_CASES) + list(AC_CASES) + list(CURVED_CASES)
+                             + list(COLOUR_CASES))
     for n in names:
         t0 = time.time()
         make(n)

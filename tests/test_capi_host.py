@@ -54,6 +54,45 @@ def test_pitch_graded_materials_matches_oracle():
         assert np.array_equal(ex[k], ot[k][order]), k
 
 
+def _colour_meshes():
+    graded = meshes.cube_kuhn(3, axis_map=lambda g: 0.3 * g + 0.7 * g * g)
+    return {"square6": (meshes.square_tri(6), None), "disk8": (meshes.disk_tri(8), None),
+            "fan32": (meshes.fan_disk(32), None), "kuhn3": (meshes.cube_kuhn(3), None),
+            "graded3_eps": (graded, meshes.materials_split(graded))}
+
+
+@pytest.mark.parametrize("name", ["square6", "disk8", "fan32", "kuhn3", "graded3_eps"])
+def test_colour_pitch_matches_oracle_bit_exact(name):
+    """The colour rule: the library's table equals the oracle's, entry for entry."""
+    mm, mat = _colour_meshes()[name]
+    eps, mu = mat if mat else (None, None)
+    T = 0.2
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    tents = mtp.Tents(M, T, 0.5, rule=mtp.MTP_PITCH_COLOUR)
+    ex = tents.export()
+    om = OMesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    ot = opitch(om, T, 0.5, rule="colour")
+    order = np.argsort(ot["layer"], kind="stable")
+    for k in ("vertex", "t_bot", "t_top", "layer"):
+        assert np.array_equal(ex[k], ot[k][order]), k
+    assert tents.n_layers == ot["layer"].max() + 1
+    validate(om, {k: np.asarray(v) for k, v in ex.items()}, T, 0.5)
+    # the explicit min-vertex rule is mtp_pitch_layers' table
+    a = mtp.Tents(M, T, 0.5).export()
+    b = mtp.Tents(M, T, 0.5, rule=mtp.MTP_PITCH_MIN_VERTEX).export()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_colour_pitch_refuses_unknown_rule():
+    mm = meshes.square_tri(2)
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    for rule in (-1, 2):
+        with pytest.raises(mtp.MTPError) as e:
+            mtp.Tents(M, 0.5, 0.5, rule=rule)
+        assert e.value.code == -1
+
+
 def test_mesh_info_patch_sizes():
     mm = meshes.cube_kuhn(3)
     info = mtp.Mesh(mm["coords"], mm["cells"]).info

@@ -29,6 +29,18 @@ def test_curved_pitch_matches_the_oracle_bit_exact(name):
         assert np.array_equal(ex_t[k], ot[k][order]), k
 
 
+def test_curved_colour_pitch_matches_the_oracle_bit_exact():
+    from cases import setup as csetup
+    c, mm, dim, eps, mu, bc, ex, u0 = csetup("disk_curved_p3_colour")
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc, curved=mm["geo"])
+    ex_t = mtp.Tents(M, c["T"], 0.5, rule=mtp.MTP_PITCH_COLOUR).export()
+    cm = curved.CurvedMesh(mm["coords"], mm["cells"], mm["geo"], eps=eps, mu=mu, face_bc=bc)
+    ot = opitch(cm.base, c["T"], 0.5, k_elem=cm.step_bounds(0.5), rule="colour")
+    order = np.argsort(ot["layer"], kind="stable")
+    for k in ("vertex", "t_bot", "t_top", "layer"):
+        assert np.array_equal(ex_t[k], ot[k][order]), k
+
+
 def _mesh():
     mm = meshes.disk_tri(2)
     return mm, meshes.p2_geometry(mm, on_circle=1.0)

@@ -45,10 +45,19 @@ def _library_preds(dag, n):
     return preds
 
 
-CASES = [("2d", 4, 0.5), ("2d", 8, 0.5), ("3d", 2, 0.4), ("3d", 3, 0.3), ("graded", 3, 0.2)]
+CASES = [("2d", 4, 0.5), ("2d", 8, 0.5), ("3d", 2, 0.4), ("3d", 3, 0.3), ("graded", 3, 0.2),
+         ("disk_colour", 4, 0.2), ("3d_colour", 2, 0.3)]
 
 
 def _setup(kind, n, T):
+    if kind == "disk_colour":       # tables of the colour rule
+        mm = meshes.disk_tri(n)
+        M = mtp.Mesh(mm["coords"], mm["cells"])
+        return mm, M, mtp.Tents(M, T, 0.5, rule=mtp.MTP_PITCH_COLOUR)
+    if kind == "3d_colour":
+        mm = meshes.cube_kuhn(n)
+        M = mtp.Mesh(mm["coords"], mm["cells"])
+        return mm, M, mtp.Tents(M, T, 0.5, rule=mtp.MTP_PITCH_COLOUR)
     if kind == "2d":
         mm = meshes.square_tri(n)
         M = mtp.Mesh(mm["coords"], mm["cells"])
@@ -83,7 +92,7 @@ def test_dag_matches_independent_construction(kind, n, T):
         assert (np.diff(s) > 0).all() and (s > i).all()
 
 
-@pytest.mark.parametrize("kind,n,T", CASES[:3] + [("graded", 2, 0.2)])
+@pytest.mark.parametrize("kind,n,T", CASES[:3] + [("graded", 2, 0.2), ("disk_colour", 3, 0.2)])
 def test_dag_orders_every_conflicting_pair(kind, n, T):
     mm, M, tents = _setup(kind, n, T)
     ex = tents.export()
