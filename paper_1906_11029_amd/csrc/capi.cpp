@@ -197,6 +197,10 @@ struct mtp_solver_s {
   bool curved = false;
   std::vector<int64_t> layer_na;
   mtp::CurvedParams cparams{};
+  // a layer's curved tents run on a side stream beside its affine tents (disjoint patches),
+  // forked from and joined back into the layer's stream by two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // one slab (slab begin, every layer or the persistent DAG launch, slab end) captured once
   // and replayed per slab
   bool use_graph = true;
@@ -390,7 +394,7 @@ static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
     require(p >= 1 && p <= 4, MTP_ERR_UNSUPPORTED, "curved elements: degrees 1..4");
     require(precision == MTP_FP64 || precision == MTP_FP64_VALU, MTP_ERR_UNSUPPORTED,
             "curved elements run in FP64");
-    require(tent_curved_lds_bytes(p, m.max_patch) <= lim, MTP_ERR_UNSUPPORTED,
+    require(tent_curved_lds_bytes(p, m.max_patch, false) <= lim, MTP_ERR_UNSUPPORTED,
             "largest vertex patch does not fit the curved-element kernel's LDS");
     for (int64_t e = 0; e < m.ne; ++e)
       for (int f = 0; f < 3; ++f) {
@@ -459,6 +463,7 @@ static std::string solver_key(mtp_solver s) {
          std::to_string(tents_class((int64_t)s->tents.vertex.size()));
 }
 static void drop_graph(mtp_solver s);
+static void release_side(mtp_solver s);
 static void validate_choice(int schedule, int tile_order, double grid_frac) {
   require(schedule == MTP_SCHEDULE_LAYERS || schedule == MTP_SCHEDULE_DAG, MTP_ERR_ARG, "unknown schedule");
   require(tile_order >= MTP_TILES_DEFAULT && tile_order <= MTP_TILES_COLUMN_MAJOR, MTP_ERR_ARG,
@@ -629,8 +634,12 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
       c.zone = reinterpret_cast<const int32_t*>(s->ws + s->off.czone);
       c.p = p;
       c.max_patch = cplan.max_patch;
-      c.lds = tent_curved_lds_bytes(p, cplan.max_patch);
+      c.geo_lds = tent_curved_lds_bytes(p, cplan.max_patch, true) <= 160 * 1024 ? 1 : 0;
+      c.lds = tent_curved_lds_bytes(p, cplan.max_patch, c.geo_lds != 0);
       check_hip(launch_tent_curved(kp, c, 0, -1, nullptr), "curved kernel attributes");
+      check_hip(hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking), "side stream");
+      check_hip(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming), "fork event");
+      check_hip(hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming), "join event");
       kp.dag_grid = 0;
     }
     check_hip(launch_slab_reset(kp, 0.0, s->tents.t_end, s->stream), "slab state");
@@ -643,11 +652,21 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
       s->tuned_from_table = true;
     }
   } catch (...) {
+    release_side(s);
     delete s;
     throw;
   }
   *out = s;
   MTP_CATCH
+}
+
+static void release_side(mtp_solver s) {
+  if (s->side) (void)hipStreamSynchronize(s->side);
+  if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+  if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+  if (s->side) (void)hipStreamDestroy(s->side);
+  s->ev_fork = s->ev_join = nullptr;
+  s->side = nullptr;
 }
 
 static void drop_graph(mtp_solver s) {
@@ -663,6 +682,7 @@ void mtp_solver_destroy(mtp_solver solver) {
   if (!solver) return;
   (void)hipStreamSynchronize(solver->stream);
   drop_graph(solver);
+  release_side(solver);
   delete solver;
 }
 
@@ -735,9 +755,22 @@ static void run_layer(mtp_solver s, int64_t layer, hipStream_t st) {
   int64_t count = T.layer_ptr[layer + 1] - first;
   if (s->curved) {   // the layer's tents with a curved element in their patch, after the others
     const int64_t na = s->layer_na[layer];
-    if (count > na) check_hip(launch_tent_curved(s->kp, s->cparams, first + na, count - na, st), "curved tent kernel");
-    count = na;
-    if (count == 0) return;
+    if (count > na && na > 0) {   // both kinds: the curved tents on the side stream, beside the others
+      check_hip(hipEventRecord(s->ev_fork, st), "fork");
+      check_hip(hipStreamWaitEvent(s->side, s->ev_fork, 0), "fork wait");
+      check_hip(launch_tent_curved(s->kp, s->cparams, first + na, count - na, s->side), "curved tent kernel");
+      check_hip(hipEventRecord(s->ev_join, s->side), "join");
+    } else if (count > na) {
+      check_hip(launch_tent_curved(s->kp, s->cparams, first + na, count - na, st), "curved tent kernel");
+    }
+    if (na > 0) {
+      if (s->kernel == 0)
+        check_hip(launch_tent_layer(s->kp, first, na, st), "tent kernel");
+      else
+        check_hip(launch_tent_layer_mfma(s->kp, first, na, s->kernel == 2, st), "tent kernel");
+    }
+    if (count > na && na > 0) check_hip(hipStreamWaitEvent(st, s->ev_join, 0), "join wait");
+    return;
   }
   if (s->kernel == 0)
     check_hip(launch_tent_layer(s->kp, first, count, st), "tent kernel");

@@ -107,6 +107,7 @@ struct CurvedParams {
   const int32_t* nbr;
   const int32_t* zone;
   int p, max_patch;
+  int geo_lds;   // 1: the patch elements' geometry blocks are staged in LDS
   size_t lds;
 };
 
@@ -139,7 +140,8 @@ hipError_t launch_batch_slab(const KernelParams* kps, int n, int end, hipStream_
 // count < 0: only set the kernel attributes
 hipError_t launch_tent_curved(const KernelParams& kp, const CurvedParams& cp, int64_t first, int64_t count,
                               hipStream_t s);
-size_t tent_curved_lds_bytes(int p, int max_patch);
+// geo: with the patch elements' geometry blocks staged in LDS
+size_t tent_curved_lds_bytes(int p, int max_patch, bool geo);
 // slab bookkeeping on the device (graph-safe: kernels, no memsets)
 hipError_t launch_slab_reset(const KernelParams& kp, double t0, double height, hipStream_t s);
 hipError_t launch_slab_begin(const KernelParams& kp, hipStream_t s);

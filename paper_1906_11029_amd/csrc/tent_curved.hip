@@ -23,7 +23,13 @@
 namespace mtp {
 namespace {
 
+// 4 waves per tent (one workgroup each); a layer's few hundred curved tents are resident at
+// once.  The kernel is bound by LDS traffic (the phases re-read the point values and tables
+// per output node), not by the lanes per tent: 8 or 16 waves per tent run no faster.
 constexpr int CBLOCK = 256;
+// the long reductions (over the volume points) run on teams of TEAM consecutive lanes, each
+// summing every TEAM-th point, combined by lane exchanges
+constexpr int TEAM = 4;
 
 template <int P>
 struct CShape {
@@ -35,12 +41,29 @@ struct CShape {
   // eps, mu, the three vertex times) and ints (element, k, zone, 2 x (face, neighbour, code))
   static constexpr int DBL = 4 * NC * NP + NQ * NC + 2 * NFQ * NC + 5;
   static constexpr int INT = 9;
+  // reference tables (V, Gr, Lam, Vf, Lamf) and the geometry block of one zone element
+  // (Q, Minv, face data), both staged in LDS
+  static constexpr int REF = NQ * NP * 3 + NQ * 3 + 3 * NFQ * (NP + 3);
+  static constexpr int PER = NQ * 5 + NP * NP + 3 * NFQ * 3;
 };
+
+template <int P>
+size_t lds_bytes(int max_patch, bool geo) {
+  using CS = CShape<P>;
+  return (size_t)max_patch * ((size_t)CS::DBL * 8 + (size_t)CS::INT * 4) + 8 + (size_t)CS::REF * 8 +
+         (geo ? (size_t)max_patch * CS::PER * 8 : 0);
+}
+
+__device__ __forceinline__ double team_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  return v;
+}
 
 template <int P>
 __global__ void __launch_bounds__(CBLOCK) tent_curved_kernel(KernelParams kp, CurvedParams cp, int64_t first) {
   using CS = CShape<P>;
-  constexpr int NP = CS::NP, NQ = CS::NQ, NFQ = CS::NFQ, NC = CS::NC;
+  constexpr int NP = CS::NP, NQ = CS::NQ, NFQ = CS::NFQ, NC = CS::NC, PER = CS::PER;
   extern __shared__ double lds[];
   const int tid = threadIdx.x;
   const int64_t t = first + blockIdx.x;
@@ -66,17 +89,24 @@ __global__ void __launch_bounds__(CBLOCK) tent_curved_kernel(KernelParams kp, Cu
   int* sFf = sZ + MT;                        // [e][2]  the two local faces containing V
   int* sNb = sFf + MT * 2;                   // [e][2]  patch index of the neighbour, or -1 - kind
   int* sNc = sNb + MT * 2;                   // [e][2]  neighbour face | reversed << 2
+  // reference tables, then (if the patch fits) the geometry blocks of its elements
+  double* sRef = reinterpret_cast<double*>(sNc + MT * 2 + (MT & 1));   // 8-byte aligned
+  double* sGeo = sRef + CS::REF;
 
-  const double* V_ = cp.ref;                                 // [q][a]
+  const double* V_ = sRef;                                   // [q][a]
   const double* Gr = V_ + NQ * NP;                           // [q][a][l]
   const double* Lam = Gr + NQ * NP * 2;                      // [q][k]
   const double* Vf = Lam + NQ * 3;                           // [f][q][a]
   const double* Lamf = Vf + 3 * NFQ * NP;                    // [f][q][k]
-  constexpr int PER = NQ * 5 + NP * NP + 3 * NFQ * 3;
+  // geometry block of patch element e: Q [q][5], Minv [b][a], face data [f][q][3]
+  auto geo_of = [&](int e) -> const double* {
+    return cp.geo_lds ? sGeo + (size_t)e * PER : cp.geo + (size_t)sZ[e] * PER;
+  };
   // gradhat lambdahat_k: (-1, -1), (1, 0), (0, 1)
   auto hat = [](int k, int l) -> double { return k == 0 ? -1.0 : (k == l + 1 ? 1.0 : 0.0); };
 
   // ---- patch set-up and gather
+  for (int i = tid; i < CS::REF; i += CBLOCK) sRef[i] = cp.ref[i];
   for (int e = tid; e < nT; e += CBLOCK) {
     const int el = kp.patch_elem[p0 + e];
     const int k = kp.patch_info[(size_t)(p0 + e) * 3];
@@ -90,6 +120,12 @@ __global__ void __launch_bounds__(CBLOCK) tent_curved_kernel(KernelParams kp, Cu
   for (int i = tid; i < nT * NC * NP; i += CBLOCK) {
     const int e = i / (NC * NP), r = i - e * NC * NP;
     sS[i] = kp.W[(size_t)kp.patch_elem[p0 + e] * NC * NP + r];
+  }
+  if (cp.geo_lds) {
+    for (int i = tid; i < nT * PER; i += CBLOCK) {
+      const int e = i / PER, r = i - e * PER;
+      sGeo[i] = cp.geo[(size_t)cp.zone[kp.patch_elem[p0 + e]] * PER + r];
+    }
   }
   __syncthreads();
   for (int e = tid; e < nT; e += CBLOCK) {
@@ -141,21 +177,28 @@ __global__ void __launch_bounds__(CBLOCK) tent_curved_kernel(KernelParams kp, Cu
   };
   // sR = V^T sQ (the weights are already in sQ), then dst = Minv sR (+ scale * into dst)
   auto project = [&](double* dst, bool add, double scale) {
-    for (int i = tid; i < nT * NP; i += CBLOCK) {
-      const int e = i / NP, a = i - e * NP;
-      double v[NC] = {0.0, 0.0, 0.0};
-      for (int q = 0; q < NQ; ++q) {
-        const double ph = V_[q * NP + a];
+    for (int base = 0; base < nT * NP; base += CBLOCK / TEAM) {
+      const int i = base + tid / TEAM, part = tid % TEAM;
+      if (i < nT * NP) {   // uniform over the team
+        const int e = i / NP, a = i - e * NP;
+        double v[NC] = {0.0, 0.0, 0.0};
+        for (int q = part; q < NQ; q += TEAM) {
+          const double ph = V_[q * NP + a];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) v[c] = fma(ph, sQ[(e * NQ + q) * NC + c], v[c]);
+          for (int c = 0; c < NC; ++c) v[c] = fma(ph, sQ[(e * NQ + q) * NC + c], v[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = team_sum(v[c]);
+        if (part == 0) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) sR[(e * NC + c) * NP + a] = v[c];
+        }
       }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) sR[(e * NC + c) * NP + a] = v[c];
     }
     __syncthreads();
     for (int i = tid; i < nT * NP; i += CBLOCK) {
       const int e = i / NP, b = i - e * NP;
-      const double* Mi = cp.geo + (size_t)sZ[e] * PER + NQ * 5 + b * NP;
+      const double* Mi = geo_of(e) + NQ * 5 + b * NP;
       double v[NC] = {0.0, 0.0, 0.0};
       for (int a = 0; a < NP; ++a) {
 #pragma unroll
@@ -175,7 +218,7 @@ __global__ void __launch_bounds__(CBLOCK) tent_curved_kernel(KernelParams kp, Cu
     __syncthreads();
     for (int i = tid; i < nT * NQ; i += CBLOCK) {
       const int e = i / NQ, q = i - e * NQ;
-      const double* Q = cp.geo + (size_t)sZ[e] * PER + q * 5;
+      const double* Q = geo_of(e) + q * 5;
       double b[2], w[NC], u[NC];
       front_grad(e, q, th, Q, b);
 #pragma unroll
@@ -199,7 +242,7 @@ __global__ void __launch_bounds__(CBLOCK) tent_curved_kernel(KernelParams kp, Cu
       for (int i2 = tid; i2 < nT * 2 * NFQ; i2 += CBLOCK) {
         const int e = i2 / (2 * NFQ), r = i2 - e * 2 * NFQ, s = r / NFQ, q = r - s * NFQ;
         const int f = sFf[e * 2 + s], pe = sNb[e * 2 + s], code = sNc[e * 2 + s];
-        const double* Fq = cp.geo + (size_t)sZ[e] * PER + NQ * 5 + NP * NP + (f * NFQ + q) * 3;
+        const double* Fq = geo_of(e) + NQ * 5 + NP * NP + (f * NFQ + q) * 3;
         double um[NC] = {0.0, 0.0, 0.0}, up[NC] = {0.0, 0.0, 0.0}, G[NC];
         for (int a = 0; a < NP; ++a) {
           const double ph = Vf[(f * NFQ + q) * NP + a];
@@ -230,37 +273,42 @@ __global__ void __launch_bounds__(CBLOCK) tent_curved_kernel(KernelParams kp, Cu
       }
       __syncthreads();
       // volume and lift into sR
-      for (int i2 = tid; i2 < nT * NP; i2 += CBLOCK) {
-        const int e = i2 / NP, b = i2 - e * NP;
-        const double* Qe = cp.geo + (size_t)sZ[e] * PER;
-        const int k = sK[e];
-        double R[NC] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < NQ; ++q) {
-          const double* Q = Qe + q * 5;
-          const double gl0 = Gr[(q * NP + b) * 2], gl1 = Gr[(q * NP + b) * 2 + 1];
-          const double g[2] = {Q[1] * gl0 + Q[3] * gl1, Q[2] * gl0 + Q[4] * gl1};   // grad phi_b
-          double AU[NC];
-          applyA<2>(g, &sQ[(e * NQ + q) * NC], AU);
-          const double w = H * Q[0] * Lam[q * 3 + k];
+      for (int base = 0; base < nT * NP; base += CBLOCK / TEAM) {
+        const int i2 = base + tid / TEAM, part = tid % TEAM;
+        if (i2 < nT * NP) {   // uniform over the team
+          const int e = i2 / NP, b = i2 - e * NP;
+          const double* Qe = geo_of(e);
+          const int k = sK[e];
+          double R[NC] = {0.0, 0.0, 0.0};
+          for (int q = part; q < NQ; q += TEAM) {
+            const double* Q = Qe + q * 5;
+            const double gl0 = Gr[(q * NP + b) * 2], gl1 = Gr[(q * NP + b) * 2 + 1];
+            const double g[2] = {Q[1] * gl0 + Q[3] * gl1, Q[2] * gl0 + Q[4] * gl1};   // grad phi_b
+            double AU[NC];
+            applyA<2>(g, &sQ[(e * NQ + q) * NC], AU);
+            const double w = H * Q[0] * Lam[q * 3 + k];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) R[c] = fma(w, AU[c], R[c]);
-        }
-        for (int s = 0; s < 2; ++s) {
-          const int f = sFf[e * 2 + s];
-          for (int q = 0; q < NFQ; ++q) {
-            const double ph = Vf[(f * NFQ + q) * NP + b];
+            for (int c = 0; c < NC; ++c) R[c] = fma(w, AU[c], R[c]);
+          }
+          for (int r = part; r < 2 * NFQ; r += TEAM) {
+            const int s = r / NFQ, q = r - s * NFQ;
+            const double ph = Vf[(sFf[e * 2 + s] * NFQ + q) * NP + b];
 #pragma unroll
             for (int c = 0; c < NC; ++c) R[c] = fma(-ph, sFx[((e * 2 + s) * NFQ + q) * NC + c], R[c]);
           }
-        }
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sR[(e * NC + c) * NP + b] = R[c];
+          for (int c = 0; c < NC; ++c) R[c] = team_sum(R[c]);
+          if (part == 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sR[(e * NC + c) * NP + b] = R[c];
+          }
+        }
       }
       __syncthreads();
       // ---- W_n = Minv R, Taylor sum
       for (int i2 = tid; i2 < nT * NP; i2 += CBLOCK) {
         const int e = i2 / NP, b = i2 - e * NP;
-        const double* Mi = cp.geo + (size_t)sZ[e] * PER + NQ * 5 + b * NP;
+        const double* Mi = geo_of(e) + NQ * 5 + b * NP;
         double v[NC] = {0.0, 0.0, 0.0};
         for (int a = 0; a < NP; ++a) {
 #pragma unroll
@@ -277,7 +325,7 @@ __global__ void __launch_bounds__(CBLOCK) tent_curved_kernel(KernelParams kp, Cu
         // W_n + n Minv int phi A(b') U, then the recovery at th
         for (int i2 = tid; i2 < nT * NQ; i2 += CBLOCK) {
           const int e = i2 / NQ, q = i2 - e * NQ;
-          const double* Q = cp.geo + (size_t)sZ[e] * PER + q * 5;
+          const double* Q = geo_of(e) + q * 5;
           const int k = sK[e];
           const double bp[2] = {H * (Q[1] * hat(k, 0) + Q[3] * hat(k, 1)),
                                 H * (Q[2] * hat(k, 0) + Q[4] * hat(k, 1))};
@@ -316,13 +364,12 @@ hipError_t launch_p(const KernelParams& kp, const CurvedParams& cp, int64_t firs
 
 }  // namespace
 
-size_t tent_curved_lds_bytes(int p, int max_patch) {
-  auto bytes = [&](int dbl, int in) { return (size_t)max_patch * ((size_t)dbl * 8 + (size_t)in * 4); };
+size_t tent_curved_lds_bytes(int p, int max_patch, bool geo) {
   switch (p) {
-    case 1: return bytes(CShape<1>::DBL, CShape<1>::INT);
-    case 2: return bytes(CShape<2>::DBL, CShape<2>::INT);
-    case 3: return bytes(CShape<3>::DBL, CShape<3>::INT);
-    case 4: return bytes(CShape<4>::DBL, CShape<4>::INT);
+    case 1: return lds_bytes<1>(max_patch, geo);
+    case 2: return lds_bytes<2>(max_patch, geo);
+    case 3: return lds_bytes<3>(max_patch, geo);
+    case 4: return lds_bytes<4>(max_patch, geo);
     default: return 0;
   }
 }
