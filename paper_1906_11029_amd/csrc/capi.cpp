@@ -37,10 +37,11 @@ struct Layout {
 struct Offsets {
   size_t W, tau, stage, grad_lam, cells, eps, mu, coords, pptr, pelem, pinfo, fptr, face, tv, tt, S, L,
       fnode, fswap, perm, mi, err, slab, dag_indeg, dag_indeg0, dag_sptr, dag_succ, dag_queue, dag_ctl,
-      cref, cgeo, cnbr, czone, total;
+      cref, cgeo, cnbr, czone, opg, total;
 };
 
-static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
+// opg_bytes: the matrix-core kernel's operator block when it stays in device memory (0 if not)
+static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc, size_t opg_bytes) {
   Layout L;
   Offsets o;
   const int d = m.d;
@@ -82,6 +83,7 @@ static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc) {
   o.cgeo = L.add(cur ? sizeof(double) * cp.n_geo() : 0);
   o.cnbr = L.add(cur ? sizeof(int32_t) * cp.zone_elem.size() * 6 : 0);
   o.czone = L.add(cur ? sizeof(int32_t) * m.ne : 0);
+  o.opg = L.add(opg_bytes);
   o.total = L.off;
   return o;
 }
@@ -427,13 +429,19 @@ static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
   return 0;
 }
 
+// Bytes of the operator block that the solver's matrix-core kernel keeps in device memory
+// (P4 patches of more than 24 tets), 0 when the kernel stages it in LDS.
+static size_t opg_bytes(const Mesh& m, int p, int kernel) {
+  return kernel == 0 ? 0 : tent_mfma_opg_bytes(m.d, p, m.max_patch, kernel == 2, m.system);
+}
+
 mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q, int32_t m,
                                      int32_t precision, size_t* bytes) {
   MTP_TRY
   require(mesh && tents && bytes, MTP_ERR_ARG, "null pointer");
-  check_config(mesh->m, p, q, m, precision);
+  const int kernel = check_config(mesh->m, p, q, m, precision);
   RefElem R = build_refelem(mesh->m.d, p);
-  *bytes = plan(mesh->m, tents->t, R, ncomp(mesh->m)).total;
+  *bytes = plan(mesh->m, tents->t, R, ncomp(mesh->m), opg_bytes(mesh->m, p, kernel)).total;
   MTP_CATCH
 }
 
@@ -524,7 +532,7 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     s->q = q;
     s->m = m;
     s->nc = ncomp(mesh->m);
-    s->off = plan(s->mesh, s->tents, s->ref, s->nc);
+    s->off = plan(s->mesh, s->tents, s->ref, s->nc, opg_bytes(s->mesh, p, kernel));
     require(bytes >= s->off.total, MTP_ERR_ARG, "workspace too small");
     s->ws = static_cast<char*>(d_workspace);
     s->stream = static_cast<hipStream_t>(hip_stream);
@@ -618,6 +626,10 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
       kp.dag_grid = s->kernel == 0 ? 0 : tent_dag_grid(kp, s->kernel == 2);
     }
     check_hip(prepare_tent_kernel(kp, s->kernel), "tent kernel attributes");
+    if (opg_bytes(s->mesh, p, kernel) > 0) {   // the operator block, written once
+      kp.opg = reinterpret_cast<double*>(s->ws + s->off.opg);
+      check_hip(stage_tent_operator_mfma(kp, s->kernel == 2, s->stream), "operator staging");
+    }
     if (s->curved) {
       // tables of the curved-element path; the persistent schedule does not cover it
       std::vector<double> cref, cgeo;

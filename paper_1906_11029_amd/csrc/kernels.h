@@ -34,6 +34,9 @@ struct KernelParams {
   const int32_t* fswap;    // nf
   // state
   double* W;               // ne*nc*np  [e][c][node]
+  // matrix-core kernels whose operator block does not fit the LDS beside the tent region:
+  // the block in device memory (null otherwise)
+  double* opg;
   double* tau;             // nv
   int32_t* err;            // device error flags
   // tents of the launch
@@ -119,6 +122,10 @@ bool tent_kernel_supported(int d, int p);
 hipError_t launch_tent_layer(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s);
 // matrix-core variant: fp32 = 0 contracts in FP64, fp32 = 1 in FP32 (mixed path)
 size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32, int system = 0);
+// bytes of the operator block a matrix-core solver keeps in device memory (0: in LDS), and
+// the launch that writes it to kp.opg once
+size_t tent_mfma_opg_bytes(int d, int p, int max_patch, int fp32, int system);
+hipError_t stage_tent_operator_mfma(const KernelParams& kp, int fp32, hipStream_t s);
 hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t count, int fp32, hipStream_t s);
 // persistent schedule: reset the DAG state for one slab, then run every tent of the slab in
 // one launch of kp.dag_grid workgroups (grid < 0: only set the kernel attributes)

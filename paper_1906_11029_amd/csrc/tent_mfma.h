@@ -159,6 +159,13 @@ struct MShape {
   static constexpr int WAVES = BLOCK / 64;
   static constexpr int TILES_PER_WAVE = (MTF * NTILE_MAX + WAVES - 1) / WAVES;
   static constexpr int MAXPAIR = (NTMAX * NP + BLOCK - 1) / BLOCK;
+  // P4 patches of more than 24 tets (up to 28 product tiles on 8 waves): each wave takes whole
+  // column blocks and writes their R at once, so only one column block's row tiles hold
+  // accumulators (4 tiles per wave do not fit the registers), and the Taylor sum of each
+  // (element, node) pair stays in the tent's own entries of W (the pair belongs to one
+  // thread for the whole tent) instead of registers
+  static constexpr bool COLB = D == 3 && P == 4 && NTMAX > 24;
+  static constexpr bool ACCG = COLB;
 };
 
 // LDS layout, identical for both variants (state, fluxes and operators stored in FP64; the
@@ -180,8 +187,18 @@ struct MLds {
       (size_t)NTMAX * (SH::NV * D + D + 2) + 3 * (size_t)NTMAX * D + 4 * (size_t)NTMAX;
   static constexpr size_t tent_ints = (size_t)NTMAX * (2 + D) + (size_t)NTMAX * D;
   static constexpr size_t common = u_elems + f_elems + geo_doubles + (tent_ints + 1) / 2;   // doubles
-  static constexpr size_t bytes = (op_block + common) * 8;
+  // An operator block that does not fit beside the tent region (P4 patches of more than 24
+  // tets) stays in device memory, written once per solver (KernelParams::opg); the products
+  // then read their A operand through the caches.
+  static constexpr size_t LDS_LIMIT = 160 * 1024;
+  static constexpr bool OPG = (op_block + common) * 8 > LDS_LIMIT && common * 8 <= LDS_LIMIT;
+  static constexpr size_t bytes = ((OPG ? 0 : op_block) + common) * 8;
 };
+
+// The capacity classes of the patch size: 8, 24, and a large class of 48 tets, or 36 for
+// P4 in 3D (the largest whose tent region fits the LDS once the operator block is moved out).
+template <int D, int P>
+__host__ __device__ constexpr int big_class() { return (D == 3 && P == 4) ? 36 : 48; }
 
 // LDS pointers of one degree's operator block and of the tent region
 struct TentLds {
@@ -339,11 +356,10 @@ __device__ __forceinline__ void tile_product(const double* sOp, const float* sOp
     accm[ts] = typename MM::mini_t{};
   }
   auto tile_of = [&](int ts) -> int { return tiles[ts]; };
-  // K groups [G0, G1) of tile ts: the volume part (U only) or the lift part (F)
-  auto part = [&](int ts, auto lift) {
+  // K groups [G0, G1) of `tile` into (acc, accmini): the volume part (U only) or the lift part (F)
+  auto part = [&](int tile, typename MM::acc_t& acc, typename MM::mini_t& accmini, auto lift) {
     constexpr bool LIFT = decltype(lift)::value;
     constexpr int G0 = LIFT ? NB : 0, G1 = LIFT ? NG : NB;
-    const int tile = tile_of(ts);
     if (tile < MTF * ntiles) {
       const int mr = tile / ntiles, nt = tile - mr * ntiles;
       const int mt = MTF - 1 - mr;
@@ -429,13 +445,13 @@ __device__ __forceinline__ void tile_product(const double* sOp, const float* sOp
               TM b = cf[0][l] * v[0];
 #pragma unroll
               for (int k = 1; k < NT; ++k) b += cf[k][l] * v[k];
-              accs[ts] = MM::mma(a[l], b, accs[ts]);
-              if constexpr (WM) accm[ts] = MM::mini(am[l], b, accm[ts]);
+              acc = MM::mma(a[l], b, acc);
+              if constexpr (WM) accmini = MM::mini(am[l], b, accmini);
             }
           } else {
             const TM b = fm * (TM)x[0];
-            accs[ts] = MM::mma(a[0], b, accs[ts]);
-            if constexpr (WM) accm[ts] = MM::mini(am[0], b, accm[ts]);
+            acc = MM::mma(a[0], b, acc);
+            if constexpr (WM) accmini = MM::mini(am[0], b, accmini);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -446,26 +462,50 @@ __device__ __forceinline__ void tile_product(const double* sOp, const float* sOp
         kloop(std::false_type{});
     }
   };
-  // every wave runs the volume part of all its tiles first: it needs U only, so it may
-  // overlap the end of the face-flux phase (the caller does not synchronise after it)
-#pragma unroll
-  for (int ts = 0; ts < TPW; ++ts) part(ts, std::false_type{});
-  __syncthreads();   // F is complete
-#pragma unroll
-  for (int ts = 0; ts < TPW; ++ts) part(ts, std::true_type{});
-  __syncthreads();   // every wave is done reading F and U
-#pragma unroll
-  for (int ts = 0; ts < TPW; ++ts) {
-    const int tile = tile_of(ts);
+  // R of `tile` from its accumulators into sFR (FP64)
+  auto write_r = [&](int tile, const typename MM::acc_t& acc, const typename MM::mini_t& accmini) {
     if (tile < MTF * ntiles) {
       const int mr = tile / ntiles, nt = tile - mr * ntiles;
       const int mt = MTF - 1 - mr;
       const int col = nt * 16 + (lane & 15);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sFR[(mt * 16 + MM::row(lane, r)) * RS + col] = (double)accs[ts][r];
-      if (MINI && mr == 0) sFR[(MTF * 16 + (lane >> 4)) * RS + col] = MM::mini_out(accm[ts], lane);
+      for (int r = 0; r < 4; ++r) sFR[(mt * 16 + MM::row(lane, r)) * RS + col] = (double)acc[r];
+      if (MINI && mr == 0) sFR[(MTF * 16 + (lane >> 4)) * RS + col] = MM::mini_out(accmini, lane);
     }
+  };
+  if constexpr (SH::COLB) {
+    // whole column blocks per wave: the volume and lift parts of the block's row tiles, then
+    // its R, which overwrites F only in the block's own columns (read by this wave alone; a
+    // wave's LDS operations complete in order)
+    __syncthreads();   // F is complete
+    for (int nt = wave; nt < ntiles; nt += WAVES) {
+      typename MM::acc_t ac[MTF];
+      typename MM::mini_t am[MTF];
+#pragma unroll
+      for (int mr = 0; mr < MTF; ++mr) {
+        ac[mr] = typename MM::acc_t{0, 0, 0, 0};
+        am[mr] = typename MM::mini_t{};
+      }
+#pragma unroll
+      for (int mr = 0; mr < MTF; ++mr) part(mr * ntiles + nt, ac[mr], am[mr], std::false_type{});
+#pragma unroll
+      for (int mr = 0; mr < MTF; ++mr) part(mr * ntiles + nt, ac[mr], am[mr], std::true_type{});
+#pragma unroll
+      for (int mr = 0; mr < MTF; ++mr) write_r(mr * ntiles + nt, ac[mr], am[mr]);
+    }
+    __syncthreads();
+    return;
   }
+  // every wave runs the volume part of all its tiles first: it needs U only, so it may
+  // overlap the end of the face-flux phase (the caller does not synchronise after it)
+#pragma unroll
+  for (int ts = 0; ts < TPW; ++ts) part(tile_of(ts), accs[ts], accm[ts], std::false_type{});
+  __syncthreads();   // F is complete
+#pragma unroll
+  for (int ts = 0; ts < TPW; ++ts) part(tile_of(ts), accs[ts], accm[ts], std::true_type{});
+  __syncthreads();   // every wave is done reading F and U
+#pragma unroll
+  for (int ts = 0; ts < TPW; ++ts) write_r(tile_of(ts), accs[ts], accm[ts]);
   __syncthreads();
 }
 
@@ -701,7 +741,14 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
 
   // gather W (FP64, registers) and U_{0,0} = K(b_0)^{-1} W (closed form in FP64)
   const int npairs = nT * NP;
-  double acc[MAXPAIR][NC];
+  constexpr bool ACCG = SH::ACCG;
+  double acc[MAXPAIR][NC];   // the Taylor sum of each owned pair (registers)
+  double* wp[MAXPAIR];       // ACCG: the pair's entries of W (stride NP per component)
+  // Taylor sum of owned pair r, component c
+  auto A = [&](int r, int c) -> double& {
+    if constexpr (ACCG) return wp[r][c * NP];
+    else return acc[r][c];
+  };
   bool ok = true;
 #pragma unroll
   for (int r = 0; r < MAXPAIR; ++r) {
@@ -709,11 +756,18 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
     if (P_ < npairs) {
       const int e = P_ / NP, b = P_ - e * NP;
       const int nold = kp.perm[sK[e] * NP + b];
-      const double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+      double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+      double w0[NC];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[r][c] = Wp[c * NP];
+      for (int c = 0; c < NC; ++c) w0[c] = Wp[c * NP];
+      if constexpr (ACCG) {
+        wp[r] = Wp;
+      } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] = w0[c];
+      }
       double u[NC];
-      ok &= PH::inv(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], acc[r], u);
+      ok &= PH::inv(&sBb[e * D], sEM[2 * e], sEM[2 * e + 1], w0, u);
 #pragma unroll
       for (int c = 0; c < NC; ++c) sU[b * RS + e * NC + c] = u[c];
     }
@@ -837,10 +891,10 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
               const double k = H * sFR[b * RS + e * NC + c];
               ks[r][c] = (s == 0) ? k : fma(wk, k, ks[r][c]);
               if (s < 3) {
-                wst[c] = fma(a, k, acc[r][c]);
+                wst[c] = fma(a, k, A(r, c));
               } else {
-                acc[r][c] = fma(invm / 6.0, ks[r][c], acc[r][c]);
-                wst[c] = acc[r][c];
+                A(r, c) = fma(invm / 6.0, ks[r][c], A(r, c));
+                wst[c] = A(r, c);
               }
             }
             if (s < 3 || i + 1 < kp.m) {
@@ -881,7 +935,7 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
 #pragma unroll
           for (int c = 0; c < NC; ++c) {
             Y[c] = H * sFR[b * RS + e * NC + c];
-            acc[r][c] = fma(coef, Y[c], acc[r][c]);
+            A(r, c) = fma(coef, Y[c], A(r, c));
           }
           const double* gv = &sGL[(e * NV + 0) * D];
           double un[NC];
@@ -901,11 +955,13 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
             PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[((i & 1) * NTMAX + e) * 2], rhs, un);
             write = true;
           } else if (i + 1 < kp.m) {
-            double bi[D];
+            double bi[D], wsum[NC];
             const double th1 = (i + 1) * invm;
 #pragma unroll
             for (int x = 0; x < D; ++x) bi[x] = sBb[e * D + x] + th1 * (H * gv[x]);
-            PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[(((i + 1) & 1) * NTMAX + e) * 2], acc[r], un);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) wsum[c] = A(r, c);
+            PH::inv_apply(bi, sEM[2 * e], sEM[2 * e + 1], &sFac[(((i + 1) & 1) * NTMAX + e) * 2], wsum, un);
             write = true;
           }
           if (write) {
@@ -919,16 +975,18 @@ __device__ __forceinline__ void tent_run(const KernelParams& kp, int64_t t, cons
     }
   }
 
-  // scatter the tent top
+  // scatter the tent top (ACCG: the sum is already in W)
+  if constexpr (!ACCG) {
 #pragma unroll
-  for (int r = 0; r < MAXPAIR; ++r) {
-    const int P_ = tid + r * BLOCK;
-    if (P_ < npairs) {
-      const int e = P_ / NP, b = P_ - e * NP;
-      const int nold = kp.perm[sK[e] * NP + b];
-      double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
+    for (int r = 0; r < MAXPAIR; ++r) {
+      const int P_ = tid + r * BLOCK;
+      if (P_ < npairs) {
+        const int e = P_ / NP, b = P_ - e * NP;
+        const int nold = kp.perm[sK[e] * NP + b];
+        double* Wp = kp.W + (size_t)sElem[e] * NC * NP + nold;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) Wp[c * NP] = acc[r][c];
+        for (int c = 0; c < NC; ++c) Wp[c * NP] = acc[r][c];
+      }
     }
   }
   if (!ok) kp.err[0] = ERRF_CAUSALITY;
@@ -948,11 +1006,14 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   using SH = MShape<D, P, NTMAX, SYS>;
   using LD = MLds<D, P, T, NTMAX, SYS>;
   extern __shared__ double lds_d[];
-  const TentLds L = tent_lds<D, P, T, NTMAX, SYS>(lds_d, lds_d + LD::op_block);
+  // the operator block in LDS (staged here), or in device memory (staged once per solver;
+  // all solvers of a batch share dimension and degree, hence its contents)
+  const TentLds L = LD::OPG ? tent_lds<D, P, T, NTMAX, SYS>(kp0.opg, lds_d)
+                            : tent_lds<D, P, T, NTMAX, SYS>(lds_d, lds_d + LD::op_block);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar registers)
-  stage_operator<D, P, T, NTMAX, SYS>(kp0, L, tid);
+  if constexpr (!LD::OPG) stage_operator<D, P, T, NTMAX, SYS>(kp0, L, tid);
   // padding rows of U and F are read by the product (times zero): keep them finite
   for (int i = tid; i < (SH::NPK - SH::NP) * SH::RS; i += SH::BLOCK) L.sU[SH::NP * SH::RS + i] = 0.0;
   for (int i = tid; i < (SH::FROWS - SH::KF) * SH::RS; i += SH::BLOCK) L.sFR[SH::KF * SH::RS + i] = 0.0;
@@ -965,6 +1026,14 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
     tent_run<D, P, T, NTMAX, RK4, SYS>(kp, t, L, tid, lane, wave);
     sched.done(kp, t, tid);
   }
+}
+
+// One workgroup writes the operator block of a class whose block stays in device memory
+// (kp.opg, MLds::op_block doubles) in the layout the products read.
+template <int D, int P, typename T, int NTMAX, int SYS>
+__global__ void __launch_bounds__(tent_block<D>()) stage_operator_kernel(KernelParams kp) {
+  const TentLds L = tent_lds<D, P, T, NTMAX, SYS>(kp.opg, kp.opg);   // only the operator block is written
+  stage_operator<D, P, T, NTMAX, SYS>(kp, L, threadIdx.x);
 }
 
 template <int D, int P, typename T, int NTMAX, int WPE, bool RK4 = false, int SYS = 0>
@@ -1101,9 +1170,10 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
 
 template <int D, int P, typename T>
 hipError_t launch_mdp(const PersistentArgs& a, int max_patch, hipStream_t s, int* resident) {
+  constexpr int NB = big_class<D, P>();
   if (max_patch <= 8) return launch_md<D, P, T, 8>(a, s, resident);
   if (max_patch <= 24) return launch_md<D, P, T, 24>(a, s, resident);
-  if (max_patch <= 48) return launch_md<D, P, T, 48>(a, s, resident);
+  if (max_patch <= NB) return launch_md<D, P, T, NB>(a, s, resident);
   return hipErrorInvalidValue;
 }
 
@@ -1123,31 +1193,77 @@ hipError_t launch_mb(const BatchLaunch& bl, hipStream_t s) {
 
 template <int D, int P, typename T>
 hipError_t launch_mbp(const BatchLaunch& bl, hipStream_t s) {
+  constexpr int NB = big_class<D, P>();
   if (bl.max_patch <= 8) return launch_mb<D, P, T, 8>(bl, s);
   if (bl.max_patch <= 24) return launch_mb<D, P, T, 24>(bl, s);
-  if (bl.max_patch <= 48) return launch_mb<D, P, T, 48>(bl, s);
+  if (bl.max_patch <= NB) return launch_mb<D, P, T, NB>(bl, s);
   return hipErrorInvalidValue;
 }
 
 template <int D, int P, typename T>
 hipError_t launch_mp(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
+  constexpr int NB = big_class<D, P>();
   if (kp.max_patch <= 8) return launch_m<D, P, T, 8>(kp, first, count, s);
   if (kp.max_patch <= 24) return launch_m<D, P, T, 24>(kp, first, count, s);
-  if (kp.max_patch <= 48) return launch_m<D, P, T, 48>(kp, first, count, s);
+  if (kp.max_patch <= NB) return launch_m<D, P, T, NB>(kp, first, count, s);
+  return hipErrorInvalidValue;
+}
+
+// Device-memory operator block of the class kp.max_patch falls in: its size in bytes (0 if
+// the class stages the operator in LDS), and the launch that writes it to kp.opg.
+template <int D, int P, typename T, int NTMAX>
+size_t opg_m(int system) {
+  return system == 1 ? (MLds<D, P, T, NTMAX, 1>::OPG ? MLds<D, P, T, NTMAX, 1>::op_block * 8 : 0)
+                     : (MLds<D, P, T, NTMAX, 0>::OPG ? MLds<D, P, T, NTMAX, 0>::op_block * 8 : 0);
+}
+
+template <int D, int P, typename T>
+size_t opg_mp(int max_patch, int system) {
+  constexpr int NB = big_class<D, P>();
+  if (max_patch <= 8) return opg_m<D, P, T, 8>(system);
+  if (max_patch <= 24) return opg_m<D, P, T, 24>(system);
+  if (max_patch <= NB) return opg_m<D, P, T, NB>(system);
+  return 0;
+}
+
+template <int D, int P, typename T, int NTMAX>
+hipError_t stage_m(const KernelParams& kp, hipStream_t s) {
+  constexpr int BLOCK = MShape<D, P, NTMAX>::BLOCK;
+  if (kp.system == 1) {
+    if constexpr (MLds<D, P, T, NTMAX, 1>::OPG) {
+      hipLaunchKernelGGL((stage_operator_kernel<D, P, T, NTMAX, 1>), dim3(1), dim3(BLOCK), 0, s, kp);
+      return hipGetLastError();
+    }
+    return hipSuccess;
+  }
+  if constexpr (MLds<D, P, T, NTMAX, 0>::OPG) {
+    hipLaunchKernelGGL((stage_operator_kernel<D, P, T, NTMAX, 0>), dim3(1), dim3(BLOCK), 0, s, kp);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+template <int D, int P, typename T>
+hipError_t stage_mp(const KernelParams& kp, hipStream_t s) {
+  constexpr int NB = big_class<D, P>();
+  if (kp.max_patch <= 8) return stage_m<D, P, T, 8>(kp, s);
+  if (kp.max_patch <= 24) return stage_m<D, P, T, 24>(kp, s);
+  if (kp.max_patch <= NB) return stage_m<D, P, T, NB>(kp, s);
   return hipErrorInvalidValue;
 }
 
 template <int D, int P, typename T>
 size_t lds_mp(int max_patch, int system) {
+  constexpr int NB = big_class<D, P>();
   if (system == 1) {
     if (max_patch <= 8) return MLds<D, P, T, 8, 1>::bytes;
     if (max_patch <= 24) return MLds<D, P, T, 24, 1>::bytes;
-    if (max_patch <= 48) return MLds<D, P, T, 48, 1>::bytes;
+    if (max_patch <= NB) return MLds<D, P, T, NB, 1>::bytes;
     return (size_t)-1;
   }
   if (max_patch <= 8) return MLds<D, P, T, 8>::bytes;
   if (max_patch <= 24) return MLds<D, P, T, 24>::bytes;
-  if (max_patch <= 48) return MLds<D, P, T, 48>::bytes;
+  if (max_patch <= NB) return MLds<D, P, T, NB>::bytes;
   return (size_t)-1;
 }
 

@@ -93,9 +93,59 @@ size_t lds_t(int d, int p, int max_patch, int system) {
   return (size_t)-1;
 }
 
+template <typename T>
+size_t opg_t(int d, int p, int max_patch, int system) {
+  if (d == 2) {
+    switch (p) {
+      case 1: return opg_mp<2, 1, T>(max_patch, system);
+      case 2: return opg_mp<2, 2, T>(max_patch, system);
+      case 3: return opg_mp<2, 3, T>(max_patch, system);
+      case 4: return opg_mp<2, 4, T>(max_patch, system);
+      case 5: return opg_mp<2, 5, T>(max_patch, system);
+    }
+  } else {
+    switch (p) {
+      case 1: return opg_mp<3, 1, T>(max_patch, system);
+      case 2: return opg_mp<3, 2, T>(max_patch, system);
+      case 3: return opg_mp<3, 3, T>(max_patch, system);
+      case 4: return opg_mp<3, 4, T>(max_patch, system);
+    }
+  }
+  return 0;
+}
+
+template <typename T>
+hipError_t stage_t(const KernelParams& kp, hipStream_t s) {
+  if (kp.d == 2) {
+    switch (kp.p) {
+      case 1: return stage_mp<2, 1, T>(kp, s);
+      case 2: return stage_mp<2, 2, T>(kp, s);
+      case 3: return stage_mp<2, 3, T>(kp, s);
+      case 4: return stage_mp<2, 4, T>(kp, s);
+      case 5: return stage_mp<2, 5, T>(kp, s);
+    }
+  } else {
+    switch (kp.p) {
+      case 1: return stage_mp<3, 1, T>(kp, s);
+      case 2: return stage_mp<3, 2, T>(kp, s);
+      case 3: return stage_mp<3, 3, T>(kp, s);
+      case 4: return stage_mp<3, 4, T>(kp, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace mfk
 
 using namespace mfk;
+
+size_t tent_mfma_opg_bytes(int d, int p, int max_patch, int fp32, int system) {
+  return fp32 ? opg_t<float>(d, p, max_patch, system) : opg_t<double>(d, p, max_patch, system);
+}
+
+hipError_t stage_tent_operator_mfma(const KernelParams& kp, int fp32, hipStream_t s) {
+  return fp32 ? stage_t<float>(kp, s) : stage_t<double>(kp, s);
+}
 
 hipError_t launch_tent_dag_mfma(const KernelParams& kp, int fp32, hipStream_t s) {
   const PersistentArgs a{&kp, nullptr, nullptr};

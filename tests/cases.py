@@ -41,6 +41,14 @@ CASES = {
                               eps_split=True),
 }
 
+# P4 on the jittered Delaunay cube, whose vertex patches hold up to 36 tets (the P4 kernels'
+# 36-tet class, with the operator block in device memory)
+LARGE_P4_CASES = {
+    "delaunay3d_p4": dict(mesh=("delaunay", 3), p=4, q=5, m=8, T=0.05, kind=PEC, exact="pec_3d"),
+    "delaunay3d_p4_pmc_eps": dict(mesh=("delaunay", 3), p=4, q=5, m=8, T=0.05, kind=PMC, exact="pec_3d",
+                                  eps_split=True),
+}
+
 # the classical RK4 variant (method="rk4"): same inputs, RK4 on the tent ODE
 RK4_CASES = {
     "te_planewave_p2_rk4": dict(mesh=("square", 8), p=2, q=3, m=4, T=0.5, kind=DATA, exact="pw_te", method="rk4"),
@@ -151,7 +159,7 @@ def planewave_params(ex, dim):
 
 def setup(name):
     c = dict(CASES.get(name) or RK4_CASES.get(name) or IMP_CASES.get(name) or CURVED_CASES.get(name)
-             or COLOUR_CASES.get(name) or AC_CASES[name])
+             or COLOUR_CASES.get(name) or LARGE_P4_CASES.get(name) or AC_CASES[name])
     c.setdefault("curved", False)
     c.setdefault("rule", "min_vertex")
     c.setdefault("system", "maxwell")

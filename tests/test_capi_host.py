@@ -193,3 +193,30 @@ def test_split_bf16_precision_is_reserved():
     with pytest.raises(mtp.MTPError) as e:
         mtp.mtp_solver_workspace_size(M.h, T.h, 2, 3, 4, mtp.MTP_BF16X3)
     assert e.value.code == -9
+
+
+def test_p4_patch_classes_accept_up_to_36_tets():
+    """P4 in 3D: patches of up to 36 tets run on the matrix-core kernels (FP64 and mixed; the
+    36-tet class keeps its operator block in device memory, which the workspace includes);
+    larger patches, and the vector-ALU kernel beyond its LDS, are refused."""
+    from cases import build_mesh
+    mm = build_mesh(("delaunay", 3))
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    assert M.info["max_patch"] == 36
+    T = mtp.Tents(M, 0.05, 0.5)
+    w64 = mtp.mtp_solver_workspace_size(M.h, T.h, 4, 5, 8, mtp.MTP_FP64)
+    wmx = mtp.mtp_solver_workspace_size(M.h, T.h, 4, 5, 8, mtp.MTP_MIXED_FP32)
+    assert wmx > w64 > 0          # the mixed operator block adds its FP32 copy
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.mtp_solver_workspace_size(M.h, T.h, 4, 5, 8, mtp.MTP_FP64_VALU)
+    assert e.value.code == -9
+    big = meshes.graded_delaunay_cube(n=8, a=2.0 / 9.0, jitter=0.15, seed=11029)
+    Mb = mtp.Mesh(big["coords"], big["cells"])
+    assert Mb.info["max_patch"] > 36
+    Tb = mtp.Tents(Mb, 0.02, 0.5)
+    for prec in (mtp.MTP_FP64, mtp.MTP_MIXED_FP32):
+        with pytest.raises(mtp.MTPError) as e:
+            mtp.mtp_solver_workspace_size(Mb.h, Tb.h, 4, 5, 8, prec)
+        assert e.value.code == -9
+    # P3 keeps its 48-tet class
+    assert mtp.mtp_solver_workspace_size(Mb.h, Tb.h, 3, 4, 6, mtp.MTP_MIXED_FP32) > 0

@@ -14,7 +14,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
-from cases import CASES, DATA, planewave_params, setup  # noqa: E402
+from cases import CASES, DATA, LARGE_P4_CASES, planewave_params, setup  # noqa: E402
 from parity import assert_parity, rel  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -346,3 +346,39 @@ def test_batch_mixed_degrees_against_oracle(dim, precision, tol, schedule):
             assert np.array_equal(w, w1), nm
         else:
             assert np.abs(w - w1).max() <= (1e-13 if precision == 0 else 1e-9) * np.abs(w1).max(), nm
+
+
+@pytest.mark.parametrize("precision,tol", [(0, TOL), (1, MIXED_TOL)])
+@pytest.mark.parametrize("name", list(LARGE_P4_CASES))
+def test_large_p4_patches_against_oracle(name, precision, tol):
+    """P4 on the jittered Delaunay cube, whose vertex patches hold up to 36 tets: the 36-tet
+    class (operator block in device memory, column-block products, Taylor sums in W) against
+    the oracle, element by element: FP64 <= 1e-10, mixed <= 1e-6."""
+    print(f"[gpu parity] {name} precision {precision}", flush=True)
+    ref = fixture(name)
+    c, S, T = gpu_solver(name, precision)
+    assert S.mesh.info["max_patch"] > 24
+    assert S.kernel() == (1 if precision == 0 else 2)
+    ex = T.export()
+    for k in ("vertex", "t_top", "layer"):
+        assert np.array_equal(ex[k], ref[k]), f"tent list differs in {k}"
+    S.advance_to(c["slabs"] * c["T"])
+    assert_parity(S.get_state(), ref["w"], tol, f"{name} w")
+
+
+def test_large_p4_patches_persistent_schedule_and_batch():
+    """The 36-tet class under the persistent schedule (bit-identical to the layers) and in a
+    batch of both cases (against the oracle)."""
+    from paper_1906_11029_amd import mtp
+    names = list(LARGE_P4_CASES)
+    print("[gpu parity] large P4 patches: persistent schedule and batch", flush=True)
+    c, A, _ = gpu_solver(names[0])
+    _, B, _ = gpu_solver(names[0])
+    B.set_schedule(mtp.MTP_SCHEDULE_DAG)
+    A.advance_to(c["T"])
+    B.advance_to(c["T"])
+    assert np.array_equal(A.get_state(), B.get_state())
+    solvers = [gpu_solver(nm)[1] for nm in names]
+    mtp.Batch(solvers).advance(1)
+    for S, nm in zip(solvers, names):
+        assert_parity(S.get_state(), fixture(nm)["w"], TOL, f"batch {nm}")
