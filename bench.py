@@ -447,6 +447,97 @@ def curved2d(args):
     print(json.dumps(out), flush=True)
 
 
+def stream3d(args):
+    """A request stream of 3D PEC cavity solves, served by continuous batching: requests
+    (seed 5) on Kuhn cubes n ~ U{8..16} (3,072-24,576 tets), p ~ U{3, 4}, q = p + 1, m = 2p,
+    eps = 1, the Gaussian pulse of the graded workload (seed per request), final time
+    T ~ U[0.25, 1] in slabs of at most 0.25.  A calibration pass serves every request at once
+    (batched, mixed) to measure the capacity; the stream then arrives as a Poisson process at
+    0.7 of it.  Served in mixed precision with every solve in flight advancing one slab per
+    step in one batch (admission FIFO while the estimated device memory fits 90 % of the free
+    HBM), and beside it by the plain FP64 path one solve at a time on the same arrivals.
+    Latency = arrival to fields read out, set-up (mesh, pitching, solver) included."""
+    import torch
+
+    from mtp_inputs import fields, meshes
+    from paper_1906_11029_amd import mtp, serve
+    rng = np.random.default_rng(5)
+    specs = [dict(n=int(rng.integers(8, 17)), p=int(rng.integers(3, 5)), T=float(rng.uniform(0.25, 1.0)),
+                  seed=int(rng.integers(1 << 30))) for _ in range(args.stream_requests)]
+
+    class GpuExecutor:
+        def __init__(self, precision):
+            self.prec = precision
+            self.batch, self.members = None, ()
+
+        def footprint(self, req):   # state, stage copy and tables: ~ (2 W + 1) per node value + per-tet tables
+            sp = req.spec
+            ne = 6 * sp["n"] ** 3
+            npl = (sp["p"] + 1) * (sp["p"] + 2) * (sp["p"] + 3) // 6
+            return ne * npl * 6 * 8 * 3 + ne * 2048
+
+        def setup(self, req):
+            sp = req.spec
+            mm = meshes.cube_kuhn(sp["n"])
+            M = mtp.Mesh(mm["coords"], mm["cells"])
+            nslab = int(np.ceil(sp["T"] / 0.25))
+            T = mtp.Tents(M, sp["T"] / nslab, 0.5)
+            S = mtp.Solver(M, T, sp["p"], sp["p"] + 1, 2 * sp["p"], precision=self.prec)
+            S.set_fields(fields.GaussianPulse3D(seed=sp["seed"]).u(meshes.equispaced_nodes(mm, sp["p"]), 0.0), 0.0)
+            return {"rid": req.rid, "S": S, "T": sp["T"], "nslab": nslab, "dof": S.slab_dof_updates()[0] * nslab}
+
+        def slabs(self, h):
+            return h["nslab"]
+
+        def step(self, hs):
+            key = tuple(h["rid"] for h in hs)
+            if key != self.members:   # the set in flight changed: a new batch over it
+                self.batch = None
+                self.batch = mtp.Batch([h["S"] for h in hs])
+                self.members = key
+            self.batch.advance(1)
+
+        def run(self, h):
+            h["S"].advance_to(h["T"])
+
+        def finish(self, h):
+            u = h["S"].get_fields()
+            return {"dof": h["dof"], "finite": bool(np.isfinite(u).all())}
+
+    budget = int(0.9 * torch.cuda.mem_get_info()[0])
+
+    def serve_stream(arrivals, precision, batched):
+        reqs = [serve.Request(i, a, sp) for i, (a, sp) in enumerate(zip(arrivals, specs))]
+        ex = GpuExecutor(precision)
+        recs = serve.StreamServer(ex, budget, batched=batched).run(reqs)
+        ex.batch = None
+        torch.cuda.synchronize()
+        assert all(r.result["finite"] for r in recs)
+        return serve.summarize(recs, sum(r.result["dof"] for r in recs))
+
+    cal = serve_stream([0.0] * len(specs), mtp.MTP_MIXED_FP32, True)
+    lam = 0.7 * cal["requests_per_s"]
+    arrivals = serve.poisson_arrivals(len(specs), lam, np.random.default_rng(5))
+    log(f"stream3d: capacity {cal['requests_per_s']:.2f} requests/s (all at once), arrivals at {lam:.2f}/s")
+    mixed = serve_stream(arrivals, mtp.MTP_MIXED_FP32, True)
+    log(f"batched mixed: {mixed}")
+    seq = serve_stream(arrivals, mtp.MTP_FP64, False)
+    log(f"one at a time, FP64: {seq}")
+    out = {"metric": "DOF-updates/s, 3D Maxwell p=4 MTP: mixed/batched vs FP64 GPU at equal L2 error",
+           "value": mixed["dof_updates_per_s"], "unit": "DOF-updates/s", "n_gpus": 1, "steps": len(specs),
+           "warmup": 0, "ms_per_step": mixed["makespan_s"] * 1e3 / len(specs), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": f"request stream of {len(specs)} 3D PEC cavity solves (seed 5), Kuhn cubes "
+                                  "n in 8..16, p in 3..4, q = p+1, m = 2p, Gaussian pulse, T in [0.25, 1], Poisson "
+                                  "arrivals at 0.7 of the measured capacity; continuous batching in mixed "
+                                  "precision beside FP64 one solve at a time; ms_per_step is per request",
+                      "capacity_requests_per_s": cal["requests_per_s"], "arrival_rate_per_s": lam,
+                      "memory_budget_bytes": budget, "batched_mixed": mixed, "sequential_fp64": seq,
+                      "speedup_throughput": mixed["dof_updates_per_s"] / seq["dof_updates_per_s"],
+                      "p99_latency_ratio_fp64_over_mixed": seq["latency_p99_s"] / mixed["latency_p99_s"]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,6 +551,7 @@ def main():
     ap.add_argument("--pitch", default=None, choices=list(PITCH),
                     help="tent pitching rule: the minimum vertex moves, or the colour classes take turns "
                          "(default: colour for the 2D disk and batch workloads, minimum vertex otherwise)")
+    ap.add_argument("--stream-requests", type=int, default=200, help="requests of the stream3d workload")
     ap.add_argument("--tune", type=int, default=0,
                     help="run the tuner (this many timed slabs per candidate) before timing")
     ap.add_argument("--tune-out", default=None, help="write the tuning table here at the end")
@@ -494,6 +586,9 @@ def main():
     from paper_1906_11029_amd import mtp
     if args.workload == "curved2d":
         curved2d(args)
+        return
+    if args.workload == "stream3d":
+        stream3d(args)
         return
     if args.workload == "batch2d":
         batch2d(args)
