@@ -299,10 +299,12 @@ mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
 
 /* Batches of independent solves (section 2: tents on different meshes are independent).
  * Every launch of a batch runs layer l of every solver in it, so small solves share the
- * GPU: solvers must use the matrix-core kernels with one dimension and precision; degrees
- * may differ (solvers of one degree form a group, and each layer index is one launch per
- * group, or each group one persistent launch).  q, m, meshes, materials and boundary
- * data may differ too.  mtp_batch_advance moves every
+ * GPU: solvers must use the matrix-core kernels with one dimension, system (Maxwell or
+ * acoustics) and precision, and the SAT recursion; degrees may differ (solvers of one degree
+ * form a group, and each layer index is one launch per group, or each group one persistent
+ * launch).  q, m, meshes, materials, fluxes and boundary data may differ too.  Errors:
+ * MTP_ERR_UNSUPPORTED for mixed systems, dimensions or precisions, RK4 or curved solvers.
+ * mtp_batch_advance moves every
  * solver forward by n_slabs of its own slab height; the first call captures one batched
  * slab into a HIP graph that later calls replay.  Solvers keep their handles and state;
  * a solver must not be advanced on its own while a batch call is in flight.

@@ -228,7 +228,7 @@ struct mtp_batch_s {
   std::vector<int> order;
   std::vector<Group> groups;
   std::vector<Launch> launches;
-  int kernel = 0, d = 0;
+  int kernel = 0, d = 0, system = 0;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   mtp::KernelParams* d_kps = nullptr;
@@ -914,7 +914,7 @@ static void batch_check(const mtp_solver* solvers, int32_t n) {
     require(s->kernel == solvers[0]->kernel && s->mesh.d == solvers[0]->mesh.d, MTP_ERR_UNSUPPORTED,
             "a batch needs one dimension and precision");
     require(s->method == MTP_METHOD_SAT, MTP_ERR_UNSUPPORTED, "batches run SAT only");
-    require(s->mesh.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED, "batches run Maxwell only");
+    require(s->mesh.system == solvers[0]->mesh.system, MTP_ERR_UNSUPPORTED, "a batch needs one system");
     require(!s->curved, MTP_ERR_UNSUPPORTED, "batches do not run curved elements");
     for (int j = 0; j < i; ++j) require(solvers[j] != s, MTP_ERR_ARG, "solver listed twice");
   }
@@ -968,7 +968,8 @@ static std::string batch_key(mtp_batch b) {
     mp = std::max(mp, g.max_patch);
   }
   for (mtp_solver s : b->solvers) tents += (int64_t)s->tents.vertex.size();
-  return "batch|" + device_tag(b->solvers[0]->device) + "|d" + std::to_string(b->d) + "|sys0|p" + degs + "|k" +
+  return "batch|" + device_tag(b->solvers[0]->device) + "|d" + std::to_string(b->d) + "|sys" + std::to_string(b->system) +
+         "|p" + degs + "|k" +
          std::to_string(b->kernel) + "|nt" + std::to_string(patch_class(mp)) + "|t" + std::to_string(tents_class(tents)) +
          "|n" + std::to_string(log2_class((int64_t)b->solvers.size()));
 }
@@ -992,6 +993,7 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     b->solvers.assign(solvers, solvers + n);
     b->kernel = solvers[0]->kernel;
     b->d = solvers[0]->mesh.d;
+    b->system = solvers[0]->mesh.system;
     // degree groups: stable sort by degree
     b->order.resize(n);
     for (int i = 0; i < n; ++i) b->order[i] = i;
@@ -1010,7 +1012,7 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
       g.max_patch = std::max(g.max_patch, s->mesh.max_patch);
     }
     for (const auto& g : b->groups)
-      require(tent_mfma_lds_bytes(b->d, g.p, g.max_patch, b->kernel == 2) <= 160 * 1024, MTP_ERR_UNSUPPORTED,
+      require(tent_mfma_lds_bytes(b->d, g.p, g.max_patch, b->kernel == 2, b->system) <= 160 * 1024, MTP_ERR_UNSUPPORTED,
               "largest vertex patch of the batch does not fit the matrix-core kernel's LDS");
     const BatchLayout lo = batch_layout(solvers, n);
     require(bytes >= lo.total, MTP_ERR_ARG, "workspace too small");
@@ -1039,7 +1041,8 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
         g.bd.nsolv = g.s1 - g.s0;
         g.bd.n = off[base + g.s1 - g.s0];
         g.bd.wait_ticks = ticks;
-        g.grid_max = tent_batch_dag_grid(b->d, g.p, g.max_patch, b->kernel == 2);
+        g.bd.system = b->system;
+        g.grid_max = tent_batch_dag_grid(b->d, g.p, g.max_patch, b->kernel == 2, b->system);
         g.bd.grid = g.grid_max;
         if (g.grid_max <= 0) b->dag_ok = false;
       }
@@ -1077,7 +1080,7 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     check_hip(hipMemcpyAsync(b->d_segs, segs.data(), segs.size() * sizeof(BatchSeg), hipMemcpyHostToDevice,
                              b->stream), "upload");
     for (const auto& g : b->groups) {
-      BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, g.p, g.max_patch};
+      BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, g.p, g.max_patch, b->system};
       check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, nullptr), "batch kernel attributes");
     }
     check_hip(hipStreamSynchronize(b->stream), "sync");
@@ -1107,7 +1110,7 @@ static void batch_slab(mtp_batch b, hipStream_t st) {
   } else {
     for (const auto& la : b->launches) {
       const auto& g = b->groups[la.group];
-      BatchLaunch bl{b->d_kps, b->d_segs + la.seg0, la.nseg, la.blocks, b->d, g.p, g.max_patch};
+      BatchLaunch bl{b->d_kps, b->d_segs + la.seg0, la.nseg, la.blocks, b->d, g.p, g.max_patch, b->system};
       check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, st), "batched tent kernel");
     }
   }

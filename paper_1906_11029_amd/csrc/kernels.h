@@ -92,6 +92,7 @@ struct BatchDag {
   const int32_t* roff;   // nsolv + 1: first queue slot of each solver's first-layer tents
   int32_t nsolv, n, grid;
   int64_t wait_ticks;
+  int32_t system;        // MTP_SYSTEM_* of every solver of the batch
 };
 
 struct BatchLaunch {
@@ -100,6 +101,7 @@ struct BatchLaunch {
   int nseg;
   int64_t blocks;            // total workgroups (-1: only set the LDS attribute)
   int d, p, max_patch;
+  int system;                // MTP_SYSTEM_* of every solver of the batch
 };
 
 // The curved-element tent path: reference tables, per zone element tables and neighbours,
@@ -137,7 +139,7 @@ int tent_dag_grid(const KernelParams& kp, int fp32);
 hipError_t launch_batch_dag_reset(const KernelParams* kps, const BatchDag& bd, hipStream_t s);
 hipError_t launch_tent_batch_dag_mfma(const KernelParams* kps, const BatchDag& bd, int d, int p, int max_patch,
                                       int fp32, hipStream_t s);
-int tent_batch_dag_grid(int d, int p, int max_patch, int fp32);
+int tent_batch_dag_grid(int d, int p, int max_patch, int fp32, int system = 0);
 hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
                              int64_t nv, hipStream_t s);
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);

@@ -1051,15 +1051,15 @@ tent_mfma_dag_kernel(KernelParams kp) {
 }
 
 // Persistent entry point of a batch: every tent of every solver's slab, in DAG order.
-template <int D, int P, typename T, int NTMAX, int WPE>
+template <int D, int P, typename T, int NTMAX, int WPE, int SYS = 0>
 __global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_batch_dag_kernel(const KernelParams* kps, BatchDag bd) {
-  tent_mfma_body<D, P, T, NTMAX>(kps[0], SchedBatchDag{kps, bd, 0});
+  tent_mfma_body<D, P, T, NTMAX, SchedBatchDag, false, SYS>(kps[0], SchedBatchDag{kps, bd, 0});
 }
 
 // Batched entry point: workgroup b runs tent b - seg.block0 of segment seg, i.e. of the
 // layer slice (first, count) of solver seg.solver; all solvers share (D, P, T).
-template <int D, int P, typename T, int NTMAX, int WPE>
+template <int D, int P, typename T, int NTMAX, int WPE, int SYS = 0>
 __global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) {
   const int64_t b = blockIdx.x;
@@ -1069,8 +1069,8 @@ tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) 
     if (segs[mid].block0 <= b) lo = mid; else hi = mid - 1;
   }
   const BatchSeg sg = segs[lo];
-  tent_mfma_body<D, P, T, NTMAX>(kps[sg.solver],
-                                 SchedRange{sg.first, sg.count, b - sg.block0, (int64_t)1 << 62});
+  tent_mfma_body<D, P, T, NTMAX, SchedRange, false, SYS>(kps[sg.solver],
+                                                         SchedRange{sg.first, sg.count, b - sg.block0, (int64_t)1 << 62});
 }
 
 template <int D, int P, typename T, int NTMAX>
@@ -1132,12 +1132,20 @@ template <int D, int P, typename T, int NTMAX>
 hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
   constexpr int BLOCK = MShape<D, P, NTMAX>::BLOCK;
-  if (a.bd) {
+  if (a.bd) {   // a batch of one system (the acoustic variant when a.bd->system == 1)
     auto kfn = tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2>;
-    if (resident) return resident_grid(reinterpret_cast<const void*>(kfn), BLOCK, lds, resident);
+    auto kfn_ac = tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2, 1>;
+    const bool ac = a.bd->system == 1;
+    const size_t lds_b = ac ? MLds<D, P, T, NTMAX, 1>::bytes : lds;
+    if (resident)
+      return resident_grid(ac ? reinterpret_cast<const void*>(kfn_ac) : reinterpret_cast<const void*>(kfn), BLOCK,
+                           lds_b, resident);
     if (a.bd->n <= 0) return hipSuccess;
     if (a.bd->grid <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kfn, dim3((unsigned)a.bd->grid), dim3(BLOCK), lds, s, a.kps, *a.bd);
+    if (ac)
+      hipLaunchKernelGGL(kfn_ac, dim3((unsigned)a.bd->grid), dim3(BLOCK), lds_b, s, a.kps, *a.bd);
+    else
+      hipLaunchKernelGGL(kfn, dim3((unsigned)a.bd->grid), dim3(BLOCK), lds_b, s, a.kps, *a.bd);
     return hipGetLastError();
   }
   auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
@@ -1179,15 +1187,25 @@ hipError_t launch_mdp(const PersistentArgs& a, int max_patch, hipStream_t s, int
 
 template <int D, int P, typename T, int NTMAX>
 hipError_t launch_mb(const BatchLaunch& bl, hipStream_t s) {
-  const size_t lds = MLds<D, P, T, NTMAX>::bytes;
   constexpr int WPE = 2;
+  constexpr int BLOCK = MShape<D, P, NTMAX>::BLOCK;
+  if (bl.system == 1) {   // acoustics
+    const size_t lds = MLds<D, P, T, NTMAX, 1>::bytes;
+    auto kfn = tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 1>;
+    if (bl.blocks < 0)
+      return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds);
+    if (bl.blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(kfn, dim3((unsigned)bl.blocks), dim3(BLOCK), lds, s, bl.kps, bl.segs, bl.nseg);
+    return hipGetLastError();
+  }
+  const size_t lds = MLds<D, P, T, NTMAX>::bytes;
   auto kfn = tent_mfma_batch_kernel<D, P, T, NTMAX, WPE>;
   if (bl.blocks < 0)
     return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds);
   if (bl.blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(kfn, dim3((unsigned)bl.blocks), dim3(MShape<D, P, NTMAX>::BLOCK), lds, s, bl.kps, bl.segs,
-                     bl.nseg);
+  hipLaunchKernelGGL(kfn, dim3((unsigned)bl.blocks), dim3(BLOCK), lds, s, bl.kps, bl.segs, bl.nseg);
   return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ def fixture(name):
     pytest.skip(f"missing oracle fixture {path}")
 
 
-def run(name, precision, schedule):
+def make(name, precision):
     from paper_1906_11029_amd import mtp
     c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
     M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc, system=mtp.MTP_SYSTEM_ACOUSTIC)
@@ -35,10 +35,15 @@ def run(name, precision, schedule):
     S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"], precision=precision)
     if c["flux"] == "impedance":
         S.set_flux(mtp.MTP_FLUX_IMPEDANCE)
-    S.set_schedule(schedule)
     S.set_fields(u0, 0.0)
     if c["kind"] == DATA:
         S.set_planewave_bc(*planewave_params(ex, dim))
+    return c, S, T
+
+
+def run(name, precision, schedule):
+    c, S, T = make(name, precision)
+    S.set_schedule(schedule)
     S.advance_to(c["slabs"] * c["T"])
     return S, T
 
@@ -93,5 +98,33 @@ def test_acoustic_rejected_where_unsupported():
     S = mtp.Solver(M, T, c["p"], c["q"], c["m"])
     with pytest.raises(mtp.MTPError):
         S.set_method(mtp.MTP_METHOD_RK4)
-    with pytest.raises(mtp.MTPError):
-        mtp.Batch([S])
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_acoustic_batches_against_oracle(dim, precision, tol, schedule):
+    """The acoustic cases of one dimension (3D: P2, P3, P4 groups; rigid and pressure-release
+    walls, two media, the impedance flux; 2D: P3 rigid walls and P2 plane-wave data) advanced
+    as one batch, per-layer or persistent, against the oracle's fixtures."""
+    from paper_1906_11029_amd import mtp
+    names = [n for n in AC_CASES if n.startswith(f"ac{dim}d")]
+    print(f"[gpu acoustic] batch {dim}D precision {precision} schedule {schedule}: {names}", flush=True)
+    made = [make(n, precision) for n in names]
+    B = mtp.Batch([S for _, S, _ in made])
+    B.set_schedule(schedule)
+    B.advance(1)
+    for (c, S, _), n in zip(made, names):
+        assert c["slabs"] == 1
+        assert_parity(S.get_state(), fixture(n)["w"], tol, f"batch {n}")
+
+
+def test_batches_refuse_mixed_systems():
+    from paper_1906_11029_amd import mtp
+    _, A, _ = make("ac3d_rigid_p2", 0)
+    c, mm, dim, eps, mu, bc, ex, u0 = setup("ac3d_rigid_p2")
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    S = mtp.Solver(M, mtp.Tents(M, c["T"], 0.5), 2, 3, 4)
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.Batch([A, S])
+    assert e.value.code == -9
