@@ -145,13 +145,15 @@ void mtp_mesh_destroy(mtp_mesh mesh);
  * gradients over the element (the largest min_i sum_{j != i} |grad lambda_j| over the
  * barycentric lattice i/12, j/12), so call this before mtp_pitch_layers, and before
  * mtp_solver_create.  Solvers then run the tents whose patch holds a curved element on a
- * separate FP64 vector-ALU path, after the layer's other tents: every patch element by
+ * separate FP64 vector-ALU path, beside the layer's other tents (on a second stream, joined
+ * before the next layer): every patch element by
  * quadrature (collapsed Gauss-Jacobi rule, p + 4 points per direction) with the element
  * map's Jacobian at the points, grad phi = J^{-T} sum_k tau_k gradhat lambdahat_k varying
  * inside the element, the closed-form inverse at the points, and the weight-adjusted
  * inverse mass Mhat^{-1} M_{1/J} Mhat^{-1} (M_{1/J} = int phi_a phi_b / |det J|, p + 8
- * points) for every projection.  Scope of such solvers: 2D Maxwell, p = 1..4, MTP_FP64 or
- * MTP_FP64_VALU (the other tents' kernel), SAT, the penalty flux, the layer schedule, walls
+ * points) for every projection.  Scope of such solvers: 2D Maxwell, p = 1..4, MTP_FP64,
+ * MTP_FP64_VALU or MTP_MIXED_FP32 (the precision of the other tents; the curved ones always
+ * run in FP64), SAT, the penalty flux, the layer schedule, walls
  * (PEC/PMC) next to curved elements; no batches.  mtp_node_coords maps a curved element's
  * nodes through its quadratic map.  Errors: MTP_ERR_ARG (null, dim != 2, the first three
  * nodes not the element's vertices, non-finite nodes), MTP_ERR_MESH (a shared edge with two

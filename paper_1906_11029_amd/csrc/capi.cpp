@@ -394,8 +394,9 @@ static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
   if (m.n_curved > 0) {
     require(m.d == 2 && m.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED, "curved elements: 2D Maxwell only");
     require(p >= 1 && p <= 4, MTP_ERR_UNSUPPORTED, "curved elements: degrees 1..4");
-    require(precision == MTP_FP64 || precision == MTP_FP64_VALU, MTP_ERR_UNSUPPORTED,
-            "curved elements run in FP64");
+    // the curved tents run in FP64 (their own kernel); the layer's other tents in the precision asked
+    require(precision == MTP_FP64 || precision == MTP_FP64_VALU || precision == MTP_MIXED_FP32,
+            MTP_ERR_UNSUPPORTED, "curved elements: FP64 or mixed (split-BF16 is not built)");
     require(tent_curved_lds_bytes(p, m.max_patch, false) <= lim, MTP_ERR_UNSUPPORTED,
             "largest vertex patch does not fit the curved-element kernel's LDS");
     for (int64_t e = 0; e < m.ne; ++e)

@@ -48,6 +48,19 @@ def test_curved_parity_against_oracle(name, precision):
     assert_parity(S.get_state(), ref["w"], TOL, f"{name} w")
 
 
+@pytest.mark.parametrize("name", list(CURVED_CASES))
+def test_curved_mixed_precision_against_oracle(name):
+    """Mixed precision on a curved mesh: the affine tents on the FP32 matrix-core kernel, the
+    curved ones on their FP64 kernel; the state against the oracle within 1e-6."""
+    from paper_1906_11029_amd import mtp
+    print(f"[gpu curved] {name} mixed", flush=True)
+    ref = fixture(name)
+    c, S, T, mm = curved_solver(name, mtp.MTP_MIXED_FP32)
+    assert S.kernel() == 2
+    S.advance_to(c["slabs"] * c["T"])
+    assert_parity(S.get_state(), ref["w"], 1e-6, f"{name} mixed")
+
+
 def test_curved_node_coords_follow_the_quadratic_map():
     from mtp_inputs import meshes
     c, S, T, mm = curved_solver("disk_curved_p3_pmc")
@@ -95,10 +108,9 @@ def test_curved_refusals():
     c, mm, dim, eps, mu, bc, ex, u0 = setup("disk_curved_p2")
     M = mtp.Mesh(mm["coords"], mm["cells"], curved=mm["geo"])
     T = mtp.Tents(M, c["T"], 0.5)
-    for prec in (mtp.MTP_MIXED_FP32, mtp.MTP_BF16X3):
-        with pytest.raises(mtp.MTPError) as e:
-            mtp.Solver(M, T, 2, 3, 4, precision=prec)
-        assert e.value.code == -9
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.Solver(M, T, 2, 3, 4, precision=mtp.MTP_BF16X3)
+    assert e.value.code == -9
     with pytest.raises(mtp.MTPError) as e:
         mtp.Solver(M, T, 5, 6, 10)
     assert e.value.code == -9
