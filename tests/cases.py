@@ -47,6 +47,9 @@ LARGE_P4_CASES = {
     "delaunay3d_p4": dict(mesh=("delaunay", 3), p=4, q=5, m=8, T=0.05, kind=PEC, exact="pec_3d"),
     "delaunay3d_p4_pmc_eps": dict(mesh=("delaunay", 3), p=4, q=5, m=8, T=0.05, kind=PMC, exact="pec_3d",
                                   eps_split=True),
+    "delaunay3d_p4_rk4": dict(mesh=("delaunay", 3), p=4, q=5, m=8, T=0.05, kind=PEC, exact="pec_3d", method="rk4"),
+    "ac_delaunay3d_p4": dict(mesh=("delaunay", 3), p=4, q=5, m=8, T=0.05, kind=PMC, exact="ac_pulse3",
+                             system="acoustic"),
 }
 
 # the classical RK4 variant (method="rk4"): same inputs, RK4 on the tent ODE

@@ -107,3 +107,18 @@ def test_colour_tables_stay_bounded_on_the_graded_p4_mesh():
     diff = np.linalg.norm(ub - ua) / np.linalg.norm(ua)
     print(f"[gpu colour] colour vs minimum-vertex after 3 slabs: relative L2 {diff:.3e}", flush=True)
     assert diff < 1e-3
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("name", [n for n in COLOUR_CASES if not COLOUR_CASES[n].get("curved")])
+def test_colour_tables_mixed_precision(name, schedule):
+    """Mixed precision on colour tables, per-layer and persistent: the state against the
+    oracle's FP64 solve within 1e-6, element by element."""
+    from paper_1906_11029_amd import mtp
+    print(f"[gpu colour] {name} mixed schedule {schedule}", flush=True)
+    ref = fixture(name)
+    c, S, T = colour_solver(name, mtp.MTP_MIXED_FP32)
+    assert S.kernel() == 2
+    S.set_schedule(schedule)
+    S.advance_to(c["slabs"] * c["T"])
+    assert_parity(S.get_state(), ref["w"], 1e-6, f"{name} mixed")

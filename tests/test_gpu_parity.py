@@ -348,8 +348,11 @@ def test_batch_mixed_degrees_against_oracle(dim, precision, tol, schedule):
             assert np.abs(w - w1).max() <= (1e-13 if precision == 0 else 1e-9) * np.abs(w1).max(), nm
 
 
+LARGE_P4_SAT = [n for n, c in LARGE_P4_CASES.items() if "method" not in c and "system" not in c]
+
+
 @pytest.mark.parametrize("precision,tol", [(0, TOL), (1, MIXED_TOL)])
-@pytest.mark.parametrize("name", list(LARGE_P4_CASES))
+@pytest.mark.parametrize("name", LARGE_P4_SAT)
 def test_large_p4_patches_against_oracle(name, precision, tol):
     """P4 on the jittered Delaunay cube, whose vertex patches hold up to 36 tets: the 36-tet
     class (operator block in device memory, column-block products, Taylor sums in W) against
@@ -370,7 +373,7 @@ def test_large_p4_patches_persistent_schedule_and_batch():
     """The 36-tet class under the persistent schedule (bit-identical to the layers) and in a
     batch of both cases (against the oracle)."""
     from paper_1906_11029_amd import mtp
-    names = list(LARGE_P4_CASES)
+    names = LARGE_P4_SAT
     print("[gpu parity] large P4 patches: persistent schedule and batch", flush=True)
     c, A, _ = gpu_solver(names[0])
     _, B, _ = gpu_solver(names[0])
@@ -382,3 +385,24 @@ def test_large_p4_patches_persistent_schedule_and_batch():
     mtp.Batch(solvers).advance(1)
     for S, nm in zip(solvers, names):
         assert_parity(S.get_state(), fixture(nm)["w"], TOL, f"batch {nm}")
+
+
+@pytest.mark.parametrize("name,precision,tol", [("delaunay3d_p4_rk4", 0, TOL), ("ac_delaunay3d_p4", 0, TOL),
+                                                ("ac_delaunay3d_p4", 1, MIXED_TOL)])
+def test_large_p4_patches_rk4_and_acoustics(name, precision, tol):
+    """The 36-tet P4 class under the classical RK4 variant (FP64) and for linear acoustics
+    (both precisions) against the oracle, element by element."""
+    from paper_1906_11029_amd import mtp
+    print(f"[gpu parity] {name} precision {precision}", flush=True)
+    ref = fixture(name)
+    c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
+    system = mtp.MTP_SYSTEM_ACOUSTIC if c["system"] == "acoustic" else mtp.MTP_SYSTEM_MAXWELL
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc, system=system)
+    assert M.info["max_patch"] > 24
+    T = mtp.Tents(M, c["T"], 0.5)
+    S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"], precision=precision)
+    if c["method"] == "rk4":
+        S.set_method(mtp.MTP_METHOD_RK4)
+    S.set_fields(u0, 0.0)
+    S.advance_to(c["slabs"] * c["T"])
+    assert_parity(S.get_state(), ref["w"], tol, f"{name} w")
