@@ -214,7 +214,8 @@ def measured_traffic(tag):
 
 
 SCHEDULES = {"layers": 0, "dag": 1}
-PITCH = {"min-vertex": 0, "colour": 1}   # tent pitching rules
+PITCH = {"min-vertex": 0, "colour": 1, "auto": 2}   # tent pitching rules
+RULE_NAME = {0: "min-vertex", 1: "colour"}          # the rule a table was pitched by
 TILE_ORDERS = {0: "default", 1: "round-robin", 2: "blocked", 3: "column-major"}
 
 
@@ -383,6 +384,8 @@ def batch2d(args):
                                   + ("one persistent launch per degree and slab" if tuning["schedule"] == "dag"
                                      else "one launch per global layer index and degree"),
                       "solves": 64, "tents_per_step": int(tents), "precision": args.precision, "pitch": args.pitch,
+                      "pitch_applied": {r: sum(1 for S, _, _ in solves if RULE_NAME[S.tents.rule] == r)
+                                        for r in RULE_NAME.values()},
                       "schedule": tuning["schedule"], "tuning": tuning,
                       "rel_l2_error_vs_exact": {"max": max(errs), "median": float(np.median(errs))},
                       "compare": compare}}
@@ -405,6 +408,10 @@ def curved2d(args):
     mm = meshes.disk_tri(96)
     geo = meshes.p2_geometry(mm, on_circle=1.0)
     p, q, m, H = 3, 4, 6, 0.05
+    if args.pitch == "auto":   # the rule the library picks for the curved disk
+        Mc = mtp.Mesh(mm["coords"], mm["cells"], curved=geo)
+        args.pitch = RULE_NAME[mtp.Tents(Mc, H, 0.5, rule=PITCH["auto"]).rule]
+        del Mc
     other = "min-vertex" if args.pitch == "colour" else "colour"
     runs = [("curved", geo, args.pitch), ("straight", None, args.pitch)]
     if not args.no_compare:
@@ -481,7 +488,7 @@ def stream3d(args):
             mm = meshes.cube_kuhn(sp["n"])
             M = mtp.Mesh(mm["coords"], mm["cells"])
             nslab = int(np.ceil(sp["T"] / 0.25))
-            T = mtp.Tents(M, sp["T"] / nslab, 0.5)
+            T = mtp.Tents(M, sp["T"] / nslab, 0.5, rule=PITCH[args.pitch])
             S = mtp.Solver(M, T, sp["p"], sp["p"] + 1, 2 * sp["p"], precision=self.prec)
             S.set_fields(fields.GaussianPulse3D(seed=sp["seed"]).u(meshes.equispaced_nodes(mm, sp["p"]), 0.0), 0.0)
             return {"rid": req.rid, "S": S, "T": sp["T"], "nslab": nslab, "dof": S.slab_dof_updates()[0] * nslab}
@@ -549,8 +556,8 @@ def main():
                     help="one launch per layer, one persistent launch per slab over the tent DAG, or "
                          "auto (default): the launch choice of the package's tuning table")
     ap.add_argument("--pitch", default=None, choices=list(PITCH),
-                    help="tent pitching rule: the minimum vertex moves, or the colour classes take turns "
-                         "(default: colour for the 2D disk and batch workloads, minimum vertex otherwise)")
+                    help="tent pitching rule: the minimum vertex moves, the colour classes take turns, or "
+                         "auto (the table with less work; the default)")
     ap.add_argument("--stream-requests", type=int, default=200, help="requests of the stream3d workload")
     ap.add_argument("--tune", type=int, default=0,
                     help="run the tuner (this many timed slabs per candidate) before timing")
@@ -568,9 +575,10 @@ def main():
               "(sharding is described in the design notes)", file=sys.stderr)
         sys.exit(2)
     if args.pitch is None:
-        # the colour rule widens the layers of irregular 2D meshes (the disk: 47 layers per slab
-        # instead of 28,069) and of the batch's squares; on the graded 3D mesh it makes more tents
-        args.pitch = "colour" if args.workload in ("curved2d", "batch2d") else "min-vertex"
+        # the library's automatic choice: the colour order where it makes less work (the disk:
+        # 47 layers per slab instead of 28,069; the batch's squares; the uniform Kuhn cubes),
+        # the minimum vertex on the graded two-media cube, where colour turns make more tents
+        args.pitch = "auto"
 
     import torch
 
@@ -654,7 +662,7 @@ def main():
         "dtype": "f32+f64" if head["kernel"] == 2 else "f64", "data": "synthetic",
         "config": {"workload": W["desc"], "tets": int(M.info["ne"]), "p": W["p"], "q": W["q"], "m": W["m"],
                    "tents_per_step": int(head["n_tents"]), "layers_per_step": int(nl), "slope_fraction": 0.5,
-                   "pitch": args.pitch,
+                   "pitch": args.pitch, "pitch_applied": RULE_NAME[T.rule],
                    "mean_slope_over_bound": round(float(slopes["mean_slope_over_bound"]), 4),
                    "tents_per_vertex_per_slab": round(float(slopes["tents_per_vertex_per_slab"]), 3),
                    "precision": args.precision, "schedule": args.schedule, "tuning": tuning,

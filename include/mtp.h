@@ -181,11 +181,13 @@ mtp_status mtp_pitch_layers(mtp_mesh mesh, double t_start, double t_end, double 
  * keeps the causality bound yields a valid tent table). */
 enum {
   MTP_PITCH_MIN_VERTEX = 0,   /* mtp_pitch_layers' rule: the (time, id)-smallest vertex moves   */
-  MTP_PITCH_COLOUR = 1        /* the vertex graph is coloured greedily (ids ascending, smallest */
+  MTP_PITCH_COLOUR = 1,       /* the vertex graph is coloured greedily (ids ascending, smallest */
                               /* colour no neighbour holds); the colours take turns, and at its */
                               /* turn every vertex of the colour below H moves (ids ascending)  */
                               /* to the target above, capped at tau_v + 1.5 min_w k_vw, if that */
                               /* lies above its time.                                           */
+  MTP_PITCH_AUTO = 2          /* both tables; the one whose tents' patch sizes sum to less (the */
+                              /* minimum-vertex table on a tie)                                 */
 };
 /* mtp_pitch_layers with a choice of rule.  Both rules keep the slope bound and put a tent
  * in layer 1 + the largest layer of itself and its neighbours, so both make tables that
@@ -200,6 +202,9 @@ enum {
  * mtp_pitch_layers, and MTP_ERR_ARG for an unknown rule. */
 mtp_status mtp_pitch_layers_rule(mtp_mesh mesh, double t_start, double t_end, double slope_fraction,
                                  int32_t rule, mtp_tents* out);
+/* The rule a tent table was pitched by (MTP_PITCH_MIN_VERTEX or MTP_PITCH_COLOUR; for
+ * MTP_PITCH_AUTO, the one chosen).  Host only.  Errors: MTP_ERR_ARG. */
+mtp_status mtp_tents_rule(mtp_tents tents, int32_t* rule);
 /* Size of a tent table (section 2: tents whose vertices are at graph distance >= 2 are
  * independent; a layer is a set of such tents).  n_tents, n_layers; layer_ptr
  * (n_layers+1 entries, may be NULL) receives the start of each layer in the layer-sorted

@@ -91,7 +91,14 @@ def pitch(mesh, t_end, sigma=0.5, k_elem=None, rule="min_vertex"):
 
     Returns dict with int arrays vertex, layer and float arrays t_bot, t_top, in
     emission order.  k_elem: per-element steps replacing the affine rule's k_T.
-    rule: "min_vertex" or "colour" (module docstring)."""
+    rule: "min_vertex", "colour" (module docstring) or "auto": both tables, and the one
+    whose tents' patch sizes sum to less (the minimum-vertex table on a tie); the returned
+    dict then names the chosen rule under "rule"."""
+    if rule == "auto":
+        a = pitch(mesh, t_end, sigma, k_elem, "min_vertex")
+        b = pitch(mesh, t_end, sigma, k_elem, "colour")
+        work = lambda t: sum(len(mesh.v2e[int(v)]) for v in t["vertex"])  # noqa: E731
+        return {**b, "rule": "colour"} if work(b) < work(a) else {**a, "rule": "min_vertex"}
     if rule == "colour":
         return _pitch_colour(mesh, t_end, sigma, k_elem)
     if rule != "min_vertex":

@@ -342,7 +342,8 @@ mtp_status mtp_pitch_layers_rule(mtp_mesh mesh, double t_start, double t_end, do
   require(std::isfinite(t_start) && std::isfinite(t_end) && t_end > t_start, MTP_ERR_ARG,
           "need finite t_start < t_end");
   require(slope_fraction > 0 && slope_fraction < 1, MTP_ERR_CAUSALITY, "slope fraction must be in (0,1)");
-  require(rule == MTP_PITCH_MIN_VERTEX || rule == MTP_PITCH_COLOUR, MTP_ERR_ARG, "unknown pitching rule");
+  require(rule == MTP_PITCH_MIN_VERTEX || rule == MTP_PITCH_COLOUR || rule == MTP_PITCH_AUTO, MTP_ERR_ARG,
+          "unknown pitching rule");
   auto* h = new mtp_tents_s();
   try {
     // times relative to t_start: the table is a slab pattern that solvers apply from their
@@ -354,6 +355,13 @@ mtp_status mtp_pitch_layers_rule(mtp_mesh mesh, double t_start, double t_end, do
     throw;
   }
   *out = h;
+  MTP_CATCH
+}
+
+mtp_status mtp_tents_rule(mtp_tents tents, int32_t* rule) {
+  MTP_TRY
+  require(tents && rule, MTP_ERR_ARG, "null pointer");
+  *rule = tents->t.rule;
   MTP_CATCH
 }
 

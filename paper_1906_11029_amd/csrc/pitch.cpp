@@ -56,7 +56,25 @@ int32_t colour_vertices(const Mesh& m, std::vector<int32_t>& col) {
 
 }  // namespace
 
+// The automatic rule: both tables, and the one with less work, the sum over its tents of
+// the patch sizes (a tent's cost grows with its patch); the minimum-vertex table on a tie.
 void pitch(const Mesh& m, double t_end, double slope, int rule, Tents& out) {
+  if (rule == MTP_PITCH_AUTO) {
+    Tents a, b;
+    pitch(m, t_end, slope, MTP_PITCH_MIN_VERTEX, a);
+    pitch(m, t_end, slope, MTP_PITCH_COLOUR, b);
+    auto work = [&](const Tents& t) {
+      int64_t w = 0;
+      for (int32_t v : t.vertex) w += m.v2e_ptr[v + 1] - m.v2e_ptr[v];
+      return w;
+    };
+    out = work(b) < work(a) ? std::move(b) : std::move(a);
+    return;
+  }
+  pitch_rule(m, t_end, slope, rule, out);
+}
+
+void pitch_rule(const Mesh& m, double t_end, double slope, int rule, Tents& out) {
   const int d = m.d, nvert = d + 1;
   const double Q = std::ldexp(1.0, -24);
   const double SAFETY = 1e-3;

@@ -21,7 +21,7 @@ MTP_METHOD_SAT, MTP_METHOD_RK4 = 0, 1
 MTP_FLUX_PENALTY, MTP_FLUX_IMPEDANCE = 0, 1
 MTP_SYSTEM_MAXWELL, MTP_SYSTEM_ACOUSTIC = 0, 1
 MTP_TILES_DEFAULT, MTP_TILES_ROUND_ROBIN, MTP_TILES_BLOCKED, MTP_TILES_COLUMN_MAJOR = 0, 1, 2, 3
-MTP_PITCH_MIN_VERTEX, MTP_PITCH_COLOUR = 0, 1
+MTP_PITCH_MIN_VERTEX, MTP_PITCH_COLOUR, MTP_PITCH_AUTO = 0, 1, 2
 
 # tuning table shipped with the package (measured on MI355X); MTP_TUNE_FILE names another
 # file to load instead, or, set to the empty string, disables loading one
@@ -55,6 +55,7 @@ def load():
         "mtp_mesh_set_curved_p2": [P, P],
         "mtp_pitch_layers": [P, dbl, dbl, dbl, pp],
         "mtp_pitch_layers_rule": [P, dbl, dbl, dbl, i32, pp],
+        "mtp_tents_rule": [P, P],
         "mtp_tents_query": [P, P, P, P],
         "mtp_tents_export": [P, P, P, P, P],
         "mtp_solver_workspace_size": [P, P, i32, i32, i32, i32, P],
@@ -493,7 +494,9 @@ class Tents:
             self.h = mtp_pitch_layers(mesh.h, t_start, t_end, slope_fraction)
         else:
             self.h = mtp_pitch_layers_rule(mesh.h, t_start, t_end, slope_fraction, rule)
-        self.rule = MTP_PITCH_MIN_VERTEX if rule is None else rule
+        r = C.c_int32()
+        _check(load().mtp_tents_rule(self.h, C.byref(r)))
+        self.rule = r.value   # the rule the table was pitched by (the chosen one for MTP_PITCH_AUTO)
         self.n_tents, self.n_layers, self.layer_ptr = mtp_tents_query(self.h)
         self.t_end = t_end
 

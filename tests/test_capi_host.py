@@ -87,7 +87,7 @@ def test_colour_pitch_matches_oracle_bit_exact(name):
 def test_colour_pitch_refuses_unknown_rule():
     mm = meshes.square_tri(2)
     M = mtp.Mesh(mm["coords"], mm["cells"])
-    for rule in (-1, 2):
+    for rule in (-1, 3):
         with pytest.raises(mtp.MTPError) as e:
             mtp.Tents(M, 0.5, 0.5, rule=rule)
         assert e.value.code == -1
@@ -220,3 +220,21 @@ def test_p4_patch_classes_accept_up_to_36_tets():
         assert e.value.code == -9
     # P3 keeps its 48-tet class
     assert mtp.mtp_solver_workspace_size(Mb.h, Tb.h, 3, 4, 6, mtp.MTP_MIXED_FP32) > 0
+
+
+@pytest.mark.parametrize("name", ["square6", "disk8", "kuhn3", "graded3_eps"])
+def test_auto_pitch_matches_oracle_bit_exact(name):
+    """MTP_PITCH_AUTO: the library picks the same ordering as the oracle and the same table,
+    and reports the ordering it chose."""
+    mm, mat = _colour_meshes()[name]
+    eps, mu = mat if mat else (None, None)
+    T = 0.2
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    tents = mtp.Tents(M, T, 0.5, rule=mtp.MTP_PITCH_AUTO)
+    ot = opitch(OMesh(mm["coords"], mm["cells"], eps=eps, mu=mu), T, 0.5, rule="auto")
+    assert tents.rule == {"min_vertex": mtp.MTP_PITCH_MIN_VERTEX, "colour": mtp.MTP_PITCH_COLOUR}[ot["rule"]]
+    ex = tents.export()
+    order = np.argsort(ot["layer"], kind="stable")
+    for k in ("vertex", "t_bot", "t_top", "layer"):
+        assert np.array_equal(ex[k], ot[k][order]), k
+    assert mtp.Tents(M, T, 0.5).rule == mtp.MTP_PITCH_MIN_VERTEX

@@ -251,3 +251,24 @@ def test_unknown_rule_refused():
     mm = meshes.square_tri(2)
     with pytest.raises(ValueError):
         pitch(Mesh(mm["coords"], mm["cells"]), 0.1, rule="random")
+
+
+@pytest.mark.parametrize("name,expected", [("disk6", "colour"), ("graded3_eps", "min_vertex"), ("square6", "colour")])
+def test_auto_rule_picks_the_table_with_less_work(name, expected):
+    """rule="auto": both orderings, and the table whose tents' patch sizes sum to less; the
+    work is recounted here from the patch sizes (the disk and square favour the colour order,
+    the graded two-media cube the minimum vertex)."""
+    mm, mat = _colour_meshes()[name]
+    eps, mu = mat if mat else (None, None)
+    mesh = Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    T = 0.3
+    t = pitch(mesh, T, sigma=0.5, rule="auto")
+    a = pitch(mesh, T, sigma=0.5)
+    b = pitch(mesh, T, sigma=0.5, rule="colour")
+    sizes = np.bincount(np.asarray(mm["cells"]).ravel(), minlength=mesh.nv)
+    wa, wb = sizes[a["vertex"]].sum(), sizes[b["vertex"]].sum()
+    assert t["rule"] == expected == ("colour" if wb < wa else "min_vertex")
+    ref = b if expected == "colour" else a
+    for k in ("vertex", "t_bot", "t_top", "layer"):
+        assert np.array_equal(t[k], ref[k]), k
+    assert validate(mesh, t, T)
