@@ -456,7 +456,7 @@ def curved2d(args):
 
 def stream3d(args):
     """A request stream of 3D PEC cavity solves, served by continuous batching: requests
-    (seed 5) on Kuhn cubes n ~ U{8..16} (3,072-24,576 tets), p ~ U{3, 4}, q = p + 1, m = 2p,
+    (seed 5) on Kuhn cubes n ~ U{8..16} (3,072-24,576 tets), p ~ U{3, 4, 5}, q = p + 1, m = 2p,
     eps = 1, the Gaussian pulse of the graded workload (seed per request), final time
     T ~ U[0.25, 1] in slabs of at most 0.25.  A calibration pass serves every request at once
     (batched, mixed) to measure the capacity; the stream then arrives as a Poisson process at
@@ -469,7 +469,7 @@ def stream3d(args):
     from mtp_inputs import fields, meshes
     from paper_1906_11029_amd import mtp, serve
     rng = np.random.default_rng(5)
-    specs = [dict(n=int(rng.integers(8, 17)), p=int(rng.integers(3, 5)), T=float(rng.uniform(0.25, 1.0)),
+    specs = [dict(n=int(rng.integers(8, 17)), p=int(rng.integers(3, 6)), T=float(rng.uniform(0.25, 1.0)),
                   seed=int(rng.integers(1 << 30))) for _ in range(args.stream_requests)]
 
     class GpuExecutor:
@@ -535,7 +535,7 @@ def stream3d(args):
            "warmup": 0, "ms_per_step": mixed["makespan_s"] * 1e3 / len(specs), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": f"request stream of {len(specs)} 3D PEC cavity solves (seed 5), Kuhn cubes "
-                                  "n in 8..16, p in 3..4, q = p+1, m = 2p, Gaussian pulse, T in [0.25, 1], Poisson "
+                                  "n in 8..16, p in 3..5, q = p+1, m = 2p, Gaussian pulse, T in [0.25, 1], Poisson "
                                   "arrivals at 0.7 of the measured capacity; continuous batching in mixed "
                                   "precision beside FP64 one solve at a time; ms_per_step is per request",
                       "capacity_requests_per_s": cal["requests_per_s"], "arrival_rate_per_s": lam,

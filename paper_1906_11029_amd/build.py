@@ -14,7 +14,7 @@ SOURCES = ["mesh.cpp", "pitch.cpp", "refelem.cpp", "dag.cpp", "capi.cpp", "tune.
            "tent_kernel.hip", "tent_mfma.hip",
            "tent_mfma_2d_p12.hip", "tent_mfma_2d_p3.hip", "tent_mfma_2d_p4.hip", "tent_mfma_2d_p5.hip",
            "tent_mfma_3d_p1.hip", "tent_mfma_3d_p2.hip", "tent_mfma_3d_p3.hip", "tent_mfma_3d_p4_f64.hip",
-           "tent_mfma_3d_p4_f32.hip", "noalloc.hip", "tent_curved.hip"]
+           "tent_mfma_3d_p4_f32.hip", "tent_mfma_3d_p5.hip", "noalloc.hip", "tent_curved.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions off for all device code

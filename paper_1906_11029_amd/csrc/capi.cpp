@@ -397,7 +397,11 @@ static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
   require(precision == MTP_FP64 || precision == MTP_MIXED_FP32 || precision == MTP_FP64_VALU,
           MTP_ERR_UNSUPPORTED, "unknown precision");
   require(q >= 1 && q <= 32 && mm >= 1 && mm <= 1024, MTP_ERR_ARG, "q must be in 1..32 and m in 1..1024");
-  require(tent_kernel_supported(m.d, p), MTP_ERR_UNSUPPORTED, "degree p not covered for this dimension");
+  // P5 in 3D runs on the matrix-core kernels only
+  const bool mfma_only = m.d == 3 && p == 5;
+  require(tent_kernel_supported(m.d, p) || mfma_only, MTP_ERR_UNSUPPORTED, "degree p not covered for this dimension");
+  require(!(mfma_only && precision == MTP_FP64_VALU), MTP_ERR_UNSUPPORTED,
+          "the vector-ALU kernel covers p <= 4 in 3D");
   const size_t lim = 160 * 1024;
   if (m.n_curved > 0) {
     require(m.d == 2 && m.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED, "curved elements: 2D Maxwell only");
@@ -434,7 +438,7 @@ static int check_config(const Mesh& m, int p, int q, int mm, int precision) {
     return 2;
   }
   if (precision == MTP_FP64 && tent_mfma_lds_bytes(m.d, p, m.max_patch, 0) <= lim) return 1;
-  require(valu_ok, MTP_ERR_UNSUPPORTED, "largest vertex patch does not fit the 160 KiB of LDS");
+  require(valu_ok && !mfma_only, MTP_ERR_UNSUPPORTED, "largest vertex patch does not fit the 160 KiB of LDS");
   return 0;
 }
 

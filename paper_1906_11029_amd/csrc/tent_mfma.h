@@ -159,12 +159,12 @@ struct MShape {
   static constexpr int WAVES = BLOCK / 64;
   static constexpr int TILES_PER_WAVE = (MTF * NTILE_MAX + WAVES - 1) / WAVES;
   static constexpr int MAXPAIR = (NTMAX * NP + BLOCK - 1) / BLOCK;
-  // P4 patches of more than 24 tets (up to 28 product tiles on 8 waves): each wave takes whole
+  // P4 patches of more than 24 tets and P5 in 3D (up to 28 or 36 product tiles on 8 waves): each wave takes whole
   // column blocks and writes their R at once, so only one column block's row tiles hold
   // accumulators (4 tiles per wave do not fit the registers), and the Taylor sum of each
   // (element, node) pair stays in the tent's own entries of W (the pair belongs to one
   // thread for the whole tent) instead of registers
-  static constexpr bool COLB = D == 3 && P == 4 && NTMAX > 24;
+  static constexpr bool COLB = D == 3 && ((P == 4 && NTMAX > 24) || P >= 5);
   static constexpr bool ACCG = COLB;
 };
 
@@ -196,9 +196,10 @@ struct MLds {
 };
 
 // The capacity classes of the patch size: 8, 24, and a large class of 48 tets, or 36 for
-// P4 in 3D (the largest whose tent region fits the LDS once the operator block is moved out).
+// P4 in 3D (the largest whose tent region fits the LDS once the operator block is moved out);
+// P5 in 3D stops at 24.
 template <int D, int P>
-__host__ __device__ constexpr int big_class() { return (D == 3 && P == 4) ? 36 : 48; }
+__host__ __device__ constexpr int big_class() { return D == 3 ? (P == 4 ? 36 : P >= 5 ? 24 : 48) : 48; }
 
 // LDS pointers of one degree's operator block and of the tent region
 struct TentLds {

@@ -25,6 +25,7 @@ hipError_t launch_dt(const PersistentArgs& a, int d, int p, int max_patch, hipSt
       case 2: return launch_mdp<3, 2, T>(a, max_patch, s, resident);
       case 3: return launch_mdp<3, 3, T>(a, max_patch, s, resident);
       case 4: return launch_mdp<3, 4, T>(a, max_patch, s, resident);
+      case 5: return launch_mdp<3, 5, T>(a, max_patch, s, resident);
     }
   }
   return hipErrorInvalidValue;
@@ -46,6 +47,7 @@ hipError_t launch_bt(const BatchLaunch& bl, hipStream_t s) {
       case 2: return launch_mbp<3, 2, T>(bl, s);
       case 3: return launch_mbp<3, 3, T>(bl, s);
       case 4: return launch_mbp<3, 4, T>(bl, s);
+      case 5: return launch_mbp<3, 5, T>(bl, s);
     }
   }
   return hipErrorInvalidValue;
@@ -67,6 +69,7 @@ hipError_t launch_t(const KernelParams& kp, int64_t first, int64_t count, hipStr
       case 2: return launch_mp<3, 2, T>(kp, first, count, s);
       case 3: return launch_mp<3, 3, T>(kp, first, count, s);
       case 4: return launch_mp<3, 4, T>(kp, first, count, s);
+      case 5: return launch_mp<3, 5, T>(kp, first, count, s);
     }
   }
   return hipErrorInvalidValue;
@@ -88,6 +91,7 @@ size_t lds_t(int d, int p, int max_patch, int system) {
       case 2: return lds_mp<3, 2, T>(max_patch, system);
       case 3: return lds_mp<3, 3, T>(max_patch, system);
       case 4: return lds_mp<3, 4, T>(max_patch, system);
+      case 5: return lds_mp<3, 5, T>(max_patch, system);
     }
   }
   return (size_t)-1;
@@ -109,6 +113,7 @@ size_t opg_t(int d, int p, int max_patch, int system) {
       case 2: return opg_mp<3, 2, T>(max_patch, system);
       case 3: return opg_mp<3, 3, T>(max_patch, system);
       case 4: return opg_mp<3, 4, T>(max_patch, system);
+      case 5: return opg_mp<3, 5, T>(max_patch, system);
     }
   }
   return 0;
@@ -130,6 +135,7 @@ hipError_t stage_t(const KernelParams& kp, hipStream_t s) {
       case 2: return stage_mp<3, 2, T>(kp, s);
       case 3: return stage_mp<3, 3, T>(kp, s);
       case 4: return stage_mp<3, 4, T>(kp, s);
+      case 5: return stage_mp<3, 5, T>(kp, s);
     }
   }
   return hipErrorInvalidValue;

@@ -29,8 +29,10 @@
 #define MTP_MFMA_CONFIGS_3D_P3(X) X(3, 3, double) X(3, 3, float)
 #define MTP_MFMA_CONFIGS_3D_P4_F64(X) X(3, 4, double)
 #define MTP_MFMA_CONFIGS_3D_P4_F32(X) X(3, 4, float)
+// tent_mfma_3d_p5.hip
+#define MTP_MFMA_CONFIGS_3D_P5(X) X(3, 5, double) X(3, 5, float)
 
 #define MTP_MFMA_CONFIGS(X)                                                                               \
   MTP_MFMA_CONFIGS_2D_P12(X) MTP_MFMA_CONFIGS_2D_P3(X) MTP_MFMA_CONFIGS_2D_P4(X) MTP_MFMA_CONFIGS_2D_P5(X)  \
   MTP_MFMA_CONFIGS_3D_P1(X) MTP_MFMA_CONFIGS_3D_P2(X) MTP_MFMA_CONFIGS_3D_P3(X) MTP_MFMA_CONFIGS_3D_P4_F64(X) \
-  MTP_MFMA_CONFIGS_3D_P4_F32(X)
+  MTP_MFMA_CONFIGS_3D_P4_F32(X) MTP_MFMA_CONFIGS_3D_P5(X)

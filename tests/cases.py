@@ -18,6 +18,9 @@ CASES = {
     "cav3d_p2": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.25, kind=PEC, exact="pec_3d"),
     "cav3d_p3": dict(mesh=("kuhn", 2), p=3, q=4, m=6, T=0.25, kind=PEC, exact="pec_3d"),
     "cav3d_p4": dict(mesh=("kuhn", 2), p=4, q=5, m=8, T=0.125, kind=PEC, exact="pec_3d"),
+    # P5 in 3D (matrix-core kernels only: operator block in device memory, column-block products)
+    "cav3d_p5": dict(mesh=("kuhn", 2), p=5, q=6, m=10, T=0.1, kind=PEC, exact="pec_3d"),
+    "cav3d_p5_pmc_eps": dict(mesh=("kuhn", 2), p=5, q=6, m=10, T=0.1, kind=PMC, exact="pec_3d", eps_split=True),
     "cav3d_p2_pmc_eps": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.2, kind=PMC, exact="pec_3d", eps_split=True),
     "planewave3d_p2": dict(mesh=("kuhn", 2), p=2, q=3, m=4, T=0.2, kind=DATA, exact="pw_3d"),
     "graded3d_p3_eps": dict(mesh=("kuhn_graded", 3), p=3, q=4, m=6, T=0.06, kind=PEC, exact="pulse",
