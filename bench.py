@@ -43,6 +43,10 @@ def workload(name):
         mm = meshes.cube_kuhn(16)
         desc = "3D PEC cavity mode, unit cube 16^3x6 Kuhn tets (24576), P3, q=4, m=6, slab T=1"
         return dict(name=name, mm=mm, p=3, q=4, m=6, T=1.0, ex=fields.Cavity3D_PEC(), desc=desc, exact=True)
+    if name == "cavity3d_p5":
+        mm = meshes.cube_kuhn(16)
+        desc = "3D PEC cavity mode, unit cube 16^3x6 Kuhn tets (24576), P5, q=6, m=10, slab T=0.5"
+        return dict(name=name, mm=mm, p=5, q=6, m=10, T=0.5, ex=fields.Cavity3D_PEC(), desc=desc, exact=True)
     if name == "graded3d_p4":
         grade = lambda g: GRADE_A * g + (1 - GRADE_A) * g * g  # noqa: E731
         mm = meshes.cube_kuhn(32, axis_map=grade)
