@@ -222,7 +222,8 @@ void mtp_tents_destroy(mtp_tents tents);
 /* Device workspace needed by a solver for (mesh, tents, p, q, m, precision). */
 mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q,
                                      int32_t m, int32_t precision, size_t* bytes);
-/* Create a solver: spatial degree p (1..5 in 2D, 1..4 in 3D), Taylor order q >= 1 and
+/* Create a solver: spatial degree p (1..5 in 2D, 1..5 in 3D; 3D P5 on the matrix-core
+ * kernels only, for vertex patches of up to 24 tets), Taylor order q >= 1 and
  * m >= 1 sub-intervals per tent (section 4; the paper uses q = p+1, m = 2p), flux
  * penalty alpha (1/2 is the exact upwind flux for unit impedance, 1 the printed
  * coefficient).  d_workspace: device pointer of at least the reported bytes, owned by
