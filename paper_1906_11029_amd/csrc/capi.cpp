@@ -1244,8 +1244,7 @@ mtp_status mtp_solver_set_method(mtp_solver s, int32_t method) {
   require(s->layers_done == 0, MTP_ERR_STATE, "front is not flat (a slab is half done)");
   require(method == MTP_METHOD_SAT || !s->curved, MTP_ERR_UNSUPPORTED, "curved elements run SAT only");
   if (method == MTP_METHOD_RK4)
-    require(s->kernel == 1 && s->mesh.system == MTP_SYSTEM_MAXWELL, MTP_ERR_UNSUPPORTED,
-            "the RK4 variant runs on the FP64 matrix-core kernel, Maxwell only");
+    require(s->kernel == 1, MTP_ERR_UNSUPPORTED, "the RK4 variant runs on the FP64 matrix-core kernel");
   if (method != s->method) {
     check_hip(hipStreamSynchronize(s->stream), "sync");
     drop_graph(s);   // the captured launches hold the old parameter block

@@ -1085,6 +1085,7 @@ hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStr
   // launched as RK4), so no kernel is instantiated by two translation units
   auto kfn_rk4 = tent_mfma_kernel<D, P, T, NTMAX, WPE, sizeof(T) == 8>;
   auto kfn_ac = tent_mfma_kernel<D, P, T, NTMAX, WPE, false, 1>;
+  auto kfn_ac_rk4 = tent_mfma_kernel<D, P, T, NTMAX, WPE, sizeof(T) == 8, 1>;   // FP64 only, as above
   if (count < 0) {   // prepare: allow the dynamic LDS size (done once, outside graph capture)
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1094,11 +1095,18 @@ hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStr
     if (e == hipSuccess && lds_ac <= 160 * 1024)
       e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn_ac), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds_ac);
+    if (e == hipSuccess && sizeof(T) == 8 && lds_ac <= 160 * 1024)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(kfn_ac_rk4),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_ac);
     return e;
   }
   if (kp.system == 1) {
-    if (kp.method != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kfn_ac, dim3((unsigned)count), dim3(BLOCK), lds_ac, s, kp, first, count);
+    if (kp.method == 1) {
+      if (sizeof(T) != 8) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(kfn_ac_rk4, dim3((unsigned)count), dim3(BLOCK), lds_ac, s, kp, first, count);
+    } else {
+      hipLaunchKernelGGL(kfn_ac, dim3((unsigned)count), dim3(BLOCK), lds_ac, s, kp, first, count);
+    }
   } else if (kp.method == 1) {
     if (sizeof(T) != 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)count), dim3(BLOCK), lds, s, kp, first, count);
@@ -1152,9 +1160,18 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
   auto kfn_rk4 = tent_mfma_dag_kernel<D, P, T, NTMAX, 2, sizeof(T) == 8>;   // FP64 only, as above
   auto kfn_ac = tent_mfma_dag_kernel<D, P, T, NTMAX, 2, false, 1>;
+  auto kfn_ac_rk4 = tent_mfma_dag_kernel<D, P, T, NTMAX, 2, sizeof(T) == 8, 1>;   // FP64 only, as above
   const size_t lds_ac = MLds<D, P, T, NTMAX, 1>::bytes;
   if (resident) {   // the residency of the variant the solver runs (all: the smallest)
-    if (a.kp && a.kp->system == 1) return resident_grid(reinterpret_cast<const void*>(kfn_ac), BLOCK, lds_ac, resident);
+    if (a.kp && a.kp->system == 1) {
+      hipError_t e = resident_grid(reinterpret_cast<const void*>(kfn_ac), BLOCK, lds_ac, resident);
+      if (e == hipSuccess && sizeof(T) == 8) {
+        int r2 = 0;
+        e = resident_grid(reinterpret_cast<const void*>(kfn_ac_rk4), BLOCK, lds_ac, &r2);
+        *resident = std::min(*resident, r2);
+      }
+      return e;
+    }
     hipError_t e = resident_grid(reinterpret_cast<const void*>(kfn), BLOCK, lds, resident);
     if (e == hipSuccess && sizeof(T) == 8) {
       int r2 = 0;
@@ -1166,8 +1183,12 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   if (a.kp->dag_n <= 0) return hipSuccess;
   if (a.kp->dag_grid <= 0) return hipErrorInvalidValue;
   if (a.kp->system == 1) {
-    if (a.kp->method != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kfn_ac, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds_ac, s, *a.kp);
+    if (a.kp->method == 1) {
+      if (sizeof(T) != 8) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(kfn_ac_rk4, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds_ac, s, *a.kp);
+    } else {
+      hipLaunchKernelGGL(kfn_ac, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds_ac, s, *a.kp);
+    }
   } else if (a.kp->method == 1) {
     if (sizeof(T) != 8) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)a.kp->dag_grid), dim3(BLOCK), lds, s, *a.kp);

@@ -88,6 +88,15 @@ AC_CASES = {
 }
 
 
+# linear acoustics under the classical RK4 variant (FP64 matrix-core kernel)
+AC_RK4_CASES = {
+    "ac2d_rigid_p3_rk4": dict(mesh=("square", 4), p=3, q=4, m=6, T=0.4, kind=PMC, exact="ac_cav2", system="acoustic",
+                              method="rk4"),
+    "ac3d_release_eps_p3_rk4": dict(mesh=("kuhn", 2), p=3, q=4, m=6, T=0.2, kind=PEC, exact="ac_pulse3",
+                                    eps_split=True, system="acoustic", method="rk4"),
+}
+
+
 # Curved cases: the disk with quadratic boundary triangles (oracle/curved.py, weight-adjusted
 # scheme), against the circular-cavity TE mode's initial data.
 CURVED_CASES = {
@@ -165,7 +174,7 @@ def planewave_params(ex, dim):
 
 def setup(name):
     c = dict(CASES.get(name) or RK4_CASES.get(name) or IMP_CASES.get(name) or CURVED_CASES.get(name)
-             or COLOUR_CASES.get(name) or LARGE_P4_CASES.get(name) or AC_CASES[name])
+             or COLOUR_CASES.get(name) or LARGE_P4_CASES.get(name) or AC_RK4_CASES.get(name) or AC_CASES[name])
     c.setdefault("curved", False)
     c.setdefault("rule", "min_vertex")
     c.setdefault("system", "maxwell")

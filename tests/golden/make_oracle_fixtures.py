@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 sys.path.insert(0, os.path.dirname(HERE))
 
-from cases import (AC_CASES, CASES, COLOUR_CASES, CURVED_CASES, DATA, IMP_CASES, LARGE_P4_CASES,  # noqa: E402
-                   RK4_CASES, setup)
+from cases import (AC_CASES, AC_RK4_CASES, CASES, COLOUR_CASES, CURVED_CASES, DATA, IMP_CASES,  # noqa: E402
+                   LARGE_P4_CASES, RK4_CASES, setup)
 from oracle import curved  # noqa: E402
 from oracle.mesh import Mesh  # noqa: E402
 from oracle.pitch import pitch  # noqa: E402
@@ -55,7 +55,7 @@ def make(name):
 
 if __name__ == "__main__":
     names = sys.argv[1:] or (list(CASES) + list(RK4_CASES) + list(IMP_CASES) + list(AC_CASES) + list(CURVED_CASES)
-                             + list(COLOUR_CASES) + list(LARGE_P4_CASES))
+                             + list(COLOUR_CASES) + list(LARGE_P4_CASES) + list(AC_RK4_CASES))
     for n in names:
         t0 = time.time()
         make(n)

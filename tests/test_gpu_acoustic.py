@@ -95,9 +95,11 @@ def test_acoustic_rejected_where_unsupported():
     c, mm, dim, eps, mu, bc, ex, u0 = setup("ac3d_rigid_p2")
     M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc, system=mtp.MTP_SYSTEM_ACOUSTIC)
     T = mtp.Tents(M, c["T"], 0.5)
-    S = mtp.Solver(M, T, c["p"], c["q"], c["m"])
-    with pytest.raises(mtp.MTPError):
+    S = mtp.Solver(M, T, c["p"], c["q"], c["m"], precision=mtp.MTP_MIXED_FP32)
+    with pytest.raises(mtp.MTPError):   # RK4 runs on the FP64 kernel only
         S.set_method(mtp.MTP_METHOD_RK4)
+    with pytest.raises(mtp.MTPError):   # acoustics has no vector-ALU kernel
+        mtp.Solver(M, T, c["p"], c["q"], c["m"], precision=mtp.MTP_FP64_VALU)
 
 
 @pytest.mark.parametrize("schedule", [0, 1])
@@ -128,3 +130,19 @@ def test_batches_refuse_mixed_systems():
     with pytest.raises(mtp.MTPError) as e:
         mtp.Batch([A, S])
     assert e.value.code == -9
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("name", ["ac2d_rigid_p3_rk4", "ac3d_release_eps_p3_rk4"])
+def test_acoustic_rk4_against_oracle(name, schedule):
+    """Linear acoustics under the classical RK4 variant (FP64 matrix-core kernel), per-layer
+    and persistent, against the oracle's RK4 solve: element by element <= 1e-10."""
+    from paper_1906_11029_amd import mtp
+    print(f"[gpu acoustic] {name} schedule {schedule}", flush=True)
+    ref = fixture(name)
+    c, S, T = make(name, 0)
+    S.set_method(mtp.MTP_METHOD_RK4)
+    S.set_schedule(schedule)
+    S.advance_to(c["slabs"] * c["T"])
+    assert_parity(S.get_state(), ref["w"], 1e-10, name)
+    assert_parity(S.get_fields(), ref["u"], 1e-10, name)
