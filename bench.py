@@ -55,6 +55,20 @@ def workload(name):
                 "eps in {1, 2.25} split at x=0.5, Gaussian-pulse E, P4, q=5, m=8, slab T=0.05")
         return dict(name=name, mm=mm, p=4, q=5, m=8, T=0.05, ex=fields.GaussianPulse3D(seed=11030),
                     desc=desc, eps=eps, mu=mu, exact=False, cert="graded3d_p4_cavity")
+    if name in ("delaunay3d_p4", "delaunay3d_p4_cavity"):
+        # the 33^3-point lattice graded toward one corner, jittered and Delaunay-triangulated:
+        # patches of 4-44 tets (61 % above 24, 410 vertices above 36: the 48-tet class)
+        mm = meshes.graded_delaunay_cube()
+        base = ("unit cube, 33^3-point lattice graded toward one corner (h ratio 1:8), jittered by 0.15 h and "
+                "Delaunay-triangulated (226989 tets, vertex patches of up to 44 tets)")
+        if name == "delaunay3d_p4":
+            eps, mu = meshes.materials_split(mm)
+            desc = ("3D PEC, " + base + ", eps in {1, 2.25} split at x=0.5, Gaussian-pulse E, P4, q=5, m=8, "
+                    "slab T=0.01")
+            return dict(name=name, mm=mm, p=4, q=5, m=8, T=0.01, ex=fields.GaussianPulse3D(seed=11030),
+                        desc=desc, eps=eps, mu=mu, exact=False, cert="delaunay3d_p4_cavity")
+        desc = "3D PEC cavity mode, " + base + ", eps = mu = 1, P4, q=5, m=8, slab T=0.01 (equal-error check)"
+        return dict(name=name, mm=mm, p=4, q=5, m=8, T=0.01, ex=fields.Cavity3D_PEC(), desc=desc, exact=True)
     if name == "graded3d_p4_cavity":
         grade = lambda g: GRADE_A * g + (1 - GRADE_A) * g * g  # noqa: E731
         mm = meshes.cube_kuhn(32, axis_map=grade)

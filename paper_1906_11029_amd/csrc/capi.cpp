@@ -37,11 +37,12 @@ struct Layout {
 struct Offsets {
   size_t W, tau, stage, grad_lam, cells, eps, mu, coords, pptr, pelem, pinfo, fptr, face, tv, tt, S, L,
       fnode, fswap, perm, mi, err, slab, dag_indeg, dag_indeg0, dag_sptr, dag_succ, dag_queue, dag_ctl,
-      cref, cgeo, cnbr, czone, opg, total;
+      cref, cgeo, cnbr, czone, opg, frg, total;
 };
 
-// opg_bytes: the matrix-core kernel's operator block when it stays in device memory (0 if not)
-static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc, size_t opg_bytes) {
+// opg_bytes: the matrix-core kernel's operator block when it stays in device memory (0 if not);
+// frg_bytes: the F/R slots of the extra-large patch class (0 if not)
+static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc, size_t opg_bytes, size_t frg_bytes) {
   Layout L;
   Offsets o;
   const int d = m.d;
@@ -84,6 +85,7 @@ static Offsets plan(const Mesh& m, const Tents& t, const RefElem& R, int nc, siz
   o.cnbr = L.add(cur ? sizeof(int32_t) * cp.zone_elem.size() * 6 : 0);
   o.czone = L.add(cur ? sizeof(int32_t) * m.ne : 0);
   o.opg = L.add(opg_bytes);
+  o.frg = L.add(frg_bytes);
   o.total = L.off;
   return o;
 }
@@ -448,13 +450,21 @@ static size_t opg_bytes(const Mesh& m, int p, int kernel) {
   return kernel == 0 ? 0 : tent_mfma_opg_bytes(m.d, p, m.max_patch, kernel == 2, m.system);
 }
 
+// P4 patches of 37-48 tets in 3D keep the tent's F/R in device memory, one slot per
+// workgroup: kFrgSlots slots (four per compute unit of the largest device; the launches cap
+// their grid at it), about 104 KB each.
+static constexpr int kFrgSlots = 1024;
+static size_t frg_bytes(const Mesh& m, int p, int kernel) {
+  return kernel == 0 ? 0 : tent_mfma_frg_bytes(m.d, p, m.max_patch, kernel == 2, m.system) * kFrgSlots;
+}
+
 mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q, int32_t m,
                                      int32_t precision, size_t* bytes) {
   MTP_TRY
   require(mesh && tents && bytes, MTP_ERR_ARG, "null pointer");
   const int kernel = check_config(mesh->m, p, q, m, precision);
   RefElem R = build_refelem(mesh->m.d, p);
-  *bytes = plan(mesh->m, tents->t, R, ncomp(mesh->m), opg_bytes(mesh->m, p, kernel)).total;
+  *bytes = plan(mesh->m, tents->t, R, ncomp(mesh->m), opg_bytes(mesh->m, p, kernel), frg_bytes(mesh->m, p, kernel)).total;
   MTP_CATCH
 }
 
@@ -468,7 +478,9 @@ static std::string device_tag(int dev) {
   if (c != std::string::npos) arch.resize(c);
   return arch + "x" + std::to_string(pr.multiProcessorCount);
 }
-static int patch_class(int max_patch) { return max_patch <= 8 ? 8 : max_patch <= 24 ? 24 : 48; }
+static int patch_class(int d, int p, int max_patch) {
+  return max_patch <= 8 ? 8 : max_patch <= 24 ? 24 : (d == 3 && p == 4 && max_patch <= 36) ? 36 : 48;
+}
 static int log2_class(int64_t n) {
   int c = 0;
   while (c < 62 && ((int64_t)1 << (c + 1)) <= n) ++c;
@@ -480,7 +492,7 @@ static int tents_class(int64_t n) { return log2_class(n) / 2; }
 static std::string solver_key(mtp_solver s) {
   return "solver|" + device_tag(s->device) + "|d" + std::to_string(s->mesh.d) + "|sys" +
          std::to_string(s->mesh.system) + "|p" + std::to_string(s->p) + "|k" + std::to_string(s->kernel) + "|m" +
-         std::to_string(s->method) + "|nt" + std::to_string(patch_class(s->mesh.max_patch)) + "|t" +
+         std::to_string(s->method) + "|nt" + std::to_string(patch_class(s->mesh.d, s->p, s->mesh.max_patch)) + "|t" +
          std::to_string(tents_class((int64_t)s->tents.vertex.size()));
 }
 static void drop_graph(mtp_solver s);
@@ -545,7 +557,7 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
     s->q = q;
     s->m = m;
     s->nc = ncomp(mesh->m);
-    s->off = plan(s->mesh, s->tents, s->ref, s->nc, opg_bytes(s->mesh, p, kernel));
+    s->off = plan(s->mesh, s->tents, s->ref, s->nc, opg_bytes(s->mesh, p, kernel), frg_bytes(s->mesh, p, kernel));
     require(bytes >= s->off.total, MTP_ERR_ARG, "workspace too small");
     s->ws = static_cast<char*>(d_workspace);
     s->stream = static_cast<hipStream_t>(hip_stream);
@@ -636,7 +648,12 @@ mtp_status mtp_solver_create(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t 
       s->device = dev;
       check_hip(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
       kp.dag_wait_ticks = (int64_t)khz * 1000 * 10;   // 10 s
+      if (frg_bytes(M, p, kernel) > 0) {   // F/R slots of the extra-large patch class
+        kp.frg = reinterpret_cast<double*>(s->ws + s->off.frg);
+        kp.frg_slots = kFrgSlots;
+      }
       kp.dag_grid = s->kernel == 0 ? 0 : tent_dag_grid(kp, s->kernel == 2);
+      if (kp.frg) kp.dag_grid = std::min(kp.dag_grid, kp.frg_slots);
     }
     check_hip(prepare_tent_kernel(kp, s->kernel), "tent kernel attributes");
     if (opg_bytes(s->mesh, p, kernel) > 0) {   // the operator block, written once
@@ -929,6 +946,7 @@ static void batch_check(const mtp_solver* solvers, int32_t n) {
     require(s->method == MTP_METHOD_SAT, MTP_ERR_UNSUPPORTED, "batches run SAT only");
     require(s->mesh.system == solvers[0]->mesh.system, MTP_ERR_UNSUPPORTED, "a batch needs one system");
     require(!s->curved, MTP_ERR_UNSUPPORTED, "batches do not run curved elements");
+    require(s->kp.frg == nullptr, MTP_ERR_UNSUPPORTED, "P4 patches of more than 36 tets run in single solves only");
     for (int j = 0; j < i; ++j) require(solvers[j] != s, MTP_ERR_ARG, "solver listed twice");
   }
 }
@@ -974,16 +992,16 @@ mtp_status mtp_batch_workspace_size(const mtp_solver* solvers, int32_t n, size_t
 
 static std::string batch_key(mtp_batch b) {
   std::string degs;
-  int mp = 0;
   int64_t tents = 0;
+  int cls = 0;
   for (const auto& g : b->groups) {
     degs += std::to_string(g.p);
-    mp = std::max(mp, g.max_patch);
+    cls = std::max(cls, patch_class(b->d, g.p, g.max_patch));
   }
   for (mtp_solver s : b->solvers) tents += (int64_t)s->tents.vertex.size();
   return "batch|" + device_tag(b->solvers[0]->device) + "|d" + std::to_string(b->d) + "|sys" + std::to_string(b->system) +
          "|p" + degs + "|k" +
-         std::to_string(b->kernel) + "|nt" + std::to_string(patch_class(mp)) + "|t" + std::to_string(tents_class(tents)) +
+         std::to_string(b->kernel) + "|nt" + std::to_string(cls) + "|t" + std::to_string(tents_class(tents)) +
          "|n" + std::to_string(log2_class((int64_t)b->solvers.size()));
 }
 static void drop_batch_graph(mtp_batch b);

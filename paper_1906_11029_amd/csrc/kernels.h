@@ -37,6 +37,10 @@ struct KernelParams {
   // matrix-core kernels whose operator block does not fit the LDS beside the tent region:
   // the block in device memory (null otherwise)
   double* opg;
+  // the extra-large patch class (F/R of the tent in device memory): frg_slots slots of one
+  // workgroup's F/R each; the launches keep their grid within frg_slots (null / 0 otherwise)
+  double* frg;
+  int32_t frg_slots;
   double* tau;             // nv
   int32_t* err;            // device error flags
   // tents of the launch
@@ -128,6 +132,8 @@ size_t tent_mfma_lds_bytes(int d, int p, int max_patch, int fp32, int system = 0
 // the launch that writes it to kp.opg once
 size_t tent_mfma_opg_bytes(int d, int p, int max_patch, int fp32, int system);
 hipError_t stage_tent_operator_mfma(const KernelParams& kp, int fp32, hipStream_t s);
+// bytes of one workgroup's F/R slot in device memory (0: F/R in LDS)
+size_t tent_mfma_frg_bytes(int d, int p, int max_patch, int fp32, int system);
 hipError_t launch_tent_layer_mfma(const KernelParams& kp, int64_t first, int64_t count, int fp32, hipStream_t s);
 // persistent schedule: reset the DAG state for one slab, then run every tent of the slab in
 // one launch of kp.dag_grid workgroups (grid < 0: only set the kernel attributes)

@@ -168,6 +168,14 @@ struct MShape {
   static constexpr bool ACCG = COLB;
 };
 
+// The capacity classes of the patch size: 8, 24, and a large class of 48 tets, or 36 for
+// P4 in 3D (the largest whose tent region fits the LDS once the operator block is moved out),
+// which has a fourth, extra-large class of 48 (F/R in device memory); P5 in 3D stops at 24.
+template <int D, int P>
+__host__ __device__ constexpr int big_class() { return D == 3 ? (P == 4 ? 36 : P >= 5 ? 24 : 48) : 48; }
+template <int D, int P>
+__host__ __device__ constexpr int xl_class() { return D == 3 && P == 4 ? 48 : -1; }
+
 // LDS layout, identical for both variants (state, fluxes and operators stored in FP64; the
 // mixed variant only changes the precision of the products of stages n >= 2): an operator
 // block (FP64 operator, in the mixed kernel the FP32 copy of its volume part, the face-node
@@ -191,15 +199,15 @@ struct MLds {
   // tets) stays in device memory, written once per solver (KernelParams::opg); the products
   // then read their A operand through the caches.
   static constexpr size_t LDS_LIMIT = 160 * 1024;
-  static constexpr bool OPG = (op_block + common) * 8 > LDS_LIMIT && common * 8 <= LDS_LIMIT;
-  static constexpr size_t bytes = ((OPG ? 0 : op_block) + common) * 8;
+  // The extra-large class (P4 patches of 37-48 tets in 3D) keeps the operator block in LDS
+  // and moves F/R instead, a slot of f_elems doubles per workgroup (KernelParams::frg): F/R
+  // is the B operand of the lift part only and the input of the pointwise update, read far
+  // less often than the operator.
+  static constexpr bool FRG = NTMAX == xl_class<D, P>();
+  static constexpr bool OPG = !FRG && (op_block + common) * 8 > LDS_LIMIT && common * 8 <= LDS_LIMIT;
+  static constexpr size_t frg_doubles = FRG ? f_elems : 0;
+  static constexpr size_t bytes = ((OPG ? 0 : op_block) + common - frg_doubles) * 8;
 };
-
-// The capacity classes of the patch size: 8, 24, and a large class of 48 tets, or 36 for
-// P4 in 3D (the largest whose tent region fits the LDS once the operator block is moved out);
-// P5 in 3D stops at 24.
-template <int D, int P>
-__host__ __device__ constexpr int big_class() { return D == 3 ? (P == 4 ? 36 : P >= 5 ? 24 : 48) : 48; }
 
 // LDS pointers of one degree's operator block and of the tent region
 struct TentLds {
@@ -221,8 +229,10 @@ struct TentLds {
   int* sPF;        // [face]: patch face code (element << 2 | face)
 };
 
+// op: the operator block; common: the tent region in LDS; fr: the workgroup's F/R slot in
+// device memory (classes with MLds::FRG only)
 template <int D, int P, typename T, int NTMAX, int SYS>
-__device__ __forceinline__ TentLds tent_lds(double* op, double* common) {
+__device__ __forceinline__ TentLds tent_lds(double* op, double* common, double* fr) {
   using SH = MShape<D, P, NTMAX, SYS>;
   using LD = MLds<D, P, T, NTMAX, SYS>;
   constexpr int NV = SH::NV;
@@ -232,8 +242,8 @@ __device__ __forceinline__ TentLds tent_lds(double* op, double* common) {
   L.sFn = reinterpret_cast<int*>(op + LD::op_elems);
   L.sFsw = L.sFn + D * 2 * SH::NF;
   L.sU = common;
-  L.sFR = L.sU + LD::u_elems;
-  L.sGL = L.sFR + LD::f_elems;
+  L.sFR = LD::FRG ? fr : L.sU + LD::u_elems;
+  L.sGL = L.sU + LD::u_elems + (LD::f_elems - LD::frg_doubles);
   L.sBb = L.sGL + NTMAX * NV * D;
   L.sEM = L.sBb + NTMAX * D;
   L.sRat = L.sEM + NTMAX * 2;
@@ -1009,8 +1019,17 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
   extern __shared__ double lds_d[];
   // the operator block in LDS (staged here), or in device memory (staged once per solver;
   // all solvers of a batch share dimension and degree, hence its contents)
-  const TentLds L = LD::OPG ? tent_lds<D, P, T, NTMAX, SYS>(kp0.opg, lds_d)
-                            : tent_lds<D, P, T, NTMAX, SYS>(lds_d, lds_d + LD::op_block);
+  // F/R slot of this workgroup (FRG classes): the launches keep the grid within kp0.frg_slots.
+  // Taken through a global-address-space pointer, so that its loads and stores are global
+  // (not flat) memory instructions and do not wait on the LDS counter.
+  double* fr = nullptr;
+  if constexpr (LD::FRG) {
+    using gdouble = __attribute__((address_space(1))) double;
+    gdouble* g = (gdouble*)(kp0.frg + (size_t)blockIdx.x * LD::frg_doubles);
+    fr = (double*)g;
+  }
+  const TentLds L = LD::OPG ? tent_lds<D, P, T, NTMAX, SYS>(kp0.opg, lds_d, fr)
+                            : tent_lds<D, P, T, NTMAX, SYS>(lds_d, lds_d + LD::op_block, fr);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform (scalar registers)
@@ -1033,7 +1052,7 @@ __device__ __forceinline__ void tent_mfma_body(const KernelParams& kp0, Sched sc
 // (kp.opg, MLds::op_block doubles) in the layout the products read.
 template <int D, int P, typename T, int NTMAX, int SYS>
 __global__ void __launch_bounds__(tent_block<D>()) stage_operator_kernel(KernelParams kp) {
-  const TentLds L = tent_lds<D, P, T, NTMAX, SYS>(kp.opg, kp.opg);   // only the operator block is written
+  const TentLds L = tent_lds<D, P, T, NTMAX, SYS>(kp.opg, kp.opg, nullptr);   // only the operator block is written
   stage_operator<D, P, T, NTMAX, SYS>(kp, L, threadIdx.x);
 }
 
@@ -1100,18 +1119,26 @@ hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStr
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_ac);
     return e;
   }
+  // one workgroup per tent; a class with F/R in device memory runs at most kp.frg_slots
+  // workgroups (one slot each), every workgroup then taking every grid-th tent of the range
+  int64_t grid = count;
+  if constexpr (MLds<D, P, T, NTMAX>::FRG) {
+    if (!kp.frg || kp.frg_slots <= 0) return hipErrorInvalidValue;
+    grid = std::min<int64_t>(count, kp.frg_slots);
+  }
+  if (grid <= 0) return hipSuccess;
   if (kp.system == 1) {
     if (kp.method == 1) {
       if (sizeof(T) != 8) return hipErrorInvalidValue;
-      hipLaunchKernelGGL(kfn_ac_rk4, dim3((unsigned)count), dim3(BLOCK), lds_ac, s, kp, first, count);
+      hipLaunchKernelGGL(kfn_ac_rk4, dim3((unsigned)grid), dim3(BLOCK), lds_ac, s, kp, first, count);
     } else {
-      hipLaunchKernelGGL(kfn_ac, dim3((unsigned)count), dim3(BLOCK), lds_ac, s, kp, first, count);
+      hipLaunchKernelGGL(kfn_ac, dim3((unsigned)grid), dim3(BLOCK), lds_ac, s, kp, first, count);
     }
   } else if (kp.method == 1) {
     if (sizeof(T) != 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)count), dim3(BLOCK), lds, s, kp, first, count);
+    hipLaunchKernelGGL(kfn_rk4, dim3((unsigned)grid), dim3(BLOCK), lds, s, kp, first, count);
   } else {
-    hipLaunchKernelGGL(kfn, dim3((unsigned)count), dim3(BLOCK), lds, s, kp, first, count);
+    hipLaunchKernelGGL(kfn, dim3((unsigned)grid), dim3(BLOCK), lds, s, kp, first, count);
   }
   return hipGetLastError();
 }
@@ -1142,6 +1169,9 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
   constexpr int BLOCK = MShape<D, P, NTMAX>::BLOCK;
   if (a.bd) {   // a batch of one system (the acoustic variant when a.bd->system == 1)
+    if constexpr (MLds<D, P, T, NTMAX>::FRG) {
+      return hipErrorNotSupported;   // the extra-large class runs single solves only
+    } else {
     auto kfn = tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2>;
     auto kfn_ac = tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2, 1>;
     const bool ac = a.bd->system == 1;
@@ -1156,6 +1186,7 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
     else
       hipLaunchKernelGGL(kfn, dim3((unsigned)a.bd->grid), dim3(BLOCK), lds_b, s, a.kps, *a.bd);
     return hipGetLastError();
+    }
   }
   auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
   auto kfn_rk4 = tent_mfma_dag_kernel<D, P, T, NTMAX, 2, sizeof(T) == 8>;   // FP64 only, as above
@@ -1182,6 +1213,7 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   }
   if (a.kp->dag_n <= 0) return hipSuccess;
   if (a.kp->dag_grid <= 0) return hipErrorInvalidValue;
+  if (MLds<D, P, T, NTMAX>::FRG && (!a.kp->frg || a.kp->dag_grid > a.kp->frg_slots)) return hipErrorInvalidValue;
   if (a.kp->system == 1) {
     if (a.kp->method == 1) {
       if (sizeof(T) != 8) return hipErrorInvalidValue;
@@ -1204,6 +1236,9 @@ hipError_t launch_mdp(const PersistentArgs& a, int max_patch, hipStream_t s, int
   if (max_patch <= 8) return launch_md<D, P, T, 8>(a, s, resident);
   if (max_patch <= 24) return launch_md<D, P, T, 24>(a, s, resident);
   if (max_patch <= NB) return launch_md<D, P, T, NB>(a, s, resident);
+  constexpr int XL = xl_class<D, P>();
+  if constexpr (XL > 0)
+    if (max_patch <= XL) return launch_md<D, P, T, XL>(a, s, resident);
   return hipErrorInvalidValue;
 }
 
@@ -1246,6 +1281,9 @@ hipError_t launch_mp(const KernelParams& kp, int64_t first, int64_t count, hipSt
   if (kp.max_patch <= 8) return launch_m<D, P, T, 8>(kp, first, count, s);
   if (kp.max_patch <= 24) return launch_m<D, P, T, 24>(kp, first, count, s);
   if (kp.max_patch <= NB) return launch_m<D, P, T, NB>(kp, first, count, s);
+  constexpr int XL = xl_class<D, P>();
+  if constexpr (XL > 0)
+    if (kp.max_patch <= XL) return launch_m<D, P, T, XL>(kp, first, count, s);
   return hipErrorInvalidValue;
 }
 
@@ -1263,6 +1301,18 @@ size_t opg_mp(int max_patch, int system) {
   if (max_patch <= 8) return opg_m<D, P, T, 8>(system);
   if (max_patch <= 24) return opg_m<D, P, T, 24>(system);
   if (max_patch <= NB) return opg_m<D, P, T, NB>(system);
+  return 0;   // the extra-large class keeps its operator in LDS
+}
+
+// Bytes of one workgroup's F/R slot in device memory for the class max_patch falls in (0 if
+// the class keeps F/R in LDS).
+template <int D, int P, typename T>
+size_t frg_mp(int max_patch, int system) {
+  constexpr int NB = big_class<D, P>(), XL = xl_class<D, P>();
+  if constexpr (XL > 0) {
+    if (max_patch > NB && max_patch <= XL)
+      return (system == 1 ? MLds<D, P, T, XL, 1>::frg_doubles : MLds<D, P, T, XL>::frg_doubles) * 8;
+  }
   return 0;
 }
 
@@ -1289,6 +1339,7 @@ hipError_t stage_mp(const KernelParams& kp, hipStream_t s) {
   if (kp.max_patch <= 8) return stage_m<D, P, T, 8>(kp, s);
   if (kp.max_patch <= 24) return stage_m<D, P, T, 24>(kp, s);
   if (kp.max_patch <= NB) return stage_m<D, P, T, NB>(kp, s);
+  if (kp.max_patch <= xl_class<D, P>()) return hipSuccess;   // operator staged in LDS
   return hipErrorInvalidValue;
 }
 
@@ -1299,11 +1350,15 @@ size_t lds_mp(int max_patch, int system) {
     if (max_patch <= 8) return MLds<D, P, T, 8, 1>::bytes;
     if (max_patch <= 24) return MLds<D, P, T, 24, 1>::bytes;
     if (max_patch <= NB) return MLds<D, P, T, NB, 1>::bytes;
+    if constexpr (xl_class<D, P>() > 0)
+      if (max_patch <= xl_class<D, P>()) return MLds<D, P, T, xl_class<D, P>(), 1>::bytes;
     return (size_t)-1;
   }
   if (max_patch <= 8) return MLds<D, P, T, 8>::bytes;
   if (max_patch <= 24) return MLds<D, P, T, 24>::bytes;
   if (max_patch <= NB) return MLds<D, P, T, NB>::bytes;
+  if constexpr (xl_class<D, P>() > 0)
+    if (max_patch <= xl_class<D, P>()) return MLds<D, P, T, xl_class<D, P>()>::bytes;
   return (size_t)-1;
 }
 

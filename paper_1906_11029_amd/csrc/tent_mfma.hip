@@ -149,6 +149,11 @@ size_t tent_mfma_opg_bytes(int d, int p, int max_patch, int fp32, int system) {
   return fp32 ? opg_t<float>(d, p, max_patch, system) : opg_t<double>(d, p, max_patch, system);
 }
 
+size_t tent_mfma_frg_bytes(int d, int p, int max_patch, int fp32, int system) {
+  if (d != 3 || p != 4) return 0;   // only P4 in 3D has the extra-large class
+  return fp32 ? frg_mp<3, 4, float>(max_patch, system) : frg_mp<3, 4, double>(max_patch, system);
+}
+
 hipError_t stage_tent_operator_mfma(const KernelParams& kp, int fp32, hipStream_t s) {
   return fp32 ? stage_t<float>(kp, s) : stage_t<double>(kp, s);
 }

@@ -8,6 +8,7 @@
   template hipError_t launch_mp<D, P, T>(const KernelParams&, int64_t, int64_t, hipStream_t);             \
   template size_t lds_mp<D, P, T>(int, int);                                                              \
   template size_t opg_mp<D, P, T>(int, int);                                                              \
+  template size_t frg_mp<D, P, T>(int, int);                                                              \
   template hipError_t stage_mp<D, P, T>(const KernelParams&, hipStream_t);
 #define MTP_MFMA_EXTERN(D, P, T)                                                                          \
   extern template hipError_t launch_mdp<D, P, T>(const PersistentArgs&, int, hipStream_t, int*);          \
@@ -15,6 +16,7 @@
   extern template hipError_t launch_mp<D, P, T>(const KernelParams&, int64_t, int64_t, hipStream_t);      \
   extern template size_t lds_mp<D, P, T>(int, int);                                                       \
   extern template size_t opg_mp<D, P, T>(int, int);                                                       \
+  extern template size_t frg_mp<D, P, T>(int, int);                                                       \
   extern template hipError_t stage_mp<D, P, T>(const KernelParams&, hipStream_t);
 
 // tent_mfma_2d_p12.hip, tent_mfma_2d_p3.hip, tent_mfma_2d_p4.hip, tent_mfma_2d_p5.hip

@@ -53,6 +53,12 @@ LARGE_P4_CASES = {
     "delaunay3d_p4_rk4": dict(mesh=("delaunay", 3), p=4, q=5, m=8, T=0.05, kind=PEC, exact="pec_3d", method="rk4"),
     "ac_delaunay3d_p4": dict(mesh=("delaunay", 3), p=4, q=5, m=8, T=0.05, kind=PMC, exact="ac_pulse3",
                              system="acoustic"),
+    # patches of 37-48 tets (F/R of the tent in device memory)
+    "delaunay48_p4": dict(mesh=("delaunay48", 4), p=4, q=5, m=8, T=0.04, kind=PEC, exact="pec_3d"),
+    "delaunay48_p4_pmc_eps": dict(mesh=("delaunay48", 4), p=4, q=5, m=8, T=0.04, kind=PMC, exact="pec_3d",
+                                  eps_split=True),
+    "ac_delaunay48_p4": dict(mesh=("delaunay48", 4), p=4, q=5, m=8, T=0.04, kind=PMC, exact="ac_pulse3",
+                             system="acoustic"),
 }
 
 # the classical RK4 variant (method="rk4"): same inputs, RK4 on the tent ODE
@@ -137,6 +143,8 @@ def build_mesh(spec):
         return meshes.fan_disk(n)
     if kind == "delaunay":   # 4^3 lattice on the unit cube, jitter 0.3 h, 179 tets, patches up to 36
         return meshes.graded_delaunay_cube(n=n, a=1.0, jitter=0.3, seed=3)
+    if kind == "delaunay48":   # 5^3 lattice, jitter 0.5 h, 420 tets, two patches above 36 (the largest 48)
+        return meshes.graded_delaunay_cube(n=n, a=1.0, jitter=0.5, seed=180)
     if kind == "disk":
         return meshes.disk_tri(n)
     if kind == "tri1":

@@ -195,10 +195,25 @@ def test_split_bf16_precision_is_reserved():
     assert e.value.code == -9
 
 
-def test_p4_patch_classes_accept_up_to_36_tets():
-    """P4 in 3D: patches of up to 36 tets run on the matrix-core kernels (FP64 and mixed; the
-    36-tet class keeps its operator block in device memory, which the workspace includes);
-    larger patches, and the vector-ALU kernel beyond its LDS, are refused."""
+def star_mesh(nfaces_min=50, seed=4):
+    """One interior vertex at the origin whose patch is the cone over the convex hull of
+    points on the unit sphere: 2 n - 4 tets around it."""
+    from scipy.spatial import ConvexHull
+    rng = np.random.default_rng(seed)
+    n = (nfaces_min + 4 + 1) // 2
+    x = rng.normal(size=(n, 3))
+    x /= np.linalg.norm(x, axis=1)[:, None]
+    hull = ConvexHull(x)
+    coords = np.vstack([np.zeros((1, 3)), x])
+    cells = np.hstack([np.zeros((len(hull.simplices), 1), np.int64), hull.simplices + 1]).astype(np.int32)
+    return {"coords": coords, "cells": meshes._orient(coords, cells)}
+
+
+def test_p4_patch_classes_accept_up_to_48_tets():
+    """P4 in 3D: patches of up to 48 tets run on the matrix-core kernels (FP64 and mixed).  The
+    36-tet class keeps its operator block in device memory, the 48-tet class the tent's F/R
+    (1024 workgroup slots, which the workspace includes); larger patches, and the vector-ALU
+    kernel beyond its LDS, are refused."""
     from cases import build_mesh
     mm = build_mesh(("delaunay", 3))
     M = mtp.Mesh(mm["coords"], mm["cells"])
@@ -210,15 +225,28 @@ def test_p4_patch_classes_accept_up_to_36_tets():
     with pytest.raises(mtp.MTPError) as e:
         mtp.mtp_solver_workspace_size(M.h, T.h, 4, 5, 8, mtp.MTP_FP64_VALU)
     assert e.value.code == -9
-    big = meshes.graded_delaunay_cube(n=8, a=2.0 / 9.0, jitter=0.15, seed=11029)
-    Mb = mtp.Mesh(big["coords"], big["cells"])
-    assert Mb.info["max_patch"] > 36
-    Tb = mtp.Tents(Mb, 0.02, 0.5)
+    m48 = build_mesh(("delaunay48", 4))
+    M48 = mtp.Mesh(m48["coords"], m48["cells"])
+    assert M48.info["max_patch"] == 48
+    T48 = mtp.Tents(M48, 0.04, 0.5)
+    slot = 45 * (6 * 48 + 1) * 8   # F/R rows (3 x 15 face nodes) x (288 columns + 1) doubles
+    for prec in (mtp.MTP_FP64, mtp.MTP_MIXED_FP32):
+        assert mtp.mtp_solver_workspace_size(M48.h, T48.h, 4, 5, 8, prec) > 1024 * slot
+    # a workspace without the slots: the same mesh at P3 (48-tet class in LDS)
+    assert mtp.mtp_solver_workspace_size(M48.h, T48.h, 3, 4, 6, mtp.MTP_FP64) < 1024 * slot
+    star = star_mesh()
+    Ms = mtp.Mesh(star["coords"], star["cells"])
+    assert Ms.info["max_patch"] > 48
+    Ts = mtp.Tents(Ms, 0.02, 0.5)
     for prec in (mtp.MTP_FP64, mtp.MTP_MIXED_FP32):
         with pytest.raises(mtp.MTPError) as e:
-            mtp.mtp_solver_workspace_size(Mb.h, Tb.h, 4, 5, 8, prec)
+            mtp.mtp_solver_workspace_size(Ms.h, Ts.h, 4, 5, 8, prec)
         assert e.value.code == -9
     # P3 keeps its 48-tet class
+    big = meshes.graded_delaunay_cube(n=8, a=2.0 / 9.0, jitter=0.15, seed=11029)
+    Mb = mtp.Mesh(big["coords"], big["cells"])
+    assert 36 < Mb.info["max_patch"] <= 48
+    Tb = mtp.Tents(Mb, 0.02, 0.5)
     assert mtp.mtp_solver_workspace_size(Mb.h, Tb.h, 3, 4, 6, mtp.MTP_MIXED_FP32) > 0
 
 

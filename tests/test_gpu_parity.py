@@ -353,7 +353,10 @@ def test_batch_mixed_degrees_against_oracle(dim, precision, tol, schedule):
             assert np.abs(w - w1).max() <= (1e-13 if precision == 0 else 1e-9) * np.abs(w1).max(), nm
 
 
-LARGE_P4_SAT = [n for n, c in LARGE_P4_CASES.items() if "method" not in c and "system" not in c]
+LARGE_P4_SAT = [n for n, c in LARGE_P4_CASES.items()
+                if "method" not in c and "system" not in c and c["mesh"][0] == "delaunay"]
+# patches of 37-48 tets: the 48-tet class (F/R of the tent in device memory)
+XL_P4 = [n for n, c in LARGE_P4_CASES.items() if c["mesh"][0] == "delaunay48"]
 
 
 @pytest.mark.parametrize("precision,tol", [(0, TOL), (1, MIXED_TOL)])
@@ -411,6 +414,43 @@ def test_large_p4_patches_rk4_and_acoustics(name, precision, tol):
     S.set_fields(u0, 0.0)
     S.advance_to(c["slabs"] * c["T"])
     assert_parity(S.get_state(), ref["w"], tol, f"{name} w")
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("precision,tol", [(0, TOL), (1, MIXED_TOL)])
+@pytest.mark.parametrize("name", XL_P4)
+def test_xl_p4_patches_against_oracle(name, precision, tol, schedule):
+    """P4 on a jittered Delaunay cube with two vertex patches above 36 tets (the largest 48):
+    the 48-tet class (operator block in LDS, the tent's F/R in a device-memory slot per
+    workgroup, column-block products, Taylor sums in W) against the oracle, element by
+    element (FP64 <= 1e-10, mixed <= 1e-6), per-layer launches and the persistent schedule."""
+    from paper_1906_11029_amd import mtp
+    print(f"[gpu parity] {name} precision {precision} schedule {schedule}", flush=True)
+    ref = fixture(name)
+    c, mm, dim, eps, mu, bc, ex, u0 = setup(name)
+    system = mtp.MTP_SYSTEM_ACOUSTIC if c["system"] == "acoustic" else mtp.MTP_SYSTEM_MAXWELL
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc, system=system)
+    assert M.info["max_patch"] == 48
+    T = mtp.Tents(M, c["T"], 0.5)
+    ex_t = T.export()
+    for k in ("vertex", "t_top", "layer"):
+        assert np.array_equal(ex_t[k], ref[k]), f"tent list differs in {k}"
+    S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"], precision=precision)
+    assert S.kernel() == (1 if precision == 0 else 2)
+    S.set_schedule(schedule)
+    S.set_fields(u0, 0.0)
+    S.advance_to(c["slabs"] * c["T"])
+    assert_parity(S.get_state(), ref["w"], tol, f"{name} w")
+
+
+def test_xl_p4_patches_refused_in_batches():
+    """Solvers of the 48-tet P4 class run alone: a batch holding one is refused."""
+    from paper_1906_11029_amd import mtp
+    print("[gpu parity] 48-tet P4 class in a batch: refused", flush=True)
+    _, S, _ = gpu_solver(XL_P4[0])
+    with pytest.raises(mtp.MTPError) as e:
+        mtp.Batch([S])
+    assert e.value.code == -9
 
 
 def test_p5_3d_persistent_schedule_and_mixed_degree_batch():
