@@ -359,6 +359,7 @@ __device__ __forceinline__ void tile_product(const double* sOp, const float* sOp
   constexpr int NG = NB + KFP / 4;         // K groups: node blocks, then lift steps
   constexpr int PDG = 2;                   // ring depth in K groups
   constexpr bool F32 = sizeof(TM) == 4;
+  constexpr bool FRGM = MLds<D, P, double, NTMAX, SYS>::FRG;   // F/R in device memory
   typename MM::acc_t accs[TPW];
   typename MM::mini_t accm[TPW];
 #pragma unroll
@@ -407,6 +408,22 @@ __device__ __forceinline__ void tile_product(const double* sOp, const float* sOp
       auto kloop = [&](auto wm) {
         constexpr bool WM = decltype(wm)::value;
         constexpr int DM = WM ? D : 1;
+        if constexpr (LIFT && FRGM) {
+          // F in device memory: every F value of the lift part is loaded first (one round
+          // trip instead of one per K step), the operator read from LDS as the steps go
+          constexpr int NL = NG - NB;
+          double fb[NL];
+#pragma unroll
+          for (int i = 0; i < NL; ++i)
+            fb[i] = (4 * i + 3 < KF) ? fr[4 * i * RS] : sFR[min(4 * i + kq, KF - 1) * RS + colp];
+#pragma unroll
+          for (int i = 0; i < NL; ++i) {
+            const TM b = fm * (TM)fb[i];
+            acc = MM::mma((TM)acol[(KV + 4 * i) * OPS], b, acc);
+            if constexpr (WM) accmini = MM::mini((TM)acolm[(KV + 4 * i) * OPS], b, accmini);
+          }
+          return;
+        }
         araw ra[PDG][D], rm[PDG][DM];
         double ru[PDG][NT];
         auto load = [&](int g, int slot) {
