@@ -312,11 +312,12 @@ mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
 /* Batches of independent solves (section 2: tents on different meshes are independent).
  * Every launch of a batch runs layer l of every solver in it, so small solves share the
  * GPU: solvers must use the matrix-core kernels with one dimension, system (Maxwell or
- * acoustics) and precision, and the SAT recursion; degrees may differ (solvers of one degree
+ * acoustics), precision and method (SAT, or the RK4 variant in FP64); degrees may differ (solvers of one degree
  * form a group, and each layer index is one launch per group, or each group one persistent
  * launch).  q, m, meshes, materials, fluxes and boundary data may differ too.  Errors:
- * MTP_ERR_UNSUPPORTED for mixed systems, dimensions or precisions, RK4 or curved solvers,
- * and for P4 solvers in 3D with vertex patches of more than 36 tets.
+ * MTP_ERR_UNSUPPORTED for mixed systems, dimensions, precisions or methods, curved solvers,
+ * and for P4 solvers in 3D with vertex patches of more than 36 tets; mtp_batch_advance
+ * returns MTP_ERR_STATE if a member's method changed after the batch was made.
  * mtp_batch_advance moves every
  * solver forward by n_slabs of its own slab height; the first call captures one batched
  * slab into a HIP graph that later calls replay.  Solvers keep their handles and state;

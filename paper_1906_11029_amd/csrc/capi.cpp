@@ -230,7 +230,7 @@ struct mtp_batch_s {
   std::vector<int> order;
   std::vector<Group> groups;
   std::vector<Launch> launches;
-  int kernel = 0, d = 0, system = 0;
+  int kernel = 0, d = 0, system = 0, method = 0;
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   mtp::KernelParams* d_kps = nullptr;
@@ -943,7 +943,7 @@ static void batch_check(const mtp_solver* solvers, int32_t n) {
     require(s->kernel == 1 || s->kernel == 2, MTP_ERR_UNSUPPORTED, "batches need the matrix-core kernels");
     require(s->kernel == solvers[0]->kernel && s->mesh.d == solvers[0]->mesh.d, MTP_ERR_UNSUPPORTED,
             "a batch needs one dimension and precision");
-    require(s->method == MTP_METHOD_SAT, MTP_ERR_UNSUPPORTED, "batches run SAT only");
+    require(s->method == solvers[0]->method, MTP_ERR_UNSUPPORTED, "a batch needs one method (SAT or RK4)");
     require(s->mesh.system == solvers[0]->mesh.system, MTP_ERR_UNSUPPORTED, "a batch needs one system");
     require(!s->curved, MTP_ERR_UNSUPPORTED, "batches do not run curved elements");
     require(s->kp.frg == nullptr, MTP_ERR_UNSUPPORTED, "P4 patches of more than 36 tets run in single solves only");
@@ -1000,7 +1000,7 @@ static std::string batch_key(mtp_batch b) {
   }
   for (mtp_solver s : b->solvers) tents += (int64_t)s->tents.vertex.size();
   return "batch|" + device_tag(b->solvers[0]->device) + "|d" + std::to_string(b->d) + "|sys" + std::to_string(b->system) +
-         "|p" + degs + "|k" +
+         "|m" + std::to_string(b->method) + "|p" + degs + "|k" +
          std::to_string(b->kernel) + "|nt" + std::to_string(cls) + "|t" + std::to_string(tents_class(tents)) +
          "|n" + std::to_string(log2_class((int64_t)b->solvers.size()));
 }
@@ -1025,6 +1025,7 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     b->kernel = solvers[0]->kernel;
     b->d = solvers[0]->mesh.d;
     b->system = solvers[0]->mesh.system;
+    b->method = solvers[0]->method;
     // degree groups: stable sort by degree
     b->order.resize(n);
     for (int i = 0; i < n; ++i) b->order[i] = i;
@@ -1073,7 +1074,8 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
         g.bd.n = off[base + g.s1 - g.s0];
         g.bd.wait_ticks = ticks;
         g.bd.system = b->system;
-        g.grid_max = tent_batch_dag_grid(b->d, g.p, g.max_patch, b->kernel == 2, b->system);
+        g.bd.method = b->method;
+        g.grid_max = tent_batch_dag_grid(b->d, g.p, g.max_patch, b->kernel == 2, b->system, b->method);
         g.bd.grid = g.grid_max;
         if (g.grid_max <= 0) b->dag_ok = false;
       }
@@ -1111,7 +1113,7 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     check_hip(hipMemcpyAsync(b->d_segs, segs.data(), segs.size() * sizeof(BatchSeg), hipMemcpyHostToDevice,
                              b->stream), "upload");
     for (const auto& g : b->groups) {
-      BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, g.p, g.max_patch, b->system};
+      BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, g.p, g.max_patch, b->system, b->method};
       check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, nullptr), "batch kernel attributes");
     }
     check_hip(hipStreamSynchronize(b->stream), "sync");
@@ -1141,7 +1143,8 @@ static void batch_slab(mtp_batch b, hipStream_t st) {
   } else {
     for (const auto& la : b->launches) {
       const auto& g = b->groups[la.group];
-      BatchLaunch bl{b->d_kps, b->d_segs + la.seg0, la.nseg, la.blocks, b->d, g.p, g.max_patch, b->system};
+      BatchLaunch bl{b->d_kps, b->d_segs + la.seg0, la.nseg, la.blocks, b->d, g.p, g.max_patch, b->system,
+                     b->method};
       check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, st), "batched tent kernel");
     }
   }
@@ -1167,6 +1170,7 @@ mtp_status mtp_batch_advance(mtp_batch b, int64_t n_slabs) {
     mtp_solver s = b->solvers[b->order[j]];
     require(s->layers_done == 0, MTP_ERR_STATE, "a solver of the batch is in the middle of a slab");
     require(!s->has_data_faces || s->kp.has_data, MTP_ERR_STATE, "data boundary faces need mtp_set_planewave_bc");
+    require(s->method == b->method, MTP_ERR_STATE, "a solver's method changed after the batch was created");
     b->h_kps[j] = s->kp;
     b->h_kps[j].tile_order = b->tile_order;
     // work the solvers enqueued on their own streams comes first

@@ -97,6 +97,7 @@ struct BatchDag {
   int32_t nsolv, n, grid;
   int64_t wait_ticks;
   int32_t system;        // MTP_SYSTEM_* of every solver of the batch
+  int32_t method;        // MTP_METHOD_* of every solver of the batch (RK4: FP64 only)
 };
 
 struct BatchLaunch {
@@ -106,6 +107,7 @@ struct BatchLaunch {
   int64_t blocks;            // total workgroups (-1: only set the LDS attribute)
   int d, p, max_patch;
   int system;                // MTP_SYSTEM_* of every solver of the batch
+  int method;                // MTP_METHOD_* of every solver of the batch (RK4: FP64 only)
 };
 
 // The curved-element tent path: reference tables, per zone element tables and neighbours,
@@ -145,7 +147,7 @@ int tent_dag_grid(const KernelParams& kp, int fp32);
 hipError_t launch_batch_dag_reset(const KernelParams* kps, const BatchDag& bd, hipStream_t s);
 hipError_t launch_tent_batch_dag_mfma(const KernelParams* kps, const BatchDag& bd, int d, int p, int max_patch,
                                       int fp32, hipStream_t s);
-int tent_batch_dag_grid(int d, int p, int max_patch, int fp32, int system = 0);
+int tent_batch_dag_grid(int d, int p, int max_patch, int fp32, int system = 0, int method = 0);
 hipError_t launch_set_fields(const KernelParams& kp, int64_t ne, const double* u_nodal, double t0,
                              int64_t nv, hipStream_t s);
 hipError_t launch_get_fields(const KernelParams& kp, int64_t ne, double* out, int raw, hipStream_t s);

@@ -1088,15 +1088,15 @@ tent_mfma_dag_kernel(KernelParams kp) {
 }
 
 // Persistent entry point of a batch: every tent of every solver's slab, in DAG order.
-template <int D, int P, typename T, int NTMAX, int WPE, int SYS = 0>
+template <int D, int P, typename T, int NTMAX, int WPE, int SYS = 0, bool RK4 = false>
 __global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_batch_dag_kernel(const KernelParams* kps, BatchDag bd) {
-  tent_mfma_body<D, P, T, NTMAX, SchedBatchDag, false, SYS>(kps[0], SchedBatchDag{kps, bd, 0});
+  tent_mfma_body<D, P, T, NTMAX, SchedBatchDag, RK4, SYS>(kps[0], SchedBatchDag{kps, bd, 0});
 }
 
 // Batched entry point: workgroup b runs tent b - seg.block0 of segment seg, i.e. of the
 // layer slice (first, count) of solver seg.solver; all solvers share (D, P, T).
-template <int D, int P, typename T, int NTMAX, int WPE, int SYS = 0>
+template <int D, int P, typename T, int NTMAX, int WPE, int SYS = 0, bool RK4 = false>
 __global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
 tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) {
   const int64_t b = blockIdx.x;
@@ -1106,8 +1106,8 @@ tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) 
     if (segs[mid].block0 <= b) lo = mid; else hi = mid - 1;
   }
   const BatchSeg sg = segs[lo];
-  tent_mfma_body<D, P, T, NTMAX, SchedRange, false, SYS>(kps[sg.solver],
-                                                         SchedRange{sg.first, sg.count, b - sg.block0, (int64_t)1 << 62});
+  tent_mfma_body<D, P, T, NTMAX, SchedRange, RK4, SYS>(kps[sg.solver],
+                                                       SchedRange{sg.first, sg.count, b - sg.block0, (int64_t)1 << 62});
 }
 
 template <int D, int P, typename T, int NTMAX>
@@ -1189,20 +1189,23 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
     if constexpr (MLds<D, P, T, NTMAX>::FRG) {
       return hipErrorNotSupported;   // the extra-large class runs single solves only
     } else {
-    auto kfn = tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2>;
-    auto kfn_ac = tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2, 1>;
-    const bool ac = a.bd->system == 1;
+    // RK4 runs in FP64 only: in the FP32 instantiation the RK4 names are the plain kernels
+    // (never launched as RK4)
+    constexpr bool R = sizeof(T) == 8;
+    const bool ac = a.bd->system == 1, rk = a.bd->method == 1;
+    if (rk && !R) return hipErrorInvalidValue;
+    const void* kf = ac ? (rk ? reinterpret_cast<const void*>(tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2, 1, R>)
+                              : reinterpret_cast<const void*>(tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2, 1>))
+                        : (rk ? reinterpret_cast<const void*>(tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2, 0, R>)
+                              : reinterpret_cast<const void*>(tent_mfma_batch_dag_kernel<D, P, T, NTMAX, 2, 0>));
     const size_t lds_b = ac ? MLds<D, P, T, NTMAX, 1>::bytes : lds;
-    if (resident)
-      return resident_grid(ac ? reinterpret_cast<const void*>(kfn_ac) : reinterpret_cast<const void*>(kfn), BLOCK,
-                           lds_b, resident);
+    if (resident) return resident_grid(kf, BLOCK, lds_b, resident);
     if (a.bd->n <= 0) return hipSuccess;
     if (a.bd->grid <= 0) return hipErrorInvalidValue;
-    if (ac)
-      hipLaunchKernelGGL(kfn_ac, dim3((unsigned)a.bd->grid), dim3(BLOCK), lds_b, s, a.kps, *a.bd);
-    else
-      hipLaunchKernelGGL(kfn, dim3((unsigned)a.bd->grid), dim3(BLOCK), lds_b, s, a.kps, *a.bd);
-    return hipGetLastError();
+    const KernelParams* kps = a.kps;
+    BatchDag bd = *a.bd;
+    void* args[] = {&kps, &bd};
+    return hipLaunchKernel(kf, dim3((unsigned)a.bd->grid), dim3(BLOCK), args, lds_b, s);
     }
   }
   auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
@@ -1263,24 +1266,22 @@ template <int D, int P, typename T, int NTMAX>
 hipError_t launch_mb(const BatchLaunch& bl, hipStream_t s) {
   constexpr int WPE = 2;
   constexpr int BLOCK = MShape<D, P, NTMAX>::BLOCK;
-  if (bl.system == 1) {   // acoustics
-    const size_t lds = MLds<D, P, T, NTMAX, 1>::bytes;
-    auto kfn = tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 1>;
-    if (bl.blocks < 0)
-      return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds);
-    if (bl.blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(kfn, dim3((unsigned)bl.blocks), dim3(BLOCK), lds, s, bl.kps, bl.segs, bl.nseg);
-    return hipGetLastError();
-  }
-  const size_t lds = MLds<D, P, T, NTMAX>::bytes;
-  auto kfn = tent_mfma_batch_kernel<D, P, T, NTMAX, WPE>;
-  if (bl.blocks < 0)
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds);
+  // RK4 runs in FP64 only: in the FP32 instantiation the RK4 names are the plain kernels
+  constexpr bool R = sizeof(T) == 8;
+  const bool ac = bl.system == 1, rk = bl.method == 1;
+  if (rk && !R) return hipErrorInvalidValue;
+  const void* kf = ac ? (rk ? reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 1, R>)
+                            : reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 1>))
+                      : (rk ? reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 0, R>)
+                            : reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 0>));
+  const size_t lds = ac ? MLds<D, P, T, NTMAX, 1>::bytes : MLds<D, P, T, NTMAX>::bytes;
+  if (bl.blocks < 0) return hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (bl.blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(kfn, dim3((unsigned)bl.blocks), dim3(BLOCK), lds, s, bl.kps, bl.segs, bl.nseg);
-  return hipGetLastError();
+  const KernelParams* kps = bl.kps;
+  const BatchSeg* segs = bl.segs;
+  int nseg = bl.nseg;
+  void* args[] = {&kps, &segs, &nseg};
+  return hipLaunchKernel(kf, dim3((unsigned)bl.blocks), dim3(BLOCK), args, lds, s);
 }
 
 template <int D, int P, typename T>

@@ -178,10 +178,11 @@ hipError_t launch_tent_batch_dag_mfma(const KernelParams* kps, const BatchDag& b
   return fp32 ? launch_dt<float>(a, d, p, max_patch, s, nullptr) : launch_dt<double>(a, d, p, max_patch, s, nullptr);
 }
 
-int tent_batch_dag_grid(int d, int p, int max_patch, int fp32, int system) {
+int tent_batch_dag_grid(int d, int p, int max_patch, int fp32, int system, int method) {
   int resident = 0;
   BatchDag bd{};
   bd.system = system;
+  bd.method = method;
   const PersistentArgs a{nullptr, nullptr, &bd};
   const hipError_t e = fp32 ? launch_dt<float>(a, d, p, max_patch, nullptr, &resident)
                             : launch_dt<double>(a, d, p, max_patch, nullptr, &resident);

@@ -59,6 +59,10 @@ LARGE_P4_CASES = {
                                   eps_split=True),
     "ac_delaunay48_p4": dict(mesh=("delaunay48", 4), p=4, q=5, m=8, T=0.04, kind=PMC, exact="ac_pulse3",
                              system="acoustic"),
+    "delaunay48_p4_rk4": dict(mesh=("delaunay48", 4), p=4, q=5, m=8, T=0.04, kind=PEC, exact="pec_3d",
+                              method="rk4"),
+    "ac_delaunay48_p4_rk4": dict(mesh=("delaunay48", 4), p=4, q=5, m=8, T=0.04, kind=PMC, exact="ac_pulse3",
+                                 system="acoustic", method="rk4"),
 }
 
 # the classical RK4 variant (method="rk4"): same inputs, RK4 on the tent ODE

@@ -355,8 +355,11 @@ def test_batch_mixed_degrees_against_oracle(dim, precision, tol, schedule):
 
 LARGE_P4_SAT = [n for n, c in LARGE_P4_CASES.items()
                 if "method" not in c and "system" not in c and c["mesh"][0] == "delaunay"]
-# patches of 37-48 tets: the 48-tet class (F/R of the tent in device memory)
-XL_P4 = [n for n, c in LARGE_P4_CASES.items() if c["mesh"][0] == "delaunay48"]
+# patches of 37-48 tets: the 48-tet class (F/R of the tent in device memory); the RK4
+# variant runs in FP64 only
+XL_P4 = [n for n, c in LARGE_P4_CASES.items() if c["mesh"][0] == "delaunay48" and "method" not in c]
+XL_P4_RK4 = [n for n, c in LARGE_P4_CASES.items() if c["mesh"][0] == "delaunay48" and c.get("method") == "rk4"]
+XL_PARAMS = [(n, 0, TOL) for n in XL_P4_RK4] + [(n, p, t) for n in XL_P4 for p, t in ((0, TOL), (1, MIXED_TOL))]
 
 
 @pytest.mark.parametrize("precision,tol", [(0, TOL), (1, MIXED_TOL)])
@@ -417,13 +420,13 @@ def test_large_p4_patches_rk4_and_acoustics(name, precision, tol):
 
 
 @pytest.mark.parametrize("schedule", [0, 1])
-@pytest.mark.parametrize("precision,tol", [(0, TOL), (1, MIXED_TOL)])
-@pytest.mark.parametrize("name", XL_P4)
+@pytest.mark.parametrize("name,precision,tol", XL_PARAMS)
 def test_xl_p4_patches_against_oracle(name, precision, tol, schedule):
     """P4 on a jittered Delaunay cube with two vertex patches above 36 tets (the largest 48):
     the 48-tet class (operator block in LDS, the tent's F/R in a device-memory slot per
     workgroup, column-block products, Taylor sums in W) against the oracle, element by
-    element (FP64 <= 1e-10, mixed <= 1e-6), per-layer launches and the persistent schedule."""
+    element (FP64 <= 1e-10, mixed <= 1e-6), per-layer launches and the persistent schedule;
+    SAT in both precisions, the RK4 variant in FP64, Maxwell and acoustics."""
     from paper_1906_11029_amd import mtp
     print(f"[gpu parity] {name} precision {precision} schedule {schedule}", flush=True)
     ref = fixture(name)
@@ -437,6 +440,8 @@ def test_xl_p4_patches_against_oracle(name, precision, tol, schedule):
         assert np.array_equal(ex_t[k], ref[k]), f"tent list differs in {k}"
     S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"], precision=precision)
     assert S.kernel() == (1 if precision == 0 else 2)
+    if c["method"] == "rk4":
+        S.set_method(mtp.MTP_METHOD_RK4)
     S.set_schedule(schedule)
     S.set_fields(u0, 0.0)
     S.advance_to(c["slabs"] * c["T"])
