@@ -73,7 +73,10 @@ void vertex_order(int d, int k, int* order);
 
 void build_topology(Mesh& m);
 void pitch(const Mesh& m, double t_end, double slope, int rule, Tents& out);
-void pitch_rule(const Mesh& m, double t_end, double slope, int rule, Tents& out);   // one ordering
+// one ordering; the colour rule gives up (returns false, out untouched) once the sum of its
+// tents' patch sizes reaches work_limit
+bool pitch_rule(const Mesh& m, double t_end, double slope, int rule, Tents& out,
+                int64_t work_limit = INT64_MAX);
 // dependency graph of the tents (table order): predecessor counts, successors (CSR) and the
 // number of leading tents without predecessor
 void tent_dag(const Mesh& m, const Tents& t, std::vector<int32_t>& pred_count, std::vector<int32_t>& succ_ptr,

@@ -58,23 +58,23 @@ int32_t colour_vertices(const Mesh& m, std::vector<int32_t>& col) {
 
 // The automatic rule: both tables, and the one with less work, the sum over its tents of
 // the patch sizes (a tent's cost grows with its patch); the minimum-vertex table on a tie.
+// The colour pitch stops as soon as its work reaches the minimum-vertex table's, since it
+// can no longer win (work only grows): the same choice, without finishing a table that can
+// be far larger (the jittered Delaunay cube: 48 times the tents).
 void pitch(const Mesh& m, double t_end, double slope, int rule, Tents& out) {
   if (rule == MTP_PITCH_AUTO) {
     Tents a, b;
-    pitch(m, t_end, slope, MTP_PITCH_MIN_VERTEX, a);
-    pitch(m, t_end, slope, MTP_PITCH_COLOUR, b);
-    auto work = [&](const Tents& t) {
-      int64_t w = 0;
-      for (int32_t v : t.vertex) w += m.v2e_ptr[v + 1] - m.v2e_ptr[v];
-      return w;
-    };
-    out = work(b) < work(a) ? std::move(b) : std::move(a);
+    pitch_rule(m, t_end, slope, MTP_PITCH_MIN_VERTEX, a);
+    int64_t wa = 0;
+    for (int32_t v : a.vertex) wa += m.v2e_ptr[v + 1] - m.v2e_ptr[v];
+    const bool done = pitch_rule(m, t_end, slope, MTP_PITCH_COLOUR, b, wa);
+    out = done ? std::move(b) : std::move(a);
     return;
   }
   pitch_rule(m, t_end, slope, rule, out);
 }
 
-void pitch_rule(const Mesh& m, double t_end, double slope, int rule, Tents& out) {
+bool pitch_rule(const Mesh& m, double t_end, double slope, int rule, Tents& out, int64_t work_limit) {
   const int d = m.d, nvert = d + 1;
   const double Q = std::ldexp(1.0, -24);
   const double SAFETY = 1e-3;
@@ -128,7 +128,9 @@ void pitch_rule(const Mesh& m, double t_end, double slope, int rule, Tents& out)
     lay += 1;
     return std::min(t_end, Q * std::floor(t_plus / Q - SAFETY));
   };
+  int64_t work = 0;   // sum of the emitted tents' patch sizes
   auto emit = [&](int32_t v, double t_new, int32_t lay) {
+    work += m.v2e_ptr[v + 1] - m.v2e_ptr[v];
     last[v] = lay;
     V.push_back(v);
     TB.push_back(tau[v]);
@@ -186,6 +188,7 @@ void pitch_rule(const Mesh& m, double t_end, double slope, int rule, Tents& out)
         emit(v, t_new, lay);
         moved = true;
         if (t_new >= t_end) --below;
+        if (work >= work_limit) return false;   // no less work than the limit: give up
       }
       idle = moved ? 0 : idle + 1;
       if (idle > n_col) throw Error(MTP_ERR_PITCH, "colour pitching made no progress");
@@ -216,6 +219,7 @@ void pitch_rule(const Mesh& m, double t_end, double slope, int rule, Tents& out)
   out.layer_ptr.assign(nl + 1, 0);
   for (size_t i = 0; i < nt; ++i) out.layer_ptr[out.layer[i] + 1]++;
   for (int32_t l = 0; l < nl; ++l) out.layer_ptr[l + 1] += out.layer_ptr[l];
+  return true;
 }
 
 }  // namespace mtp
