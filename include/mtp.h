@@ -226,8 +226,8 @@ mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, 
  * kernels only, for vertex patches of up to 24 tets; P4 in 3D takes vertex patches of up to
  * 48 tets (section 2: a tent covers the vertex patch): up to 36 with the operator block in
  * device memory, 37-48 with the tent's face fluxes and stage residual in device memory,
- * 1024 workgroup slots of about 104 KB that the workspace includes; such solvers are not
- * accepted in batches), Taylor order q >= 1 and
+ * 1024 workgroup slots of about 104 KB that the workspace includes; a batch holding such
+ * a degree group has slots of its own in its workspace), Taylor order q >= 1 and
  * m >= 1 sub-intervals per tent (section 4; the paper uses q = p+1, m = 2p), flux
  * penalty alpha (1/2 is the exact upwind flux for unit impedance, 1 the printed
  * coefficient).  d_workspace: device pointer of at least the reported bytes, owned by
@@ -315,8 +315,8 @@ mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
  * acoustics), precision and method (SAT, or the RK4 variant in FP64); degrees may differ (solvers of one degree
  * form a group, and each layer index is one launch per group, or each group one persistent
  * launch).  q, m, meshes, materials, fluxes and boundary data may differ too.  Errors:
- * MTP_ERR_UNSUPPORTED for mixed systems, dimensions, precisions or methods, curved solvers,
- * and for P4 solvers in 3D with vertex patches of more than 36 tets; mtp_batch_advance
+ * MTP_ERR_UNSUPPORTED for mixed systems, dimensions, precisions or methods, and curved
+ * solvers; mtp_batch_advance
  * returns MTP_ERR_STATE if a member's method changed after the batch was made.
  * mtp_batch_advance moves every
  * solver forward by n_slabs of its own slab height; the first call captures one batched

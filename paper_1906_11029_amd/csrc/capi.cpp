@@ -231,6 +231,7 @@ struct mtp_batch_s {
   std::vector<Group> groups;
   std::vector<Launch> launches;
   int kernel = 0, d = 0, system = 0, method = 0;
+  double* frg = nullptr;          // F/R slots of the 48-tet P4 class (kFrgSlots of them), or null
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   mtp::KernelParams* d_kps = nullptr;
@@ -946,7 +947,6 @@ static void batch_check(const mtp_solver* solvers, int32_t n) {
     require(s->method == solvers[0]->method, MTP_ERR_UNSUPPORTED, "a batch needs one method (SAT or RK4)");
     require(s->mesh.system == solvers[0]->mesh.system, MTP_ERR_UNSUPPORTED, "a batch needs one system");
     require(!s->curved, MTP_ERR_UNSUPPORTED, "batches do not run curved elements");
-    require(s->kp.frg == nullptr, MTP_ERR_UNSUPPORTED, "P4 patches of more than 36 tets run in single solves only");
     for (int j = 0; j < i; ++j) require(solvers[j] != s, MTP_ERR_ARG, "solver listed twice");
   }
 }
@@ -967,7 +967,8 @@ static int64_t batch_tents(const mtp_solver* solvers, int32_t n) {
 constexpr int kMaxBatchGroups = 8;
 
 struct BatchLayout {
-  size_t kps, segs, queue, ctl, off, roff, total;
+  size_t kps, segs, queue, ctl, off, roff, frg, total;
+  size_t frg_bytes = 0;   // F/R slots of a degree group in the 48-tet P4 class (shared by the groups)
 };
 static BatchLayout batch_layout(const mtp_solver* solvers, int32_t n) {
   Layout L;
@@ -978,6 +979,18 @@ static BatchLayout batch_layout(const mtp_solver* solvers, int32_t n) {
   o.ctl = L.add(sizeof(int32_t) * 4);
   o.off = L.add(sizeof(int32_t) * (n + kMaxBatchGroups));    // per group: n_g + 1 entries
   o.roff = L.add(sizeof(int32_t) * (n + kMaxBatchGroups));
+  // a degree group whose largest patch falls in the 48-tet P4 class keeps its tents' F/R in
+  // kFrgSlots slots; the groups run one after another on the batch's stream and share them
+  size_t slot = 0;
+  for (int i = 0; i < n; ++i) {
+    int gmax = 0;
+    for (int j = 0; j < n; ++j)
+      if (solvers[j]->p == solvers[i]->p) gmax = std::max(gmax, solvers[j]->mesh.max_patch);
+    const mtp_solver s = solvers[i];
+    slot = std::max(slot, tent_mfma_frg_bytes(s->mesh.d, s->p, gmax, s->kernel == 2, s->mesh.system));
+  }
+  o.frg_bytes = slot * kFrgSlots;
+  o.frg = L.add(o.frg_bytes);
   o.total = L.off;
   return o;
 }
@@ -1053,6 +1066,7 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->d_kps = reinterpret_cast<KernelParams*>(b->ws + lo.kps);
     b->d_segs = reinterpret_cast<BatchSeg*>(b->ws + lo.segs);
+    if (lo.frg_bytes > 0) b->frg = reinterpret_cast<double*>(b->ws + lo.frg);
     // persistent schedule, per group: tent ids solver by solver, first-layer tents first in the queue
     {
       std::vector<int32_t> off(n + kMaxBatchGroups, 0), roff(n + kMaxBatchGroups, 0);
@@ -1076,6 +1090,7 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
         g.bd.system = b->system;
         g.bd.method = b->method;
         g.grid_max = tent_batch_dag_grid(b->d, g.p, g.max_patch, b->kernel == 2, b->system, b->method);
+        if (b->frg) g.grid_max = std::min(g.grid_max, kFrgSlots);   // one F/R slot per workgroup
         g.bd.grid = g.grid_max;
         if (g.grid_max <= 0) b->dag_ok = false;
       }
@@ -1113,7 +1128,8 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     check_hip(hipMemcpyAsync(b->d_segs, segs.data(), segs.size() * sizeof(BatchSeg), hipMemcpyHostToDevice,
                              b->stream), "upload");
     for (const auto& g : b->groups) {
-      BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, g.p, g.max_patch, b->system, b->method};
+      BatchLaunch bl{b->d_kps, b->d_segs, 0, -1, b->d, g.p, g.max_patch, b->system, b->method,
+                     b->frg ? kFrgSlots : 0};
       check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, nullptr), "batch kernel attributes");
     }
     check_hip(hipStreamSynchronize(b->stream), "sync");
@@ -1144,7 +1160,7 @@ static void batch_slab(mtp_batch b, hipStream_t st) {
     for (const auto& la : b->launches) {
       const auto& g = b->groups[la.group];
       BatchLaunch bl{b->d_kps, b->d_segs + la.seg0, la.nseg, la.blocks, b->d, g.p, g.max_patch, b->system,
-                     b->method};
+                     b->method, b->frg ? kFrgSlots : 0};
       check_hip(launch_tent_batch_mfma(bl, b->kernel == 2, st), "batched tent kernel");
     }
   }
@@ -1173,6 +1189,9 @@ mtp_status mtp_batch_advance(mtp_batch b, int64_t n_slabs) {
     require(s->method == b->method, MTP_ERR_STATE, "a solver's method changed after the batch was created");
     b->h_kps[j] = s->kp;
     b->h_kps[j].tile_order = b->tile_order;
+    // the 48-tet P4 class: every launch takes its F/R slots from the batch's own
+    b->h_kps[j].frg = b->frg;
+    b->h_kps[j].frg_slots = b->frg ? kFrgSlots : 0;
     // work the solvers enqueued on their own streams comes first
     if (s->stream != b->stream) check_hip(hipStreamSynchronize(s->stream), "sync solver stream");
   }

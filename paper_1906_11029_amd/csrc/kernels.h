@@ -108,6 +108,7 @@ struct BatchLaunch {
   int d, p, max_patch;
   int system;                // MTP_SYSTEM_* of every solver of the batch
   int method;                // MTP_METHOD_* of every solver of the batch (RK4: FP64 only)
+  int frg_slots;             // the batch's F/R slots (classes with F/R in device memory; 0: none)
 };
 
 // The curved-element tent path: reference tables, per zone element tables and neighbours,

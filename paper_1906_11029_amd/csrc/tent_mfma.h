@@ -627,6 +627,29 @@ struct SchedRange {   // tents first + it, it = begin, begin + step, ... < count
   __device__ void done(const KernelParams&, int64_t, int) {}
 };
 
+struct SchedBatchRange {   // the tents of a batched launch's segments: it, it + step, ... < total
+  const KernelParams* kps;
+  const BatchSeg* segs;
+  int nseg;
+  int64_t total, it, step;
+  int solver;
+  __device__ bool next(const KernelParams&, int*, int, int64_t& t) {
+    if (it >= total) return false;
+    int lo = 0, hi = nseg - 1;   // last segment with block0 <= it
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].block0 <= it) lo = mid; else hi = mid - 1;
+    }
+    const BatchSeg sg = segs[lo];
+    t = sg.first + (it - sg.block0);
+    solver = sg.solver;
+    it += step;
+    return true;
+  }
+  __device__ const KernelParams& params(const KernelParams&) const { return kps[solver]; }
+  __device__ void done(const KernelParams&, int64_t, int) {}
+};
+
 struct SchedDag {     // one solver's tent DAG
   __device__ bool next(const KernelParams& kp0, int* sh, int tid, int64_t& t) {
     const int c = dag_claim(kp0, sh, tid);
@@ -1110,6 +1133,17 @@ tent_mfma_batch_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg) 
                                                        SchedRange{sg.first, sg.count, b - sg.block0, (int64_t)1 << 62});
 }
 
+// Batched entry point with a capped grid (classes with F/R in device memory: one slot per
+// workgroup): workgroup b runs tents b, b + gridDim.x, ... of the launch's segments; the
+// operator and the slots come from the first segment's solver (one degree per launch, and
+// every solver of the batch points at the batch's slots).
+template <int D, int P, typename T, int NTMAX, int WPE, int SYS = 0, bool RK4 = false>
+__global__ void __launch_bounds__(tent_block<D>()) __attribute__((amdgpu_waves_per_eu(WPE)))
+tent_mfma_batch_range_kernel(const KernelParams* kps, const BatchSeg* segs, int nseg, int64_t total) {
+  tent_mfma_body<D, P, T, NTMAX, SchedBatchRange, RK4, SYS>(
+      kps[segs[0].solver], SchedBatchRange{kps, segs, nseg, total, (int64_t)blockIdx.x, (int64_t)gridDim.x, 0});
+}
+
 template <int D, int P, typename T, int NTMAX>
 hipError_t launch_m(const KernelParams& kp, int64_t first, int64_t count, hipStream_t s) {
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
@@ -1186,11 +1220,9 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
   const size_t lds = MLds<D, P, T, NTMAX>::bytes;
   constexpr int BLOCK = MShape<D, P, NTMAX>::BLOCK;
   if (a.bd) {   // a batch of one system (the acoustic variant when a.bd->system == 1)
-    if constexpr (MLds<D, P, T, NTMAX>::FRG) {
-      return hipErrorNotSupported;   // the extra-large class runs single solves only
-    } else {
     // RK4 runs in FP64 only: in the FP32 instantiation the RK4 names are the plain kernels
-    // (never launched as RK4)
+    // (never launched as RK4).  Classes with F/R in device memory: the host keeps the grid
+    // within the batch's slots.
     constexpr bool R = sizeof(T) == 8;
     const bool ac = a.bd->system == 1, rk = a.bd->method == 1;
     if (rk && !R) return hipErrorInvalidValue;
@@ -1206,7 +1238,6 @@ hipError_t launch_md(const PersistentArgs& a, hipStream_t s, int* resident) {
     BatchDag bd = *a.bd;
     void* args[] = {&kps, &bd};
     return hipLaunchKernel(kf, dim3((unsigned)a.bd->grid), dim3(BLOCK), args, lds_b, s);
-    }
   }
   auto kfn = tent_mfma_dag_kernel<D, P, T, NTMAX, 2>;
   auto kfn_rk4 = tent_mfma_dag_kernel<D, P, T, NTMAX, 2, sizeof(T) == 8>;   // FP64 only, as above
@@ -1270,18 +1301,35 @@ hipError_t launch_mb(const BatchLaunch& bl, hipStream_t s) {
   constexpr bool R = sizeof(T) == 8;
   const bool ac = bl.system == 1, rk = bl.method == 1;
   if (rk && !R) return hipErrorInvalidValue;
-  const void* kf = ac ? (rk ? reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 1, R>)
-                            : reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 1>))
-                      : (rk ? reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 0, R>)
-                            : reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 0>));
   const size_t lds = ac ? MLds<D, P, T, NTMAX, 1>::bytes : MLds<D, P, T, NTMAX>::bytes;
-  if (bl.blocks < 0) return hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (bl.blocks == 0) return hipSuccess;
-  const KernelParams* kps = bl.kps;
-  const BatchSeg* segs = bl.segs;
-  int nseg = bl.nseg;
-  void* args[] = {&kps, &segs, &nseg};
-  return hipLaunchKernel(kf, dim3((unsigned)bl.blocks), dim3(BLOCK), args, lds, s);
+  if constexpr (MLds<D, P, T, NTMAX>::FRG) {
+    // F/R in device memory: at most bl.frg_slots workgroups, each taking every grid-th tent
+    const void* kr = ac ? (rk ? reinterpret_cast<const void*>(tent_mfma_batch_range_kernel<D, P, T, NTMAX, WPE, 1, R>)
+                              : reinterpret_cast<const void*>(tent_mfma_batch_range_kernel<D, P, T, NTMAX, WPE, 1>))
+                        : (rk ? reinterpret_cast<const void*>(tent_mfma_batch_range_kernel<D, P, T, NTMAX, WPE, 0, R>)
+                              : reinterpret_cast<const void*>(tent_mfma_batch_range_kernel<D, P, T, NTMAX, WPE, 0>));
+    if (bl.blocks < 0) return hipFuncSetAttribute(kr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (bl.blocks == 0) return hipSuccess;
+    if (bl.frg_slots <= 0) return hipErrorInvalidValue;
+    const KernelParams* kps = bl.kps;
+    const BatchSeg* segs = bl.segs;
+    int nseg = bl.nseg;
+    int64_t total = bl.blocks;
+    void* args[] = {&kps, &segs, &nseg, &total};
+    return hipLaunchKernel(kr, dim3((unsigned)std::min<int64_t>(bl.blocks, bl.frg_slots)), dim3(BLOCK), args, lds, s);
+  } else {
+    const void* kf = ac ? (rk ? reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 1, R>)
+                              : reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 1>))
+                        : (rk ? reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 0, R>)
+                              : reinterpret_cast<const void*>(tent_mfma_batch_kernel<D, P, T, NTMAX, WPE, 0>));
+    if (bl.blocks < 0) return hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (bl.blocks == 0) return hipSuccess;
+    const KernelParams* kps = bl.kps;
+    const BatchSeg* segs = bl.segs;
+    int nseg = bl.nseg;
+    void* args[] = {&kps, &segs, &nseg};
+    return hipLaunchKernel(kf, dim3((unsigned)bl.blocks), dim3(BLOCK), args, lds, s);
+  }
 }
 
 template <int D, int P, typename T>
@@ -1290,6 +1338,9 @@ hipError_t launch_mbp(const BatchLaunch& bl, hipStream_t s) {
   if (bl.max_patch <= 8) return launch_mb<D, P, T, 8>(bl, s);
   if (bl.max_patch <= 24) return launch_mb<D, P, T, 24>(bl, s);
   if (bl.max_patch <= NB) return launch_mb<D, P, T, NB>(bl, s);
+  constexpr int XL = xl_class<D, P>();
+  if constexpr (XL > 0)
+    if (bl.max_patch <= XL) return launch_mb<D, P, T, XL>(bl, s);
   return hipErrorInvalidValue;
 }
 

@@ -448,14 +448,41 @@ def test_xl_p4_patches_against_oracle(name, precision, tol, schedule):
     assert_parity(S.get_state(), ref["w"], tol, f"{name} w")
 
 
-def test_xl_p4_patches_refused_in_batches():
-    """Solvers of the 48-tet P4 class run alone: a batch holding one is refused."""
+# batches with a degree group in the 48-tet P4 class (a 36-tet-patch solve joins the group
+# and runs in its class): name, cases, precisions
+XL_BATCHES = [("maxwell", ["delaunay48_p4", "delaunay48_p4_pmc_eps", "delaunay3d_p4"], (0, 1)),
+              ("acoustic", ["ac_delaunay48_p4", "ac_delaunay3d_p4"], (0, 1)),
+              ("rk4", ["delaunay48_p4_rk4", "delaunay3d_p4_rk4"], (0,))]
+XL_BATCH_PARAMS = [(n, cs, p) for n, cs, ps in XL_BATCHES for p in ps]
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("batch,names,precision", XL_BATCH_PARAMS)
+def test_xl_p4_batches_against_oracle(batch, names, precision, schedule):
+    """A batch whose P4 group falls in the 48-tet class (the batch's own F/R slots, a capped
+    per-layer grid striding over the layer's segments, or the persistent schedule) against
+    the oracle, element by element: FP64 <= 1e-10, mixed <= 1e-6."""
     from paper_1906_11029_amd import mtp
-    print("[gpu parity] 48-tet P4 class in a batch: refused", flush=True)
-    _, S, _ = gpu_solver(XL_P4[0])
-    with pytest.raises(mtp.MTPError) as e:
-        mtp.Batch([S])
-    assert e.value.code == -9
+    print(f"[gpu parity] 48-tet P4 batch {batch} precision {precision} schedule {schedule}", flush=True)
+    refs = [fixture(n) for n in names]
+    solvers = []
+    for n in names:
+        c, mm, dim, eps, mu, bc, ex, u0 = setup(n)
+        system = mtp.MTP_SYSTEM_ACOUSTIC if c["system"] == "acoustic" else mtp.MTP_SYSTEM_MAXWELL
+        M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu, face_bc=bc, system=system)
+        T = mtp.Tents(M, c["T"], 0.5)
+        S = mtp.Solver(M, T, c["p"], c["q"], c["m"], alpha=c["alpha"], precision=precision)
+        if c["method"] == "rk4":
+            S.set_method(mtp.MTP_METHOD_RK4)
+        S.set_fields(u0, 0.0)
+        solvers.append(S)
+    assert max(S.mesh.info["max_patch"] for S in solvers) > 36
+    B = mtp.Batch(solvers)
+    B.set_schedule(schedule)
+    B.advance(1)
+    tol = TOL if precision == 0 else MIXED_TOL
+    for S, n, ref in zip(solvers, names, refs):
+        assert_parity(S.get_state(), ref["w"], tol, f"batch {batch}: {n}")
 
 
 def test_p5_3d_persistent_schedule_and_mixed_degree_batch():
