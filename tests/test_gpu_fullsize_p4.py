@@ -182,3 +182,51 @@ def test_full_size_delaunay_p4_dag_slab_equals_layers(precision):
     wa, wb = A.get_state(), B.get_state()
     assert np.all(np.isfinite(wa))
     assert np.array_equal(wa, wb)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-6)])
+def test_full_size_delaunay_p4_layers_wider_than_the_slots(precision, tol):
+    """The Delaunay cube on colour tables over a short slab (0.0005: layers of up to 5765
+    tents): the 48-tet class's per-layer launches run at most 1024 workgroups (one F/R slot
+    each), so a workgroup takes several tents of a wide layer.  One slab equals the persistent
+    schedule bitwise; in the widest layer, tents at positions 1024, 2047 and the last (a
+    workgroup's second and later tents) against the oracle."""
+    from oracle.mesh import Mesh as OMesh
+    from oracle.solve import OracleSolver
+    from paper_1906_11029_amd import mtp
+    print(f"[gpu full-size Delaunay P4] colour tables, wide layers, precision {precision}", flush=True)
+    mm, eps, mu, u0 = _delaunay()
+    M = mtp.Mesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    T = mtp.Tents(M, 0.0005, 0.5, rule=mtp.MTP_PITCH_COLOUR)
+    width = np.diff(T.layer_ptr)
+    L = int(np.argmax(width))
+    assert width[L] > 2048
+    _, _, A = _delaunay_solver(mm, eps, mu, u0, precision, M, T)
+    _, _, B = _delaunay_solver(mm, eps, mu, u0, precision, M, T)
+    A.set_schedule(mtp.MTP_SCHEDULE_DAG)
+    A.advance_to(0.0005)
+    B.set_graph(False)
+    for layer in range(L):
+        B.layer_advance(layer)
+    w_before = B.get_state()
+    B.layer_advance(L)
+    w_after = B.get_state()
+    for layer in range(L + 1, T.n_layers):
+        B.layer_advance(layer)
+    assert np.array_equal(A.get_state(), B.get_state())
+    tl = T.export()
+    om = OMesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
+    tau = np.zeros(M.info["nv"])
+    sel = tl["layer"] < L
+    tau[tl["vertex"][sel]] = tl["t_top"][sel]
+    O = OracleSolver(om, 4, 5, 8)
+    O.set_nodal_w(w_before)
+    O.tau[:] = tau
+    first = int(T.layer_ptr[L])
+    pick = [first + 1024, first + 2047, int(T.layer_ptr[L + 1]) - 1]
+    for i in pick:
+        O.run_tent(int(tl["vertex"][i]), float(tl["t_top"][i]))
+    w_or = O.nodal_w()
+    for i in pick:
+        es = om.v2e[int(tl["vertex"][i])]
+        assert_parity(w_after[es], w_or[es], tol, f"tent {i - first} of layer {L} ({len(es)} tets)")
