@@ -189,8 +189,9 @@ def test_full_size_delaunay_p4_layers_wider_than_the_slots(precision, tol):
     """The Delaunay cube on colour tables over a short slab (0.0005: layers of up to 5765
     tents): the 48-tet class's per-layer launches run at most 1024 workgroups (one F/R slot
     each), so a workgroup takes several tents of a wide layer.  One slab equals the persistent
-    schedule bitwise; in the widest layer, tents at positions 1024, 2047 and the last (a
-    workgroup's second and later tents) against the oracle."""
+    schedule bitwise, and so does the slab run as a batch (per-layer and persistent); in the
+    widest layer, tents at positions 1024, 2047 and the last (a workgroup's second and later
+    tents) against the oracle."""
     from oracle.mesh import Mesh as OMesh
     from oracle.solve import OracleSolver
     from paper_1906_11029_amd import mtp
@@ -214,6 +215,15 @@ def test_full_size_delaunay_p4_layers_wider_than_the_slots(precision, tol):
     for layer in range(L + 1, T.n_layers):
         B.layer_advance(layer)
     assert np.array_equal(A.get_state(), B.get_state())
+    # the same slab as a batch (its own slots; per-layer launches of up to 5765 tents on at
+    # most 1024 workgroups, and the persistent schedule)
+    for schedule in (mtp.MTP_SCHEDULE_LAYERS, mtp.MTP_SCHEDULE_DAG):
+        _, _, C = _delaunay_solver(mm, eps, mu, u0, precision, M, T)
+        Bt = mtp.Batch([C])
+        Bt.set_schedule(schedule)
+        Bt.advance(1)
+        assert np.array_equal(C.get_state(), A.get_state()), f"batch, schedule {schedule}"
+        del Bt, C
     tl = T.export()
     om = OMesh(mm["coords"], mm["cells"], eps=eps, mu=mu)
     tau = np.zeros(M.info["nv"])
