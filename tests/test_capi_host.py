@@ -250,6 +250,25 @@ def test_p4_patch_classes_accept_up_to_48_tets():
     assert mtp.mtp_solver_workspace_size(Mb.h, Tb.h, 3, 4, 6, mtp.MTP_MIXED_FP32) > 0
 
 
+def test_auto_pitch_stops_the_losing_colour_table():
+    """On a jittered Delaunay cube the colour table makes more work (761 against 484 tents
+    at slab 0.05); the library stops its colour pitch once that work reaches the minimum-vertex
+    table's, and still returns the oracle's choice, bit for bit."""
+    from cases import build_mesh
+    mm = build_mesh(("delaunay48", 4))
+    om = OMesh(mm["coords"], mm["cells"])
+    ot = opitch(om, 0.05, 0.5, rule="auto")
+    assert ot["rule"] == "min_vertex"
+    assert len(opitch(om, 0.05, 0.5, rule="colour")["vertex"]) > len(ot["vertex"])
+    M = mtp.Mesh(mm["coords"], mm["cells"])
+    tents = mtp.Tents(M, 0.05, 0.5, rule=mtp.MTP_PITCH_AUTO)
+    assert tents.rule == mtp.MTP_PITCH_MIN_VERTEX
+    ex = tents.export()
+    order = np.argsort(ot["layer"], kind="stable")
+    for k in ("vertex", "t_bot", "t_top", "layer"):
+        assert np.array_equal(ex[k], ot[k][order]), k
+
+
 @pytest.mark.parametrize("name", ["square6", "disk8", "kuhn3", "graded3_eps"])
 def test_auto_pitch_matches_oracle_bit_exact(name):
     """MTP_PITCH_AUTO: the library picks the same ordering as the oracle and the same table,
