@@ -223,11 +223,12 @@ void mtp_tents_destroy(mtp_tents tents);
 mtp_status mtp_solver_workspace_size(mtp_mesh mesh, mtp_tents tents, int32_t p, int32_t q,
                                      int32_t m, int32_t precision, size_t* bytes);
 /* Create a solver: spatial degree p (1..5 in 2D, 1..5 in 3D; 3D P5 on the matrix-core
- * kernels only, for vertex patches of up to 24 tets; P4 in 3D takes vertex patches of up to
- * 48 tets (section 2: a tent covers the vertex patch): up to 36 with the operator block in
- * device memory, 37-48 with the tent's face fluxes and stage residual in device memory,
- * 1024 workgroup slots of about 104 KB that the workspace includes; a batch holding such
- * a degree group has slots of its own in its workspace), Taylor order q >= 1 and
+ * kernels only).  Vertex patches of up to 48 tets (section 2: a tent covers the vertex
+ * patch).  P4 in 3D: up to 36 with the operator block in device memory, 37-48 with the
+ * tent's face fluxes and stage residual in device memory as well (1024 workgroup slots of
+ * about 104 KB that the workspace includes).  P5 in 3D: the operator block in device
+ * memory, and for 25-48 tets the slots too (about 130 KB each).  A batch holding a degree
+ * group with such slots has slots of its own in its workspace.  Taylor order q >= 1 and
  * m >= 1 sub-intervals per tent (section 4; the paper uses q = p+1, m = 2p), flux
  * penalty alpha (1/2 is the exact upwind flux for unit impedance, 1 the printed
  * coefficient).  d_workspace: device pointer of at least the reported bytes, owned by

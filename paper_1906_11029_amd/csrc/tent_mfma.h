@@ -169,12 +169,13 @@ struct MShape {
 };
 
 // The capacity classes of the patch size: 8, 24, and a large class of 48 tets, or 36 for
-// P4 in 3D (the largest whose tent region fits the LDS once the operator block is moved out),
-// which has a fourth, extra-large class of 48 (F/R in device memory); P5 in 3D stops at 24.
+// P4 in 3D (the largest whose tent region fits the LDS once the operator block is moved out)
+// and 24 for P5 in 3D; these two have a further, extra-large class of 48 (F/R in device
+// memory, and at P5 the operator block too).
 template <int D, int P>
 __host__ __device__ constexpr int big_class() { return D == 3 ? (P == 4 ? 36 : P >= 5 ? 24 : 48) : 48; }
 template <int D, int P>
-__host__ __device__ constexpr int xl_class() { return D == 3 && P == 4 ? 48 : -1; }
+__host__ __device__ constexpr int xl_class() { return D == 3 && (P == 4 || P == 5) ? 48 : -1; }
 
 // LDS layout, identical for both variants (state, fluxes and operators stored in FP64; the
 // mixed variant only changes the precision of the products of stages n >= 2): an operator
@@ -204,9 +205,10 @@ struct MLds {
   // is the B operand of the lift part only and the input of the pointwise update, read far
   // less often than the operator.
   static constexpr bool FRG = NTMAX == xl_class<D, P>();
-  static constexpr bool OPG = !FRG && (op_block + common) * 8 > LDS_LIMIT && common * 8 <= LDS_LIMIT;
+  static constexpr size_t lds_common = common - (FRG ? f_elems : 0);   // the tent region in LDS
+  static constexpr bool OPG = (op_block + lds_common) * 8 > LDS_LIMIT && lds_common * 8 <= LDS_LIMIT;
   static constexpr size_t frg_doubles = FRG ? f_elems : 0;
-  static constexpr size_t bytes = ((OPG ? 0 : op_block) + common - frg_doubles) * 8;
+  static constexpr size_t bytes = ((OPG ? 0 : op_block) + lds_common) * 8;
 };
 
 // LDS pointers of one degree's operator block and of the tent region
@@ -1370,7 +1372,10 @@ size_t opg_mp(int max_patch, int system) {
   if (max_patch <= 8) return opg_m<D, P, T, 8>(system);
   if (max_patch <= 24) return opg_m<D, P, T, 24>(system);
   if (max_patch <= NB) return opg_m<D, P, T, NB>(system);
-  return 0;   // the extra-large class keeps its operator in LDS
+  constexpr int XL = xl_class<D, P>();
+  if constexpr (XL > 0)
+    if (max_patch <= XL) return opg_m<D, P, T, XL>(system);
+  return 0;
 }
 
 // Bytes of one workgroup's F/R slot in device memory for the class max_patch falls in (0 if
@@ -1408,7 +1413,9 @@ hipError_t stage_mp(const KernelParams& kp, hipStream_t s) {
   if (kp.max_patch <= 8) return stage_m<D, P, T, 8>(kp, s);
   if (kp.max_patch <= 24) return stage_m<D, P, T, 24>(kp, s);
   if (kp.max_patch <= NB) return stage_m<D, P, T, NB>(kp, s);
-  if (kp.max_patch <= xl_class<D, P>()) return hipSuccess;   // operator staged in LDS
+  constexpr int XL = xl_class<D, P>();
+  if constexpr (XL > 0)
+    if (kp.max_patch <= XL) return stage_m<D, P, T, XL>(kp, s);
   return hipErrorInvalidValue;
 }
 

@@ -150,7 +150,8 @@ size_t tent_mfma_opg_bytes(int d, int p, int max_patch, int fp32, int system) {
 }
 
 size_t tent_mfma_frg_bytes(int d, int p, int max_patch, int fp32, int system) {
-  if (d != 3 || p != 4) return 0;   // only P4 in 3D has the extra-large class
+  if (d != 3 || (p != 4 && p != 5)) return 0;   // only P4 and P5 in 3D have the extra-large class
+  if (p == 5) return fp32 ? frg_mp<3, 5, float>(max_patch, system) : frg_mp<3, 5, double>(max_patch, system);
   return fp32 ? frg_mp<3, 4, float>(max_patch, system) : frg_mp<3, 4, double>(max_patch, system);
 }
 

@@ -63,6 +63,10 @@ LARGE_P4_CASES = {
                               method="rk4"),
     "ac_delaunay48_p4_rk4": dict(mesh=("delaunay48", 4), p=4, q=5, m=8, T=0.04, kind=PMC, exact="ac_pulse3",
                                  system="acoustic", method="rk4"),
+    # P5 on the same cubes: patches of 25-36 and 37-48 tets (operator block and F/R in device memory)
+    "delaunay3d_p5": dict(mesh=("delaunay", 3), p=5, q=6, m=10, T=0.02, kind=PEC, exact="pec_3d"),
+    "delaunay48_p5_pmc_eps": dict(mesh=("delaunay48", 4), p=5, q=6, m=10, T=0.02, kind=PMC, exact="pec_3d",
+                                  eps_split=True),
 }
 
 # the classical RK4 variant (method="rk4"): same inputs, RK4 on the tent ODE
