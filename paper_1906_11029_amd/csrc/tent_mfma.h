@@ -518,8 +518,40 @@ __device__ __forceinline__ void tile_product(const double* sOp, const float* sOp
       }
 #pragma unroll
       for (int mr = 0; mr < MTF; ++mr) part(mr * ntiles + nt, ac[mr], am[mr], std::false_type{});
+      if constexpr (FRGM) {
+        // F in device memory: the lift part of every row tile of the block in one loop over
+        // K, the block's F values (the B operand the row tiles share) loaded once, in one
+        // round trip, the operator (the A operands) read from LDS as the steps go
+        constexpr int NL = NG - NB;
+        const int kq = lane >> 4;
+        const int col = nt * 16 + (lane & 15);
+        const bool live = col < ncols;
+        const int colp = live ? col : 0;
+        const TM fm = live ? (TM)1 : (TM)0;
+        const double* fr = sFR + kq * RS + colp;
+        double fb[NL];
 #pragma unroll
-      for (int mr = 0; mr < MTF; ++mr) part(mr * ntiles + nt, ac[mr], am[mr], std::true_type{});
+        for (int i = 0; i < NL; ++i)
+          fb[i] = (4 * i + 3 < KF) ? fr[4 * i * RS] : sFR[min(4 * i + kq, KF - 1) * RS + colp];
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+          const TM b = fm * (TM)fb[i];
+#pragma unroll
+          for (int mr = 0; mr < MTF; ++mr) {
+            const double* acol = sOp + (MTF - 1 - mr) * 16 + (lane & 15) + kq * OPS;
+            ac[mr] = MM::mma((TM)acol[(KV + 4 * i) * OPS], b, ac[mr]);
+            if constexpr (MINI) {
+              if (mr == 0) {
+                const double* acolm = sOp + MTF * 16 + (lane & 3) + kq * OPS;
+                am[0] = MM::mini((TM)acolm[(KV + 4 * i) * OPS], b, am[0]);
+              }
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int mr = 0; mr < MTF; ++mr) part(mr * ntiles + nt, ac[mr], am[mr], std::true_type{});
+      }
 #pragma unroll
       for (int mr = 0; mr < MTF; ++mr) write_r(mr * ntiles + nt, ac[mr], am[mr]);
     }
