@@ -221,6 +221,8 @@ struct mtp_batch_s {
     int p = 0, max_patch = 0, s0 = 0, s1 = 0;
     int grid_max = 0;             // resident maximum of the group's persistent kernel
     mtp::BatchDag bd{};           // persistent schedule over the group's tent DAGs
+    double* opg = nullptr;        // the group's operator block in device memory (classes that
+                                  // keep it there), staged by the batch; null otherwise
   };
   struct Launch {                 // one layer of one degree group
     int64_t seg0 = 0, blocks = 0;
@@ -231,7 +233,7 @@ struct mtp_batch_s {
   std::vector<Group> groups;
   std::vector<Launch> launches;
   int kernel = 0, d = 0, system = 0, method = 0;
-  double* frg = nullptr;          // F/R slots of the 48-tet P4 class (kFrgSlots of them), or null
+  double* frg = nullptr;          // F/R slots of the 48-tet class (kFrgSlots of them), or null
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   mtp::KernelParams* d_kps = nullptr;
@@ -967,9 +969,17 @@ static int64_t batch_tents(const mtp_solver* solvers, int32_t n) {
 constexpr int kMaxBatchGroups = 8;
 
 struct BatchLayout {
-  size_t kps, segs, queue, ctl, off, roff, frg, total;
-  size_t frg_bytes = 0;   // F/R slots of a degree group in the 48-tet P4 class (shared by the groups)
+  size_t kps, segs, queue, ctl, off, roff, frg, opg, total;
+  size_t frg_bytes = 0;   // F/R slots of a degree group in the 48-tet class (shared by the groups)
+  size_t opg_bytes = 0;   // operator blocks of the degree groups whose class keeps it in device memory
 };
+// largest vertex patch of the batch's solvers of degree p
+static int group_max_patch(const mtp_solver* solvers, int32_t n, int p) {
+  int g = 0;
+  for (int j = 0; j < n; ++j)
+    if (solvers[j]->p == p) g = std::max(g, solvers[j]->mesh.max_patch);
+  return g;
+}
 static BatchLayout batch_layout(const mtp_solver* solvers, int32_t n) {
   Layout L;
   BatchLayout o;
@@ -983,14 +993,23 @@ static BatchLayout batch_layout(const mtp_solver* solvers, int32_t n) {
   // kFrgSlots slots; the groups run one after another on the batch's stream and share them
   size_t slot = 0;
   for (int i = 0; i < n; ++i) {
-    int gmax = 0;
-    for (int j = 0; j < n; ++j)
-      if (solvers[j]->p == solvers[i]->p) gmax = std::max(gmax, solvers[j]->mesh.max_patch);
     const mtp_solver s = solvers[i];
-    slot = std::max(slot, tent_mfma_frg_bytes(s->mesh.d, s->p, gmax, s->kernel == 2, s->mesh.system));
+    slot = std::max(slot, tent_mfma_frg_bytes(s->mesh.d, s->p, group_max_patch(solvers, n, s->p), s->kernel == 2,
+                                              s->mesh.system));
   }
   o.frg_bytes = slot * kFrgSlots;
   o.frg = L.add(o.frg_bytes);
+  // a degree group whose class keeps the operator block in device memory runs on the batch's
+  // own copy: a member whose own patches fit a smaller class has none
+  std::vector<int> degs;
+  for (int i = 0; i < n; ++i)
+    if (std::find(degs.begin(), degs.end(), solvers[i]->p) == degs.end()) degs.push_back(solvers[i]->p);
+  for (int p : degs) {
+    const mtp_solver s = solvers[0];
+    o.opg_bytes += (tent_mfma_opg_bytes(s->mesh.d, p, group_max_patch(solvers, n, p), s->kernel == 2, s->mesh.system) +
+                    255) / 256 * 256;
+  }
+  o.opg = L.add(o.opg_bytes);
   o.total = L.off;
   return o;
 }
@@ -1067,6 +1086,21 @@ mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_worksp
     b->d_kps = reinterpret_cast<KernelParams*>(b->ws + lo.kps);
     b->d_segs = reinterpret_cast<BatchSeg*>(b->ws + lo.segs);
     if (lo.frg_bytes > 0) b->frg = reinterpret_cast<double*>(b->ws + lo.frg);
+    // the operator blocks of the groups that keep it in device memory, staged once here
+    {
+      size_t off = 0;
+      for (auto& g : b->groups) {
+        const size_t nb = tent_mfma_opg_bytes(b->d, g.p, g.max_patch, b->kernel == 2, b->system);
+        if (nb == 0) continue;
+        require(off + nb <= lo.opg_bytes, MTP_ERR_STATE, "batch operator blocks exceed their region");
+        KernelParams kp = solvers[b->order[g.s0]]->kp;   // the degree's reference tables
+        kp.max_patch = g.max_patch;
+        kp.opg = reinterpret_cast<double*>(b->ws + lo.opg + off);
+        check_hip(stage_tent_operator_mfma(kp, b->kernel == 2, b->stream), "batch operator staging");
+        g.opg = kp.opg;
+        off += (nb + 255) / 256 * 256;
+      }
+    }
     // persistent schedule, per group: tent ids solver by solver, first-layer tents first in the queue
     {
       std::vector<int32_t> off(n + kMaxBatchGroups, 0), roff(n + kMaxBatchGroups, 0);
@@ -1189,9 +1223,12 @@ mtp_status mtp_batch_advance(mtp_batch b, int64_t n_slabs) {
     require(s->method == b->method, MTP_ERR_STATE, "a solver's method changed after the batch was created");
     b->h_kps[j] = s->kp;
     b->h_kps[j].tile_order = b->tile_order;
-    // the 48-tet P4 class: every launch takes its F/R slots from the batch's own
+    // the 48-tet class: every launch takes its F/R slots from the batch's own; a group whose
+    // class keeps the operator block in device memory reads the batch's copy
     b->h_kps[j].frg = b->frg;
     b->h_kps[j].frg_slots = b->frg ? kFrgSlots : 0;
+    for (const auto& g : b->groups)
+      if (j >= g.s0 && j < g.s1 && g.opg) b->h_kps[j].opg = g.opg;
     // work the solvers enqueued on their own streams comes first
     if (s->stream != b->stream) check_hip(hipStreamSynchronize(s->stream), "sync solver stream");
   }

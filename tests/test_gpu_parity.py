@@ -448,6 +448,27 @@ def test_xl_p4_patches_against_oracle(name, precision, tol, schedule):
     assert_parity(S.get_state(), ref["w"], tol, f"{name} w")
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("precision,tol", [(0, TOL), (1, MIXED_TOL)])
+def test_p4_batch_mixing_patch_classes(precision, tol, schedule):
+    """A P4 group of a Kuhn cube (patches up to 24 tets: its own solver keeps the operator in
+    LDS) and the jittered Delaunay cube (up to 36): the group runs in the 36-tet class, whose
+    operator block the batch stages in its own workspace for every member, against the
+    oracle."""
+    from paper_1906_11029_amd import mtp
+    names = ["cav3d_p4", "delaunay3d_p4"]
+    print(f"[gpu parity] P4 batch of a 24- and a 36-tet-patch solve, precision {precision} schedule {schedule}",
+          flush=True)
+    refs = [fixture(n) for n in names]
+    made = [gpu_solver(n, precision) for n in names]
+    assert made[0][1].mesh.info["max_patch"] <= 24 < made[1][1].mesh.info["max_patch"] <= 36
+    B = mtp.Batch([S for _, S, _ in made])
+    B.set_schedule(schedule)
+    B.advance(1)
+    for (c, S, _), n, ref in zip(made, names, refs):
+        assert_parity(S.get_state(), ref["w"], tol, f"batch {n}")
+
+
 # batches with a degree group in the 48-tet P4 class (a 36-tet-patch solve joins the group
 # and runs in its class): name, cases, precisions
 XL_BATCHES = [("maxwell", ["delaunay48_p4", "delaunay48_p4_pmc_eps", "delaunay3d_p4"], (0, 1)),
