@@ -323,7 +323,11 @@ mtp_status mtp_get_state(mtp_solver solver, double* nodal, int32_t on_device);
  * solver forward by n_slabs of its own slab height; the first call captures one batched
  * slab into a HIP graph that later calls replay.  Solvers keep their handles and state;
  * a solver must not be advanced on its own while a batch call is in flight.
- * d_workspace: caller-owned device memory of mtp_batch_workspace_size bytes. */
+ * d_workspace: caller-owned device memory of mtp_batch_workspace_size bytes: the parameter
+ * blocks, layer segments and persistent-schedule queues, plus, for a degree group whose
+ * largest patch puts it in a class that keeps the operator block or the face fluxes and
+ * stage residual in device memory (3D P4 beyond 24 tets, 3D P5), the batch's own copy of
+ * that block (staged at creation) and its own F/R slots. */
 mtp_status mtp_batch_workspace_size(const mtp_solver* solvers, int32_t n, size_t* bytes);
 mtp_status mtp_batch_create(const mtp_solver* solvers, int32_t n, void* d_workspace, size_t bytes,
                             void* hip_stream, mtp_batch* out);
